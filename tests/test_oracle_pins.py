@@ -1,0 +1,402 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here runs on a GPU.  Every oracle function is tied to at least one of:
+a brute-force tensor contraction (n <= 4), a closed form, a value the paper
+prints, an end point of a channel's parameter range, or a gate identity.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from oracle import channels as ch
+from oracle.core import OracleDM
+from oracle.emulator import emulate
+from workloads import c1_line_circuit, random_matrix_ops
+from tests import _brute as bf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def random_state(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((1 << n, 1 << n)) + 1j * rng.standard_normal((1 << n, 1 << n))
+    rho = A @ A.conj().T
+    return rho / np.trace(rho)
+
+
+def random_nonhermitian(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((1 << n, 1 << n)) + 1j * rng.standard_normal((1 << n, 1 << n))
+
+
+def oracle_with(rho):
+    n = int(round(math.log2(rho.shape[0])))
+    dm = OracleDM(n)
+    dm.set(rho)
+    return dm
+
+
+# ------------------------------------------------------------ brute force --
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_matrix_and_kraus_match_bruteforce(n):
+    """Random (non-unitary, non-TP) matrices and Kraus sets on random targets,
+    applied to a non-Hermitian start so that a swapped or missing conjugate
+    shows up."""
+    rho = random_nonhermitian(n, 11 + n)
+    dm = oracle_with(rho)
+    ref = rho.copy()
+    for kind, tg, params in random_matrix_ops(n, 24, seed=100 + n, max_k=min(2, n)):
+        if kind == "matrix":
+            dm.apply_matrix(tg, params[0])
+            ref = bf.apply_op(ref, n, tg, params[0])
+        else:
+            dm.apply_kraus(tg, params)
+            ref = bf.apply_kraus(ref, n, tg, params)
+    scale = np.abs(ref).max()
+    assert np.abs(dm.R - ref).max() <= 1e-12 * max(scale, 1.0)
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_wide_ops_match_bruteforce(k):
+    n = 4
+    rng = np.random.default_rng(k)
+    rho = random_nonhermitian(n, 3)
+    tg = tuple(int(x) for x in rng.permutation(n)[:k])
+    M = (rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))) / 4
+    Ks = [(rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))) / 6
+          for _ in range(2)]
+    dm = oracle_with(rho)
+    dm.apply_matrix(tg, M)
+    dm.apply_kraus(tg, Ks)
+    ref = bf.apply_kraus(bf.apply_op(rho, n, tg, M), n, tg, Ks)
+    assert np.abs(dm.R - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_embedding_bit_order():
+    """targets[0] is the least significant bit: X on qubit 2 of |0000> gives
+    basis state 4; a 2-qubit matrix mapping index 1 -> 2 on targets (3, 0)
+    moves a 1 from qubit 3 to qubit 0."""
+    dm = OracleDM(4)
+    dm.apply_matrix((2,), ch.X)
+    assert dm.R[4, 4] == 1.0
+    M = np.zeros((4, 4), dtype=complex)
+    M[2, 1] = 1.0   # |b0=1,b1=0> -> |b0=0,b1=1>, b0 on target 3, b1 on target 0
+    for i in (0, 1, 3):
+        M[i, i] = 1.0
+    M[1, 2] = 1.0
+    dm.init_basis(8)
+    dm.apply_matrix((3, 0), M)
+    assert dm.R[1, 1] == 1.0
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_readouts_match_bruteforce(n):
+    rho = random_state(n, 7 * n)
+    dm = oracle_with(rho)
+    D = 1 << n
+    assert abs(dm.trace() - np.trace(rho)) < 1e-14
+    assert np.allclose(dm.probs(), np.real(np.diag(rho)), atol=1e-15)
+    Zs = [np.real(np.trace(bf.pauli_string([3 if q == i else 0 for q in range(n)]) @ rho))
+          for i in range(n)]
+    assert np.allclose(dm.expec_z(), Zs, atol=1e-14)
+    pairs = [(i, j) for i in range(n) for j in range(n) if i != j]
+    ZZ = [np.real(np.trace(bf.pauli_string([3 if q in (i, j) else 0 for q in range(n)]) @ rho))
+          for i, j in pairs]
+    assert np.allclose(dm.expec_zz(pairs), ZZ, atol=1e-14)
+    assert abs(dm.purity() - np.real(np.trace(rho @ rho))) < 1e-14
+    rng = np.random.default_rng(n)
+    for _ in range(12):
+        codes = rng.integers(0, 4, n)
+        ref = np.trace(bf.pauli_string(codes) @ rho)
+        assert abs(dm.expec_pauli(codes) - ref) < 1e-14
+    assert D == rho.shape[0]
+
+
+def test_initial_states():
+    dm = OracleDM(3)
+    dm.init_basis(5)
+    assert dm.R[5, 5] == 1 and np.count_nonzero(dm.R) == 1
+    p0 = np.array([0.9, 0.8, 0.7])
+    dm.init_product_diag(p0)
+    # eq. (thermalstate): tensor product of p|0><0| + (1-p)|1><1|
+    ref = np.array([[1.0]])
+    for p in p0:
+        ref = np.kron(np.diag([p, 1 - p]), ref)
+    assert np.allclose(dm.R, ref, atol=1e-16)
+
+
+# --------------------------------------------------- pure-state reference --
+
+def test_noise_free_circuit_matches_state_vector():
+    """Gates only: rho must equal |psi><psi| of an independent state-vector run."""
+    n = 5
+    ops = [op for op in c1_line_circuit(n=n, n_gates=60) if op[0] in ("rx", "ry", "rz", "cz")]
+    dm = emulate(n, ops)
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[0] = 1
+    for kind, tg, params in ops:
+        U = ch.gate_matrix(kind, params)
+        psi = bf.embed(n, tg, U) @ psi
+    assert np.abs(dm.R - np.outer(psi, psi.conj())).max() < 1e-13
+    assert abs(dm.purity() - 1) < 1e-13
+
+
+# ------------------------------------------------------ textbook states --
+
+def bell_ops(a, b):
+    """H on a, then CNOT(a -> b) written as H_b CZ H_b."""
+    return [("h", (a,), ()), ("h", (b,), ()), ("cz", (a, b), ()), ("h", (b,), ())]
+
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_ghz(n):
+    ops = [("h", (0,), ())]
+    for q in range(1, n):
+        ops += [("h", (q,), ()), ("cz", (q - 1, q), ()), ("h", (q,), ())]
+    dm = emulate(n, ops)
+    D = 1 << n
+    nz = np.argwhere(np.abs(dm.R) > 1e-12)
+    assert sorted(map(tuple, nz)) == [(0, 0), (0, D - 1), (D - 1, 0), (D - 1, D - 1)]
+    assert np.allclose(dm.R[[0, 0, D - 1, D - 1], [0, D - 1, 0, D - 1]], 0.5, atol=1e-14)
+    assert np.allclose(dm.expec_z(), 0, atol=1e-14)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    assert np.allclose(dm.expec_zz(pairs), 1, atol=1e-14)
+    assert abs(dm.purity() - 1) < 1e-14
+
+
+# -------------------------------------------------------- closed forms --
+
+@pytest.mark.parametrize("p,k", [(0.01, 7), (0.2, 3), (0.75, 2)])
+def test_depol1_purity_decay(p, k):
+    """Each depol1(p) scales the Bloch vector by 1 - 4p/3, so k applications on
+    |0> give purity (1 + (1-4p/3)^(2k)) / 2 (on one qubit of a 3-qubit product)."""
+    dm = emulate(3, [("depol1", (1,), (p,))] * k)
+    assert abs(dm.purity() - (1 + (1 - 4 * p / 3) ** (2 * k)) / 2) < 1e-14
+
+
+@pytest.mark.parametrize("p,k", [(0.05, 4), (0.3, 2)])
+def test_dephasing_x_decay(p, k):
+    """deph1(p) k times on |+>: <X> = (1-2p)^k."""
+    dm = emulate(2, [("h", (0,), ())] + [("deph1", (0,), (p,))] * k)
+    assert abs(dm.expec_pauli([1, 0]).real - (1 - 2 * p) ** k) < 1e-14
+
+
+def test_t1_t2_exponentials():
+    """eq. (ampt1) compounded over total time t: P(1) = exp(-t/T1) exactly.
+    With eq. (depht2) as well, on |+>: <X> = exp(-t/T2) exp(-t/(2 T1))."""
+    T1, T2, dt, steps = 100.0, 50.0, 0.5, 40
+    t = dt * steps
+    dm = emulate(2, [("x", (1,), ())] + [("amp_t1", (1,), (dt, T1))] * steps)
+    assert abs(dm.probs()[2] - math.exp(-t / T1)) < 1e-14
+    ops = [("h", (0,), ())]
+    for _ in range(steps):
+        ops += [("amp_t1", (0,), (dt, T1)), ("deph_t2", (0,), (dt, T2))]
+    dm = emulate(2, ops)
+    assert abs(dm.expec_pauli([1, 0]).real - math.exp(-t / T2) * math.exp(-t / (2 * T1))) < 1e-14
+
+
+@pytest.mark.parametrize("p", [0.0, 0.05, 0.5, 15 / 16])
+def test_depol2_on_bell(p):
+    """depol2(p) on |Phi+>: fidelity 1 - 4p/5 (3 of the 15 Paulis stabilise it)."""
+    dm = emulate(2, bell_ops(0, 1) + [("depol2", (0, 1), (p,))])
+    phi = np.array([1, 0, 0, 1]) / math.sqrt(2)
+    assert abs(phi @ dm.R @ phi - (1 - 4 * p / 5)) < 1e-14
+
+
+@pytest.mark.parametrize("p,q", [(0.07, 0.13), (0.0, 0.3), (0.25, 0.0), (0.5, 0.75)])
+def test_entanglement_fidelity_1q(p, q):
+    """App. B eq. (fe1): F_e of deph(p) o depol(q) on one half of |Phi+> is
+    1 - p - q + 4/3 p q."""
+    dm = emulate(2, bell_ops(0, 1) + [("depol1", (0,), (q,)), ("deph1", (0,), (p,))])
+    phi = np.array([1, 0, 0, 1]) / math.sqrt(2)
+    assert abs(phi @ dm.R @ phi - (1 - p - q + 4 / 3 * p * q)) < 1e-14
+
+
+@pytest.mark.parametrize("p,q", [(0.07, 0.13), (0.3, 0.6)])
+def test_entanglement_fidelity_2q(p, q):
+    """App. B: on two Bell pairs (qubits 0-2 and 1-3), deph2(p) o depol2(q) on
+    (0, 1) gives F_e = 1 - p - q + 16/15 p q."""
+    ops = bell_ops(0, 2) + bell_ops(1, 3) + [("depol2", (0, 1), (q,)), ("deph2", (0, 1), (p,))]
+    dm = emulate(4, ops)
+    ref = emulate(4, bell_ops(0, 2) + bell_ops(1, 3))
+    F = np.real(np.trace(ref.R @ dm.R))
+    assert abs(F - (1 - p - q + 16 / 15 * p * q)) < 1e-14
+
+
+def test_ion_bell_pair_psi_minus_population():
+    """The paper prints 0.046 for the |Psi^-> population of the raw ion Bell pair."""
+    g = json.load(open(os.path.join(GOLDEN, "ion_bell_psi_minus.json")))
+    psi_p = np.array([0, 1, 1, 0]) / math.sqrt(2)
+    psi_m = np.array([0, 1, -1, 0]) / math.sqrt(2)
+    base = bell_ops(0, 1) + [("x", (1,), ())]          # |Psi+>
+
+    def state(eps):
+        return emulate(2, base + [("depol2", (0, 1), (g["depol_fraction"] * eps,)),
+                                  ("deph2", (0, 1), (g["deph_fraction"] * eps,))]).R
+
+    eps = brentq(lambda e: np.real(psi_p @ state(e) @ psi_p) - g["fid_ent"], 0.0, 0.5, xtol=1e-15)
+    pm = np.real(psi_m @ state(eps) @ psi_m)
+    assert abs(pm - g["psi_minus_population"]) <= g["abs_tolerance"]
+
+
+# ------------------------------------------------------ channel end points --
+
+def test_channel_end_points():
+    rho = random_state(2, 5)
+    # eq. (damp): p = 1 sends every state of that qubit to |0><0|
+    dm = oracle_with(rho)
+    dm.apply_kraus((0,), ch.amp(1.0))
+    red = dm.R.reshape(2, 2, 2, 2).trace(axis1=0, axis2=2)   # trace out qubit 1
+    assert np.allclose(red, np.diag([1, 0]), atol=1e-15)
+    # eq. (depol1) at p = 3/4: the qubit becomes maximally mixed
+    dm = oracle_with(rho)
+    dm.apply_kraus((1,), ch.depol1(0.75))
+    red0 = dm.R.reshape(2, 2, 2, 2).trace(axis1=1, axis2=3)  # trace out qubit 0
+    assert np.allclose(red0, np.eye(2) / 2, atol=1e-15)
+    # eq. (depol2) at p = 15/16: the pair becomes I/4
+    dm = oracle_with(rho)
+    dm.apply_kraus((0, 1), ch.depol2(15 / 16))
+    assert np.allclose(dm.R, np.eye(4) / 4, atol=1e-15)
+    # eq. (deph1) at p = 1/2: coherences of that qubit vanish
+    dm = oracle_with(rho)
+    dm.apply_kraus((0,), ch.deph1(0.5))
+    R4 = dm.R.reshape(2, 2, 2, 2)        # (r1, r0, c1, c0)
+    assert np.allclose(R4[:, 0, :, 1], 0, atol=1e-16) and np.allclose(R4[:, 1, :, 0], 0, atol=1e-16)
+    # eq. (bf) at b = 1/2: <Z> of that qubit is 0
+    dm = oracle_with(rho)
+    dm.apply_kraus((1,), ch.bitflip1(0.5))
+    assert abs(dm.expec_z()[1]) < 1e-15
+    # eq. (gdamp) with gamma = 1 sends the qubit to p|0><0| + (1-p)|1><1|
+    dm = oracle_with(rho)
+    dm.apply_kraus((0,), ch.gamp(0.8, 1.0))
+    red = dm.R.reshape(2, 2, 2, 2).trace(axis1=0, axis2=2)
+    assert np.allclose(red, np.diag([0.8, 0.2]), atol=1e-15)
+
+
+def test_cptp_sets_and_cptn_leakage():
+    for Ks in (ch.depol1(0.1), ch.depol2(0.2), ch.deph1(0.3), ch.deph2(0.4), ch.amp(0.5),
+               ch.gamp(0.7, 0.2), ch.bitflip1(0.1), ch.bitflip2(0.2)):
+        d = Ks[0].shape[0]
+        assert np.allclose(sum(K.conj().T @ K for K in Ks), np.eye(d), atol=1e-15)
+    # eq. (czleak): K = diag(1, sqrt(1-a), sqrt(1-a), sqrt(1-b)) is trace
+    # decreasing; the trace lost from |11> is exactly b
+    a, b = 0.02, 0.05
+    K = np.diag([1, math.sqrt(1 - a), math.sqrt(1 - a), math.sqrt(1 - b)])
+    dm = OracleDM(2)
+    dm.init_basis(3)
+    dm.apply_kraus((0, 1), [K])
+    assert abs(dm.trace() - (1 - b)) < 1e-15
+
+
+def test_silicon_parity_decay_map():
+    """Sec. 7: K = {|00><00|, |11><11|, |10><10|, |10><01|} sums to the identity and
+    sends |0_i 1_j> to |1_i 0_j> (ket |a b> on (i, j) means a on i)."""
+    def ket(a, b):       # a on qubits[0] (LSB), b on qubits[1]
+        v = np.zeros(4)
+        v[a + 2 * b] = 1
+        return v
+    Ks = [np.outer(ket(0, 0), ket(0, 0)), np.outer(ket(1, 1), ket(1, 1)),
+          np.outer(ket(1, 0), ket(1, 0)), np.outer(ket(1, 0), ket(0, 1))]
+    assert np.allclose(sum(K.T @ K for K in Ks), np.eye(4))
+    dm = OracleDM(3)
+    dm.init_basis(0b100)         # qubit i=1 is 0, qubit j=2 is 1
+    dm.apply_kraus((1, 2), Ks)
+    assert abs(dm.R[0b010, 0b010] - 1) < 1e-15
+
+
+# ------------------------------------------------------- gate identities --
+
+def raman_u(phi, delta, omega, t):
+    """eq. (u) of Sec. 6 (neutral atoms)."""
+    w = math.sqrt(omega ** 2 + delta ** 2)
+    c, s = math.cos(w * t / 2), math.sin(w * t / 2)
+    return np.array([[c - 1j * delta / w * s, -1j * omega / w * s * np.exp(1j * phi)],
+                     [-1j * omega / w * s * np.exp(-1j * phi), c + 1j * delta / w * s]])
+
+
+def same_up_to_phase(A, B):
+    k = np.argmax(np.abs(B))
+    ph = A.flat[k] / B.flat[k]
+    return abs(abs(ph) - 1) < 1e-12 and np.allclose(A, ph * B, atol=1e-12)
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.7, 4.0])
+def test_rx_is_raman_u_at_zero_detuning(theta):
+    omega = 2.3
+    assert np.allclose(ch.gate_matrix("rx", (theta,)), raman_u(0, 0, omega, theta / omega), atol=1e-14)
+
+
+def test_hadamard_from_raman_u():
+    omega = 1.1
+    w = math.sqrt(2) * omega
+    assert same_up_to_phase(raman_u(0, omega, omega, math.pi / w), ch.gate_matrix("h", ()))
+
+
+def test_rydberg_cz_phi_zero_is_cz():
+    phi = 0.0
+    czphi = np.diag([1, np.exp(1j * phi), np.exp(1j * phi), np.exp(1j * (2 * phi - math.pi))])
+    assert np.allclose(czphi, ch.gate_matrix("cz", ()), atol=1e-15)
+
+
+def test_exchange_at_pi_is_swap():
+    """eq. (exchange_pauli) at theta = pi is SWAP up to a global phase."""
+    G = sum(ch.on2(P, P) for P in (ch.X, ch.Y, ch.Z))
+    from scipy.linalg import expm
+    U = expm(-1j * G * math.pi / 4)
+    dm = OracleDM(2)
+    dm.init_basis(0b01)
+    dm.apply_matrix((0, 1), U)
+    assert abs(dm.R[0b10, 0b10] - 1) < 1e-14
+
+
+def test_off_resonant_tends_to_identity():
+    """eq. (off_resonant) approaches the identity (up to phases on the diagonal
+    that cancel in rho) as the detuning grows."""
+    omega, t = 1.0, 3.0
+    dm = OracleDM(1)
+    dm.apply_matrix((0,), ch.gate_matrix("h", ()))
+    ref = dm.R.copy()
+    for delta, tol in ((1e2, 1e-2), (1e4, 1e-4)):
+        w = math.sqrt(omega ** 2 + delta ** 2)
+        c, s = math.cos(w * t / 2), math.sin(w * t / 2)
+        U = np.array([[(c - 1j * delta / w * s) * np.exp(1j * w * t / 2), -1j * omega / w * s * np.exp(1j * w * t / 2)],
+                      [-1j * omega / w * s * np.exp(-1j * w * t / 2), (c + 1j * delta / w * s) * np.exp(-1j * w * t / 2)]])
+        d2 = OracleDM(1)
+        d2.set(ref)
+        d2.apply_matrix((0,), U)
+        # populations are unchanged up to O(omega/delta)
+        assert abs(d2.R[0, 0] - ref[0, 0]) < tol
+
+
+def test_xx_at_half_pi_is_maximally_entangling():
+    dm = emulate(2, [("xx", (0, 1), (math.pi / 2,))])
+    # (|00> - i|11>)/sqrt2: populations 1/2, 1/2 and |coherence| 1/2
+    assert abs(dm.R[0, 0] - 0.5) < 1e-15 and abs(dm.R[3, 3] - 0.5) < 1e-15
+    assert abs(abs(dm.R[0, 3]) - 0.5) < 1e-15
+
+
+# ------------------------------------------------------------- invariants --
+
+def test_invariants_on_noisy_circuit():
+    """CPTP stream: trace 1, Hermitian, purity in (0, 1]."""
+    dm = emulate(6, c1_line_circuit(n=6, n_gates=60))
+    assert abs(dm.trace() - 1) < 1e-13
+    assert np.abs(dm.R - dm.R.conj().T).max() < 1e-14
+    assert 0 < dm.purity() <= 1 + 1e-14
+
+
+def test_unital_channels_do_not_raise_purity():
+    rho = random_state(3, 9)
+    dm = oracle_with(rho)
+    last = dm.purity()
+    for Ks, tg in ((ch.depol1(0.1), (0,)), (ch.deph2(0.2), (1, 2)), (ch.bitflip2(0.3), (2, 0)),
+                   (ch.depol2(0.05), (0, 2))):
+        dm.apply_kraus(tg, Ks)
+        cur = dm.purity()
+        assert cur <= last + 1e-15
+        last = cur

@@ -1,0 +1,20 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+This package only draws random numbers and lays out op streams.  It holds
+none of the emulation arithmetic: every gate or channel is emitted as
+``(kind, qubits, params)`` with the physical parameters (angles, times,
+probabilities) and each consumer builds its own matrices from them.
+"""
+from .circuits import (  # noqa: F401
+    SEED_BASE,
+    Op,
+    c1_line_circuit,
+    c2_grid_circuit,
+    c3_all_to_all_circuit,
+    c4_batch_instances,
+    c5_ansatz_circuit,
+    c5_draw_samples,
+    random_matrix_ops,
+    count_gates,
+    GATE_KINDS,
+)
