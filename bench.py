@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Benchmark of the density-matrix emulation hot path on one MI355X.
+
+A step is one whole noisy circuit on the 14-qubit density matrix (4^14
+complex128 amplitudes, 4.29 GB): init |0..0><0..0|, every gate and channel of
+the seeded 2x7-grid circuit (2000 SU(2)/CZ gates, 9378 density-matrix ops in
+all, including depolarising, T1/T2 and ZZ-crosstalk ops), then the read-outs
+<Z_i> and purity.  The op program is planned once (outside the timed region)
+into fused HBM passes.
+
+Prints one JSON line (see the fields below).  `value` is density-matrix ops
+per second (gates and channels); gates-only throughput is reported beside it.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DM gate-ops/s & HBM GB/s at 14q; surrogate vs emulator evals/s @ |ΔZ|<1e-2"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
+N_QUBITS = 14
+# planner options of the timed configuration (the GPU parity tests use the same)
+PLAN_OPTS = dict(tile_bits=12, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload():
+    from workloads import c2_grid_circuit
+    ops = c2_grid_circuit(rows=2, cols=7, n_gates=2000)
+    n_gates = sum(1 for k, _, _ in ops if k in ("su2", "cz"))
+    return ops, n_gates
+
+
+def cpu_baseline(ops, n, sample_every):
+    """The oracle (as it is) on a bounded sample of the same workload: every
+    `sample_every`-th op of the circuit applied to a 14-qubit state."""
+    from oracle.core import OracleDM
+    from oracle.emulator import emulate
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    sample = ops[::sample_every]
+    dm = OracleDM(n)
+    t0 = time.perf_counter()
+    emulate(n, sample, dm)
+    dt = time.perf_counter() - t0
+    return {"value": len(sample) / dt, "unit": "DM ops/s", "cores": threads, "kind": "oracle",
+            "sample": "%d ops (every %d-th op of the 14-qubit grid circuit) on a 14-qubit state, %.1f s"
+                      % (len(sample), sample_every, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-every", type=int, default=782)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2306_07342_amd import vqd
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    ops, n_gates = workload()
+    n = N_QUBITS
+    log("planning %d ops (%d gates) on %d qubits" % (len(ops), n_gates, n))
+    t = time.perf_counter()
+    prog = vqd.Program(n, ops).compile(vqd.plan_opts(**PLAN_OPTS))
+    info = prog.info()
+    log("plan: %s (%.2f s)" % (info, time.perf_counter() - t))
+    dm = vqd.DensityMatrix(n)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        dm.init_zero()
+        if ev:
+            ev[0].record(stream)
+        prog.run(dm)
+        if ev:
+            ev[1].record(stream)
+        z = dm.expec_z()
+        pur = dm.purity()
+        return z, pur
+
+    for w in range(args.warmup):
+        step()
+        log("warmup %d done" % w)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        z, pur = step(evs[k])
+        log("step %d done" % k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pass_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    tr = dm.trace()
+
+    amps = 4 ** n
+    bytes_per_pass = 32.0 * amps                 # read + write of every amplitude
+    avg_launch_s = pass_ms / 1e3 / info["n_passes"]
+    achieved_gbs = bytes_per_pass / avg_launch_s / 1e9
+    fp64_tflops = 2.0 * info["fma_per_amp"] * amps / (pass_ms / 1e3) / 1e12
+    hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    alu = {"bound": "alu", "achieved": round(fp64_tflops, 2), "peak": FP64_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(fp64_tflops / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    roof = hbm if hbm["frac"] >= alu["frac"] else alu
+
+    ms_per_step = wall / args.steps * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(len(ops) * args.steps / wall, 1),
+        "unit": "DM ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "14-qubit density matrix (complex128, 4^14 amps), 2x7 grid, "
+                               "2000-gate layered SU(2)+CZ circuit with depol2, ZZ crosstalk and T1/T2 noise",
+                   "n_qubits": n, "dm_ops_per_step": len(ops), "gates_per_step": n_gates,
+                   "seed": 2306073421, "parallelism": "single GPU"},
+        "gates_per_s": round(n_gates * args.steps / wall, 1),
+        "passes_per_step": info["n_passes"],
+        "phases_per_step": info["n_phases"],
+        "planned_fp64_fma_per_amp": round(info["fma_per_amp"], 1),
+        "pass_kernel_ms_per_step": round(pass_ms, 3),
+        "pass_kernel_avg_launch_us": round(avg_launch_s * 1e6, 2),
+        "roofline": roof,
+        "roofline_other": alu if roof is hbm else hbm,
+        "check": {"trace_re": tr.real, "purity": pur, "z0": float(z[0])},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_sample_every)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,252 @@
+/*
+ * vqd.h -- C ABI of the MI355X (gfx950) density-matrix emulation library.
+ *
+ * The library applies gates and Kraus channels to an N-qubit density matrix
+ * held in GPU memory and reads results out of it.  It is the data-parallel
+ * core of the noisy-device emulation described in "The Virtual Quantum Device
+ * (VQD)" (Gustiani, Jones, Benjamin): Sec. 2 chooses the density-matrix
+ * representation with general Kraus operators; Sec. 3 defines the channels.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * State layout.  rho is stored VECTORISED as 4^n complex128 values
+ *   amp[r + 2^n c] = rho[r][c]       (interleaved re, im; FP64)
+ * so qubit q of the register is vector bit q (row) and vector bit q + n
+ * (column).  Because vec(U rho U^dagger) = (conj(U) (x) U) vec(rho), a gate U
+ * on qubit q acts as U on bit q and conj(U) on bit q + n.
+ *
+ * Matrices.  All matrices are host pointers to row-major complex arrays of
+ * interleaved (re, im) doubles, read during the call (the caller may free
+ * them on return).  For a k-qubit op on targets t[0..k-1] the matrix index
+ * is sum_j b(t[j]) 2^j: t[0] is the least significant bit.  A superoperator
+ * acts on the 2k vector bits (t, t + n) with local index
+ *   sum_j b(t[j]) 2^j  +  2^k sum_j b(t[j] + n) 2^j,
+ * i.e. row bits first.  Built from Kraus operators K_j it is
+ *   S = sum_j conj(K_j) (x) K_j     (S[(r',c'),(r,c)] = sum_j K_j[r'][r] conj(K_j[c'][c])).
+ * Trace preservation is never checked: trace-decreasing (CPTN) maps such as
+ * the leakage maps of Sec. 6 are legal.
+ *
+ * Memory.  The caller owns the device buffer of the state (for example a
+ * torch tensor); the library never frees it, and a handle must not outlive
+ * it.  The library owns small internal buffers (operation descriptors,
+ * reduction partials), freed by the matching destroy call.
+ *
+ * Streams.  Apply and init calls are asynchronous on the handle's HIP stream.
+ * vqd_calc_* calls synchronise that stream and write host outputs.
+ *
+ * Errors.  Every call returns 0 (VQD_OK) or a negative code; the message of
+ * the last failure on the calling thread is returned by vqd_last_error().  No
+ * exception crosses the ABI.  On an error nothing has been enqueued.
+ */
+#ifndef VQD_H
+#define VQD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VQD_OK        0
+#define VQD_E_ARG    (-1)   /* bad qubit index, duplicate targets, null pointer, non-finite entry */
+#define VQD_E_SIZE   (-2)   /* n out of range, buffer too small, k too large */
+#define VQD_E_NOMEM  (-3)   /* an internal allocation failed */
+#define VQD_E_HIP    (-4)   /* a HIP runtime call failed */
+#define VQD_E_STATE  (-5)   /* call out of order (e.g. running an uncompiled program) */
+
+#define VQD_MAX_QUBITS 16   /* 4^16 amplitudes = 64 GiB of complex128 */
+
+typedef struct vqd_dm vqd_dm;
+typedef struct vqd_prog vqd_prog;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *vqd_last_error(void);
+
+/* Library version string. */
+const char *vqd_version(void);
+
+/* ------------------------------------------------------------------ state */
+
+/* Wrap a caller-owned device buffer of `bytes` bytes holding 4^n complex128
+ * amplitudes (n in [1, 16]) and a hipStream_t (NULL = default stream).
+ * VQD_E_SIZE if bytes < 16 * 4^n.  The buffer is not modified. */
+int vqd_dm_wrap(void *dev_amps, int n, size_t bytes, void *hip_stream, vqd_dm **out);
+
+/* Release the handle and its internal buffers (not the wrapped buffer).
+ * Synchronises the stream first.  NULL is accepted. */
+int vqd_dm_destroy(vqd_dm *dm);
+
+/* Change the stream later calls are enqueued on. */
+int vqd_dm_set_stream(vqd_dm *dm, void *hip_stream);
+
+/* |0..0><0..0|: one write pass over the buffer (Sec. 2 initial register). */
+int vqd_dm_init_zero(vqd_dm *dm);
+
+/* |b><b| for a computational basis state b < 2^n. */
+int vqd_dm_init_basis(vqd_dm *dm, uint64_t b);
+
+/* Product of single-qubit diagonal states (x)_j (p0[j]|0><0| + (1-p0[j])|1><1|),
+ * the thermal initial state of the superconducting model (eq. thermalstate,
+ * Sec. 8).  p0[j] is the ground-state population of qubit j (host array of n). */
+int vqd_dm_init_product_diag(vqd_dm *dm, const double *p0);
+
+/* Copy the 4^n amplitudes to / from a host array of 2 * 4^n doubles in the
+ * vectorised order.  Synchronous.  Used as checkpoint and by tests. */
+int vqd_dm_copy_to_host(const vqd_dm *dm, double *host);
+int vqd_dm_copy_from_host(vqd_dm *dm, const double *host);
+
+/* --------------------------------------------------------------- apply ops */
+
+/* rho <- U rho U^dagger for a 2x2 U (8 doubles) on qubit q: U on vector bit q,
+ * conj(U) on bit q + n, in one pass (Sec. 2; gates of Secs. 4-8). */
+int vqd_apply_unitary1(vqd_dm *dm, int q, const double *u);
+
+/* Same for a 4x4 U (32 doubles) on (q0, q1), q0 the low bit of U's index. */
+int vqd_apply_unitary2(vqd_dm *dm, int q0, int q1, const double *u);
+
+/* rho <- S(rho) for a single-qubit channel given as its 4x4 superoperator
+ * (32 doubles) on the vector bits (q, q + n) -- e.g. the channels of eqs.
+ * depol1, deph1, damp, gdamp, bf, depht2, ampt1 (Sec. 3). */
+int vqd_apply_superop1(vqd_dm *dm, int q, const double *s);
+
+/* Two-qubit channel as a 16x16 superoperator (512 doubles) on
+ * (q0, q1, q0 + n, q1 + n) -- eqs. depol2, deph2, bf2, czleak and the
+ * silicon parity-decay map (Secs. 3, 6, 7). */
+int vqd_apply_superop2(vqd_dm *dm, int q0, int q1, const double *s);
+
+/* A fused k-qubit block.  kind VQD_BLOCK_UNITARY: m is a 2^k x 2^k matrix U,
+ * applied as U on the row bits and conj(U) on the column bits, k in [1, 4].
+ * kind VQD_BLOCK_SUPEROP: m is a 4^k x 4^k superoperator, k in [1, 2].
+ * Fusing a run of gates and channels on the same qubits into one block is
+ * exact: the block is the product of the ops' superoperators (for channels,
+ * the paper's own composition E(p,q) = deph o depol of eq. stderr, Sec. 3.2). */
+#define VQD_BLOCK_UNITARY 0
+#define VQD_BLOCK_SUPEROP 1
+int vqd_apply_fused(vqd_dm *dm, int k, const int *targets, int kind, const double *m);
+
+/* An element-wise (diagonal) superoperator on k <= 2 qubits: amp[i] is
+ * multiplied by d[idx(i)], idx the local superoperator index of i (4^k
+ * complex factors, 2 * 4^k doubles).  Covers the diagonal gates and channels
+ * (Rz, CZ, CPh, ZZ crosstalk eq. weak_dephasing_zz, dephasing eq. deph1/2). */
+int vqd_apply_diagonal(vqd_dm *dm, int k, const int *targets, const double *d);
+
+/* ----------------------------------------------------- op programs (fusion) */
+
+/* Named ops, parameters in the order listed (angles in radians, times in the
+ * same unit as T1/T2). */
+enum vqd_kind {
+    VQD_K_RX = 1,       /* theta: exp(-i theta X / 2)                         */
+    VQD_K_RY,           /* theta: exp(-i theta Y / 2)                         */
+    VQD_K_RZ,           /* theta: exp(-i theta Z / 2)                         */
+    VQD_K_H,            /* Hadamard                                           */
+    VQD_K_X, VQD_K_Y, VQD_K_Z,
+    VQD_K_SU2,          /* g0..g3: a0 I - i(a1 X + a2 Y + a3 Z), a = g/|g|    */
+    VQD_K_CZ,           /* diag(1,1,1,-1)                                     */
+    VQD_K_CPHASE,       /* theta: diag(1,1,1,e^{i theta})                     */
+    VQD_K_XX,           /* theta: exp(-i theta/2 X(x)X)                       */
+    VQD_K_ZZ,           /* alpha: exp(-i alpha Z(x)Z)  (eq. weak_dephasing_zz)*/
+    VQD_K_DEPOL1,       /* p   (eq. depol1)                                   */
+    VQD_K_DEPOL2,       /* p   (eq. depol2)                                   */
+    VQD_K_DEPH1,        /* p   (eq. deph1)                                    */
+    VQD_K_DEPH2,        /* p   (eq. deph2)                                    */
+    VQD_K_AMP,          /* p   (eq. damp)                                     */
+    VQD_K_GAMP,         /* p, gamma (eq. gdamp)                               */
+    VQD_K_BITFLIP1,     /* b   (eq. bf)                                       */
+    VQD_K_BITFLIP2,     /* b   (eq. bf2)                                      */
+    VQD_K_AMP_T1,       /* dt, T1: amp(1 - exp(-dt/T1))          (eq. ampt1)  */
+    VQD_K_DEPH_T2,      /* dt, T2: deph((1 - exp(-dt/T2)) / 2)   (eq. depht2) */
+    VQD_K_COUNT
+};
+
+/* Number of qubits and parameters of a named kind (-1 for an unknown kind). */
+int vqd_kind_arity(int kind, int *n_qubits, int *n_params);
+
+/* Build the matrix of a named gate (2^k x 2^k, interleaved complex) or the
+ * superoperator of a named gate or channel (4^k x 4^k).  `out` must hold
+ * 2 * 4^k (matrix) or 2 * 16^k (superop) doubles. */
+int vqd_kind_matrix(int kind, const double *params, double *out);
+int vqd_kind_superop(int kind, const double *params, double *out);
+
+/* Superoperator of a Kraus set: nk matrices of 2^k x 2^k, k in [1, 2]. */
+int vqd_kraus_to_superop(int k, int nk, const double *kraus, double *out);
+
+/* An op program: an ordered list of ops on an n-qubit register that the
+ * library plans into fused passes.  A pass streams the state through HBM
+ * once: a tile of 2^L amplitudes (L <= 12) is staged in registers and LDS and
+ * every op of the pass is applied in-tile before the tile is written back.
+ * The planner groups ops whose qubits fit one tile, fuses consecutive ops on
+ * the same qubits into one block where that costs fewer flops, and applies
+ * diagonal ops element-wise wherever their dependencies allow. */
+int vqd_prog_create(int n, vqd_prog **out);
+int vqd_prog_destroy(vqd_prog *p);
+int vqd_prog_add_named(vqd_prog *p, int kind, const int *targets, const double *params);
+int vqd_prog_add_unitary(vqd_prog *p, int k, const int *targets, const double *u);
+int vqd_prog_add_superop(vqd_prog *p, int k, const int *targets, const double *s);
+int vqd_prog_add_kraus(vqd_prog *p, int k, const int *targets, int nk, const double *kraus);
+
+/* Planner options.  max_ops_per_pass = 1 disables fusion (one op per pass);
+ * tile_bits in [4, 12]; min_contig_bits: low vector bits every tile keeps for
+ * coalesced access (0..tile_bits). */
+typedef struct vqd_plan_opts {
+    int tile_bits;          /* default 12 */
+    int min_contig_bits;    /* default 3  */
+    int max_ops_per_pass;   /* default 0 = unlimited */
+    int fuse_blocks;        /* default 1: multiply runs of ops into one block when cheaper */
+} vqd_plan_opts;
+void vqd_plan_opts_default(vqd_plan_opts *o);
+
+/* Plan the program and upload its descriptors to the current device.
+ * opts may be NULL (defaults).  May be called again to re-plan. */
+int vqd_prog_compile(vqd_prog *p, const vqd_plan_opts *opts);
+
+/* Plan the program on the host only (no device memory touched). */
+int vqd_prog_plan(vqd_prog *p, const vqd_plan_opts *opts);
+
+/* Export the planned descriptors for inspection by tools and tests.  Layout:
+ * 12 uint32 header {magic 0x56514450, version 1, n_passes, n_phases,
+ * n_kernel_ops, n_mats, sizeof pass, sizeof phase, sizeof op, n, tile
+ * bits, 0} followed by the pass, phase and op records and n_mats complex
+ * doubles.  The record layouts are internal to this library version.
+ * With buf NULL or cap too small only *needed is written (and 0 returned
+ * when buf is NULL; VQD_E_SIZE otherwise). */
+int vqd_prog_export(const vqd_prog *p, void *buf, size_t cap, size_t *needed);
+
+/* Enqueue all passes of a compiled program on dm's stream (dm->n == p->n). */
+int vqd_prog_run(vqd_prog *p, vqd_dm *dm);
+
+typedef struct vqd_prog_info {
+    int n;
+    int n_ops;              /* ops added                                   */
+    int n_passes;           /* HBM passes after planning                   */
+    int n_phases;           /* register phases over all passes             */
+    int n_kernel_ops;       /* ops applied in-tile after block fusion      */
+    double fma_per_amp;     /* planned FP64 FMAs per amplitude, all passes */
+} vqd_prog_info;
+int vqd_prog_info_get(const vqd_prog *p, vqd_prog_info *out);
+
+/* ---------------------------------------------------------------- read-out */
+
+/* Tr rho (complex). */
+int vqd_calc_trace(const vqd_dm *dm, double *re, double *im);
+
+/* Tr rho^2 = sum_i |amp_i|^2 (Hermitian rho). */
+int vqd_calc_purity(const vqd_dm *dm, double *out);
+
+/* p_r = Re rho[r][r], r < 2^n; not clamped or renormalised (host array 2^n). */
+int vqd_calc_probs(const vqd_dm *dm, double *out);
+
+/* <Z_i> = sum_r (-1)^{r_i} p_r for i < n (host array n). */
+int vqd_calc_expec_z(const vqd_dm *dm, double *out);
+
+/* <Z_i Z_j> for npairs pairs given as 2*npairs qubit indices. */
+int vqd_calc_expec_zz(const vqd_dm *dm, const int *pairs, int npairs, double *out);
+
+/* Tr(P rho) for the Pauli string P = (x)_q sigma_{codes[q]}, codes[q] in
+ * {0=I, 1=X, 2=Y, 3=Z} (Sec. 2: expectation values of Pauli strings). */
+int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, double *im);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VQD_H */

@@ -1,0 +1,310 @@
+// Gate matrices and channel superoperators built on the host in FP64.
+//
+// Gates follow the conventions R_sigma(theta) = exp(-i theta sigma / 2)
+// (Rx is eq. u of Sec. 6 at zero detuning), the Rydberg/ZZ/exchange forms of
+// Secs. 3.4 and 6, and the Kraus maps of Sec. 3 (eqs. depol1, depol2, deph1,
+// deph2, damp, gdamp, bf, bf2, ampt1, depht2).  A two-qubit operator A on
+// targets[0] and B on targets[1] has matrix kron(B, A) (targets[0] is the
+// least significant bit of the index).
+#include <array>
+#include <cmath>
+#include <cstring>
+
+#include "vqd_internal.h"
+
+namespace vqd {
+
+namespace {
+
+const cd I(0.0, 1.0);
+
+using M2 = std::array<cd, 4>;
+
+M2 pauli(int a)
+{
+    switch (a) {
+    case 0: return {cd(1), cd(0), cd(0), cd(1)};
+    case 1: return {cd(0), cd(1), cd(1), cd(0)};
+    case 2: return {cd(0), -I, I, cd(0)};
+    default: return {cd(1), cd(0), cd(0), cd(-1)};
+    }
+}
+
+// kron(B, A): A on the low qubit, B on the high qubit.
+std::vector<cd> kron2(const M2 &A, const M2 &B)
+{
+    std::vector<cd> M(16);
+    for (int r1 = 0; r1 < 2; ++r1)
+        for (int r0 = 0; r0 < 2; ++r0)
+            for (int c1 = 0; c1 < 2; ++c1)
+                for (int c0 = 0; c0 < 2; ++c0)
+                    M[(r0 + 2 * r1) * 4 + (c0 + 2 * c1)] = A[r0 * 2 + c0] * B[r1 * 2 + c1];
+    return M;
+}
+
+std::vector<cd> scaled(const std::vector<cd> &M, double s)
+{
+    std::vector<cd> o(M);
+    for (auto &x : o) x *= s;
+    return o;
+}
+
+std::vector<cd> m2v(const M2 &m) { return std::vector<cd>(m.begin(), m.end()); }
+
+// Kraus sets of the named channels (each a list of d x d matrices).
+int channel_kraus(int kind, const double *p, int &k, std::vector<std::vector<cd>> &Ks)
+{
+    Ks.clear();
+    auto need_prob = [&](double x, double hi) {
+        return std::isfinite(x) && x >= 0.0 && x <= hi;
+    };
+    switch (kind) {
+    case VQD_K_DEPOL1: {
+        if (!need_prob(p[0], 1.0)) return fail(VQD_E_ARG, "depol1: p outside [0, 1]");
+        k = 1;
+        Ks.push_back(scaled(m2v(pauli(0)), std::sqrt(1 - p[0])));
+        for (int a = 1; a < 4; ++a) Ks.push_back(scaled(m2v(pauli(a)), std::sqrt(p[0] / 3)));
+        return VQD_OK;
+    }
+    case VQD_K_DEPOL2: {
+        if (!need_prob(p[0], 1.0)) return fail(VQD_E_ARG, "depol2: p outside [0, 1]");
+        k = 2;
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                double w = (a == 0 && b == 0) ? 1 - p[0] : p[0] / 15;
+                Ks.push_back(scaled(kron2(pauli(a), pauli(b)), std::sqrt(w)));
+            }
+        return VQD_OK;
+    }
+    case VQD_K_DEPH1: case VQD_K_DEPH_T2: {
+        double q = p[0];
+        if (kind == VQD_K_DEPH_T2) {
+            if (!(p[1] > 0) || !(p[0] >= 0)) return fail(VQD_E_ARG, "deph_t2: need dt >= 0, T2 > 0");
+            q = 0.5 * (1.0 - std::exp(-p[0] / p[1]));
+        }
+        if (!need_prob(q, 1.0)) return fail(VQD_E_ARG, "deph1: p outside [0, 1]");
+        k = 1;
+        Ks.push_back(scaled(m2v(pauli(0)), std::sqrt(1 - q)));
+        Ks.push_back(scaled(m2v(pauli(3)), std::sqrt(q)));
+        return VQD_OK;
+    }
+    case VQD_K_DEPH2: {
+        if (!need_prob(p[0], 1.0)) return fail(VQD_E_ARG, "deph2: p outside [0, 1]");
+        k = 2;
+        Ks.push_back(scaled(kron2(pauli(0), pauli(0)), std::sqrt(1 - p[0])));
+        Ks.push_back(scaled(kron2(pauli(3), pauli(0)), std::sqrt(p[0] / 3)));
+        Ks.push_back(scaled(kron2(pauli(0), pauli(3)), std::sqrt(p[0] / 3)));
+        Ks.push_back(scaled(kron2(pauli(3), pauli(3)), std::sqrt(p[0] / 3)));
+        return VQD_OK;
+    }
+    case VQD_K_AMP: case VQD_K_AMP_T1: {
+        double g = p[0];
+        if (kind == VQD_K_AMP_T1) {
+            if (!(p[1] > 0) || !(p[0] >= 0)) return fail(VQD_E_ARG, "amp_t1: need dt >= 0, T1 > 0");
+            g = 1.0 - std::exp(-p[0] / p[1]);
+        }
+        if (!need_prob(g, 1.0)) return fail(VQD_E_ARG, "amp: p outside [0, 1]");
+        k = 1;
+        Ks.push_back({cd(1), cd(0), cd(0), cd(std::sqrt(1 - g))});
+        Ks.push_back({cd(0), cd(std::sqrt(g)), cd(0), cd(0)});
+        return VQD_OK;
+    }
+    case VQD_K_GAMP: {
+        double pp = p[0], g = p[1];
+        if (!need_prob(pp, 1.0) || !need_prob(g, 1.0)) return fail(VQD_E_ARG, "gamp: p, gamma outside [0, 1]");
+        k = 1;
+        double a = std::sqrt(pp), b = std::sqrt(1 - pp);
+        Ks.push_back({cd(a), cd(0), cd(0), cd(a * std::sqrt(1 - g))});
+        Ks.push_back({cd(0), cd(a * std::sqrt(g)), cd(0), cd(0)});
+        Ks.push_back({cd(b * std::sqrt(1 - g)), cd(0), cd(0), cd(b)});
+        Ks.push_back({cd(0), cd(0), cd(b * std::sqrt(g)), cd(0)});
+        return VQD_OK;
+    }
+    case VQD_K_BITFLIP1: {
+        if (!need_prob(p[0], 1.0)) return fail(VQD_E_ARG, "bitflip1: b outside [0, 1]");
+        k = 1;
+        Ks.push_back(scaled(m2v(pauli(0)), std::sqrt(1 - p[0])));
+        Ks.push_back(scaled(m2v(pauli(1)), std::sqrt(p[0])));
+        return VQD_OK;
+    }
+    case VQD_K_BITFLIP2: {
+        if (!need_prob(p[0], 1.0)) return fail(VQD_E_ARG, "bitflip2: b outside [0, 1]");
+        k = 2;
+        Ks.push_back(scaled(kron2(pauli(0), pauli(0)), std::sqrt(1 - p[0])));
+        Ks.push_back(scaled(kron2(pauli(1), pauli(0)), std::sqrt(p[0] / 3)));
+        Ks.push_back(scaled(kron2(pauli(0), pauli(1)), std::sqrt(p[0] / 3)));
+        Ks.push_back(scaled(kron2(pauli(1), pauli(1)), std::sqrt(p[0] / 3)));
+        return VQD_OK;
+    }
+    default:
+        return fail(VQD_E_ARG, "not a channel kind: " + std::to_string(kind));
+    }
+}
+
+bool is_channel(int kind)
+{
+    return kind >= VQD_K_DEPOL1 && kind < VQD_K_COUNT;
+}
+
+}  // namespace
+
+int kind_arity(int kind, int *nq, int *np)
+{
+    static const int Q[VQD_K_COUNT] = {0, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2,
+                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1};
+    static const int P[VQD_K_COUNT] = {0, 1, 1, 1, 0, 0, 0, 0, 4, 0, 1, 1, 1,
+                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2};
+    if (kind <= 0 || kind >= VQD_K_COUNT) return -1;
+    if (nq) *nq = Q[kind];
+    if (np) *np = P[kind];
+    return 0;
+}
+
+int kind_matrix(int kind, const double *p, std::vector<cd> &U, int &k)
+{
+    int nq = 0, np = 0;
+    if (kind_arity(kind, &nq, &np) != 0 || is_channel(kind))
+        return fail(VQD_E_ARG, "not a gate kind: " + std::to_string(kind));
+    for (int i = 0; i < np; ++i)
+        if (!std::isfinite(p[i])) return fail(VQD_E_ARG, "non-finite gate parameter");
+    k = nq;
+    U.assign(size_t(1) << (2 * k), cd(0));
+    switch (kind) {
+    case VQD_K_RX: {
+        double c = std::cos(p[0] / 2), s = std::sin(p[0] / 2);
+        U = {cd(c), -I * s, -I * s, cd(c)};
+        break;
+    }
+    case VQD_K_RY: {
+        double c = std::cos(p[0] / 2), s = std::sin(p[0] / 2);
+        U = {cd(c), cd(-s), cd(s), cd(c)};
+        break;
+    }
+    case VQD_K_RZ:
+        U = {std::exp(-I * (p[0] / 2)), cd(0), cd(0), std::exp(I * (p[0] / 2))};
+        break;
+    case VQD_K_H: {
+        double r = 1.0 / std::sqrt(2.0);
+        U = {cd(r), cd(r), cd(r), cd(-r)};
+        break;
+    }
+    case VQD_K_X: U = m2v(pauli(1)); break;
+    case VQD_K_Y: U = m2v(pauli(2)); break;
+    case VQD_K_Z: U = m2v(pauli(3)); break;
+    case VQD_K_SU2: {
+        double nrm = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+        if (!(nrm > 0)) return fail(VQD_E_ARG, "su2: zero quaternion");
+        double a0 = p[0] / nrm, a1 = p[1] / nrm, a2 = p[2] / nrm, a3 = p[3] / nrm;
+        // a0 I - i (a1 X + a2 Y + a3 Z)
+        U = {cd(a0, -a3), cd(-a2, -a1), cd(a2, -a1), cd(a0, a3)};
+        break;
+    }
+    case VQD_K_CZ:
+        U[0] = 1; U[5] = 1; U[10] = 1; U[15] = -1;
+        break;
+    case VQD_K_CPHASE:
+        U[0] = 1; U[5] = 1; U[10] = 1; U[15] = std::exp(I * p[0]);
+        break;
+    case VQD_K_XX: {
+        // cos(theta/2) I - i sin(theta/2) X(x)X; X(x)X flips both index bits
+        double c = std::cos(p[0] / 2), s = std::sin(p[0] / 2);
+        for (int i = 0; i < 4; ++i) {
+            U[i * 4 + i] = c;
+            U[i * 4 + (i ^ 3)] = -I * s;
+        }
+        break;
+    }
+    case VQD_K_ZZ: {
+        // exp(-i alpha Z(x)Z): phase e^{-i alpha} on even parity, e^{+i alpha} on odd
+        for (int i = 0; i < 4; ++i) {
+            int par = (i ^ (i >> 1)) & 1;
+            U[i * 4 + i] = std::exp(-I * (par ? -p[0] : p[0]));
+        }
+        break;
+    }
+    default:
+        return fail(VQD_E_ARG, "not a gate kind");
+    }
+    return VQD_OK;
+}
+
+void unitary_to_superop(int k, const cd *U, std::vector<cd> &S)
+{
+    kraus_to_superop(k, 1, U, S);
+}
+
+void kraus_to_superop(int k, int nk, const cd *K, std::vector<cd> &S)
+{
+    const int d = 1 << k, D = d * d;
+    S.assign(size_t(D) * D, cd(0));
+    for (int j = 0; j < nk; ++j) {
+        const cd *Kj = K + size_t(j) * d * d;
+        for (int c2 = 0; c2 < d; ++c2)
+            for (int r2 = 0; r2 < d; ++r2)
+                for (int c = 0; c < d; ++c)
+                    for (int r = 0; r < d; ++r)
+                        S[size_t(r2 + d * c2) * D + (r + d * c)] +=
+                            Kj[r2 * d + r] * std::conj(Kj[c2 * d + c]);
+    }
+}
+
+int kind_superop(int kind, const double *p, std::vector<cd> &S, int &k)
+{
+    int nq = 0, np = 0;
+    if (kind_arity(kind, &nq, &np) != 0) return fail(VQD_E_ARG, "unknown kind " + std::to_string(kind));
+    for (int i = 0; i < np; ++i)
+        if (!std::isfinite(p[i])) return fail(VQD_E_ARG, "non-finite op parameter");
+    if (!is_channel(kind)) {
+        std::vector<cd> U;
+        int rc = kind_matrix(kind, p, U, k);
+        if (rc) return rc;
+        unitary_to_superop(k, U.data(), S);
+        return VQD_OK;
+    }
+    std::vector<std::vector<cd>> Ks;
+    int rc = channel_kraus(kind, p, k, Ks);
+    if (rc) return rc;
+    const int d = 1 << k;
+    std::vector<cd> flat;
+    for (auto &m : Ks) flat.insert(flat.end(), m.begin(), m.end());
+    kraus_to_superop(k, int(Ks.size()), flat.data(), S);
+    (void)d;
+    return VQD_OK;
+}
+
+LOp make_superop_op(int k, const int *targets, const cd *S)
+{
+    LOp op;
+    op.k = k;
+    for (int j = 0; j < k; ++j) op.q[j] = targets[j];
+    const int D = 1 << (2 * k);
+    bool diag = true;
+    for (int i = 0; i < D && diag; ++i)
+        for (int j = 0; j < D; ++j)
+            if (i != j && S[size_t(i) * D + j] != cd(0)) { diag = false; break; }
+    op.diag = diag;
+    if (diag) {
+        op.D.resize(D);
+        for (int i = 0; i < D; ++i) op.D[i] = S[size_t(i) * D + i];
+    } else {
+        op.S.assign(S, S + size_t(D) * D);
+    }
+    return op;
+}
+
+LOp make_unitary_op(int k, const int *targets, const cd *U)
+{
+    if (k <= 2) {
+        std::vector<cd> S;
+        unitary_to_superop(k, U, S);
+        return make_superop_op(k, targets, S.data());
+    }
+    LOp op;
+    op.k = k;
+    for (int j = 0; j < k; ++j) op.q[j] = targets[j];
+    op.wide_unitary = true;
+    op.U.assign(U, U + (size_t(1) << (2 * k)));
+    return op;
+}
+
+}  // namespace vqd

@@ -1,0 +1,586 @@
+// Host planner: turns an ordered op list into HBM passes, register phases and
+// kernel ops.
+//
+// Dependencies.  Two ops must keep their order if they share a qubit, unless
+// both are diagonal (element-wise products commute).
+//
+// Passes.  A pass owns a qubit set Q whose row and column bits, plus the
+// lowest `min_contig_bits` vector bits, fit in the tile (<= tile_bits bits).
+// Non-diagonal ops may join the pass only if their qubits lie in Q;
+// diagonal ops may join wherever their dependencies allow, because their
+// factor depends only on an amplitude's own index.  Q is grown greedily,
+// each step adding the blocked op's qubits that let the most ops join.
+//
+// Phases.  Inside a pass, ops are grouped into register phases of at most
+// two qubits (4 register bits: row and column bit of each).  Ops of a phase
+// are moved into the phase's 16-slot space, where runs that act on
+// overlapping bits are multiplied into one block when that costs fewer FMAs
+// (the product of superoperators is exact; this is the paper's own channel
+// composition, eq. stderr, generalised).  Each resulting block is encoded in
+// its cheapest form: a matrix on 2 or 4 register bits with its zero and real
+// entries flagged, or element-wise factors.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+
+#include "vqd_internal.h"
+
+namespace vqd {
+
+namespace {
+
+using Mat16 = std::array<cd, 256>;
+
+uint32_t qmask(const LOp &op)
+{
+    uint32_t m = 0;
+    for (int j = 0; j < op.k; ++j) m |= 1u << op.q[j];
+    return m;
+}
+
+int popc(uint32_t x) { return __builtin_popcount(x); }
+
+// Global vector-bit positions of the pass tile for qubit set Q.
+std::vector<int> tile_bits_for(uint32_t Q, int n, int contig)
+{
+    std::vector<int> b;
+    for (int i = 0; i < contig && i < 2 * n; ++i) b.push_back(i);
+    for (int q = 0; q < n; ++q)
+        if (Q >> q & 1) {
+            b.push_back(q);
+            b.push_back(q + n);
+        }
+    std::sort(b.begin(), b.end());
+    b.erase(std::unique(b.begin(), b.end()), b.end());
+    return b;
+}
+
+struct SimResult {
+    std::vector<int> taken;
+    std::vector<uint32_t> cands;   // qubit sets of blocked non-diagonal ops
+};
+
+// Which ops (from `first`, not yet applied) can join a pass on qubit set Q.
+void simulate(const std::vector<LOp> &ops, const std::vector<uint32_t> &qm,
+              const std::vector<char> &applied, size_t first, uint32_t Q, int n,
+              int max_take, SimResult &res, bool want_cands)
+{
+    res.taken.clear();
+    res.cands.clear();
+    const uint32_t all = (n >= 32) ? 0xffffffffu : ((1u << n) - 1);
+    uint32_t blk_any = 0, blk_nd = 0;
+    for (size_t i = first; i < ops.size(); ++i) {
+        if (applied[i]) continue;
+        const LOp &op = ops[i];
+        const uint32_t m = qm[i];
+        bool take = false, cand = false;
+        if (m & blk_any) {
+        } else if (!op.diag && (m & blk_nd)) {
+        } else if (op.diag) {
+            take = true;
+        } else if ((m & ~Q) == 0) {
+            take = true;
+        } else {
+            cand = true;
+        }
+        if (take) {
+            res.taken.push_back((int)i);
+            if (max_take > 0 && (int)res.taken.size() >= max_take) break;
+        } else {
+            if (op.diag) blk_nd |= m;
+            else blk_any |= m;
+            if (cand && want_cands) {
+                if (std::find(res.cands.begin(), res.cands.end(), m) == res.cands.end() &&
+                    res.cands.size() < 32)
+                    res.cands.push_back(m);
+            }
+            if (blk_any == all) break;
+        }
+    }
+}
+
+// ---- slot-space blocks --------------------------------------------------
+
+struct Block {
+    bool rt = false;            // runtime-indexed diagonal (KOP_DIAG_RT)
+    Mat16 m{};                  // slot-space matrix (when !rt)
+    uint32_t support = 0;       // register bits the block depends on
+    bool diag = false;
+    int op_index = -1;          // for rt blocks
+};
+
+bool is_zero(cd x) { return x.real() == 0.0 && x.imag() == 0.0; }
+
+// Does m act as identity-extended on the complement of `mask`?  If so,
+// extract the dim x dim matrix on `mask` (bits in ascending order).
+bool restrict_to(const Mat16 &m, int mask, std::vector<cd> &sub)
+{
+    const int rest = (~mask) & 15;
+    int nb = popc((uint32_t)mask), dim = 1 << nb;
+    auto dep = [](int v, int msk) {
+        int out = 0, k = 0;
+        for (int b = 0; b < 4; ++b)
+            if (msk >> b & 1) {
+                if (v >> k & 1) out |= 1 << b;
+                ++k;
+            }
+        return out;
+    };
+    sub.assign(size_t(dim) * dim, cd(0));
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) sub[i * dim + j] = m[dep(i, mask) * 16 + dep(j, mask)];
+    // verify: every entry equals the block value when rest bits agree, else 0
+    for (int so = 0; so < 16; ++so)
+        for (int si = 0; si < 16; ++si) {
+            cd v = m[so * 16 + si];
+            if ((so & rest) != (si & rest)) {
+                if (!is_zero(v)) return false;
+                continue;
+            }
+            int i = 0, j = 0, k = 0;
+            for (int b = 0; b < 4; ++b)
+                if (mask >> b & 1) {
+                    i |= ((so >> b) & 1) << k;
+                    j |= ((si >> b) & 1) << k;
+                    ++k;
+                }
+            if (v != sub[i * dim + j]) return false;
+        }
+    return true;
+}
+
+double entry_cost(cd v) { return is_zero(v) ? 0.0 : (v.imag() != 0.0 ? 4.0 : 2.0); }
+
+struct Encoded {
+    uint32_t kind = KOP_MAT;
+    int mask = 15;
+    std::vector<cd> data;   // matrix or 16 factors
+    double cost = 0;        // FMAs per 16 slots
+};
+
+Encoded encode(const Mat16 &m)
+{
+    Encoded best;
+    best.cost = 1e30;
+    bool diag = true;
+    for (int i = 0; i < 16 && diag; ++i)
+        for (int j = 0; j < 16; ++j)
+            if (i != j && !is_zero(m[i * 16 + j])) { diag = false; break; }
+    if (diag) {
+        best.kind = KOP_DIAG;
+        best.data.resize(16);
+        best.cost = 0;
+        for (int e = 0; e < 16; ++e) {
+            best.data[e] = m[e * 16 + e];
+            if (best.data[e] != cd(1)) best.cost += entry_cost(best.data[e]);
+        }
+        return best;
+    }
+    static const int masks[] = {5, 10, 7, 15};
+    std::vector<cd> sub;
+    for (int mask : masks) {
+        if (!restrict_to(m, mask, sub)) continue;
+        const int nb = popc((uint32_t)mask), groups = 16 >> nb;
+        double c = 0;
+        for (auto &v : sub) c += entry_cost(v);
+        c *= groups;
+        if (c < best.cost) {
+            best.kind = KOP_MAT;
+            best.mask = mask;
+            best.data = sub;
+            best.cost = c;
+        }
+    }
+    return best;
+}
+
+Mat16 mul(const Mat16 &B, const Mat16 &A)   // B * A (A applied first)
+{
+    Mat16 C{};
+    for (int i = 0; i < 16; ++i)
+        for (int k = 0; k < 16; ++k) {
+            const cd b = B[i * 16 + k];
+            if (is_zero(b)) continue;
+            for (int j = 0; j < 16; ++j) C[i * 16 + j] += b * A[k * 16 + j];
+        }
+    return C;
+}
+
+// Embed a k<=2 op into slot space.  slot_of_gpos maps a global bit to its
+// register bit (or -1).
+Mat16 embed(const LOp &op, int n, const int *reg_gpos, uint32_t &support)
+{
+    const int k = op.k, nb = 2 * k, D = 1 << nb;
+    int sbit[4];
+    support = 0;
+    for (int j = 0; j < nb; ++j) {
+        const int g = (j < k) ? op.q[j] : op.q[j - k] + n;
+        sbit[j] = -1;
+        for (int b = 0; b < 4; ++b)
+            if (reg_gpos[b] == g) sbit[j] = b;
+        support |= 1u << sbit[j];
+    }
+    auto local = [&](int slot) {
+        int l = 0;
+        for (int j = 0; j < nb; ++j) l |= ((slot >> sbit[j]) & 1) << j;
+        return l;
+    };
+    Mat16 m{};
+    for (int so = 0; so < 16; ++so)
+        for (int si = 0; si < 16; ++si) {
+            if ((so & ~support) != (si & ~support)) continue;
+            const int lo = local(so), li = local(si);
+            cd v;
+            if (op.diag) v = (lo == li) ? op.D[lo] : cd(0);
+            else v = op.S[size_t(lo) * D + li];
+            m[so * 16 + si] = v;
+        }
+    return m;
+}
+
+void set_bits(uint32_t *w, int bit) { w[bit >> 5] |= 1u << (bit & 31); }
+
+}  // namespace
+
+int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out)
+{
+    out = HostPlan{};
+    const int n2 = 2 * n;
+    if (opt.tile_bits < 4 || opt.tile_bits > kMaxTileBits)
+        return fail(VQD_E_ARG, "tile_bits must be in [4, 12]");
+    // tile size actually used: 2n bits at most, but never fewer than the 4
+    // register bits (tiny registers get phantom bits)
+    const int L = std::max(4, std::min(opt.tile_bits, n2));
+    const int contig = std::max(0, std::min(opt.min_contig_bits, std::min(L, n2)));
+    const int max_take = opt.max_ops_per_pass;
+
+    std::vector<uint32_t> qm(ops.size());
+    for (size_t i = 0; i < ops.size(); ++i) {
+        qm[i] = qmask(ops[i]);
+        const int need = (int)tile_bits_for(qm[i], n, 0).size();
+        if (!ops[i].diag && need > L)
+            return fail(VQD_E_SIZE, "op " + std::to_string(i) + " needs " + std::to_string(need) +
+                                        " tile bits; tile has " + std::to_string(L));
+    }
+
+    std::vector<char> applied(ops.size(), 0);
+    size_t first = 0;
+    SimResult sim, sim2;
+    while (true) {
+        while (first < ops.size() && applied[first]) ++first;
+        if (first >= ops.size()) break;
+
+        // ---- choose the pass qubit set
+        uint32_t Q = 0;
+        while (true) {
+            simulate(ops, qm, applied, first, Q, n, max_take, sim, true);
+            const size_t base = sim.taken.size();
+            if (max_take > 0 && (int)base >= max_take) break;
+            uint32_t bestQ = Q;
+            size_t bestc = base;
+            for (uint32_t c : sim.cands) {
+                const uint32_t Q2 = Q | c;
+                // the contiguous low bits are a preference: the first op of a
+                // pass may use them when it cannot fit otherwise
+                const bool fits = (int)tile_bits_for(Q2, n, contig).size() <= L ||
+                                  (Q == 0 && (int)tile_bits_for(Q2, n, 0).size() <= L);
+                if (!fits) continue;
+                simulate(ops, qm, applied, first, Q2, n, max_take, sim2, false);
+                if (sim2.taken.size() > bestc) {
+                    bestc = sim2.taken.size();
+                    bestQ = Q2;
+                }
+            }
+            if (bestQ == Q) break;
+            Q = bestQ;
+        }
+        simulate(ops, qm, applied, first, Q, n, max_take, sim, false);
+        if (sim.taken.empty()) return fail(VQD_E_STATE, "planner made no progress");
+        for (int i : sim.taken) applied[i] = 1;
+
+        // ---- tile bits
+        std::vector<int> tb = tile_bits_for(Q, n, contig);
+        if ((int)tb.size() > L) tb = tile_bits_for(Q, n, 0);
+        for (int b = 0; (int)tb.size() < std::min(L, n2) && b < n2; ++b)
+            if (std::find(tb.begin(), tb.end(), b) == tb.end()) tb.push_back(b);
+        std::sort(tb.begin(), tb.end());
+        for (uint32_t ph = kPhantomPos; (int)tb.size() < L; ++ph) tb.push_back((int)ph);  // phantom bits (tiny n)
+        KPass kp{};
+        kp.L = (uint32_t)L;
+        kp.phantom = (n2 < L) ? 1u : 0u;
+        int ng = 0;
+        for (int b = 0; b < n2; ++b)
+            if (std::find(tb.begin(), tb.end(), b) == tb.end()) kp.group_gpos[ng++] = (uint32_t)b;
+        kp.n_group_bits = (uint32_t)ng;
+        kp.n_tiles = 1ull << ng;
+        // tiles lacking the lowest vector bits share cache lines with their
+        // neighbours in the low group bits; keep those on one XCD
+        bool low_in_tile = true;
+        for (int b = 0; b < std::min(3, n2); ++b)
+            if (std::find(tb.begin(), tb.end(), b) == tb.end()) low_in_tile = false;
+        kp.xcd_swizzle = (!low_in_tile && kp.n_tiles >= 64 && kp.n_tiles % 64 == 0) ? 1u : 0u;
+        kp.phase_begin = (uint32_t)out.phases.size();
+        auto local_of = [&](int g) {
+            for (int i = 0; i < (int)tb.size(); ++i)
+                if (tb[i] == g) return i;
+            return -1;
+        };
+
+        // ---- phases
+        std::vector<int> rem = sim.taken;
+        while (!rem.empty()) {
+            uint32_t P = 0;
+            std::vector<int> take, keep;
+            uint32_t blk_any = 0, blk_nd = 0;
+            int wide = -1;
+            for (int idx : rem) {
+                const LOp &op = ops[idx];
+                const uint32_t m = qm[idx];
+                bool ok = false;
+                if (wide >= 0) {
+                    ok = false;
+                } else if (m & blk_any) {
+                } else if (!op.diag && (m & blk_nd)) {
+                } else if (op.diag) {
+                    ok = true;
+                } else if (op.wide_unitary) {
+                    if (P == 0) {
+                        bool nd_taken = false;
+                        for (int t : take) nd_taken |= !ops[t].diag;
+                        if (!nd_taken) { ok = true; wide = idx; P = m; }
+                    }
+                } else if ((m & ~P) == 0) {
+                    ok = true;
+                } else if (popc(P | m) <= 2) {
+                    P |= m;
+                    ok = true;
+                }
+                if (ok) {
+                    take.push_back(idx);
+                } else {
+                    keep.push_back(idx);
+                    if (op.diag) blk_nd |= m;
+                    else blk_any |= m;
+                }
+            }
+            rem.swap(keep);
+
+            auto emit_phase = [&](const int *reg_gpos, const std::vector<Block> &blocks,
+                                  const std::vector<int> &rt_ops_unused) {
+                (void)rt_ops_unused;
+                KPhase H{};
+                bool used[kMaxTileBits] = {false};
+                for (int b = 0; b < 4; ++b) {
+                    const int l = local_of(reg_gpos[b]);
+                    H.reg_local[b] = (uint32_t)l;
+                    H.reg_gpos[b] = (uint32_t)reg_gpos[b];
+                    used[l] = true;
+                }
+                int t = 0;
+                for (int l = 0; l < L; ++l)
+                    if (!used[l]) {
+                        H.thr_local[t] = (uint32_t)l;
+                        H.thr_gpos[t] = (uint32_t)tb[l];
+                        ++t;
+                    }
+                H.op_begin = (uint32_t)out.ops.size();
+                for (const Block &bk : blocks) {
+                    KOp ko{};
+                    if (bk.rt) {
+                        const LOp &op = ops[bk.op_index];
+                        ko.kind = KOP_DIAG_RT;
+                        ko.nbits = (uint32_t)(2 * op.k);
+                        ko.regdep = 0;
+                        for (int j = 0; j < 2 * op.k; ++j) {
+                            const int g = (j < op.k) ? op.q[j] : op.q[j - op.k] + n;
+                            ko.gpos[j] = (uint32_t)g;
+                            for (int b = 0; b < 4; ++b)
+                                if (reg_gpos[b] == g) ko.regdep = 1;
+                        }
+                        ko.mat = (uint32_t)out.mats.size();
+                        out.mats.insert(out.mats.end(), op.D.begin(), op.D.end());
+                        out.fma_per_amp += 4.0;
+                    } else {
+                        Encoded enc = encode(bk.m);
+                        ko.kind = enc.kind;
+                        ko.opmask = (uint32_t)enc.mask;
+                        ko.mat = (uint32_t)out.mats.size();
+                        out.mats.insert(out.mats.end(), enc.data.begin(), enc.data.end());
+                        if (enc.kind == KOP_DIAG) {
+                            for (int e = 0; e < 16; ++e) {
+                                if (enc.data[e] != cd(1)) set_bits(ko.nz, e);
+                                if (enc.data[e].imag() != 0.0) set_bits(ko.cx, e);
+                            }
+                        } else {
+                            for (size_t e = 0; e < enc.data.size(); ++e) {
+                                if (!is_zero(enc.data[e])) set_bits(ko.nz, (int)e);
+                                if (enc.data[e].imag() != 0.0) set_bits(ko.cx, (int)e);
+                            }
+                        }
+                        out.fma_per_amp += enc.cost / 16.0;
+                    }
+                    out.ops.push_back(ko);
+                }
+                H.op_end = (uint32_t)out.ops.size();
+                out.phases.push_back(H);
+            };
+
+            // filler register bits: highest tile bits not otherwise used
+            auto fill_regs = [&](int *reg, const std::vector<int> &fixed_idx) {
+                std::vector<int> avoid;
+                for (int b : fixed_idx) avoid.push_back(reg[b]);
+                int li = L - 1;
+                for (int b = 0; b < 4; ++b) {
+                    if (std::find(fixed_idx.begin(), fixed_idx.end(), b) != fixed_idx.end()) continue;
+                    while (li >= 0 && std::find(avoid.begin(), avoid.end(), tb[li]) != avoid.end()) --li;
+                    reg[b] = tb[li];
+                    avoid.push_back(tb[li]);
+                    --li;
+                }
+            };
+
+            if (wide >= 0) {
+                // diagonal ops taken before the wide op go into the row phase
+                const LOp &w = ops[wide];
+                const int k = w.k, d = 1 << k;
+                for (int half = 0; half < 2; ++half) {
+                    int reg[4];
+                    std::vector<int> fixed;
+                    for (int j = 0; j < k; ++j) {
+                        reg[j] = w.q[j] + (half ? n : 0);
+                        fixed.push_back(j);
+                    }
+                    fill_regs(reg, fixed);
+                    std::vector<Block> blocks;
+                    if (half == 0)
+                        for (int idx : take)
+                            if (idx != wide) {
+                                Block bk;
+                                bk.rt = true;
+                                bk.op_index = idx;
+                                blocks.push_back(bk);
+                            }
+                    // matrix on register bits 0..k-1 (mask 7 or 15), embedded
+                    Mat16 m{};
+                    const int mask = (1 << k) - 1, rest = (~mask) & 15;
+                    for (int so = 0; so < 16; ++so)
+                        for (int si = 0; si < 16; ++si) {
+                            if ((so & rest) != (si & rest)) continue;
+                            const cd u = w.U[size_t(so & mask) * d + (si & mask)];
+                            m[so * 16 + si] = half ? std::conj(u) : u;
+                        }
+                    Block bk;
+                    bk.m = m;
+                    blocks.push_back(bk);
+                    emit_phase(reg, blocks, {});
+                }
+                continue;
+            }
+
+            // register bits: [qa, qb, qa+n, qb+n] (fillers when fewer qubits)
+            int reg[4];
+            std::vector<int> fixed;
+            int qs[2], nq = 0;
+            for (int q = 0; q < n && nq < 2; ++q)
+                if (P >> q & 1) qs[nq++] = q;
+            if (nq >= 1) { reg[0] = qs[0]; reg[2] = qs[0] + n; fixed.push_back(0); fixed.push_back(2); }
+            if (nq == 2) { reg[1] = qs[1]; reg[3] = qs[1] + n; fixed.push_back(1); fixed.push_back(3); }
+            fill_regs(reg, fixed);
+
+            // blocks in order, fusing across commuting blocks where cheaper
+            std::vector<Block> blocks;
+            for (int idx : take) {
+                const LOp &op = ops[idx];
+                const uint32_t m = qm[idx];
+                if (op.diag && (m & ~P) != 0) {
+                    Block bk;
+                    bk.rt = true;
+                    bk.op_index = idx;
+                    blocks.push_back(bk);
+                    continue;
+                }
+                Block nb;
+                nb.m = embed(op, n, reg, nb.support);
+                nb.diag = op.diag;
+                bool merged = false;
+                if (opt.fuse_blocks) {
+                    for (int j = (int)blocks.size() - 1; j >= 0; --j) {
+                        Block &pb = blocks[j];
+                        if (pb.rt) break;
+                        // blocks on disjoint register bits commute: look further back
+                        if ((pb.support & nb.support) == 0) continue;
+                        // first overlapping block: fuse with it if that is cheaper
+                        Mat16 prod = mul(nb.m, pb.m);
+                        const double cp = encode(prod).cost;
+                        if (cp <= encode(pb.m).cost + encode(nb.m).cost) {
+                            pb.m = prod;
+                            pb.support |= nb.support;
+                            pb.diag = pb.diag && nb.diag;
+                            merged = true;
+                        }
+                        break;
+                    }
+                }
+                if (!merged) blocks.push_back(nb);
+            }
+            emit_phase(reg, blocks, {});
+        }
+        kp.phase_end = (uint32_t)out.phases.size();
+        out.passes.push_back(kp);
+    }
+    return VQD_OK;
+}
+
+int upload_plan(const HostPlan &plan, DevProgram &dev, hipStream_t stream)
+{
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t b_pass = align(plan.passes.size() * sizeof(KPass));
+    const size_t b_phase = align(plan.phases.size() * sizeof(KPhase));
+    const size_t b_ops = align(plan.ops.size() * sizeof(KOp));
+    const size_t b_mats = align(plan.mats.size() * sizeof(double2));
+    const size_t total = b_pass + b_phase + b_ops + b_mats + 256;
+    if (dev.bytes < total) {
+        if (dev.buf) {
+            VQD_HIP(hipStreamSynchronize(stream));
+            (void)hipFree(dev.buf);
+        }
+        dev.buf = nullptr;
+        dev.bytes = 0;
+        if (hipMalloc(&dev.buf, total) != hipSuccess)
+            return fail(VQD_E_NOMEM, "descriptor allocation failed");
+        dev.bytes = total;
+    }
+    std::vector<unsigned char> host(total, 0);
+    size_t off = 0;
+    std::memcpy(host.data() + off, plan.passes.data(), plan.passes.size() * sizeof(KPass));
+    dev.passes = reinterpret_cast<KPass *>((char *)dev.buf + off);
+    off += b_pass;
+    std::memcpy(host.data() + off, plan.phases.data(), plan.phases.size() * sizeof(KPhase));
+    dev.phases = reinterpret_cast<KPhase *>((char *)dev.buf + off);
+    off += b_phase;
+    std::memcpy(host.data() + off, plan.ops.data(), plan.ops.size() * sizeof(KOp));
+    dev.ops = reinterpret_cast<KOp *>((char *)dev.buf + off);
+    off += b_ops;
+    for (size_t i = 0; i < plan.mats.size(); ++i) {
+        double2 v;
+        v.x = plan.mats[i].real();
+        v.y = plan.mats[i].imag();
+        std::memcpy(host.data() + off + i * sizeof(double2), &v, sizeof(double2));
+    }
+    dev.mats = reinterpret_cast<double2 *>((char *)dev.buf + off);
+    off += b_mats;
+    // ordered on the stream after earlier work that read the old descriptors;
+    // the synchronisation keeps the staging vector alive until the copy ends
+    VQD_HIP(hipMemcpyAsync(dev.buf, host.data(), off, hipMemcpyHostToDevice, stream));
+    VQD_HIP(hipStreamSynchronize(stream));
+    return VQD_OK;
+}
+
+void free_dev_program(DevProgram &dev)
+{
+    if (dev.buf) (void)hipFree(dev.buf);
+    dev = DevProgram{};
+}
+
+}  // namespace vqd

@@ -1,0 +1,178 @@
+// Internal definitions of the vqd library: descriptor structs shared by the
+// host planner and the gfx950 kernels, handle structs, error helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/vqd.h"
+
+namespace vqd {
+
+using cd = std::complex<double>;
+
+// ----------------------------------------------------------------- errors --
+void set_error(const std::string &msg);
+void clear_error();
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define VQD_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------- kernel descriptors --
+// A pass streams every amplitude through HBM once.  The 2n vector bits are
+// split into L "tile" bits (local index 0..2^L-1, kept inside one workgroup)
+// and 2n-L "group" bits (one workgroup per tile).  A pass runs a sequence of
+// register phases: in a phase each thread holds 16 amplitudes whose local
+// indices differ in 4 "register" bits; the other L-4 local bits come from
+// the thread id.  Between phases the tile is exchanged through LDS.
+
+constexpr int kMaxTileBits = 12;
+constexpr int kRegBits = 4;
+constexpr int kSlots = 16;
+constexpr uint32_t kPhantomPos = 62;   // global position of a bit beyond 2n
+
+enum KOpKind : uint32_t {
+    KOP_MAT = 1,      // matrix on a subset of register bits (opmask)
+    KOP_DIAG = 2,     // element-wise factors indexed by the 4 register bits
+    KOP_DIAG_RT = 3,  // element-wise factors indexed by arbitrary global bits
+};
+
+struct alignas(16) KOp {
+    uint32_t kind;
+    uint32_t opmask;    // KOP_MAT: register bits the matrix acts on (ascending)
+    uint32_t mat;       // offset of the matrix / factor table in the pool (complex entries)
+    uint32_t nbits;     // KOP_DIAG_RT: number of index bits
+    uint32_t nz[8];     // entry (i*dim + j) is nonzero; KOP_DIAG: factor e != 1
+    uint32_t cx[8];     // entry has a nonzero imaginary part
+    uint32_t gpos[4];   // KOP_DIAG_RT: global bit position of index bit j
+    uint32_t regdep;    // KOP_DIAG_RT: some index bit is a register bit
+    uint32_t pad[3];
+};
+
+struct alignas(16) KPhase {
+    uint32_t op_begin, op_end;
+    uint32_t reg_local[4];
+    uint32_t reg_gpos[4];
+    uint32_t thr_local[8];
+    uint32_t thr_gpos[8];
+};
+
+struct alignas(16) KPass {
+    uint32_t L;               // tile bits (threads = 2^(L-4))
+    uint32_t n_group_bits;
+    uint32_t phase_begin, phase_end;
+    uint32_t phantom;         // some tile bit lies beyond 2n (tiny registers)
+    uint32_t xcd_swizzle;     // remap workgroup ids so tiles sharing cache lines share an XCD
+    uint32_t pad[2];
+    uint64_t n_tiles;
+    uint32_t group_gpos[32];
+};
+
+// Device-side image of a planned program.
+struct DevProgram {
+    void *buf = nullptr;      // one allocation holding everything below
+    size_t bytes = 0;
+    KPass *passes = nullptr;
+    KPhase *phases = nullptr;
+    KOp *ops = nullptr;
+    double2 *mats = nullptr;
+};
+
+// Host-side planned program.
+struct HostPlan {
+    std::vector<KPass> passes;
+    std::vector<KPhase> phases;
+    std::vector<KOp> ops;
+    std::vector<cd> mats;
+    double fma_per_amp = 0;
+};
+
+// ------------------------------------------------------------- logical ops --
+struct LOp {
+    int k = 0;                    // number of qubits
+    int q[4] = {0, 0, 0, 0};      // targets, q[0] = least significant
+    bool diag = false;            // element-wise superoperator (factors in D)
+    bool wide_unitary = false;    // k >= 3 unitary applied as U on rows, conj(U) on columns
+    std::vector<cd> S;            // superoperator 4^k x 4^k (k <= 2), local index order
+    std::vector<cd> D;            // diagonal factors 4^k (diag ops)
+    std::vector<cd> U;            // 2^k x 2^k (wide unitaries)
+};
+
+// Build a logical op from a superoperator; detects diagonal structure.
+LOp make_superop_op(int k, const int *targets, const cd *S);
+LOp make_unitary_op(int k, const int *targets, const cd *U);
+
+// Planner entry point.  Returns VQD_OK or an error code (message set).
+struct PlanOpts {
+    int tile_bits = 12;
+    int min_contig_bits = 3;
+    int max_ops_per_pass = 0;
+    bool fuse_blocks = true;
+};
+int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out);
+
+// Upload a plan into a device program (re-using its buffer when large enough).
+int upload_plan(const HostPlan &plan, DevProgram &dev, hipStream_t stream);
+void free_dev_program(DevProgram &dev);
+
+// ------------------------------------------------------------- launches --
+int launch_pass(double2 *amps, const DevProgram &dev, const KPass &pass, uint32_t pass_idx,
+                hipStream_t stream);
+int launch_init(double2 *amps, int n, int mode, uint64_t b, const double *p0, hipStream_t stream);
+
+struct ReduceScratch {
+    double *dev = nullptr;      // partials + results
+    size_t cap = 0;             // doubles
+    double *host = nullptr;     // pinned host staging
+    size_t host_cap = 0;
+};
+int ensure_scratch(ReduceScratch &s, size_t dev_doubles, size_t host_doubles);
+void free_scratch(ReduceScratch &s);
+
+int reduce_purity(const double2 *amps, int n, ReduceScratch &s, hipStream_t st, double *out);
+int reduce_diag(const double2 *amps, int n, ReduceScratch &s, hipStream_t st, double *trace2,
+                double *z, double *probs);
+int reduce_zz(const double2 *amps, int n, const int *pairs, int npairs, ReduceScratch &s,
+              hipStream_t st, double *out);
+int reduce_pauli(const double2 *amps, int n, uint64_t xmask, uint64_t zmask, int ny,
+                 ReduceScratch &s, hipStream_t st, double *re, double *im);
+
+// ------------------------------------------------------------- builders --
+int kind_arity(int kind, int *nq, int *np);
+int kind_matrix(int kind, const double *params, std::vector<cd> &U, int &k);
+int kind_superop(int kind, const double *params, std::vector<cd> &S, int &k);
+void kraus_to_superop(int k, int nk, const cd *K, std::vector<cd> &S);
+void unitary_to_superop(int k, const cd *U, std::vector<cd> &S);
+
+}  // namespace vqd
+
+// ------------------------------------------------------------- handles --
+struct vqd_dm {
+    double2 *amps = nullptr;
+    int n = 0;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    vqd::DevProgram imm;            // descriptors of immediate (single-op) calls
+    vqd::ReduceScratch red;
+};
+
+struct vqd_prog {
+    int n = 0;
+    std::vector<vqd::LOp> ops;
+    vqd::HostPlan plan;
+    vqd::DevProgram dev;
+    bool compiled = false;
+    int device = -1;
+    int n_kernel_ops = 0;
+    int tile_bits = 12;
+};

@@ -1,0 +1,348 @@
+"""Thin Python binding of libvqd.so (include/vqd.h).
+
+Only argument marshalling happens here: torch provides the device buffer and
+the stream, every step of the emulation runs in the library's HIP kernels.
+If the library is not built the binding raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvqd.so")
+
+_lib = None
+
+# op kind names -> enum vqd_kind (include/vqd.h)
+KINDS = {
+    "rx": 1, "ry": 2, "rz": 3, "h": 4, "x": 5, "y": 6, "z": 7, "su2": 8,
+    "cz": 9, "cphase": 10, "xx": 11, "zz": 12,
+    "depol1": 13, "depol2": 14, "deph1": 15, "deph2": 16, "amp": 17, "gamp": 18,
+    "bitflip1": 19, "bitflip2": 20, "amp_t1": 21, "deph_t2": 22,
+}
+BLOCK_UNITARY = 0
+BLOCK_SUPEROP = 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class VQDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("vqd error %d: %s" % (code, msg))
+        self.code = code
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("tile_bits", ctypes.c_int), ("min_contig_bits", ctypes.c_int),
+                ("max_ops_per_pass", ctypes.c_int), ("fuse_blocks", ctypes.c_int)]
+
+
+class ProgInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("n_ops", ctypes.c_int), ("n_passes", ctypes.c_int),
+                ("n_phases", ctypes.c_int), ("n_kernel_ops", ctypes.c_int),
+                ("fma_per_amp", ctypes.c_double)]
+
+
+def load(path: str = LIB_PATH):
+    """Load libvqd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libvqd.so is not built (%s); run `python -m paper_2306_07342_amd.build`" % path)
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    sig = {
+        "vqd_last_error": ([], ctypes.c_char_p),
+        "vqd_version": ([], ctypes.c_char_p),
+        "vqd_dm_wrap": ([vp, ctypes.c_int, ctypes.c_size_t, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "vqd_dm_destroy": ([vp], ctypes.c_int),
+        "vqd_dm_set_stream": ([vp, vp], ctypes.c_int),
+        "vqd_dm_init_zero": ([vp], ctypes.c_int),
+        "vqd_dm_init_basis": ([vp, ctypes.c_uint64], ctypes.c_int),
+        "vqd_dm_init_product_diag": ([vp, _dp], ctypes.c_int),
+        "vqd_dm_copy_to_host": ([vp, _dp], ctypes.c_int),
+        "vqd_dm_copy_from_host": ([vp, _dp], ctypes.c_int),
+        "vqd_apply_unitary1": ([vp, ctypes.c_int, _dp], ctypes.c_int),
+        "vqd_apply_unitary2": ([vp, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
+        "vqd_apply_superop1": ([vp, ctypes.c_int, _dp], ctypes.c_int),
+        "vqd_apply_superop2": ([vp, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
+        "vqd_apply_fused": ([vp, ctypes.c_int, _ip, ctypes.c_int, _dp], ctypes.c_int),
+        "vqd_apply_diagonal": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+        "vqd_kind_arity": ([ctypes.c_int, _ip, _ip], ctypes.c_int),
+        "vqd_kind_matrix": ([ctypes.c_int, _dp, _dp], ctypes.c_int),
+        "vqd_kind_superop": ([ctypes.c_int, _dp, _dp], ctypes.c_int),
+        "vqd_kraus_to_superop": ([ctypes.c_int, ctypes.c_int, _dp, _dp], ctypes.c_int),
+        "vqd_prog_create": ([ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "vqd_prog_destroy": ([vp], ctypes.c_int),
+        "vqd_prog_add_named": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+        "vqd_prog_add_unitary": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+        "vqd_prog_add_superop": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+        "vqd_prog_add_kraus": ([vp, ctypes.c_int, _ip, ctypes.c_int, _dp], ctypes.c_int),
+        "vqd_plan_opts_default": ([ctypes.POINTER(PlanOpts)], None),
+        "vqd_prog_compile": ([vp, ctypes.POINTER(PlanOpts)], ctypes.c_int),
+        "vqd_prog_plan": ([vp, ctypes.POINTER(PlanOpts)], ctypes.c_int),
+        "vqd_prog_export": ([vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "vqd_prog_run": ([vp, vp], ctypes.c_int),
+        "vqd_prog_info_get": ([vp, ctypes.POINTER(ProgInfo)], ctypes.c_int),
+        "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
+        "vqd_calc_purity": ([vp, _dp], ctypes.c_int),
+        "vqd_calc_probs": ([vp, _dp], ctypes.c_int),
+        "vqd_calc_expec_z": ([vp, _dp], ctypes.c_int),
+        "vqd_calc_expec_zz": ([vp, _ip, ctypes.c_int, _dp], ctypes.c_int),
+        "vqd_calc_expec_pauli": ([vp, ctypes.POINTER(ctypes.c_uint8), _dp, _dp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def lib():
+    return _lib if _lib is not None else load()
+
+
+def check(rc: int):
+    if rc != 0:
+        raise VQDError(rc, lib().vqd_last_error().decode())
+
+
+def _cplx(M) -> np.ndarray:
+    """Row-major interleaved (re, im) doubles."""
+    a = np.ascontiguousarray(np.asarray(M, dtype=np.complex128))
+    return a.view(np.float64).reshape(-1)
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a: np.ndarray):
+    return a.ctypes.data_as(_ip)
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def kind_superop(kind: str, params: Sequence[float]) -> np.ndarray:
+    nq, np_ = ctypes.c_int(), ctypes.c_int()
+    check(lib().vqd_kind_arity(KINDS[kind], ctypes.byref(nq), ctypes.byref(np_)))
+    d = 4 ** nq.value
+    out = np.empty(2 * d * d)
+    p = np.ascontiguousarray(params, dtype=np.float64) if len(params) else np.zeros(1)
+    check(lib().vqd_kind_superop(KINDS[kind], _d(p), _d(out)))
+    return out.view(np.complex128).reshape(d, d)
+
+
+def kind_matrix(kind: str, params: Sequence[float]) -> np.ndarray:
+    nq, np_ = ctypes.c_int(), ctypes.c_int()
+    check(lib().vqd_kind_arity(KINDS[kind], ctypes.byref(nq), ctypes.byref(np_)))
+    d = 2 ** nq.value
+    out = np.empty(2 * d * d)
+    p = np.ascontiguousarray(params, dtype=np.float64) if len(params) else np.zeros(1)
+    check(lib().vqd_kind_matrix(KINDS[kind], _d(p), _d(out)))
+    return out.view(np.complex128).reshape(d, d)
+
+
+def kraus_to_superop(Ks) -> np.ndarray:
+    K = np.ascontiguousarray(np.stack([np.asarray(x, dtype=np.complex128) for x in Ks]))
+    d = K.shape[1]
+    k = int(round(np.log2(d)))
+    out = np.empty(2 * d ** 4)
+    check(lib().vqd_kraus_to_superop(k, K.shape[0], _d(_cplx(K)), _d(out)))
+    return out.view(np.complex128).reshape(d * d, d * d)
+
+
+class DensityMatrix:
+    """An n-qubit density matrix in GPU memory (vectorised, complex128).
+
+    The buffer is a torch float64 tensor of 2 * 4^n values (interleaved
+    re, im) with amp[r + 2^n c] = rho[r][c]."""
+
+    def __init__(self, n: int, device="cuda", stream=None, buffer=None):
+        import torch
+        load()
+        self.n = n
+        if buffer is None:
+            buffer = torch.empty(2 * 4 ** n, dtype=torch.float64, device=device)
+        self.buffer = buffer
+        h = ctypes.c_void_p()
+        check(lib().vqd_dm_wrap(ctypes.c_void_p(buffer.data_ptr()), n,
+                                buffer.numel() * buffer.element_size(), _stream_ptr(stream),
+                                ctypes.byref(h)))
+        self.handle = h
+        self.init_zero()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().vqd_dm_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state ---------------------------------------------------------
+    def init_zero(self):
+        check(lib().vqd_dm_init_zero(self.handle))
+
+    def init_basis(self, b: int):
+        check(lib().vqd_dm_init_basis(self.handle, int(b)))
+
+    def init_product_diag(self, p0):
+        p = np.ascontiguousarray(p0, dtype=np.float64)
+        check(lib().vqd_dm_init_product_diag(self.handle, _d(p)))
+
+    def to_numpy(self) -> np.ndarray:
+        """Vectorised amplitudes as complex128[4^n] (synchronous copy)."""
+        out = np.empty(2 * 4 ** self.n)
+        check(lib().vqd_dm_copy_to_host(self.handle, _d(out)))
+        return out.view(np.complex128)
+
+    def to_matrix(self) -> np.ndarray:
+        """rho as a (2^n, 2^n) matrix (rho[r][c] = amp[r + 2^n c])."""
+        D = 1 << self.n
+        return self.to_numpy().reshape(D, D).T.copy()
+
+    def from_numpy(self, amps: np.ndarray):
+        a = np.ascontiguousarray(np.asarray(amps, dtype=np.complex128).reshape(-1))
+        check(lib().vqd_dm_copy_from_host(self.handle, _d(a.view(np.float64))))
+
+    # -- ops -----------------------------------------------------------
+    def apply_unitary1(self, q, U):
+        check(lib().vqd_apply_unitary1(self.handle, int(q), _d(_cplx(U))))
+
+    def apply_unitary2(self, q0, q1, U):
+        check(lib().vqd_apply_unitary2(self.handle, int(q0), int(q1), _d(_cplx(U))))
+
+    def apply_superop1(self, q, S):
+        check(lib().vqd_apply_superop1(self.handle, int(q), _d(_cplx(S))))
+
+    def apply_superop2(self, q0, q1, S):
+        check(lib().vqd_apply_superop2(self.handle, int(q0), int(q1), _d(_cplx(S))))
+
+    def apply_fused(self, targets, M, kind=BLOCK_UNITARY):
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        check(lib().vqd_apply_fused(self.handle, len(t), _i(t), kind, _d(_cplx(M))))
+
+    def apply_diagonal(self, targets, d):
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        check(lib().vqd_apply_diagonal(self.handle, len(t), _i(t), _d(_cplx(d))))
+
+    # -- read-out ------------------------------------------------------
+    def trace(self) -> complex:
+        re, im = ctypes.c_double(), ctypes.c_double()
+        check(lib().vqd_calc_trace(self.handle, ctypes.byref(re), ctypes.byref(im)))
+        return complex(re.value, im.value)
+
+    def purity(self) -> float:
+        out = ctypes.c_double()
+        check(lib().vqd_calc_purity(self.handle, ctypes.byref(out)))
+        return out.value
+
+    def probs(self) -> np.ndarray:
+        out = np.empty(1 << self.n)
+        check(lib().vqd_calc_probs(self.handle, _d(out)))
+        return out
+
+    def expec_z(self) -> np.ndarray:
+        out = np.empty(self.n)
+        check(lib().vqd_calc_expec_z(self.handle, _d(out)))
+        return out
+
+    def expec_zz(self, pairs) -> np.ndarray:
+        p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        out = np.empty(p.shape[0])
+        check(lib().vqd_calc_expec_zz(self.handle, _i(p), p.shape[0], _d(out)))
+        return out
+
+    def expec_pauli(self, codes) -> complex:
+        c = np.ascontiguousarray(codes, dtype=np.uint8)
+        re, im = ctypes.c_double(), ctypes.c_double()
+        check(lib().vqd_calc_expec_pauli(self.handle, c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                         ctypes.byref(re), ctypes.byref(im)))
+        return complex(re.value, im.value)
+
+
+def plan_opts(tile_bits=12, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True) -> PlanOpts:
+    return PlanOpts(tile_bits, min_contig_bits, max_ops_per_pass, 1 if fuse_blocks else 0)
+
+
+class Program:
+    """An op program planned by the library into fused HBM passes."""
+
+    def __init__(self, n: int, ops: Optional[Iterable] = None):
+        load()
+        self.n = n
+        h = ctypes.c_void_p()
+        check(lib().vqd_prog_create(n, ctypes.byref(h)))
+        self.handle = h
+        if ops is not None:
+            self.extend(ops)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().vqd_prog_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, op):
+        kind, qubits, params = op
+        t = np.ascontiguousarray(qubits, dtype=np.int32)
+        if kind == "matrix":
+            check(lib().vqd_prog_add_unitary(self.handle, len(t), _i(t), _d(_cplx(params[0]))))
+        elif kind == "kraus":
+            K = np.stack([np.asarray(x, dtype=np.complex128) for x in params])
+            check(lib().vqd_prog_add_kraus(self.handle, len(t), _i(t), K.shape[0], _d(_cplx(K))))
+        elif kind == "superop":
+            check(lib().vqd_prog_add_superop(self.handle, len(t), _i(t), _d(_cplx(params[0]))))
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float64) if len(params) else np.zeros(1)
+            check(lib().vqd_prog_add_named(self.handle, KINDS[kind], _i(t), _d(p)))
+
+    def extend(self, ops: Iterable):
+        for op in ops:
+            self.add(op)
+
+    def compile(self, opts: Optional[PlanOpts] = None):
+        check(lib().vqd_prog_compile(self.handle, ctypes.byref(opts) if opts is not None else None))
+        return self
+
+    def plan(self, opts: Optional[PlanOpts] = None):
+        """Plan on the host only (no device needed)."""
+        check(lib().vqd_prog_plan(self.handle, ctypes.byref(opts) if opts is not None else None))
+        return self
+
+    def export(self) -> bytes:
+        """Planned descriptors (see vqd_prog_export in include/vqd.h)."""
+        need = ctypes.c_size_t()
+        check(lib().vqd_prog_export(self.handle, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        check(lib().vqd_prog_export(self.handle, buf, need.value, ctypes.byref(need)))
+        return buf.raw
+
+    def run(self, dm: DensityMatrix):
+        check(lib().vqd_prog_run(self.handle, dm.handle))
+
+    def info(self) -> dict:
+        i = ProgInfo()
+        check(lib().vqd_prog_info_get(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in ProgInfo._fields_}

@@ -1,0 +1,125 @@
+"""CPU emulation of the pass kernel, driven by descriptors exported from the
+library planner (vqd_prog_export).  Test-only: it lets the planner and the
+descriptor encoding be checked against the oracle without a GPU.
+
+It reproduces what k_pass does with each descriptor field: the tile/thread/
+register-slot address split, matrix entries skipped when their nonzero bit is
+clear and imaginary parts dropped when their complex bit is clear, diagonal
+factors indexed by register slots or by global bits, phantom bits.  The LDS
+exchange between phases only moves values between threads of a tile, so it
+is emulated by scattering back to the state and gathering again.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MAGIC = 0x56514450
+
+
+def _dtypes(sz_pass, sz_phase, sz_op):
+    dpass = np.dtype({"names": ["L", "ngb", "pb", "pe", "phantom", "xcd", "n_tiles", "group_gpos"],
+                      "formats": ["<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u8", ("<u4", 32)],
+                      "offsets": [0, 4, 8, 12, 16, 20, 32, 40], "itemsize": sz_pass})
+    dphase = np.dtype({"names": ["ob", "oe", "reg_local", "reg_gpos", "thr_local", "thr_gpos"],
+                       "formats": ["<u4", "<u4", ("<u4", 4), ("<u4", 4), ("<u4", 8), ("<u4", 8)],
+                       "offsets": [0, 4, 8, 24, 40, 72], "itemsize": sz_phase})
+    dop = np.dtype({"names": ["kind", "opmask", "mat", "nbits", "nz", "cx", "gpos", "regdep"],
+                    "formats": ["<u4", "<u4", "<u4", "<u4", ("<u4", 8), ("<u4", 8), ("<u4", 4), "<u4"],
+                    "offsets": [0, 4, 8, 12, 16, 48, 80, 96], "itemsize": sz_op})
+    return dpass, dphase, dop
+
+
+def parse(blob: bytes):
+    h = np.frombuffer(blob, dtype="<u4", count=12)
+    assert h[0] == MAGIC and h[1] == 1
+    npass, nphase, nop, nmat, szp, szh, szo = (int(x) for x in h[2:9])
+    dpass, dphase, dop = _dtypes(szp, szh, szo)
+    off = 48
+    passes = np.frombuffer(blob, dtype=dpass, count=npass, offset=off)
+    off += npass * szp
+    phases = np.frombuffer(blob, dtype=dphase, count=nphase, offset=off)
+    off += nphase * szh
+    ops = np.frombuffer(blob, dtype=dop, count=nop, offset=off)
+    off += nop * szo
+    mats = np.frombuffer(blob, dtype="<f8", count=2 * nmat, offset=off).view(np.complex128)
+    return {"n": int(h[9]), "passes": passes, "phases": phases, "ops": ops, "mats": mats}
+
+
+def _dep4(v, mask):
+    out, k = 0, 0
+    for b in range(4):
+        if mask >> b & 1:
+            if v >> k & 1:
+                out |= 1 << b
+            k += 1
+    return out
+
+
+def _bit(words, b):
+    return (int(words[b >> 5]) >> (b & 31)) & 1
+
+
+def run(plan, amps: np.ndarray) -> np.ndarray:
+    """Apply every pass of `plan` to the vectorised state `amps` (complex128)."""
+    amps = amps.copy()
+    n2 = 2 * plan["n"]
+    mats = plan["mats"]
+    for P in plan["passes"]:
+        L = int(P["L"])
+        nthr_bits = L - 4
+        T = int(P["n_tiles"])
+        gb = np.zeros(T, dtype=np.uint64)
+        tiles = np.arange(T, dtype=np.uint64)
+        for i in range(int(P["ngb"])):
+            gb |= ((tiles >> np.uint64(i)) & np.uint64(1)) << np.uint64(P["group_gpos"][i])
+        for ph in range(int(P["pb"]), int(P["pe"])):
+            H = plan["phases"][ph]
+            thr = np.arange(1 << nthr_bits, dtype=np.uint64)
+            tg = np.zeros_like(thr)
+            for i in range(nthr_bits):
+                tg |= ((thr >> np.uint64(i)) & np.uint64(1)) << np.uint64(H["thr_gpos"][i])
+            rg = [np.uint64(1) << np.uint64(H["reg_gpos"][b]) for b in range(4)]
+            slot = np.zeros(16, dtype=np.uint64)
+            for e in range(16):
+                for b in range(4):
+                    if e >> b & 1:
+                        slot[e] |= rg[b]
+            base = gb[:, None] | tg[None, :]                       # (T, threads)
+            gidx = base[:, :, None] | slot[None, None, :]          # (T, threads, 16)
+            valid = (gidx >> np.uint64(n2)) == 0
+            gi = np.where(valid, gidx, 0).astype(np.int64)
+            a = np.where(valid, amps[gi], 0)
+            for oi in range(int(H["ob"]), int(H["oe"])):
+                op = plan["ops"][oi]
+                M = mats[int(op["mat"]):]
+                kind = int(op["kind"])
+                if kind == 1:
+                    mask = int(op["opmask"])
+                    nb = bin(mask).count("1")
+                    dim = 1 << nb
+                    rest = (~mask) & 15
+                    y = np.zeros_like(a)
+                    for i in range(dim):
+                        for j in range(dim):
+                            bit = i * dim + j
+                            if not _bit(op["nz"], bit):
+                                continue
+                            m = M[bit] if _bit(op["cx"], bit) else M[bit].real
+                            for g in range(16 >> nb):
+                                so = _dep4(i, mask) | _dep4(g, rest)
+                                si = _dep4(j, mask) | _dep4(g, rest)
+                                y[..., so] += m * a[..., si]
+                    a = y
+                elif kind == 2:
+                    for e in range(16):
+                        if _bit(op["nz"], e):
+                            a[..., e] *= M[e] if _bit(op["cx"], e) else M[e].real
+                elif kind == 3:
+                    idx = np.zeros(gidx.shape, dtype=np.int64)
+                    for j in range(int(op["nbits"])):
+                        idx |= ((gidx >> np.uint64(op["gpos"][j])) & np.uint64(1)).astype(np.int64) << j
+                    a = a * M[idx]
+                else:
+                    raise AssertionError("unknown kernel op kind %d" % kind)
+            amps[gi[valid]] = a[valid]
+    return amps

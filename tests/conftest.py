@@ -22,3 +22,14 @@ def gpu_lib():
     from paper_2306_07342_amd import vqd
     vqd.load()
     return vqd
+
+
+@pytest.fixture(scope="session")
+def vqd_host():
+    """The library loaded for host-only use (planning, builders); built if missing."""
+    from paper_2306_07342_amd import build as vbuild, vqd
+    import os
+    if not os.path.exists(vqd.LIB_PATH):
+        vbuild.build()
+    vqd.load()
+    return vqd

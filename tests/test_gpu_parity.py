@@ -1,0 +1,209 @@
+"""GPU parity: every C-ABI call of libvqd against the CPU oracle.
+
+Tolerance: 1e-10 max-abs per amplitude (real and imaginary parts) and per
+observable, the bar the spec requirement fixes for FP64.  States are
+normalised (trace 1 or, for random non-trace-preserving maps, entries of
+order one), so the absolute bar is meaningful.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.core import OracleDM
+from oracle.emulator import emulate, readouts
+from workloads import (c1_line_circuit, c2_grid_circuit, c3_all_to_all_circuit,
+                       random_matrix_ops)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def random_state(n, seed):
+    rng = np.random.default_rng(seed)
+    D = 1 << n
+    A = rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))
+    rho = A @ A.conj().T
+    return rho / np.trace(rho)
+
+
+def to_vec(R):
+    return np.ascontiguousarray(R.T).reshape(-1)
+
+
+def gpu_dm(vqd, R):
+    n = int(round(np.log2(R.shape[0])))
+    dm = vqd.DensityMatrix(n)
+    dm.from_numpy(to_vec(R))
+    return dm
+
+
+def max_err(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return max(np.abs(a.real - b.real).max(), np.abs(np.imag(a) - np.imag(b)).max())
+
+
+# ------------------------------------------------------------------ init --
+
+@pytest.mark.parametrize("n", [1, 2, 5, 7])
+def test_init_states(gpu_lib, n):
+    say("init n=%d" % n)
+    dm = gpu_lib.DensityMatrix(n)
+    ref = OracleDM(n)
+    assert max_err(dm.to_numpy(), ref.to_vectorised()) == 0
+    b = (1 << n) - 2 if n > 1 else 1
+    dm.init_basis(b)
+    ref.init_basis(b)
+    assert max_err(dm.to_numpy(), ref.to_vectorised()) == 0
+    p0 = np.linspace(0.6, 0.95, n)
+    dm.init_product_diag(p0)
+    ref.init_product_diag(p0)
+    assert max_err(dm.to_numpy(), ref.to_vectorised()) < 1e-15
+
+
+# ------------------------------------------------------- immediate calls --
+
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 9])
+def test_single_op_calls(gpu_lib, n):
+    """unitary1/2, superop1/2, fused (k = 1..4 unitary, k = 1..2 superop),
+    diagonal; random targets (both orders), random non-unitary matrices."""
+    say("single ops n=%d" % n)
+    vqd = gpu_lib
+    R = random_state(n, 10 + n)
+    dm = gpu_dm(vqd, R)
+    ref = OracleDM(n)
+    ref.set(R)
+    rng = np.random.default_rng(n)
+    for it in range(40):
+        k = int(rng.integers(1, min(2, n) + 1))
+        t = [int(x) for x in rng.choice(n, k, replace=False)]
+        d = 1 << k
+        M = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / np.sqrt(2 * d)
+        Ks = [(rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / np.sqrt(4 * d)
+              for _ in range(2)]
+        which = it % 5
+        if which == 0:
+            (dm.apply_unitary1(t[0], M) if k == 1 else dm.apply_unitary2(t[0], t[1], M))
+            ref.apply_matrix(t, M)
+        elif which == 1:
+            S = vqd.kraus_to_superop(Ks)
+            (dm.apply_superop1(t[0], S) if k == 1 else dm.apply_superop2(t[0], t[1], S))
+            ref.apply_kraus(t, Ks)
+        elif which == 2:
+            dm.apply_fused(t, M, vqd.BLOCK_UNITARY)
+            ref.apply_matrix(t, M)
+        elif which == 3:
+            dm.apply_fused(t, vqd.kraus_to_superop(Ks), vqd.BLOCK_SUPEROP)
+            ref.apply_kraus(t, Ks)
+        else:
+            dg = np.exp(1j * rng.uniform(0, 6.3, d * d)) * rng.uniform(0.5, 1.0, d * d)
+            dm.apply_diagonal(t, dg)
+            # a diagonal superoperator multiplies amp by d[local index]
+            vec = ref.to_vectorised()
+            idx = np.zeros(vec.shape[0], dtype=np.int64)
+            ar = np.arange(vec.shape[0])
+            for j in range(k):
+                idx |= ((ar >> t[j]) & 1) << j
+                idx |= ((ar >> (t[j] + n)) & 1) << (j + k)
+            vec = vec * dg[idx]
+            ref.set(vec.reshape(1 << n, 1 << n).T)
+        if n >= 3 and it % 8 == 7:
+            k3 = min(4, n)
+            t3 = [int(x) for x in rng.choice(n, k3, replace=False)]
+            d3 = 1 << k3
+            U = (rng.standard_normal((d3, d3)) + 1j * rng.standard_normal((d3, d3))) / np.sqrt(2 * d3)
+            dm.apply_fused(t3, U, vqd.BLOCK_UNITARY)
+            ref.apply_matrix(t3, U)
+    assert max_err(dm.to_numpy(), ref.to_vectorised()) <= TOL
+
+
+# ------------------------------------------------------------ read-outs --
+
+@pytest.mark.parametrize("n", [1, 3, 6, 8])
+def test_readouts(gpu_lib, n):
+    say("readouts n=%d" % n)
+    R = random_state(n, 3 * n)
+    dm = gpu_dm(gpu_lib, R)
+    ref = OracleDM(n)
+    ref.set(R)
+    assert abs(dm.trace() - ref.trace()) <= TOL
+    assert abs(dm.purity() - ref.purity()) <= TOL
+    assert max_err(dm.probs(), ref.probs()) <= TOL
+    assert max_err(dm.expec_z(), ref.expec_z()) <= TOL
+    if n >= 2:
+        pairs = [(i, j) for i in range(n) for j in range(n) if i != j]
+        assert max_err(dm.expec_zz(pairs), ref.expec_zz(pairs)) <= TOL
+    rng = np.random.default_rng(n)
+    for _ in range(10):
+        codes = rng.integers(0, 4, n)
+        assert abs(dm.expec_pauli(codes) - ref.expec_pauli(codes)) <= TOL
+
+
+# -------------------------------------------------------------- programs --
+
+def check_program(vqd, n, ops, opts=None, R=None, seed=0):
+    ref = OracleDM(n)
+    if R is not None:
+        ref.set(R)
+    emulate(n, ops, ref)
+    dm = vqd.DensityMatrix(n)
+    if R is not None:
+        dm.from_numpy(to_vec(R))
+    prog = vqd.Program(n, ops).compile(opts)
+    prog.run(dm)
+    assert max_err(dm.to_numpy(), ref.to_vectorised()) <= TOL
+    r = readouts(ref, with_probs=True)
+    assert max_err(dm.expec_z(), r["expec_z"]) <= TOL
+    assert abs(dm.purity() - r["purity"]) <= TOL
+    assert max_err(dm.probs(), r["probs"]) <= TOL
+    assert abs(dm.trace() - r["trace"]) <= TOL
+    if n >= 2:
+        pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+        assert max_err(dm.expec_zz(pairs), r["expec_zz"]) <= TOL
+    return prog.info()
+
+
+def test_c1_six_qubit_circuit(gpu_lib):
+    """The 6-qubit line workload: 200 gates with depol/T1/T2 noise after each."""
+    say("C1 6q")
+    info = check_program(gpu_lib, 6, c1_line_circuit())
+    assert info["n_passes"] >= 1
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(max_ops_per_pass=1), dict(fuse_blocks=False),
+                                  dict(tile_bits=8, min_contig_bits=0),
+                                  dict(tile_bits=10, min_contig_bits=2)])
+def test_c2_grid_ten_qubits(gpu_lib, opts):
+    """The grid workload's generator on a 2 x 5 grid, several plans."""
+    say("C2 2x5 opts=%r" % (opts,))
+    ops = c2_grid_circuit(rows=2, cols=5, n_gates=150)
+    check_program(gpu_lib, 10, ops, gpu_lib.plan_opts(**opts))
+
+
+def test_c3_all_to_all_eight_qubits(gpu_lib):
+    say("C3 8q")
+    ops = c3_all_to_all_circuit(n=8, n_gates=120)
+    check_program(gpu_lib, 8, ops)
+
+
+@pytest.mark.parametrize("n", [2, 5, 7])
+def test_random_program_nonhermitian_start(gpu_lib, n):
+    say("random program n=%d" % n)
+    rng = np.random.default_rng(n)
+    D = 1 << n
+    R = (rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))) / D
+    ops = random_matrix_ops(n, 40, seed=n, max_k=min(2, n))
+    ops += random_matrix_ops(n, 4, seed=n + 1, max_k=min(4, n), kraus=False)
+    ref = OracleDM(n)
+    ref.set(R)
+    emulate(n, ops, ref)
+    dm = gpu_lib.DensityMatrix(n)
+    dm.from_numpy(to_vec(R))
+    gpu_lib.Program(n, ops).compile().run(dm)
+    assert max_err(dm.to_numpy(), ref.to_vectorised()) <= TOL * max(1.0, np.abs(ref.R).max())

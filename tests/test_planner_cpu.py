@@ -1,0 +1,115 @@
+"""Planner checks on the CPU: plans exported by the library are executed by a
+numpy emulation of the pass kernel (tests/_plan_emu.py) and compared with the
+oracle.  Covers fusion on/off, one op per pass, tile sizes from the 4-bit
+minimum to 12 bits, tiles without contiguous low bits, phantom bits (n = 1),
+wide (3- and 4-qubit) unitary blocks, diagonal ops inside and outside the
+tile, and non-Hermitian starting states (a missing conjugate shows)."""
+import numpy as np
+import pytest
+
+from oracle.core import OracleDM
+from oracle.emulator import emulate
+from tests import _plan_emu as emu
+from workloads import (c1_line_circuit, c2_grid_circuit, c3_all_to_all_circuit,
+                       random_matrix_ops)
+
+
+def start_state(n, seed):
+    rng = np.random.default_rng(seed)
+    D = 1 << n
+    R = (rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))) / D
+    return R
+
+
+def run_both(vqd, n, ops, seed=0, **opts):
+    R0 = start_state(n, seed)
+    dm = OracleDM(n)
+    dm.set(R0)
+    emulate(n, ops, dm)
+    ref = dm.to_vectorised()
+    prog = vqd.Program(n, ops)
+    prog.plan(vqd.plan_opts(**opts))
+    plan = emu.parse(prog.export())
+    got = emu.run(plan, np.ascontiguousarray(R0.T).reshape(-1))
+    info = prog.info()
+    return got, ref, info
+
+
+def assert_close(got, ref, tol=1e-12):
+    err = np.abs(got - ref).max()
+    assert err <= tol * max(1.0, np.abs(ref).max()), err
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_c1_circuit_default_plan(vqd_host, n):
+    ops = c1_line_circuit(n=n, n_gates=80)
+    got, ref, info = run_both(vqd_host, n, ops)
+    assert_close(got, ref)
+    assert info["n_passes"] >= 1
+
+
+@pytest.mark.parametrize("tile_bits,contig,max_ops,fuse", [
+    (12, 3, 0, True), (12, 3, 0, False), (8, 3, 0, True), (6, 0, 0, True),
+    (4, 0, 0, True), (12, 3, 1, True), (10, 2, 3, True), (7, 7, 0, True)])
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_random_matrices_all_plans(vqd_host, n, tile_bits, contig, max_ops, fuse):
+    ops = random_matrix_ops(n, 30, seed=7 * n + tile_bits, max_k=2)
+    if n >= 2 and tile_bits >= 8:
+        ops += random_matrix_ops(n, 6, seed=3, max_k=min(4, n), kraus=False)
+    got, ref, info = run_both(vqd_host, n, ops, seed=n, tile_bits=tile_bits,
+                              min_contig_bits=contig, max_ops_per_pass=max_ops,
+                              fuse_blocks=fuse)
+    assert_close(got, ref)
+    if max_ops == 1:
+        assert info["n_passes"] == len(ops)
+
+
+@pytest.mark.parametrize("tile_bits", [6, 8, 12])
+def test_diagonal_ops_inside_and_outside_tile(vqd_host, tile_bits):
+    n = 6
+    rng = np.random.default_rng(tile_bits)
+    ops = []
+    for _ in range(60):
+        r = rng.integers(0, 7)
+        a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+        if r == 0:
+            ops.append(("rz", (a,), (float(rng.uniform(0, 6.3)),)))
+        elif r == 1:
+            ops.append(("cz", (a, b), ()))
+        elif r == 2:
+            ops.append(("zz", (a, b), (float(rng.uniform(0, 1)),)))
+        elif r == 3:
+            ops.append(("deph1", (a,), (float(rng.uniform(0, 0.5)),)))
+        elif r == 4:
+            ops.append(("deph2", (a, b), (float(rng.uniform(0, 0.7)),)))
+        elif r == 5:
+            ops.append(("ry", (a,), (float(rng.uniform(0, 6.3)),)))
+        else:
+            ops.append(("depol2", (a, b), (float(rng.uniform(0, 0.9)),)))
+    got, ref, _ = run_both(vqd_host, n, ops, seed=1, tile_bits=tile_bits, min_contig_bits=3)
+    assert_close(got, ref)
+
+
+def test_c2_grid_small(vqd_host):
+    ops = c2_grid_circuit(rows=2, cols=3, n_gates=120)
+    got, ref, info = run_both(vqd_host, 6, ops, seed=2, tile_bits=8)
+    assert_close(got, ref)
+    assert info["n_passes"] < len(ops)
+
+
+def test_c3_all_to_all_small(vqd_host):
+    ops = c3_all_to_all_circuit(n=6, n_gates=60)
+    got, ref, _ = run_both(vqd_host, 6, ops, seed=3, tile_bits=8)
+    assert_close(got, ref)
+
+
+def test_named_channels_and_gates(vqd_host):
+    n = 4
+    ops = [("h", (0,), ()), ("x", (1,), ()), ("y", (2,), ()), ("z", (3,), ()),
+           ("su2", (1,), (0.3, -1.2, 0.7, 0.1)), ("cphase", (2, 0), (0.4,)),
+           ("xx", (3, 1), (0.9,)), ("gamp", (2,), (0.8, 0.3)), ("bitflip2", (0, 3), (0.2,)),
+           ("bitflip1", (1,), (0.1,)), ("amp", (0,), (0.3,)), ("depol1", (3,), (0.2,)),
+           ("amp_t1", (2,), (0.5, 20.0)), ("deph_t2", (1,), (0.5, 10.0)), ("deph2", (3, 0), (0.3,))]
+    for tb in (4, 8, 12):
+        got, ref, _ = run_both(vqd_host, n, ops, seed=4, tile_bits=tb, min_contig_bits=0)
+        assert_close(got, ref)
