@@ -45,119 +45,281 @@ __device__ __forceinline__ uint32_t uni(uint32_t x)
     return __builtin_amdgcn_readfirstlane(x);
 }
 
-// y <- M x on the register bits in MASK, for every setting of the other bits.
-template <int MASK>
-__device__ __forceinline__ void apply_mat(double2 (&a)[16], const KOp *__restrict__ op,
-                                          const double2 *__restrict__ M)
+// Coefficient c of an op: complex entries as stored, real ones packed two
+// per pool entry.
+template <bool REAL>
+__device__ __forceinline__ double2 coef(const double2 *__restrict__ M, int c)
 {
-    constexpr int NB = popc4(MASK);
-    constexpr int DIM = 1 << NB;
-    constexpr int NG = 16 >> NB;
-    constexpr int REST = (~MASK) & 15;
-    uint32_t nz[(DIM * DIM + 31) / 32], cx[(DIM * DIM + 31) / 32];
-#pragma unroll
-    for (int w = 0; w < (DIM * DIM + 31) / 32; ++w) {
-        nz[w] = uni(op->nz[w]);
-        cx[w] = uni(op->cx[w]);
+    if (REAL) {
+        const double2 p = M[c >> 1];
+        return make_double2((c & 1) ? p.y : p.x, 0.0);
     }
+    return M[c];
+}
+
+template <bool REAL>
+__device__ __forceinline__ void cmac(double2 &y, const double2 m, const double2 x)
+{
+    y.x = fma(m.x, x.x, y.x);
+    y.y = fma(m.x, x.y, y.y);
+    if (!REAL) {
+        y.x = fma(-m.y, x.y, y.x);
+        y.y = fma(m.y, x.x, y.y);
+    }
+}
+
+// Dense matrix on the register bits in MASK (column-major coefficients), for
+// every setting of the other register bits.  Column-outer order: each
+// coefficient column feeds DIM * NG independent accumulators; the first
+// column initialises them.
+template <int MASK, bool REAL>
+__device__ __forceinline__ void apply_mat(double2 (&a)[16], const double2 *__restrict__ M)
+{
+    constexpr int NB = popc4(MASK), DIM = 1 << NB, NG = 16 >> NB, REST = (~MASK) & 15;
     double2 y[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) y[e] = make_double2(0.0, 0.0);
+    for (int j = 0; j < DIM; ++j) {
+        double2 col[DIM];
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) {
+        for (int i = 0; i < DIM; ++i) col[i] = coef<REAL>(M, j * DIM + i);
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-            const int bit = i * DIM + j;
-            if ((nz[bit >> 5] >> (bit & 31)) & 1u) {
-                const double2 m = M[bit];
-                if ((cx[bit >> 5] >> (bit & 31)) & 1u) {
+        for (int i = 0; i < DIM; ++i)
 #pragma unroll
-                    for (int g = 0; g < NG; ++g) {
-                        const int so = dep4(i, MASK) | dep4(g, REST);
-                        const int si = dep4(j, MASK) | dep4(g, REST);
-                        y[so].x = fma(m.x, a[si].x, y[so].x);
-                        y[so].y = fma(m.x, a[si].y, y[so].y);
-                        y[so].x = fma(-m.y, a[si].y, y[so].x);
-                        y[so].y = fma(m.y, a[si].x, y[so].y);
+            for (int g = 0; g < NG; ++g) {
+                const int so = dep4(i, MASK) | dep4(g, REST), si = dep4(j, MASK) | dep4(g, REST);
+                if (j == 0) {
+                    y[so].x = col[i].x * a[si].x;
+                    y[so].y = col[i].x * a[si].y;
+                    if (!REAL) {
+                        y[so].x = fma(-col[i].y, a[si].y, y[so].x);
+                        y[so].y = fma(col[i].y, a[si].x, y[so].y);
                     }
                 } else {
-#pragma unroll
-                    for (int g = 0; g < NG; ++g) {
-                        const int so = dep4(i, MASK) | dep4(g, REST);
-                        const int si = dep4(j, MASK) | dep4(g, REST);
-                        y[so].x = fma(m.x, a[si].x, y[so].x);
-                        y[so].y = fma(m.x, a[si].y, y[so].y);
-                    }
+                    cmac<REAL>(y[so], col[i], a[si]);
                 }
             }
-        }
     }
 #pragma unroll
     for (int e = 0; e < 16; ++e) a[e] = y[e];
 }
 
-// Element-wise factors indexed by the slot (register bits).
-__device__ __forceinline__ void apply_diag(double2 (&a)[16], const KOp *__restrict__ op,
-                                           const double2 *__restrict__ M)
+// Flip-pattern matrix: y[i] = sum_x W[x][i] a[i ^ flip(x)], flip(x) flipping
+// the row and the column bit of the same qubit(s).  Pauli channels, amplitude
+// damping and their products with diagonal ops have this form.
+template <int MASK>
+__host__ __device__ constexpr int slot_flip(int x)
 {
-    const uint32_t nz = uni(op->nz[0]), cx = uni(op->cx[0]);
+    return MASK == 5 ? (x ? 5 : 0) : MASK == 10 ? (x ? 10 : 0) : ((x & 1) ? 5 : 0) | ((x & 2) ? 10 : 0);
+}
+
+template <int MASK, bool REAL>
+__device__ __forceinline__ void apply_xor(double2 (&a)[16], const double2 *__restrict__ M)
+{
+    constexpr int NB = popc4(MASK), DIM = 1 << NB, NG = 16 >> NB, REST = (~MASK) & 15;
+    constexpr int NX = (MASK == 15) ? 4 : 2;
+    double2 y[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        if ((nz >> e) & 1u) {
-            const double2 m = M[e];
-            if ((cx >> e) & 1u) {
-                const double re = a[e].x * m.x - a[e].y * m.y;
-                const double im = a[e].x * m.y + a[e].y * m.x;
-                a[e] = make_double2(re, im);
-            } else {
-                a[e].x *= m.x;
-                a[e].y *= m.x;
+    for (int x = 0; x < NX; ++x) {
+        double2 w[DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) w[i] = coef<REAL>(M, x * DIM + i);
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int so = dep4(i, MASK) | dep4(g, REST), si = so ^ slot_flip<MASK>(x);
+                if (x == 0) {
+                    y[so].x = w[i].x * a[si].x;
+                    y[so].y = w[i].x * a[si].y;
+                    if (!REAL) {
+                        y[so].x = fma(-w[i].y, a[si].y, y[so].x);
+                        y[so].y = fma(w[i].y, a[si].x, y[so].y);
+                    }
+                } else {
+                    cmac<REAL>(y[so], w[i], a[si]);
+                }
+            }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) a[e] = y[e];
+}
+
+__device__ __forceinline__ double2 cmul(const double2 m, const double2 x)
+{
+    return make_double2(fma(m.x, x.x, -m.y * x.y), fma(m.x, x.y, m.y * x.x));
+}
+
+template <bool REAL>
+__device__ __forceinline__ double2 fmul(const double2 m, const double2 x)
+{
+    return REAL ? make_double2(m.x * x.x, m.x * x.y) : cmul(m, x);
+}
+
+// Element-wise factors indexed by the register slot.
+template <bool REAL>
+__device__ __forceinline__ void apply_diag(double2 (&a)[16], const double2 *__restrict__ M)
+{
+#pragma unroll
+    for (int e = 0; e < 16; ++e) a[e] = fmul<REAL>(coef<REAL>(M, e), a[e]);
+}
+
+// Per-phase, per-thread context of the op loop.
+struct Ctx {
+    uint64_t gb;        // global index bits of the tile (workgroup-uniform)
+    uint32_t tl;        // local index bits from the thread id
+    uint32_t rl[4];     // local bit of register bit b
+};
+
+__device__ __forceinline__ uint32_t slot_l(const uint32_t (&rl)[4], int e)
+{
+    return ((e & 1) ? rl[0] : 0) | ((e & 2) ? rl[1] : 0) | ((e & 4) ? rl[2] : 0) | ((e & 8) ? rl[3] : 0);
+}
+
+// Table index of a runtime diagonal: gathered bit j comes from the tile's
+// group bits (uniform) or from local index bits of `loc`.
+__device__ __forceinline__ uint32_t rt_index(const KOp *__restrict__ op, uint32_t nb, uint64_t gb,
+                                             uint32_t loc)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if ((uint32_t)j < nb) {
+            const uint32_t lp = uni(op->lpos[j]);
+            if (lp == kNotLocal) r |= (uint32_t)((gb >> uni(op->gpos[j])) & 1u) << j;
+            else r |= ((loc >> lp) & 1u) << j;
+        }
+    }
+    return r;
+}
+
+// Element-wise factors from an LDS table indexed by global bits (see RtMode).
+template <uint32_t MODE, bool REAL>
+__device__ __forceinline__ void apply_diag_rt(double2 (&a)[16], const KOp *__restrict__ op,
+                                              const double2 *T, const Ctx &c)
+{
+    const uint32_t nb = uni(op->nbits);
+    if (MODE == RT_NONE) {
+        const double2 f = T[rt_index(op, nb, c.gb, c.tl)];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a[e] = fmul<REAL>(f, a[e]);
+    } else if (MODE == RT_PAIR_A || MODE == RT_PAIR_B) {
+        constexpr int R = (MODE == RT_PAIR_A) ? 0 : 1;
+        const uint32_t base = 4 * rt_index(op, nb, c.gb, c.tl);
+        double2 f[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[k] = T[base + k];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a[e] = fmul<REAL>(f[((e >> R) & 1) | (((e >> (R + 2)) & 1) << 1)], a[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            a[e] = fmul<REAL>(T[rt_index(op, nb, c.gb, c.tl | slot_l(c.rl, e))], a[e]);
+    }
+}
+
+// Global bits of tile t (workgroup-uniform).
+__device__ __forceinline__ uint64_t group_base(const KPass *__restrict__ P, uint64_t t, uint32_t ngb,
+                                               bool xcd)
+{
+    if (xcd) {
+        // workgroup b runs on XCD b % 8: the tiles that differ in the lowest
+        // group bits (and share cache lines) are given to one XCD
+        const uint64_t x = t & 7u, s = t >> 3;
+        t = (s & 7u) | (x << 3) | ((s >> 3) << 6);
+    }
+    uint64_t g = 0;
+    for (uint32_t i = 0; i < ngb; ++i) g |= ((t >> i) & 1ull) << uni(P->group_gpos[i]);
+    return g;
+}
+
+// Local and global index bits contributed by the thread id in phase H.
+__device__ __forceinline__ void thread_bits(const KPhase *__restrict__ H, uint32_t tid, uint32_t nthr,
+                                            uint32_t &tl, uint64_t &tg)
+{
+    tl = 0;
+    tg = 0;
+    for (uint32_t i = 0; i < nthr; ++i) {
+        const uint32_t b = (tid >> i) & 1u;
+        tl |= b << uni(H->thr_local[i]);
+        tg |= (uint64_t)b << uni(H->thr_gpos[i]);
+    }
+}
+
+__device__ __forceinline__ uint32_t thread_local_bits(const KPhase *__restrict__ H, uint32_t tid,
+                                                      uint32_t nthr)
+{
+    uint32_t tl = 0;
+    for (uint32_t i = 0; i < nthr; ++i) tl |= ((tid >> i) & 1u) << uni(H->thr_local[i]);
+    return tl;
+}
+
+__device__ __forceinline__ uint64_t slot_g(const KPhase *__restrict__ H, int e)
+{
+    uint64_t g = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (e >> b & 1) g |= 1ull << uni(H->reg_gpos[b]);
+    return g;
+}
+
+__device__ __forceinline__ void apply_ops(double2 (&a)[16], const KPhase *__restrict__ H,
+                                          const KOp *__restrict__ ops,
+                                          const double2 *__restrict__ mats, const double2 *lds_rt,
+                                          const Ctx &c)
+{
+    const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
+    for (uint32_t oi = ob; oi < oe; ++oi) {
+        const KOp *op = ops + oi;
+        const uint32_t kind = uni(op->kind);
+        const uint32_t sel = uni(op->opmask) | (uni(op->real) << 4);
+        const double2 *M = mats + uni(op->mat);
+        if (kind == KOP_MAT) {
+            switch (sel) {
+            case 5: apply_mat<5, false>(a, M); break;
+            case 10: apply_mat<10, false>(a, M); break;
+            case 15: apply_mat<15, false>(a, M); break;
+            case 7: apply_mat<7, false>(a, M); break;
+            case 16 | 5: apply_mat<5, true>(a, M); break;
+            case 16 | 10: apply_mat<10, true>(a, M); break;
+            case 16 | 15: apply_mat<15, true>(a, M); break;
+            case 16 | 7: apply_mat<7, true>(a, M); break;
+            default: break;
+            }
+        } else if (kind == KOP_XOR) {
+            switch (sel) {
+            case 5: apply_xor<5, false>(a, M); break;
+            case 10: apply_xor<10, false>(a, M); break;
+            case 15: apply_xor<15, false>(a, M); break;
+            case 16 | 5: apply_xor<5, true>(a, M); break;
+            case 16 | 10: apply_xor<10, true>(a, M); break;
+            case 16 | 15: apply_xor<15, true>(a, M); break;
+            default: break;
+            }
+        } else if (kind == KOP_DIAG) {
+            if (sel & 16) apply_diag<true>(a, M);
+            else apply_diag<false>(a, M);
+        } else {
+            const double2 *T = lds_rt + uni(op->mat);
+            switch (uni(op->mode) | (sel & 16)) {
+            case RT_NONE: apply_diag_rt<RT_NONE, false>(a, op, T, c); break;
+            case RT_PAIR_A: apply_diag_rt<RT_PAIR_A, false>(a, op, T, c); break;
+            case RT_PAIR_B: apply_diag_rt<RT_PAIR_B, false>(a, op, T, c); break;
+            case RT_GENERIC: apply_diag_rt<RT_GENERIC, false>(a, op, T, c); break;
+            case 16 | RT_NONE: apply_diag_rt<RT_NONE, true>(a, op, T, c); break;
+            case 16 | RT_PAIR_A: apply_diag_rt<RT_PAIR_A, true>(a, op, T, c); break;
+            case 16 | RT_PAIR_B: apply_diag_rt<RT_PAIR_B, true>(a, op, T, c); break;
+            default: apply_diag_rt<RT_GENERIC, true>(a, op, T, c); break;
             }
         }
     }
 }
 
-__device__ __forceinline__ uint32_t gather_bits(uint64_t gi, const uint32_t (&pos)[4], uint32_t nb)
-{
-    uint32_t r = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if ((uint32_t)j < nb) r |= (uint32_t)((gi >> pos[j]) & 1u) << j;
-    return r;
-}
-
-// Element-wise factors indexed by arbitrary global bits.
-__device__ __forceinline__ void apply_diag_rt(double2 (&a)[16], const KOp *__restrict__ op,
-                                              const double2 *__restrict__ M, uint64_t base,
-                                              const uint64_t (&rg)[4])
-{
-    const uint32_t nb = uni(op->nbits);
-    uint32_t pos[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) pos[j] = uni(op->gpos[j]);
-    const uint32_t rt = gather_bits(base, pos, nb);
-    if (!uni(op->regdep)) {
-        const double2 m = M[rt];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const double re = a[e].x * m.x - a[e].y * m.y;
-            const double im = a[e].x * m.y + a[e].y * m.x;
-            a[e] = make_double2(re, im);
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const uint64_t ge = ((e & 1) ? rg[0] : 0) | ((e & 2) ? rg[1] : 0) |
-                                ((e & 4) ? rg[2] : 0) | ((e & 8) ? rg[3] : 0);
-            const uint32_t ct = gather_bits(ge, pos, nb);
-            const double2 m = M[rt | ct];
-            const double re = a[e].x * m.x - a[e].y * m.y;
-            const double im = a[e].x * m.y + a[e].y * m.x;
-            a[e] = make_double2(re, im);
-        }
-    }
-}
-
+// One HBM pass.  Persistent: workgroup b handles tiles b, b + G, b + 2G, ...
+// and issues the loads of its next tile before working on the current one,
+// so HBM traffic overlaps the FP64 work and the LDS exchanges.  Address
+// parts that depend only on the thread are computed once; the tile and
+// register-slot parts are workgroup-uniform (scalar unit).
+template <bool PHANTOM>
 __global__ void __launch_bounds__(kThreads)
 k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
        const KPhase *__restrict__ phases, const KOp *__restrict__ ops,
@@ -167,94 +329,88 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     const KPass *P = passes + pass_idx;
     const uint32_t L = uni(P->L);
     const uint32_t nthr = L - 4;
-    uint64_t tile = blockIdx.x;
-    if (uni(P->xcd_swizzle)) {
-        // workgroup b runs on XCD b % 8: give consecutive workgroups of one
-        // XCD the tiles that differ in the lowest group bits
-        const uint64_t x = tile & 7u, s = tile >> 3;
-        tile = (s & 7u) | (x << 3) | ((s >> 3) << 6);
-    }
-    uint64_t gbase = 0;
     const uint32_t ngb = uni(P->n_group_bits);
-    for (uint32_t i = 0; i < ngb; ++i)
-        gbase |= ((tile >> i) & 1ull) << uni(P->group_gpos[i]);
-
+    const bool xcd = uni(P->xcd_swizzle) != 0;
+    const uint64_t n_tiles = P->n_tiles;
     const uint32_t tid = threadIdx.x;
     const uint32_t pb = uni(P->phase_begin), pe = uni(P->phase_end);
-    const bool phantom = uni(P->phantom) != 0;
-    double2 a[16];
+    const KPhase *H0 = phases + pb, *HL = phases + pe - 1;
 
-    for (uint32_t ph = pb; ph < pe; ++ph) {
-        const KPhase *H = phases + ph;
-        uint32_t tl = 0;
-        uint64_t tg = 0;
-        for (uint32_t i = 0; i < nthr; ++i) {
-            const uint32_t b = (tid >> i) & 1u;
-            tl |= b << uni(H->thr_local[i]);
-            tg |= (uint64_t)b << uni(H->thr_gpos[i]);
-        }
-        uint32_t rl[4];
-        uint64_t rg[4];
+    // stage the pass's runtime-diagonal factor tables in LDS after the tile
+    const uint32_t rt_count = uni(P->rt_count);
+    double2 *lds_rt = lds + ((pe - pb > 1) ? (1u << L) : 0u);
+    if (rt_count) {
+        const double2 *src = mats + uni(P->rt_mat);
+        for (uint32_t i = tid; i < rt_count; i += blockDim.x) lds_rt[i] = src[i];
+        __syncthreads();
+    }
+
+    // thread parts of the load (first phase) and store (last phase) addresses
+    uint32_t tl0, tlL;
+    uint64_t tg0, tgL;
+    thread_bits(H0, tid, nthr, tl0, tg0);
+    thread_bits(HL, tid, nthr, tlL, tgL);
+    const double2 *ld_lane = amps + tg0;
+    double2 *st_lane = amps + tgL;
+
+    uint64_t t = blockIdx.x;
+    double2 nxt[16];
+    if (t < n_tiles) {
+        const uint64_t gb = group_base(P, t, ngb, xcd);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            rl[b] = 1u << uni(H->reg_local[b]);
-            rg[b] = 1ull << uni(H->reg_gpos[b]);
+        for (int e = 0; e < 16; ++e) {
+            const uint64_t u = gb | slot_g(H0, e);
+            nxt[e] = (PHANTOM && ((u | tg0) >> kPhantomPos)) ? make_double2(0.0, 0.0) : ld_lane[u];
         }
-        const uint64_t base = gbase | tg;
-        if (ph == pb) {
+    }
+
+    for (; t < n_tiles; t += gridDim.x) {
+        double2 a[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a[e] = nxt[e];
+        const uint64_t gb = group_base(P, t, ngb, xcd);
+        {
+            // prefetch the next tile (the last iteration re-reads its own
+            // tile, which keeps the loads unconditional)
+            const uint64_t t2 = (t + gridDim.x < n_tiles) ? t + gridDim.x : t;
+            const uint64_t gb2 = group_base(P, t2, ngb, xcd);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const uint64_t gi = base | ((e & 1) ? rg[0] : 0) | ((e & 2) ? rg[1] : 0) |
-                                    ((e & 4) ? rg[2] : 0) | ((e & 8) ? rg[3] : 0);
-                if (phantom && (gi >> kPhantomPos))
-                    a[e] = make_double2(0.0, 0.0);
-                else
-                    a[e] = amps[gi];
+                const uint64_t u = gb2 | slot_g(H0, e);
+                nxt[e] = (PHANTOM && ((u | tg0) >> kPhantomPos)) ? make_double2(0.0, 0.0) : ld_lane[u];
             }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t li = tl | ((e & 1) ? rl[0] : 0) | ((e & 2) ? rl[1] : 0) |
-                                    ((e & 4) ? rl[2] : 0) | ((e & 8) ? rl[3] : 0);
-                a[e] = lds[swz(li)];
-            }
-            __syncthreads();
         }
 
-        const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
-        for (uint32_t oi = ob; oi < oe; ++oi) {
-            const KOp *op = ops + oi;
-            const uint32_t kind = uni(op->kind);
-            const double2 *M = mats + uni(op->mat);
-            if (kind == KOP_MAT) {
-                switch (uni(op->opmask)) {
-                case 5: apply_mat<5>(a, op, M); break;
-                case 10: apply_mat<10>(a, op, M); break;
-                case 15: apply_mat<15>(a, op, M); break;
-                case 7: apply_mat<7>(a, op, M); break;
-                default: break;
-                }
-            } else if (kind == KOP_DIAG) {
-                apply_diag(a, op, M);
+        for (uint32_t ph = pb; ph < pe; ++ph) {
+            const KPhase *H = phases + ph;
+            Ctx c;
+            c.gb = gb;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) c.rl[b] = 1u << uni(H->reg_local[b]);
+            c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL : thread_local_bits(H, tid, nthr);
+            // LDS byte address of slot e: swizzle is xor-linear, so it splits
+            // into a per-thread part and a uniform per-slot part
+            const uint32_t lds_thr = swz(c.tl) << 4;
+            if (ph != pb) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    a[e] = *reinterpret_cast<const double2 *>(
+                        reinterpret_cast<const char *>(lds) + (lds_thr ^ (swz(slot_l(c.rl, e)) << 4)));
+                __syncthreads();
+            }
+            apply_ops(a, H, ops, mats, lds_rt, c);
+            if (ph + 1 < pe) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
+                                                 (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
+                __syncthreads();
             } else {
-                apply_diag_rt(a, op, M, base, rg);
-            }
-        }
-
-        if (ph + 1 < pe) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t li = tl | ((e & 1) ? rl[0] : 0) | ((e & 2) ? rl[1] : 0) |
-                                    ((e & 4) ? rl[2] : 0) | ((e & 8) ? rl[3] : 0);
-                lds[swz(li)] = a[e];
-            }
-            __syncthreads();
-        } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint64_t gi = base | ((e & 1) ? rg[0] : 0) | ((e & 2) ? rg[1] : 0) |
-                                    ((e & 4) ? rg[2] : 0) | ((e & 8) ? rg[3] : 0);
-                if (!(phantom && (gi >> kPhantomPos))) amps[gi] = a[e];
+                for (int e = 0; e < 16; ++e) {
+                    const uint64_t u = gb | slot_g(HL, e);
+                    if (!(PHANTOM && ((u | tgL) >> kPhantomPos))) st_lane[u] = a[e];
+                }
             }
         }
     }
@@ -429,16 +585,36 @@ int launch_pass(double2 *amps, const DevProgram &dev, const KPass &pass, uint32_
                 hipStream_t stream)
 {
     const uint32_t threads = 1u << (pass.L - 4);
-    const size_t lds = (pass.phase_end - pass.phase_begin > 1) ? (size_t(16) << pass.L) : 0;
-    if (pass.n_tiles > 0xffffffffull) return fail(VQD_E_SIZE, "too many tiles for one launch");
+    const size_t lds = ((pass.phase_end - pass.phase_begin > 1) ? (size_t(16) << pass.L) : 0) +
+                       size_t(16) * pass.rt_count;
+    if (lds > 160 * 1024) return fail(VQD_E_SIZE, "pass needs more LDS than a workgroup has");
     static bool attr_set = false;
+    static int n_cu = 0;
+    const void *kfn = pass.phantom ? (const void *)k_pass<true> : (const void *)k_pass<false>;
     if (!attr_set) {
-        VQD_HIP(hipFuncSetAttribute((const void *)k_pass, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    16 << kMaxTileBits));
+        VQD_HIP(hipFuncSetAttribute((const void *)k_pass<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024));
+        VQD_HIP(hipFuncSetAttribute((const void *)k_pass<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024));
+        int dev_id = 0;
+        VQD_HIP(hipGetDevice(&dev_id));
+        VQD_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_pass, dim3((uint32_t)pass.n_tiles), dim3(threads), lds, stream, amps,
-                       dev.passes, dev.phases, dev.ops, dev.mats, pass_idx);
+    // persistent grid: as many workgroups as fit on the device at once
+    int per_cu = 0;
+    VQD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, (int)threads, lds));
+    if (per_cu < 1) per_cu = 1;
+    uint64_t grid = (uint64_t)per_cu * (uint64_t)n_cu;
+    grid -= grid % 64;               // keeps the XCD tile mapping a bijection
+    if (grid == 0) grid = 64;
+    if (grid > pass.n_tiles) grid = pass.n_tiles;
+    if (pass.phantom)
+        hipLaunchKernelGGL(k_pass<true>, dim3((uint32_t)grid), dim3(threads), lds, stream, amps,
+                           dev.passes, dev.phases, dev.ops, dev.mats, pass_idx);
+    else
+        hipLaunchKernelGGL(k_pass<false>, dim3((uint32_t)grid), dim3(threads), lds, stream, amps,
+                           dev.passes, dev.phases, dev.ops, dev.mats, pass_idx);
     VQD_HIP(hipGetLastError());
     return VQD_OK;
 }

@@ -150,46 +150,109 @@ bool restrict_to(const Mat16 &m, int mask, std::vector<cd> &sub)
     return true;
 }
 
-double entry_cost(cd v) { return is_zero(v) ? 0.0 : (v.imag() != 0.0 ? 4.0 : 2.0); }
+bool all_real(const std::vector<cd> &v)
+{
+    for (const cd &x : v)
+        if (x.imag() != 0.0) return false;
+    return true;
+}
+
+// Flip patterns of a register mask: flipping the row and the column bit of
+// the same qubit together.  In slot space mask 5 holds one qubit on slot
+// bits (0, 2), mask 10 one on (1, 3), mask 15 both.  Returned as local
+// indices inside the mask (dep4 order).
+std::vector<int> local_flips(int mask)
+{
+    if (mask == 5 || mask == 10) return {0, 3};
+    if (mask == 15) return {0, 5, 10, 15};
+    return {};
+}
 
 struct Encoded {
     uint32_t kind = KOP_MAT;
     int mask = 15;
-    std::vector<cd> data;   // matrix or 16 factors
+    bool real = false;
+    bool identity = false;
+    std::vector<cd> data;   // kernel layout (see KOp)
     double cost = 0;        // FMAs per 16 slots
 };
 
+// Pack coefficients into the pool layout: complex as is, real ones two per entry.
+std::vector<cd> pack(const std::vector<cd> &c, bool real)
+{
+    if (!real) return c;
+    std::vector<cd> o((c.size() + 1) / 2);
+    for (size_t i = 0; i < c.size(); ++i) {
+        if (i & 1) o[i / 2].imag(c[i].real());
+        else o[i / 2].real(c[i].real());
+    }
+    return o;
+}
+
+// Cheapest branch-free kernel form of a slot-space matrix.
 Encoded encode(const Mat16 &m)
 {
     Encoded best;
     best.cost = 1e30;
-    bool diag = true;
-    for (int i = 0; i < 16 && diag; ++i)
-        for (int j = 0; j < 16; ++j)
-            if (i != j && !is_zero(m[i * 16 + j])) { diag = false; break; }
-    if (diag) {
-        best.kind = KOP_DIAG;
-        best.data.resize(16);
-        best.cost = 0;
-        for (int e = 0; e < 16; ++e) {
-            best.data[e] = m[e * 16 + e];
-            if (best.data[e] != cd(1)) best.cost += entry_cost(best.data[e]);
+    bool diag = true, ident = true;
+    for (int i = 0; i < 16; ++i)
+        for (int j = 0; j < 16; ++j) {
+            const cd v = m[i * 16 + j];
+            if (i != j && !is_zero(v)) diag = false;
+            if (v != (i == j ? cd(1) : cd(0))) ident = false;
         }
+    if (ident) {
+        best.identity = true;
+        best.cost = 0;
         return best;
     }
-    static const int masks[] = {5, 10, 7, 15};
+    if (diag) {
+        std::vector<cd> f(16);
+        for (int e = 0; e < 16; ++e) f[e] = m[e * 16 + e];
+        best.kind = KOP_DIAG;
+        best.real = all_real(f);
+        best.data = pack(f, best.real);
+        best.cost = 16.0 * (best.real ? 2 : 4);
+        return best;
+    }
+    static const int masks[] = {5, 10, 15, 7};
     std::vector<cd> sub;
     for (int mask : masks) {
         if (!restrict_to(m, mask, sub)) continue;
-        const int nb = popc((uint32_t)mask), groups = 16 >> nb;
-        double c = 0;
-        for (auto &v : sub) c += entry_cost(v);
-        c *= groups;
-        if (c < best.cost) {
+        const int nb = popc((uint32_t)mask), dim = 1 << nb, groups = 16 >> nb;
+        const bool real = all_real(sub);
+        const double per = real ? 2.0 : 4.0;
+        // dense, column-major
+        const double dense = groups * dim * dim * per;
+        if (dense < best.cost) {
+            std::vector<cd> cm(size_t(dim) * dim);
+            for (int j = 0; j < dim; ++j)
+                for (int i = 0; i < dim; ++i) cm[j * dim + i] = sub[i * dim + j];
             best.kind = KOP_MAT;
             best.mask = mask;
-            best.data = sub;
-            best.cost = c;
+            best.real = real;
+            best.data = pack(cm, real);
+            best.cost = dense;
+        }
+        // flip pattern: nonzeros only where row and column bits flip together
+        const std::vector<int> fl = local_flips(mask);
+        if (fl.empty()) continue;
+        bool ok = true;
+        for (int i = 0; i < dim && ok; ++i)
+            for (int j = 0; j < dim; ++j)
+                if (!is_zero(sub[i * dim + j]) &&
+                    std::find(fl.begin(), fl.end(), i ^ j) == fl.end()) { ok = false; break; }
+        if (!ok) continue;
+        const double xcost = groups * dim * (double)fl.size() * per;
+        if (xcost < best.cost) {
+            std::vector<cd> w(fl.size() * dim);
+            for (size_t x = 0; x < fl.size(); ++x)
+                for (int i = 0; i < dim; ++i) w[x * dim + i] = sub[i * dim + (i ^ fl[x])];
+            best.kind = KOP_XOR;
+            best.mask = mask;
+            best.real = real;
+            best.data = pack(w, real);
+            best.cost = xcost;
         }
     }
     return best;
@@ -239,7 +302,6 @@ Mat16 embed(const LOp &op, int n, const int *reg_gpos, uint32_t &support)
     return m;
 }
 
-void set_bits(uint32_t *w, int bit) { w[bit >> 5] |= 1u << (bit & 31); }
 
 }  // namespace
 
@@ -264,7 +326,16 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                                         " tile bits; tile has " + std::to_string(L));
     }
 
+    // exact identities (e.g. a zero-probability channel) are dropped
     std::vector<char> applied(ops.size(), 0);
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const LOp &op = ops[i];
+        if (!op.diag || op.wide_unitary) continue;
+        bool ident = true;
+        for (const cd &f : op.D)
+            if (f != cd(1)) { ident = false; break; }
+        if (ident) applied[i] = 1;
+    }
     size_t first = 0;
     SimResult sim, sim2;
     while (true) {
@@ -321,6 +392,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             if (std::find(tb.begin(), tb.end(), b) == tb.end()) low_in_tile = false;
         kp.xcd_swizzle = (!low_in_tile && kp.n_tiles >= 64 && kp.n_tiles % 64 == 0) ? 1u : 0u;
         kp.phase_begin = (uint32_t)out.phases.size();
+        std::vector<cd> rt_tables;      // runtime-diagonal tables of this pass (LDS-staged)
         auto local_of = [&](int g) {
             for (int i = 0; i < (int)tb.size(); ++i)
                 if (tb[i] == g) return i;
@@ -328,6 +400,132 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         };
 
         // ---- phases
+        auto emit_phase = [&](const int *reg_gpos, const std::vector<Block> &blocks,
+                              const std::vector<int> &rt_ops_unused) {
+            (void)rt_ops_unused;
+            KPhase H{};
+            bool used[kMaxTileBits] = {false};
+            for (int b = 0; b < 4; ++b) {
+                const int l = local_of(reg_gpos[b]);
+                H.reg_local[b] = (uint32_t)l;
+                H.reg_gpos[b] = (uint32_t)reg_gpos[b];
+                used[l] = true;
+            }
+            // thread bits: the first three (lanes 0..7 of a wave) take one free
+            // local bit from each residue class mod 3, so that the LDS swizzle
+            // (low three bits xor bits 3-5, 6-8, 9-11) spreads every group of 8
+            // lanes over all banks; the rest follow in ascending order
+            std::vector<int> tl_order;
+            for (int cls = 0; cls < 3; ++cls)
+                for (int l = 0; l < L; ++l)
+                    if (!used[l] && l % 3 == cls) {
+                        tl_order.push_back(l);
+                        break;
+                    }
+            if ((int)tl_order.size() < 3) tl_order.clear();
+            std::sort(tl_order.begin(), tl_order.end());
+            for (int l = 0; l < L; ++l)
+                if (!used[l] && std::find(tl_order.begin(), tl_order.end(), l) == tl_order.end())
+                    tl_order.push_back(l);
+            for (int t = 0; t < L - 4; ++t) {
+                H.thr_local[t] = (uint32_t)tl_order[t];
+                H.thr_gpos[t] = (uint32_t)tb[tl_order[t]];
+            }
+            H.op_begin = (uint32_t)out.ops.size();
+            for (const Block &bk : blocks) {
+                KOp ko{};
+                if (bk.rt) {
+                    const LOp &op = ops[bk.op_index];
+                    const int nb = 2 * op.k;
+                    int g[4], sb[4];     // global position and register slot bit of index bit j
+                    for (int j = 0; j < nb; ++j) {
+                        g[j] = (j < op.k) ? op.q[j] : op.q[j - op.k] + n;
+                        sb[j] = -1;
+                        for (int b = 0; b < 4; ++b)
+                            if (reg_gpos[b] == g[j]) sb[j] = b;
+                    }
+                    // which index bits come from register slots
+                    std::vector<int> regj, rtj;
+                    for (int j = 0; j < nb; ++j) (sb[j] >= 0 ? regj : rtj).push_back(j);
+                    std::vector<cd> table;
+                    ko.kind = KOP_DIAG_RT;
+                    uint32_t mode = RT_GENERIC;
+                    int row_j = -1, col_j = -1;
+                    if (regj.empty()) {
+                        mode = RT_NONE;
+                    } else if (regj.size() == 2) {
+                        for (int j : regj) {
+                            if (sb[j] == 0 || sb[j] == 1) row_j = j;
+                            if (sb[j] == 2 || sb[j] == 3) col_j = j;
+                        }
+                        if (row_j >= 0 && col_j >= 0 && sb[col_j] == sb[row_j] + 2)
+                            mode = sb[row_j] == 0 ? RT_PAIR_A : RT_PAIR_B;
+                    }
+                    ko.mode = mode;
+                    if (mode == RT_GENERIC) {
+                        ko.nbits = (uint32_t)nb;
+                        for (int j = 0; j < nb; ++j) ko.gpos[j] = (uint32_t)g[j];
+                        table = op.D;
+                    } else {
+                        ko.nbits = (uint32_t)rtj.size();
+                        for (size_t t = 0; t < rtj.size(); ++t) ko.gpos[t] = (uint32_t)g[rtj[t]];
+                        const int shift = (mode == RT_NONE) ? 0 : 2;
+                        table.assign(size_t(1) << (shift + rtj.size()), cd(0));
+                        for (int idx = 0; idx < (1 << nb); ++idx) {
+                            int t = 0;
+                            for (size_t r = 0; r < rtj.size(); ++r) t |= ((idx >> rtj[r]) & 1) << r;
+                            int c = 0;
+                            if (mode != RT_NONE) c = ((idx >> row_j) & 1) | (((idx >> col_j) & 1) << 1);
+                            table[size_t(c) + (size_t(t) << shift)] = op.D[idx];
+                        }
+                    }
+                    for (uint32_t j = 0; j < ko.nbits; ++j) {
+                        const int l = local_of((int)ko.gpos[j]);
+                        ko.lpos[j] = (l >= 0) ? (uint32_t)l : kNotLocal;
+                    }
+                    ko.real = all_real(table) ? 1u : 0u;
+                    ko.mat = (uint32_t)rt_tables.size();
+                    rt_tables.insert(rt_tables.end(), table.begin(), table.end());
+                    out.fma_per_amp += ko.real ? 2.0 : 4.0;
+                } else {
+                    Encoded enc = encode(bk.m);
+                    if (enc.identity) continue;
+                    ko.kind = enc.kind;
+                    ko.opmask = (uint32_t)enc.mask;
+                    ko.real = enc.real ? 1u : 0u;
+                    ko.mat = (uint32_t)out.mats.size();
+                    out.mats.insert(out.mats.end(), enc.data.begin(), enc.data.end());
+                    out.fma_per_amp += enc.cost / 16.0;
+                }
+                out.ops.push_back(ko);
+            }
+            H.op_end = (uint32_t)out.ops.size();
+            out.phases.push_back(H);
+        };
+
+        // filler register bits: highest tile bits not otherwise used
+        // filler register bits: the highest tile bits not otherwise used,
+        // preferring bits that no runtime-diagonal op of the phase reads
+        auto fill_regs = [&](int *reg, const std::vector<int> &fixed_idx,
+                             const std::vector<int> &prefer_not) {
+            std::vector<int> taken;
+            for (int b : fixed_idx) taken.push_back(reg[b]);
+            std::vector<int> order;          // candidate tile bits, best first
+            for (int li = L - 1; li >= 0; --li)
+                if (std::find(prefer_not.begin(), prefer_not.end(), tb[li]) == prefer_not.end())
+                    order.push_back(tb[li]);
+            for (int li = L - 1; li >= 0; --li)
+                if (std::find(prefer_not.begin(), prefer_not.end(), tb[li]) != prefer_not.end())
+                    order.push_back(tb[li]);
+            size_t oi = 0;
+            for (int b = 0; b < 4; ++b) {
+                if (std::find(fixed_idx.begin(), fixed_idx.end(), b) != fixed_idx.end()) continue;
+                while (std::find(taken.begin(), taken.end(), order[oi]) != taken.end()) ++oi;
+                reg[b] = order[oi];
+                taken.push_back(order[oi]);
+            }
+        };
+
         std::vector<int> rem = sim.taken;
         while (!rem.empty()) {
             uint32_t P = 0;
@@ -366,80 +564,6 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             }
             rem.swap(keep);
 
-            auto emit_phase = [&](const int *reg_gpos, const std::vector<Block> &blocks,
-                                  const std::vector<int> &rt_ops_unused) {
-                (void)rt_ops_unused;
-                KPhase H{};
-                bool used[kMaxTileBits] = {false};
-                for (int b = 0; b < 4; ++b) {
-                    const int l = local_of(reg_gpos[b]);
-                    H.reg_local[b] = (uint32_t)l;
-                    H.reg_gpos[b] = (uint32_t)reg_gpos[b];
-                    used[l] = true;
-                }
-                int t = 0;
-                for (int l = 0; l < L; ++l)
-                    if (!used[l]) {
-                        H.thr_local[t] = (uint32_t)l;
-                        H.thr_gpos[t] = (uint32_t)tb[l];
-                        ++t;
-                    }
-                H.op_begin = (uint32_t)out.ops.size();
-                for (const Block &bk : blocks) {
-                    KOp ko{};
-                    if (bk.rt) {
-                        const LOp &op = ops[bk.op_index];
-                        ko.kind = KOP_DIAG_RT;
-                        ko.nbits = (uint32_t)(2 * op.k);
-                        ko.regdep = 0;
-                        for (int j = 0; j < 2 * op.k; ++j) {
-                            const int g = (j < op.k) ? op.q[j] : op.q[j - op.k] + n;
-                            ko.gpos[j] = (uint32_t)g;
-                            for (int b = 0; b < 4; ++b)
-                                if (reg_gpos[b] == g) ko.regdep = 1;
-                        }
-                        ko.mat = (uint32_t)out.mats.size();
-                        out.mats.insert(out.mats.end(), op.D.begin(), op.D.end());
-                        out.fma_per_amp += 4.0;
-                    } else {
-                        Encoded enc = encode(bk.m);
-                        ko.kind = enc.kind;
-                        ko.opmask = (uint32_t)enc.mask;
-                        ko.mat = (uint32_t)out.mats.size();
-                        out.mats.insert(out.mats.end(), enc.data.begin(), enc.data.end());
-                        if (enc.kind == KOP_DIAG) {
-                            for (int e = 0; e < 16; ++e) {
-                                if (enc.data[e] != cd(1)) set_bits(ko.nz, e);
-                                if (enc.data[e].imag() != 0.0) set_bits(ko.cx, e);
-                            }
-                        } else {
-                            for (size_t e = 0; e < enc.data.size(); ++e) {
-                                if (!is_zero(enc.data[e])) set_bits(ko.nz, (int)e);
-                                if (enc.data[e].imag() != 0.0) set_bits(ko.cx, (int)e);
-                            }
-                        }
-                        out.fma_per_amp += enc.cost / 16.0;
-                    }
-                    out.ops.push_back(ko);
-                }
-                H.op_end = (uint32_t)out.ops.size();
-                out.phases.push_back(H);
-            };
-
-            // filler register bits: highest tile bits not otherwise used
-            auto fill_regs = [&](int *reg, const std::vector<int> &fixed_idx) {
-                std::vector<int> avoid;
-                for (int b : fixed_idx) avoid.push_back(reg[b]);
-                int li = L - 1;
-                for (int b = 0; b < 4; ++b) {
-                    if (std::find(fixed_idx.begin(), fixed_idx.end(), b) != fixed_idx.end()) continue;
-                    while (li >= 0 && std::find(avoid.begin(), avoid.end(), tb[li]) != avoid.end()) --li;
-                    reg[b] = tb[li];
-                    avoid.push_back(tb[li]);
-                    --li;
-                }
-            };
-
             if (wide >= 0) {
                 // diagonal ops taken before the wide op go into the row phase
                 const LOp &w = ops[wide];
@@ -451,7 +575,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                         reg[j] = w.q[j] + (half ? n : 0);
                         fixed.push_back(j);
                     }
-                    fill_regs(reg, fixed);
+                    fill_regs(reg, fixed, {});
                     std::vector<Block> blocks;
                     if (half == 0)
                         for (int idx : take)
@@ -486,7 +610,16 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 if (P >> q & 1) qs[nq++] = q;
             if (nq >= 1) { reg[0] = qs[0]; reg[2] = qs[0] + n; fixed.push_back(0); fixed.push_back(2); }
             if (nq == 2) { reg[1] = qs[1]; reg[3] = qs[1] + n; fixed.push_back(1); fixed.push_back(3); }
-            fill_regs(reg, fixed);
+            std::vector<int> rt_bits;           // bits read by this phase's runtime diagonals
+            for (int idx : take) {
+                const LOp &op = ops[idx];
+                if (op.diag && (qm[idx] & ~P) != 0)
+                    for (int j = 0; j < op.k; ++j) {
+                        rt_bits.push_back(op.q[j]);
+                        rt_bits.push_back(op.q[j] + n);
+                    }
+            }
+            fill_regs(reg, fixed, rt_bits);
 
             // blocks in order, fusing across commuting blocks where cheaper
             std::vector<Block> blocks;
@@ -526,7 +659,39 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             }
             emit_phase(reg, blocks, {});
         }
+        // The first phase's register mapping also serves the HBM loads and the
+        // last one's the stores.  If a register bit is one of the lowest
+        // (contiguous) vector bits, lanes would stride; an op-free phase on
+        // high tile bits is added instead (an LDS exchange is cheaper).
+        {
+            const int low = std::min(3, std::min(contig, n2));
+            auto strided = [&](const KPhase &H) {
+                for (int b = 0; b < 4; ++b)
+                    if ((int)H.reg_gpos[b] < low) return true;
+                return false;
+            };
+            const size_t first_ph = kp.phase_begin;
+            const bool pad_front = low > 0 && out.phases.size() > first_ph && strided(out.phases[first_ph]);
+            const bool pad_back = low > 0 && out.phases.size() > first_ph && strided(out.phases.back());
+            if (pad_front || pad_back) {
+                int reg[4];
+                fill_regs(reg, {}, {});
+                const std::vector<Block> none;
+                if (pad_back) emit_phase(reg, none, {});
+                if (pad_front) {
+                    const uint32_t ob = out.phases[first_ph].op_begin;
+                    emit_phase(reg, none, {});
+                    KPhase dummy = out.phases.back();
+                    dummy.op_begin = dummy.op_end = ob;
+                    out.phases.pop_back();
+                    out.phases.insert(out.phases.begin() + first_ph, dummy);
+                }
+            }
+        }
         kp.phase_end = (uint32_t)out.phases.size();
+        kp.rt_mat = (uint32_t)out.mats.size();
+        kp.rt_count = (uint32_t)rt_tables.size();
+        out.mats.insert(out.mats.end(), rt_tables.begin(), rt_tables.end());
         out.passes.push_back(kp);
     }
     return VQD_OK;

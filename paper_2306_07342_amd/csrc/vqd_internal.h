@@ -39,23 +39,37 @@ constexpr int kMaxTileBits = 12;
 constexpr int kRegBits = 4;
 constexpr int kSlots = 16;
 constexpr uint32_t kPhantomPos = 62;   // global position of a bit beyond 2n
+constexpr uint32_t kNotLocal = 0xffu;  // KOp::lpos of a group (non-tile) bit
 
 enum KOpKind : uint32_t {
-    KOP_MAT = 1,      // matrix on a subset of register bits (opmask)
-    KOP_DIAG = 2,     // element-wise factors indexed by the 4 register bits
-    KOP_DIAG_RT = 3,  // element-wise factors indexed by arbitrary global bits
+    KOP_MAT = 1,      // dense matrix on the register bits `opmask`, stored column-major
+    KOP_XOR = 2,      // flip-pattern matrix on `opmask`: y[i] = sum_x W[x][i] a[i ^ flip(x)],
+                      // flip(x) flipping the row and column bit of the same qubits
+    KOP_DIAG = 3,     // 16 element-wise factors indexed by the register slot
+    KOP_DIAG_RT = 4,  // element-wise factors from an LDS table indexed by global bits
+};
+
+// KOP_DIAG_RT index modes: which register slot bits feed the table index.
+enum RtMode : uint32_t {
+    RT_NONE = 0,      // index = gathered global bits (same factor for all 16 slots)
+    RT_PAIR_A = 1,    // index = b(slot 0) + 2 b(slot 2) + 4 * gathered bits
+    RT_PAIR_B = 2,    // index = b(slot 1) + 2 b(slot 3) + 4 * gathered bits
+    RT_GENERIC = 3,   // every index bit gathered from the slot's own global index
 };
 
 struct alignas(16) KOp {
     uint32_t kind;
-    uint32_t opmask;    // KOP_MAT: register bits the matrix acts on (ascending)
-    uint32_t mat;       // offset of the matrix / factor table in the pool (complex entries)
-    uint32_t nbits;     // KOP_DIAG_RT: number of index bits
-    uint32_t nz[8];     // entry (i*dim + j) is nonzero; KOP_DIAG: factor e != 1
-    uint32_t cx[8];     // entry has a nonzero imaginary part
-    uint32_t gpos[4];   // KOP_DIAG_RT: global bit position of index bit j
-    uint32_t regdep;    // KOP_DIAG_RT: some index bit is a register bit
-    uint32_t pad[3];
+    uint32_t opmask;    // KOP_MAT / KOP_XOR: register bits acted on (ascending)
+    uint32_t mat;       // offset of the coefficients in the pool (complex entries; real-only
+                        // coefficients are packed two per entry); KOP_DIAG_RT: offset inside
+                        // the pass's LDS-staged table block
+    uint32_t real;      // all coefficients are real
+    uint32_t mode;      // KOP_DIAG_RT: RtMode
+    uint32_t nbits;     // KOP_DIAG_RT: number of gathered index bits
+    uint32_t gpos[4];   // KOP_DIAG_RT: their global bit positions (gathered bit j -> index bit j)
+    uint32_t lpos[4];   // KOP_DIAG_RT: local tile bit of gathered bit j, or kNotLocal for a
+                        // group bit (uniform over the workgroup's tile)
+    uint32_t pad[2];
 };
 
 struct alignas(16) KPhase {
@@ -72,7 +86,8 @@ struct alignas(16) KPass {
     uint32_t phase_begin, phase_end;
     uint32_t phantom;         // some tile bit lies beyond 2n (tiny registers)
     uint32_t xcd_swizzle;     // remap workgroup ids so tiles sharing cache lines share an XCD
-    uint32_t pad[2];
+    uint32_t rt_mat;          // start (complex entries) of this pass's runtime-diagonal tables
+    uint32_t rt_count;        // their total size; staged in LDS after the tile
     uint64_t n_tiles;
     uint32_t group_gpos[32];
 };

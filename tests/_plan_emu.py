@@ -3,9 +3,9 @@ library planner (vqd_prog_export).  Test-only: it lets the planner and the
 descriptor encoding be checked against the oracle without a GPU.
 
 It reproduces what k_pass does with each descriptor field: the tile/thread/
-register-slot address split, matrix entries skipped when their nonzero bit is
-clear and imaginary parts dropped when their complex bit is clear, diagonal
-factors indexed by register slots or by global bits, phantom bits.  The LDS
+register-slot address split, dense (column-major) and flip-pattern matrices
+with real coefficients packed two per entry, diagonal factors indexed by
+register slots or by global bits in each index mode, phantom bits.  The LDS
 exchange between phases only moves values between threads of a tile, so it
 is emulated by scattering back to the state and gathering again.
 """
@@ -17,15 +17,17 @@ MAGIC = 0x56514450
 
 
 def _dtypes(sz_pass, sz_phase, sz_op):
-    dpass = np.dtype({"names": ["L", "ngb", "pb", "pe", "phantom", "xcd", "n_tiles", "group_gpos"],
-                      "formats": ["<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u8", ("<u4", 32)],
-                      "offsets": [0, 4, 8, 12, 16, 20, 32, 40], "itemsize": sz_pass})
+    dpass = np.dtype({"names": ["L", "ngb", "pb", "pe", "phantom", "xcd", "rt_mat", "rt_count",
+                                "n_tiles", "group_gpos"],
+                      "formats": ["<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u8",
+                                  ("<u4", 32)],
+                      "offsets": [0, 4, 8, 12, 16, 20, 24, 28, 32, 40], "itemsize": sz_pass})
     dphase = np.dtype({"names": ["ob", "oe", "reg_local", "reg_gpos", "thr_local", "thr_gpos"],
                        "formats": ["<u4", "<u4", ("<u4", 4), ("<u4", 4), ("<u4", 8), ("<u4", 8)],
                        "offsets": [0, 4, 8, 24, 40, 72], "itemsize": sz_phase})
-    dop = np.dtype({"names": ["kind", "opmask", "mat", "nbits", "nz", "cx", "gpos", "regdep"],
-                    "formats": ["<u4", "<u4", "<u4", "<u4", ("<u4", 8), ("<u4", 8), ("<u4", 4), "<u4"],
-                    "offsets": [0, 4, 8, 12, 16, 48, 80, 96], "itemsize": sz_op})
+    dop = np.dtype({"names": ["kind", "opmask", "mat", "real", "mode", "nbits", "gpos"],
+                    "formats": ["<u4", "<u4", "<u4", "<u4", "<u4", "<u4", ("<u4", 4)],
+                    "offsets": [0, 4, 8, 12, 16, 20, 24], "itemsize": sz_op})
     return dpass, dphase, dop
 
 
@@ -55,8 +57,19 @@ def _dep4(v, mask):
     return out
 
 
-def _bit(words, b):
-    return (int(words[b >> 5]) >> (b & 31)) & 1
+def _coefs(mats, off, count, real):
+    if real:
+        packed = mats[off:off + (count + 1) // 2]
+        return np.stack([packed.real, packed.imag], axis=1).reshape(-1)[:count].astype(complex)
+    return mats[off:off + count]
+
+
+def _flip(mask, x):
+    if mask == 5:
+        return 5 if x else 0
+    if mask == 10:
+        return 10 if x else 0
+    return (5 if x & 1 else 0) | (10 if x & 2 else 0)
 
 
 def run(plan, amps: np.ndarray) -> np.ndarray:
@@ -91,34 +104,47 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
             a = np.where(valid, amps[gi], 0)
             for oi in range(int(H["ob"]), int(H["oe"])):
                 op = plan["ops"][oi]
-                M = mats[int(op["mat"]):]
-                kind = int(op["kind"])
-                if kind == 1:
-                    mask = int(op["opmask"])
+                kind, mask, real = int(op["kind"]), int(op["opmask"]), bool(op["real"])
+                if kind in (1, 2):
                     nb = bin(mask).count("1")
                     dim = 1 << nb
                     rest = (~mask) & 15
                     y = np.zeros_like(a)
-                    for i in range(dim):
+                    if kind == 1:          # dense, column-major
+                        C = _coefs(mats, int(op["mat"]), dim * dim, real)
                         for j in range(dim):
-                            bit = i * dim + j
-                            if not _bit(op["nz"], bit):
-                                continue
-                            m = M[bit] if _bit(op["cx"], bit) else M[bit].real
-                            for g in range(16 >> nb):
-                                so = _dep4(i, mask) | _dep4(g, rest)
-                                si = _dep4(j, mask) | _dep4(g, rest)
-                                y[..., so] += m * a[..., si]
+                            for i in range(dim):
+                                for g in range(16 >> nb):
+                                    so = _dep4(i, mask) | _dep4(g, rest)
+                                    si = _dep4(j, mask) | _dep4(g, rest)
+                                    y[..., so] += C[j * dim + i] * a[..., si]
+                    else:                  # flip pattern
+                        nx = 4 if mask == 15 else 2
+                        W = _coefs(mats, int(op["mat"]), nx * dim, real)
+                        for x in range(nx):
+                            for i in range(dim):
+                                for g in range(16 >> nb):
+                                    so = _dep4(i, mask) | _dep4(g, rest)
+                                    y[..., so] += W[x * dim + i] * a[..., so ^ _flip(mask, x)]
                     a = y
-                elif kind == 2:
-                    for e in range(16):
-                        if _bit(op["nz"], e):
-                            a[..., e] *= M[e] if _bit(op["cx"], e) else M[e].real
                 elif kind == 3:
-                    idx = np.zeros(gidx.shape, dtype=np.int64)
+                    F = _coefs(mats, int(op["mat"]), 16, real)
+                    a = a * F[None, None, :]
+                elif kind == 4:
+                    T = mats[int(P["rt_mat"]) + int(op["mat"]):]
+                    rt = np.zeros(gidx.shape, dtype=np.int64)
+                    mode = int(op["mode"])
+                    src = gidx if mode == 3 else np.broadcast_to(base[:, :, None], gidx.shape)
                     for j in range(int(op["nbits"])):
-                        idx |= ((gidx >> np.uint64(op["gpos"][j])) & np.uint64(1)).astype(np.int64) << j
-                    a = a * M[idx]
+                        rt |= ((src >> np.uint64(op["gpos"][j])) & np.uint64(1)).astype(np.int64) << j
+                    if mode in (1, 2):
+                        r0 = 0 if mode == 1 else 1
+                        e = np.arange(16)
+                        c = ((e >> r0) & 1) | (((e >> (r0 + 2)) & 1) << 1)
+                        idx = c[None, None, :] + 4 * rt
+                    else:
+                        idx = rt
+                    a = a * T[idx]
                 else:
                     raise AssertionError("unknown kernel op kind %d" % kind)
             amps[gi[valid]] = a[valid]
