@@ -29,7 +29,34 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 N_QUBITS = 14
 # planner options of the timed configuration (the GPU parity tests use the same)
-PLAN_OPTS = dict(tile_bits=12, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True)
+PLAN_OPTS = dict(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True, pad_coalesce=True)
+# HBM traffic of the pass kernel measured with rocprofv3 counters (FETCH_SIZE,
+# WRITE_SIZE) on this workload; valid only for the kernel source it was taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_grid14_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_07342_amd", "csrc", f)
+                  for f in ("kernels.hip", "planner.cpp")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per pass-kernel launch from the committed counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
 
 
 def log(*a):
@@ -66,6 +93,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-every", type=int, default=782)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device-to-device copy of the state buffer "
+                         "(known size) for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -112,16 +142,23 @@ def main():
     wall = time.perf_counter() - t0
     pass_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
     tr = dm.trace()
+    if args.calibrate_copy:
+        y = torch.empty_like(dm.buffer)
+        y.copy_(dm.buffer)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (dm.buffer.numel() * 8, y.numel() * 8))
+        del y
 
     amps = 4 ** n
     bytes_per_pass = 32.0 * amps                 # read + write of every amplitude
     avg_launch_s = pass_ms / 1e3 / info["n_passes"]
     achieved_gbs = bytes_per_pass / avg_launch_s / 1e9
     fp64_tflops = 2.0 * info["fma_per_amp"] * amps / (pass_ms / 1e3) / 1e12
+    traffic = measured_traffic()
     hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     alu = {"bound": "alu", "achieved": round(fp64_tflops, 2), "peak": FP64_PEAK_TFLOPS,
-           "unit": "TFLOP/s", "frac": round(fp64_tflops / FP64_PEAK_TFLOPS, 4), "traffic": None}
+           "unit": "TFLOP/s", "frac": round(fp64_tflops / FP64_PEAK_TFLOPS, 4), "traffic": traffic}
     roof = hbm if hbm["frac"] >= alu["frac"] else alu
 
     ms_per_step = wall / args.steps * 1e3

@@ -173,7 +173,7 @@ int vqd_kraus_to_superop(int k, int nk, const double *kraus, double *out);
 
 /* An op program: an ordered list of ops on an n-qubit register that the
  * library plans into fused passes.  A pass streams the state through HBM
- * once: a tile of 2^L amplitudes (L <= 12) is staged in registers and LDS and
+ * once: a tile of 2^L amplitudes (L <= 13) is staged in registers and LDS and
  * every op of the pass is applied in-tile before the tile is written back.
  * The planner groups ops whose qubits fit one tile, fuses consecutive ops on
  * the same qubits into one block where that costs fewer flops, and applies
@@ -186,13 +186,18 @@ int vqd_prog_add_superop(vqd_prog *p, int k, const int *targets, const double *s
 int vqd_prog_add_kraus(vqd_prog *p, int k, const int *targets, int nk, const double *kraus);
 
 /* Planner options.  max_ops_per_pass = 1 disables fusion (one op per pass);
- * tile_bits in [4, 12]; min_contig_bits: low vector bits every tile keeps for
- * coalesced access (0..tile_bits). */
+ * tile_bits in [4, 13] (a tile of 2^tile_bits amplitudes is one workgroup of
+ * 2^(tile_bits-4) threads, staged through 16 * 2^tile_bits bytes of LDS);
+ * min_contig_bits: low vector bits every tile keeps for coalesced access
+ * (0..tile_bits). */
 typedef struct vqd_plan_opts {
-    int tile_bits;          /* default 12 */
+    int tile_bits;          /* default 13 */
     int min_contig_bits;    /* default 3  */
     int max_ops_per_pass;   /* default 0 = unlimited */
     int fuse_blocks;        /* default 1: multiply runs of ops into one block when cheaper */
+    int pad_coalesce;       /* default 1: in passes with little FP64 work, add an op-free
+                               first/last phase when the first/last register bits would
+                               make HBM access strided */
 } vqd_plan_opts;
 void vqd_plan_opts_default(vqd_plan_opts *o);
 

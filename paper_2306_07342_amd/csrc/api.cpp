@@ -313,10 +313,11 @@ int vqd_kraus_to_superop(int k, int nk, const double *kraus, double *out)
 void vqd_plan_opts_default(vqd_plan_opts *o)
 {
     if (!o) return;
-    o->tile_bits = 12;
+    o->tile_bits = 13;
     o->min_contig_bits = 3;
     o->max_ops_per_pass = 0;
     o->fuse_blocks = 1;
+    o->pad_coalesce = 1;
 }
 
 int vqd_prog_create(int n, vqd_prog **out)
@@ -415,6 +416,7 @@ int vqd_prog_plan(vqd_prog *p, const vqd_plan_opts *opts)
     po.min_contig_bits = o.min_contig_bits;
     po.max_ops_per_pass = o.max_ops_per_pass;
     po.fuse_blocks = o.fuse_blocks != 0;
+    po.pad_coalesce = o.pad_coalesce != 0;
     p->compiled = false;
     p->tile_bits = o.tile_bits;
     return plan_program(p->n, p->ops, po, p->plan);

@@ -320,7 +320,7 @@ __device__ __forceinline__ void apply_ops(double2 (&a)[16], const KPhase *__rest
 // parts that depend only on the thread are computed once; the tile and
 // register-slot parts are workgroup-uniform (scalar unit).
 template <bool PHANTOM>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(1 << (kMaxTileBits - 4))
 k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
        const KPhase *__restrict__ phases, const KOp *__restrict__ ops,
        const double2 *__restrict__ mats, uint32_t pass_idx)

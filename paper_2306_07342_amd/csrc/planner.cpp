@@ -310,7 +310,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
     out = HostPlan{};
     const int n2 = 2 * n;
     if (opt.tile_bits < 4 || opt.tile_bits > kMaxTileBits)
-        return fail(VQD_E_ARG, "tile_bits must be in [4, 12]");
+        return fail(VQD_E_ARG, "tile_bits must be in [4, 13]");
     // tile size actually used: 2n bits at most, but never fewer than the 4
     // register bits (tiny registers get phantom bits)
     const int L = std::max(4, std::min(opt.tile_bits, n2));
@@ -392,6 +392,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             if (std::find(tb.begin(), tb.end(), b) == tb.end()) low_in_tile = false;
         kp.xcd_swizzle = (!low_in_tile && kp.n_tiles >= 64 && kp.n_tiles % 64 == 0) ? 1u : 0u;
         kp.phase_begin = (uint32_t)out.phases.size();
+        const double fma_before = out.fma_per_amp;
         std::vector<cd> rt_tables;      // runtime-diagonal tables of this pass (LDS-staged)
         auto local_of = [&](int g) {
             for (int i = 0; i < (int)tb.size(); ++i)
@@ -671,8 +672,11 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 return false;
             };
             const size_t first_ph = kp.phase_begin;
-            const bool pad_front = low > 0 && out.phases.size() > first_ph && strided(out.phases[first_ph]);
-            const bool pad_back = low > 0 && out.phases.size() > first_ph && strided(out.phases.back());
+            // only for light passes: in a pass dominated by FP64 work the
+            // strided access is hidden and the extra exchange is not
+            const bool light = (out.fma_per_amp - fma_before) < 32.0;
+            const bool pad_front = opt.pad_coalesce && light && low > 0 && out.phases.size() > first_ph && strided(out.phases[first_ph]);
+            const bool pad_back = opt.pad_coalesce && light && low > 0 && out.phases.size() > first_ph && strided(out.phases.back());
             if (pad_front || pad_back) {
                 int reg[4];
                 fill_regs(reg, {}, {});

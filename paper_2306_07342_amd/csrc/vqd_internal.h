@@ -35,7 +35,8 @@ int hip_fail(hipError_t e, const char *what);
 // indices differ in 4 "register" bits; the other L-4 local bits come from
 // the thread id.  Between phases the tile is exchanged through LDS.
 
-constexpr int kMaxTileBits = 12;
+constexpr int kMaxTileBits = 13;
+constexpr int kMaxThreadBits = kMaxTileBits - 4;
 constexpr int kRegBits = 4;
 constexpr int kSlots = 16;
 constexpr uint32_t kPhantomPos = 62;   // global position of a bit beyond 2n
@@ -76,8 +77,8 @@ struct alignas(16) KPhase {
     uint32_t op_begin, op_end;
     uint32_t reg_local[4];
     uint32_t reg_gpos[4];
-    uint32_t thr_local[8];
-    uint32_t thr_gpos[8];
+    uint32_t thr_local[kMaxThreadBits];
+    uint32_t thr_gpos[kMaxThreadBits];
 };
 
 struct alignas(16) KPass {
@@ -128,10 +129,11 @@ LOp make_unitary_op(int k, const int *targets, const cd *U);
 
 // Planner entry point.  Returns VQD_OK or an error code (message set).
 struct PlanOpts {
-    int tile_bits = 12;
+    int tile_bits = 13;
     int min_contig_bits = 3;
     int max_ops_per_pass = 0;
     bool fuse_blocks = true;
+    bool pad_coalesce = true;
 };
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out);
 
@@ -189,5 +191,5 @@ struct vqd_prog {
     bool compiled = false;
     int device = -1;
     int n_kernel_ops = 0;
-    int tile_bits = 12;
+    int tile_bits = 13;
 };

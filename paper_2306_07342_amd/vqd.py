@@ -39,7 +39,8 @@ class VQDError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("tile_bits", ctypes.c_int), ("min_contig_bits", ctypes.c_int),
-                ("max_ops_per_pass", ctypes.c_int), ("fuse_blocks", ctypes.c_int)]
+                ("max_ops_per_pass", ctypes.c_int), ("fuse_blocks", ctypes.c_int),
+                ("pad_coalesce", ctypes.c_int)]
 
 
 class ProgInfo(ctypes.Structure):
@@ -277,8 +278,10 @@ class DensityMatrix:
         return complex(re.value, im.value)
 
 
-def plan_opts(tile_bits=12, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True) -> PlanOpts:
-    return PlanOpts(tile_bits, min_contig_bits, max_ops_per_pass, 1 if fuse_blocks else 0)
+def plan_opts(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True,
+              pad_coalesce=True) -> PlanOpts:
+    return PlanOpts(tile_bits, min_contig_bits, max_ops_per_pass, 1 if fuse_blocks else 0,
+                    1 if pad_coalesce else 0)
 
 
 class Program:

@@ -23,8 +23,8 @@ def _dtypes(sz_pass, sz_phase, sz_op):
                                   ("<u4", 32)],
                       "offsets": [0, 4, 8, 12, 16, 20, 24, 28, 32, 40], "itemsize": sz_pass})
     dphase = np.dtype({"names": ["ob", "oe", "reg_local", "reg_gpos", "thr_local", "thr_gpos"],
-                       "formats": ["<u4", "<u4", ("<u4", 4), ("<u4", 4), ("<u4", 8), ("<u4", 8)],
-                       "offsets": [0, 4, 8, 24, 40, 72], "itemsize": sz_phase})
+                       "formats": ["<u4", "<u4", ("<u4", 4), ("<u4", 4), ("<u4", 9), ("<u4", 9)],
+                       "offsets": [0, 4, 8, 24, 40, 76], "itemsize": sz_phase})
     dop = np.dtype({"names": ["kind", "opmask", "mat", "real", "mode", "nbits", "gpos"],
                     "formats": ["<u4", "<u4", "<u4", "<u4", "<u4", "<u4", ("<u4", 4)],
                     "offsets": [0, 4, 8, 12, 16, 20, 24], "itemsize": sz_op})

@@ -49,7 +49,7 @@ def test_c1_circuit_default_plan(vqd_host, n):
 
 
 @pytest.mark.parametrize("tile_bits,contig,max_ops,fuse", [
-    (12, 3, 0, True), (12, 3, 0, False), (8, 3, 0, True), (6, 0, 0, True),
+    (13, 3, 0, True), (12, 3, 0, False), (8, 3, 0, True), (6, 0, 0, True),
     (4, 0, 0, True), (12, 3, 1, True), (10, 2, 3, True), (7, 7, 0, True)])
 @pytest.mark.parametrize("n", [1, 2, 3, 5])
 def test_random_matrices_all_plans(vqd_host, n, tile_bits, contig, max_ops, fuse):
