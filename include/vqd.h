@@ -181,6 +181,9 @@ int vqd_kraus_to_superop(int k, int nk, const double *kraus, double *out);
 int vqd_prog_create(int n, vqd_prog **out);
 int vqd_prog_destroy(vqd_prog *p);
 int vqd_prog_add_named(vqd_prog *p, int kind, const int *targets, const double *params);
+/* count named ops at once: kinds[i], targets[4*i .. 4*i+arity), params[4*i ..]. */
+int vqd_prog_add_named_many(vqd_prog *p, int count, const int *kinds, const int *targets,
+                            const double *params);
 int vqd_prog_add_unitary(vqd_prog *p, int k, const int *targets, const double *u);
 int vqd_prog_add_superop(vqd_prog *p, int k, const int *targets, const double *s);
 int vqd_prog_add_kraus(vqd_prog *p, int k, const int *targets, int nk, const double *kraus);
@@ -229,6 +232,66 @@ typedef struct vqd_prog_info {
     double fma_per_amp;     /* planned FP64 FMAs per amplitude, all passes */
 } vqd_prog_info;
 int vqd_prog_info_get(const vqd_prog *p, vqd_prog_info *out);
+
+/* ----------------------------------------------------------------- batched */
+
+/* A batch of independent density matrices of uneven size (n in [2, 16]),
+ * each with its own op program, run by ONE persistent kernel launch.  Each
+ * workgroup takes the next instance from a largest-first queue, sets it to
+ * |0..0><0..0|, applies all of its planned passes tile by tile (tiles of at
+ * most 2^12 amplitudes), and writes <Z_i>, i < n, of the final state.  This is
+ * the many-small-density-matrix use of the emulator: the same circuit family
+ * evaluated under many device variants (Sec. 4: repeated runs across
+ * parameter choices; Sec. 8: parameter sweeps).
+ *
+ * Memory: the caller owns the arena (device memory holding every final
+ * state; instance i's 4^n complex128 amplitudes start at the byte offset
+ * vqd_batch_offsets() reports, 256-byte aligned) and the output buffer
+ * (device doubles, n per instance).  The library owns the plan image, the
+ * queue and its counter.  Calls that run must not overlap on one batch. */
+typedef struct vqd_batch vqd_batch;
+
+typedef struct vqd_batch_info {
+    int n_instances;
+    long long total_passes;   /* passes over all instances      */
+    size_t arena_bytes;       /* arena size vqd_batch_run needs  */
+    size_t n_outputs;         /* sum of the instances' n         */
+    unsigned grid_items;      /* queue length                    */
+} vqd_batch_info;
+
+int vqd_batch_create(vqd_batch **out);
+int vqd_batch_destroy(vqd_batch *b);
+
+/* Append a copy of program p's ops as a new instance (its index in *index). */
+int vqd_batch_add(vqd_batch *b, const vqd_prog *p, int *index);
+
+/* Plan options for every instance with n qubits (tile_bits in [4, 12]). */
+int vqd_batch_set_opts(vqd_batch *b, int n, const vqd_plan_opts *opts);
+int vqd_batch_plan_opts(const vqd_batch *b, int n, vqd_plan_opts *opts);
+
+/* Plan all instances (host threads), lay out arena and outputs, upload the
+ * plan image to the current device.  Reports the sizes the run needs. */
+int vqd_batch_compile(vqd_batch *b, size_t *arena_bytes, size_t *n_outputs);
+
+/* Where instance `index` lives in the arena and in the outputs. */
+int vqd_batch_offsets(const vqd_batch *b, int index, size_t *arena_offset_bytes, size_t *out_offset);
+
+/* Enqueue the batched run on hip_stream.  use_graph != 0 captures the launch
+ * (queue reset kernel + persistent kernel) into a HIP graph on first use and
+ * replays it (on a library stream ordered after and before hip_stream by
+ * events) while arena and out stay the same. */
+int vqd_batch_run(vqd_batch *b, void *arena, size_t arena_bytes, double *out, void *hip_stream,
+                  int use_graph);
+
+/* Autotuner: for every qubit count in the batch, time candidate tile shapes
+ * (tile bits, contiguous low bits) on up to max_per_n instances of that
+ * count using the caller's arena and outputs, keep the fastest, and record
+ * it in the JSON file cache_path (read first; entries found there are used
+ * without timing).  Synchronous.  The batch must be compiled again after. */
+int vqd_batch_autotune(vqd_batch *b, void *arena, size_t arena_bytes, double *out, void *hip_stream,
+                       const char *cache_path, int max_per_n);
+
+int vqd_batch_info_get(const vqd_batch *b, vqd_batch_info *out);
 
 /* ---------------------------------------------------------------- read-out */
 

@@ -364,6 +364,23 @@ int vqd_prog_add_named(vqd_prog *p, int kind, const int *targets, const double *
     return prog_push(p, make_superop_op(k, targets, S.data()));
 }
 
+int vqd_prog_add_named_many(vqd_prog *p, int count, const int *kinds, const int *targets,
+                            const double *params)
+{
+    clear_error();
+    if (!p) return fail(VQD_E_ARG, "null program");
+    if (count < 0 || (count > 0 && (!kinds || !targets || !params))) return fail(VQD_E_ARG, "bad arrays");
+    const size_t before = p->ops.size();
+    for (int i = 0; i < count; ++i) {
+        const int rc = vqd_prog_add_named(p, kinds[i], targets + 4 * (size_t)i, params + 4 * (size_t)i);
+        if (rc) {
+            p->ops.resize(before);      // all or nothing
+            return fail(rc, "op " + std::to_string(i) + ": " + vqd_last_error());
+        }
+    }
+    return VQD_OK;
+}
+
 int vqd_prog_add_unitary(vqd_prog *p, int k, const int *targets, const double *u)
 {
     clear_error();

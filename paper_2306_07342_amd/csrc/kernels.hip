@@ -578,6 +578,147 @@ k_pauli(const double2 *__restrict__ amps, int n, uint64_t xmask, uint64_t zmask,
     }
 }
 
+// ------------------------------------------------------------- batched --
+// One tile of a pass for the batched kernel: load, register phases with LDS
+// exchanges, store.  Threads at or above 2^(L-4) hold no amplitudes but take
+// part in every barrier.
+__device__ __forceinline__ void batch_tile(double2 *__restrict__ amps, const KPass *__restrict__ P,
+                                           const KPhase *__restrict__ phases,
+                                           const KOp *__restrict__ ops,
+                                           const double2 *__restrict__ mats, double2 *lds,
+                                           const double2 *lds_rt, uint64_t t, uint32_t tid,
+                                           uint32_t nthr, bool active)
+{
+    const uint32_t pb = uni(P->phase_begin), pe = uni(P->phase_end);
+    const uint64_t gb = group_base(P, t, uni(P->n_group_bits), false);
+    double2 a[16];
+    for (uint32_t ph = pb; ph < pe; ++ph) {
+        const KPhase *H = phases + ph;
+        Ctx c;
+        c.gb = gb;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c.rl[b] = 1u << uni(H->reg_local[b]);
+        uint64_t tg = 0;
+        thread_bits(H, active ? tid : 0u, nthr, c.tl, tg);
+        const uint32_t lds_thr = swz(c.tl) << 4;
+        if (ph == pb) {
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) a[e] = amps[gb | tg | slot_g(H, e)];
+            }
+        } else {
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    a[e] = *reinterpret_cast<const double2 *>(
+                        reinterpret_cast<const char *>(lds) + (lds_thr ^ (swz(slot_l(c.rl, e)) << 4)));
+            }
+            __syncthreads();
+        }
+        if (active) apply_ops(a, H, ops, mats, lds_rt, c);
+        if (ph + 1 < pe) {
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
+                                                 (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
+            }
+            __syncthreads();
+        } else if (active) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) amps[gb | tg | slot_g(H, e)] = a[e];
+        }
+    }
+}
+
+// Global stores of this workgroup become visible to its own later loads
+// (the vector L1 is not coherent with writes of other waves).
+__device__ __forceinline__ void wg_global_sync()
+{
+    __threadfence();
+    __syncthreads();
+    __threadfence();
+}
+
+constexpr int kBatchThreads = 256;
+constexpr int kBatchTileBits = 12;
+
+// Persistent batched run: each workgroup takes the next instance from a
+// largest-first queue, sets it to |0..0><0..0|, applies all of its passes
+// (every tile of a pass by this workgroup, then a workgroup-wide sync), and
+// writes <Z_i>, i < n, of the final state to its output slots.
+__global__ void __launch_bounds__(kBatchThreads)
+k_batch(double2 *__restrict__ arena, const BatchItem *__restrict__ items, uint32_t n_items,
+        uint32_t *__restrict__ counter, const KPass *__restrict__ passes,
+        const KPhase *__restrict__ phases, const KOp *__restrict__ ops,
+        const double2 *__restrict__ mats, double *__restrict__ out)
+{
+    extern __shared__ double2 lds[];
+    __shared__ uint32_t s_item;
+    __shared__ double s_red[VQD_MAX_QUBITS * 4];
+    double2 *lds_rt = lds + (1u << kBatchTileBits);
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const BatchItem *B = items + it;
+        const uint32_t n = uni(B->n);
+        double2 *amps = arena + B->arena_off;
+        const uint64_t count = 1ull << (2 * n);
+        for (uint64_t i = tid; i < count; i += blockDim.x) amps[i] = make_double2(i == 0 ? 1.0 : 0.0, 0.0);
+        wg_global_sync();
+        const uint32_t qb = uni(B->pass_begin), qe = uni(B->pass_end);
+        for (uint32_t p = qb; p < qe; ++p) {
+            const KPass *P = passes + p;
+            const uint32_t L = uni(P->L), nthr = L - 4;
+            const bool active = tid < (1u << nthr);
+            const uint32_t rt_count = uni(P->rt_count);
+            if (rt_count) {
+                const double2 *src = mats + uni(P->rt_mat);
+                for (uint32_t i = tid; i < rt_count; i += blockDim.x) lds_rt[i] = src[i];
+                __syncthreads();
+            }
+            const uint64_t n_tiles = P->n_tiles;
+            for (uint64_t t = 0; t < n_tiles; ++t)
+                batch_tile(amps, P, phases, ops, mats, lds, lds_rt, t, tid, nthr, active);
+            wg_global_sync();
+        }
+        // <Z_q> = sum_r (-1)^{r_q} Re rho[r][r]
+        double z[VQD_MAX_QUBITS];
+#pragma unroll
+        for (int q = 0; q < VQD_MAX_QUBITS; ++q) z[q] = 0.0;
+        const uint64_t D = 1ull << n;
+        for (uint64_t r = tid; r < D; r += blockDim.x) {
+            const double pr = amps[r * (D + 1)].x;
+#pragma unroll
+            for (int q = 0; q < VQD_MAX_QUBITS; ++q)
+                if ((uint32_t)q < n) z[q] += ((r >> q) & 1u) ? -pr : pr;
+        }
+        const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+        for (int q = 0; q < VQD_MAX_QUBITS; ++q) {
+            double v = z[q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) s_red[q * 4 + wv] = v;
+        }
+        __syncthreads();
+        if (tid < n) {
+            const double v = (s_red[tid * 4] + s_red[tid * 4 + 1]) + (s_red[tid * 4 + 2] + s_red[tid * 4 + 3]);
+            out[B->out_off + tid] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset(uint32_t *counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launches --
@@ -753,6 +894,33 @@ int reduce_pauli(const double2 *amps, int n, uint64_t xmask, uint64_t zmask, int
     }
     *re = a;
     *im = b;
+    return VQD_OK;
+}
+
+int launch_batch(double2 *arena, const BatchDev &bd, double *out, hipStream_t stream)
+{
+    static bool attr = false;
+    if (!attr) {
+        // dynamic LDS plus the kernel's static queue and reduction slots
+        VQD_HIP(hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    159 * 1024));
+        attr = true;
+    }
+    const size_t lds = (size_t(16) << kBatchTileBits) + size_t(16) * bd.max_rt;
+    if (lds + 1024 > 160 * 1024) return fail(VQD_E_SIZE, "batched pass needs more LDS than a workgroup has");
+    int per_cu = 0, n_cu = 0, dev_id = 0;
+    VQD_HIP(hipGetDevice(&dev_id));
+    VQD_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id));
+    VQD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch, kBatchThreads, lds));
+    if (per_cu < 1) per_cu = 1;
+    uint32_t grid = (uint32_t)per_cu * (uint32_t)n_cu;
+    if (grid > bd.n_items) grid = bd.n_items;
+    if (grid == 0) return VQD_OK;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, bd.counter);
+    VQD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchThreads), lds, stream, arena, bd.items, bd.n_items,
+                       bd.counter, bd.prog.passes, bd.prog.phases, bd.prog.ops, bd.prog.mats, out);
+    VQD_HIP(hipGetLastError());
     return VQD_OK;
 }
 

@@ -141,10 +141,30 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
 int upload_plan(const HostPlan &plan, DevProgram &dev, hipStream_t stream);
 void free_dev_program(DevProgram &dev);
 
+// ------------------------------------------------------------- batched --
+// One density matrix of a batch (queue order).
+struct alignas(16) BatchItem {
+    uint64_t arena_off;       // first amplitude of the instance in the arena
+    uint32_t n;
+    uint32_t pass_begin, pass_end;
+    uint32_t out_off;         // first of its n <Z_i> outputs
+    uint32_t pad[2];
+};
+
+struct BatchDev {
+    DevProgram prog;          // all instances' passes, phases, ops, coefficients
+    BatchItem *items = nullptr;
+    uint32_t *counter = nullptr;
+    void *buf = nullptr;      // allocation holding items and counter
+    uint32_t n_items = 0;
+    uint32_t max_rt = 0;      // largest runtime-diagonal table block of any pass
+};
+
 // ------------------------------------------------------------- launches --
 int launch_pass(double2 *amps, const DevProgram &dev, const KPass &pass, uint32_t pass_idx,
                 hipStream_t stream);
 int launch_init(double2 *amps, int n, int mode, uint64_t b, const double *p0, hipStream_t stream);
+int launch_batch(double2 *arena, const BatchDev &bd, double *out, hipStream_t stream);
 
 struct ReduceScratch {
     double *dev = nullptr;      // partials + results

@@ -43,6 +43,12 @@ class PlanOpts(ctypes.Structure):
                 ("pad_coalesce", ctypes.c_int)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_int), ("total_passes", ctypes.c_longlong),
+                ("arena_bytes", ctypes.c_size_t), ("n_outputs", ctypes.c_size_t),
+                ("grid_items", ctypes.c_uint)]
+
+
 class ProgInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("n_ops", ctypes.c_int), ("n_passes", ctypes.c_int),
                 ("n_phases", ctypes.c_int), ("n_kernel_ops", ctypes.c_int),
@@ -83,6 +89,7 @@ def load(path: str = LIB_PATH):
         "vqd_prog_destroy": ([vp], ctypes.c_int),
         "vqd_prog_add_named": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
         "vqd_prog_add_unitary": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+        "vqd_prog_add_named_many": ([vp, ctypes.c_int, _ip, _ip, _dp], ctypes.c_int),
         "vqd_prog_add_superop": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
         "vqd_prog_add_kraus": ([vp, ctypes.c_int, _ip, ctypes.c_int, _dp], ctypes.c_int),
         "vqd_plan_opts_default": ([ctypes.POINTER(PlanOpts)], None),
@@ -91,6 +98,16 @@ def load(path: str = LIB_PATH):
         "vqd_prog_export": ([vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "vqd_prog_run": ([vp, vp], ctypes.c_int),
         "vqd_prog_info_get": ([vp, ctypes.POINTER(ProgInfo)], ctypes.c_int),
+        "vqd_batch_create": ([ctypes.POINTER(vp)], ctypes.c_int),
+        "vqd_batch_destroy": ([vp], ctypes.c_int),
+        "vqd_batch_add": ([vp, vp, _ip], ctypes.c_int),
+        "vqd_batch_set_opts": ([vp, ctypes.c_int, ctypes.POINTER(PlanOpts)], ctypes.c_int),
+        "vqd_batch_plan_opts": ([vp, ctypes.c_int, ctypes.POINTER(PlanOpts)], ctypes.c_int),
+        "vqd_batch_compile": ([vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "vqd_batch_offsets": ([vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "vqd_batch_run": ([vp, vp, ctypes.c_size_t, _dp, vp, ctypes.c_int], ctypes.c_int),
+        "vqd_batch_autotune": ([vp, vp, ctypes.c_size_t, _dp, vp, ctypes.c_char_p, ctypes.c_int], ctypes.c_int),
+        "vqd_batch_info_get": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
         "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_calc_purity": ([vp, _dp], ctypes.c_int),
         "vqd_calc_probs": ([vp, _dp], ctypes.c_int),
@@ -322,8 +339,28 @@ class Program:
             check(lib().vqd_prog_add_named(self.handle, KINDS[kind], _i(t), _d(p)))
 
     def extend(self, ops: Iterable):
+        """Append ops; runs of named ops are passed in one call."""
+        run = []
+
+        def flush():
+            if not run:
+                return
+            k = np.fromiter((KINDS[o[0]] for o in run), dtype=np.int32, count=len(run))
+            t = np.zeros((len(run), 4), dtype=np.int32)
+            pr = np.zeros((len(run), 4), dtype=np.float64)
+            for i, (_, q, par) in enumerate(run):
+                t[i, :len(q)] = q
+                pr[i, :len(par)] = par
+            check(lib().vqd_prog_add_named_many(self.handle, len(run), _i(k), _i(t), _d(pr)))
+            run.clear()
+
         for op in ops:
-            self.add(op)
+            if op[0] in KINDS:
+                run.append(op)
+            else:
+                flush()
+                self.add(op)
+        flush()
 
     def compile(self, opts: Optional[PlanOpts] = None):
         check(lib().vqd_prog_compile(self.handle, ctypes.byref(opts) if opts is not None else None))
@@ -349,3 +386,101 @@ class Program:
         i = ProgInfo()
         check(lib().vqd_prog_info_get(self.handle, ctypes.byref(i)))
         return {f: getattr(i, f) for f, _ in ProgInfo._fields_}
+
+
+class Batch:
+    """Many independent density matrices run by one persistent launch.
+
+    Build with add(n, ops) per instance, then compile(); run() writes <Z_i> of
+    every instance into a device float64 tensor and keeps the final states in
+    a device arena (both torch-owned)."""
+
+    def __init__(self):
+        load()
+        h = ctypes.c_void_p()
+        check(lib().vqd_batch_create(ctypes.byref(h)))
+        self.handle = h
+        self.ns = []
+        self.arena = None
+        self.out = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().vqd_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, n: int, ops) -> int:
+        p = Program(n, ops)
+        idx = ctypes.c_int()
+        check(lib().vqd_batch_add(self.handle, p.handle, ctypes.byref(idx)))
+        p.close()
+        self.ns.append(n)
+        return idx.value
+
+    def set_opts(self, n: int, opts: PlanOpts):
+        check(lib().vqd_batch_set_opts(self.handle, n, ctypes.byref(opts)))
+
+    def plan_opts(self, n: int) -> dict:
+        o = PlanOpts()
+        check(lib().vqd_batch_plan_opts(self.handle, n, ctypes.byref(o)))
+        return {f: getattr(o, f) for f, _ in PlanOpts._fields_}
+
+    def compile(self, device="cuda"):
+        """Plan and upload; (re)allocate the arena and output tensors."""
+        import torch
+        ab, no = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().vqd_batch_compile(self.handle, ctypes.byref(ab), ctypes.byref(no)))
+        need_a = (ab.value + 7) // 8
+        if self.arena is None or self.arena.numel() < need_a:
+            self.arena = torch.empty(max(need_a, 1), dtype=torch.float64, device=device)
+        if self.out is None or self.out.numel() < no.value:
+            self.out = torch.empty(max(no.value, 1), dtype=torch.float64, device=device)
+        return self
+
+    def ensure_buffers(self, arena_bytes: int, n_outputs: int, device="cuda"):
+        import torch
+        need_a = (arena_bytes + 7) // 8
+        if self.arena is None or self.arena.numel() < need_a:
+            self.arena = torch.empty(max(need_a, 1), dtype=torch.float64, device=device)
+        if self.out is None or self.out.numel() < n_outputs:
+            self.out = torch.empty(max(n_outputs, 1), dtype=torch.float64, device=device)
+
+    def autotune(self, cache_path: str, max_per_n: int = 32, stream=None):
+        check(lib().vqd_batch_autotune(self.handle, ctypes.c_void_p(self.arena.data_ptr()),
+                                       self.arena.numel() * 8,
+                                       ctypes.cast(ctypes.c_void_p(self.out.data_ptr()), _dp),
+                                       _stream_ptr(stream), cache_path.encode(), max_per_n))
+
+    def run(self, use_graph: bool = False, stream=None):
+        check(lib().vqd_batch_run(self.handle, ctypes.c_void_p(self.arena.data_ptr()),
+                                  self.arena.numel() * 8,
+                                  ctypes.cast(ctypes.c_void_p(self.out.data_ptr()), _dp),
+                                  _stream_ptr(stream), 1 if use_graph else 0))
+
+    def offsets(self, index: int):
+        a, o = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().vqd_batch_offsets(self.handle, index, ctypes.byref(a), ctypes.byref(o)))
+        return a.value, o.value
+
+    def expec_z(self, index: int):
+        """<Z_i> of instance `index` (host copy)."""
+        _, o = self.offsets(index)
+        return self.out[o:o + self.ns[index]].cpu().numpy()
+
+    def state(self, index: int) -> np.ndarray:
+        """Final vectorised state of instance `index` (host copy)."""
+        a, _ = self.offsets(index)
+        n = self.ns[index]
+        v = self.arena[a // 8: a // 8 + 2 * 4 ** n].cpu().numpy()
+        return v.view(np.complex128)
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        check(lib().vqd_batch_info_get(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in BatchInfo._fields_}
