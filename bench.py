@@ -86,6 +86,79 @@ def cpu_baseline(ops, n, sample_every):
                       % (len(sample), sample_every, dt)}
 
 
+BATCH_TUNE_FILE = os.path.join(ROOT, "paper_2306_07342_amd", "tune", "batch_tiles.json")
+
+
+def batched_leg(vqd, torch, steps):
+    """4096 independent 3..10-qubit noisy line circuits (own noise parameters)
+    in one persistent, graph-captured launch, against looping the
+    single-density-matrix path over a random subset of 512 of them."""
+    import random
+    from workloads import c4_batch_instances
+    t0 = time.perf_counter()
+    insts = c4_batch_instances(4096)
+    n_ops = sum(len(x["ops"]) for x in insts)
+
+    def make(sel):
+        b = vqd.Batch()
+        for i in sel:
+            b.add(insts[i]["n"], insts[i]["ops"])
+        return b
+
+    b = make(range(len(insts)))
+    b.compile()
+    tuned = os.path.exists(BATCH_TUNE_FILE)
+    b.autotune(BATCH_TUNE_FILE if tuned else os.path.join("/tmp", "vqd_batch_tiles.json"), max_per_n=32)
+    b.compile()
+    log("batched: setup %.1f s, %s" % (time.perf_counter() - t0, b.info()))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    t_batch = timed(lambda: b.run(use_graph=True), max(1, steps))
+    # the same circuits, one single-state program each, looped
+    sel = random.Random(7).sample(range(len(insts)), 512)
+    progs = [(insts[i]["n"], vqd.Program(insts[i]["n"], insts[i]["ops"]).compile()) for i in sel]
+    dms = {}
+    for n, _ in progs:
+        if n not in dms:
+            dms[n] = vqd.DensityMatrix(n)
+
+    def loop():
+        for n, p in progs:
+            dm = dms[n]
+            dm.init_zero()
+            p.run(dm)
+            dm.expec_z()
+
+    t_loop = timed(loop, 1)
+    sub = make(sel)
+    sub.compile()
+    t_sub = timed(lambda: sub.run(use_graph=True), 2)
+    # the subset is a uniform random eighth of the batch: looping the single
+    # path over all 4096 circuits takes about 8x its time
+    loop_full = t_loop * len(insts) / len(sel)
+    return {"metric": "batched noisy circuits per second (4096 density matrices, 3-10 qubits)",
+            "circuits_per_s": round(len(insts) / t_batch, 1),
+            "dm_ops_per_s": round(n_ops / t_batch, 1),
+            "ms_per_batch": round(t_batch * 1e3, 3),
+            "dm_ops": n_ops,
+            "looped_single_ms_extrapolated_4096": round(loop_full * 1e3, 3),
+            "speedup_vs_looped_single": round(loop_full / t_batch, 2),
+            "subset512_batched_ms": round(t_sub * 1e3, 3),
+            "subset512_looped_single_ms": round(t_loop * 1e3, 3),
+            "tiles": "autotuned (%s)" % ("cached" if tuned else "fresh")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +166,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-every", type=int, default=782)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-emulation leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device-to-device copy of the state buffer "
                          "(known size) for scaling HBM counters")
@@ -189,6 +263,9 @@ def main():
         "roofline_other": alu if roof is hbm else hbm,
         "check": {"trace_re": tr.real, "purity": pur, "z0": float(z[0])},
     }
+    if not args.no_batched:
+        log("batched leg ...")
+        out["batched"] = batched_leg(vqd, torch, args.steps)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_sample_every)
