@@ -276,6 +276,38 @@ int vqd_batch_compile(vqd_batch *b, size_t *arena_bytes, size_t *n_outputs);
 /* Where instance `index` lives in the arena and in the outputs. */
 int vqd_batch_offsets(const vqd_batch *b, int index, size_t *arena_offset_bytes, size_t *out_offset);
 
+/* Parametric templates: many instances of one circuit structure that differ
+ * only in their parameters (rotation angles, noise rates), as in a sweep over
+ * ansatz angles and device noise (Sec. 2 and 3: one noisy ansatz evaluated for
+ * many parameter and noise settings).  The structure is planned once, with
+ * generic parameters; each instance gets only its own coefficient block.
+ *
+ * vqd_batch_add_template: `count` ops of named kinds (enum vqd_kind) on
+ * `targets` (4 ints per op, the first arity(kind) used) of an n-qubit state
+ * (2 <= n <= 16).  Writes its id to *template_id.  Nothing is planned yet.
+ *
+ * vqd_batch_add_instances: `count` instances of template `template_id`;
+ * params holds count x n_ops x 4 doubles (host, copied; per op the first
+ * arity(kind) parameters are used, the rest ignored).  Instance indices (for
+ * vqd_batch_offsets) count every vqd_batch_add and every template instance in
+ * the order added; the first of these `count` is written to *first_index.
+ * All or nothing: a non-finite parameter adds none.  Each instance starts
+ * from |0..0><0..0| and yields its <Z_i> like any other.
+ *
+ * vqd_batch_compile then checks every instance against the planned form:
+ * parameters under which a coefficient that the generic plan found zero (or
+ * real) is not, fail with VQD_E_ARG naming the instance. */
+int vqd_batch_add_template(vqd_batch *b, int n, int count, const int *kinds, const int *targets,
+                           int *template_id);
+int vqd_batch_add_instances(vqd_batch *b, int template_id, int count, const double *params, int *first_index);
+
+/* Plan a template on the host (as vqd_batch_compile does, without a GPU) and
+ * serialise it in the layout of vqd_prog_export, with the coefficients for
+ * `params` (n_ops x 4 doubles; NULL keeps the generic planning parameters).
+ * buf == NULL: only *needed is set. */
+int vqd_template_export(int n, int count, const int *kinds, const int *targets, const double *params,
+                        const vqd_plan_opts *opts, void *buf, size_t cap, size_t *needed);
+
 /* Enqueue the batched run on hip_stream.  use_graph != 0 captures the launch
  * (queue reset kernel + persistent kernel) into a HIP graph on first use and
  * replays it (on a library stream ordered after and before hip_stream by

@@ -77,6 +77,47 @@ int run_single(vqd_dm *dm, const LOp &op)
 }
 
 }  // namespace
+
+PlanOpts to_plan_opts(const vqd_plan_opts &o)
+{
+    PlanOpts po;
+    po.tile_bits = o.tile_bits;
+    po.min_contig_bits = o.min_contig_bits;
+    po.max_ops_per_pass = o.max_ops_per_pass;
+    po.fuse_blocks = o.fuse_blocks != 0;
+    po.pad_coalesce = o.pad_coalesce != 0;
+    return po;
+}
+
+int export_plan(const HostPlan &pl, int n, int tile_bits, void *buf, size_t cap, size_t *needed)
+{
+    const size_t hdr = 12 * sizeof(uint32_t);
+    const size_t total = hdr + pl.passes.size() * sizeof(KPass) + pl.phases.size() * sizeof(KPhase) +
+                         pl.ops.size() * sizeof(KOp) + pl.mats.size() * 2 * sizeof(double);
+    *needed = total;
+    if (!buf) return VQD_OK;
+    if (cap < total) return fail(VQD_E_SIZE, "export buffer too small");
+    uint32_t h[12] = {0x56514450u, 1u, (uint32_t)pl.passes.size(), (uint32_t)pl.phases.size(),
+                      (uint32_t)pl.ops.size(), (uint32_t)pl.mats.size(), (uint32_t)sizeof(KPass),
+                      (uint32_t)sizeof(KPhase), (uint32_t)sizeof(KOp), (uint32_t)n,
+                      (uint32_t)tile_bits, 0u};
+    char *o = static_cast<char *>(buf);
+    std::memcpy(o, h, hdr);
+    o += hdr;
+    std::memcpy(o, pl.passes.data(), pl.passes.size() * sizeof(KPass));
+    o += pl.passes.size() * sizeof(KPass);
+    std::memcpy(o, pl.phases.data(), pl.phases.size() * sizeof(KPhase));
+    o += pl.phases.size() * sizeof(KPhase);
+    std::memcpy(o, pl.ops.data(), pl.ops.size() * sizeof(KOp));
+    o += pl.ops.size() * sizeof(KOp);
+    for (const cd &z : pl.mats) {
+        const double v[2] = {z.real(), z.imag()};
+        std::memcpy(o, v, sizeof v);
+        o += sizeof v;
+    }
+    return VQD_OK;
+}
+
 }  // namespace vqd
 
 using namespace vqd;
@@ -421,6 +462,7 @@ int vqd_prog_add_kraus(vqd_prog *p, int k, const int *targets, int nk, const dou
     return prog_push(p, make_superop_op(k, targets, S.data()));
 }
 
+
 int vqd_prog_plan(vqd_prog *p, const vqd_plan_opts *opts)
 {
     clear_error();
@@ -428,48 +470,18 @@ int vqd_prog_plan(vqd_prog *p, const vqd_plan_opts *opts)
     vqd_plan_opts o;
     vqd_plan_opts_default(&o);
     if (opts) o = *opts;
-    PlanOpts po;
-    po.tile_bits = o.tile_bits;
-    po.min_contig_bits = o.min_contig_bits;
-    po.max_ops_per_pass = o.max_ops_per_pass;
-    po.fuse_blocks = o.fuse_blocks != 0;
-    po.pad_coalesce = o.pad_coalesce != 0;
     p->compiled = false;
     p->tile_bits = o.tile_bits;
-    return plan_program(p->n, p->ops, po, p->plan);
+    return plan_program(p->n, p->ops, to_plan_opts(o), p->plan);
 }
 
 int vqd_prog_export(const vqd_prog *p, void *buf, size_t cap, size_t *needed)
 {
     clear_error();
     if (!p || !needed) return fail(VQD_E_ARG, "null argument");
-    const HostPlan &pl = p->plan;
-    const size_t hdr = 12 * sizeof(uint32_t);
-    const size_t total = hdr + pl.passes.size() * sizeof(KPass) + pl.phases.size() * sizeof(KPhase) +
-                         pl.ops.size() * sizeof(KOp) + pl.mats.size() * 2 * sizeof(double);
-    *needed = total;
-    if (!buf) return VQD_OK;
-    if (cap < total) return fail(VQD_E_SIZE, "export buffer too small");
-    uint32_t h[12] = {0x56514450u, 1u, (uint32_t)pl.passes.size(), (uint32_t)pl.phases.size(),
-                      (uint32_t)pl.ops.size(), (uint32_t)pl.mats.size(), (uint32_t)sizeof(KPass),
-                      (uint32_t)sizeof(KPhase), (uint32_t)sizeof(KOp), (uint32_t)p->n,
-                      (uint32_t)p->tile_bits, 0u};
-    char *o = static_cast<char *>(buf);
-    std::memcpy(o, h, hdr);
-    o += hdr;
-    std::memcpy(o, pl.passes.data(), pl.passes.size() * sizeof(KPass));
-    o += pl.passes.size() * sizeof(KPass);
-    std::memcpy(o, pl.phases.data(), pl.phases.size() * sizeof(KPhase));
-    o += pl.phases.size() * sizeof(KPhase);
-    std::memcpy(o, pl.ops.data(), pl.ops.size() * sizeof(KOp));
-    o += pl.ops.size() * sizeof(KOp);
-    for (const cd &z : pl.mats) {
-        const double v[2] = {z.real(), z.imag()};
-        std::memcpy(o, v, sizeof v);
-        o += sizeof v;
-    }
-    return VQD_OK;
+    return export_plan(p->plan, p->n, p->tile_bits, buf, cap, needed);
 }
+
 
 int vqd_prog_compile(vqd_prog *p, const vqd_plan_opts *opts)
 {

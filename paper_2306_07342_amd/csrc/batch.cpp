@@ -31,6 +31,18 @@ struct vqd_batch {
         double cost = 0;
     };
     std::vector<Inst> inst;
+    // parametric templates: one planned structure, per-instance parameters
+    struct Template {
+        int n = 0;
+        std::vector<int> kinds, targets;              // 4 targets per op
+        vqd::HostPlan plan;
+        std::vector<std::vector<double>> params;      // per instance, 4 per op
+        std::vector<uint64_t> arena_off;
+        std::vector<uint32_t> out_off;
+    };
+    std::vector<Template> tmpl;
+    // instance index -> (template id or -1, index within inst or the template)
+    std::vector<std::pair<int, uint32_t>> refs;
     std::map<int, vqd::PlanOpts> opts_by_n;
     vqd::BatchDev dev;
     std::vector<vqd::BatchItem> items;
@@ -114,8 +126,11 @@ int plan_all(vqd_batch *b, const std::vector<int> &sel, const std::map<int, Plan
     return VQD_OK;
 }
 
-// Concatenate the plans of `sel`, lay out arena and outputs, upload.
-int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream)
+// Concatenate the plans of `sel` and of template instances (all templates if
+// tmpl_n < 0, else those on tmpl_n qubits, tmpl_n == 0: none; at most
+// tmpl_cap instances each), lay out arena and outputs, upload.
+int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream, int tmpl_n = -1,
+                 size_t tmpl_cap = SIZE_MAX)
 {
     HostPlan all;
     std::vector<BatchItem> items;
@@ -153,6 +168,7 @@ int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream)
         outs += (uint32_t)I.n;
         I.cost = (double)(I.plan.passes.size() + 1) * (double)(1ull << (2 * I.n));
         BatchItem it{};
+        it.mat_base = 0;
         it.arena_off = I.arena_off;
         it.n = (uint32_t)I.n;
         it.pass_begin = pass_base;
@@ -161,11 +177,82 @@ int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream)
         items.push_back(it);
         passes += I.plan.passes.size();
     }
+    std::vector<double> cost;
+    for (int i : sel) cost.push_back(b->inst[i].cost);
+    // parametric templates: the structure once, a coefficient block per instance
+    {
+        for (auto &T : b->tmpl) {
+            if (T.params.empty() || tmpl_n == 0 || (tmpl_n > 0 && T.n != tmpl_n)) continue;
+            const uint32_t pass_base = (uint32_t)all.passes.size();
+            const uint32_t phase_base = (uint32_t)all.phases.size();
+            const uint32_t op_base = (uint32_t)all.ops.size();
+            for (KPass P : T.plan.passes) {
+                if (P.L > (uint32_t)kBatchTile || P.phantom)
+                    return fail(VQD_E_SIZE, "batched instances need tiles of at most 12 bits and n >= 2");
+                P.phase_begin += phase_base;
+                P.phase_end += phase_base;
+                max_rt = std::max(max_rt, P.rt_count);
+                all.passes.push_back(P);
+            }
+            for (KPhase H : T.plan.phases) {
+                H.op_begin += op_base;
+                H.op_end += op_base;
+                all.phases.push_back(H);
+            }
+            for (const KOp &o : T.plan.ops) all.ops.push_back(o);
+            const size_t block = T.plan.mats.size();
+            const size_t mbase = all.mats.size();
+            const size_t count = std::min(T.params.size(), tmpl_cap);
+            all.mats.resize(mbase + block * count);
+            T.arena_off.resize(count);
+            T.out_off.resize(count);
+            // coefficients of every instance, in host threads
+            std::vector<int> rc(count, VQD_OK);
+            std::vector<std::string> msg(count);
+            std::atomic<size_t> next(0);
+            auto worker = [&]() {
+                std::vector<LOp> lops;
+                std::vector<cd> mats;
+                for (;;) {
+                    const size_t k = next.fetch_add(1);
+                    if (k >= count) break;
+                    const int r = template_mats(T.n, T.kinds, T.targets, T.plan, T.params[k].data(), lops, mats);
+                    if (r) {
+                        rc[k] = r;
+                        msg[k] = vqd_last_error();
+                        continue;
+                    }
+                    std::copy(mats.begin(), mats.end(), all.mats.begin() + mbase + k * block);
+                }
+            };
+            const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+            std::vector<std::thread> th;
+            for (unsigned i = 0; i < nt; ++i) th.emplace_back(worker);
+            for (auto &t : th) t.join();
+            for (size_t k = 0; k < count; ++k)
+                if (rc[k]) return fail(rc[k], "template instance " + std::to_string(k) + ": " + msg[k]);
+            for (size_t k = 0; k < count; ++k) {
+                BatchItem it{};
+                it.arena_off = arena;
+                it.mat_base = mbase + k * block;
+                it.n = (uint32_t)T.n;
+                it.pass_begin = pass_base;
+                it.pass_end = (uint32_t)all.passes.size();
+                it.out_off = outs;
+                T.arena_off[k] = arena;
+                T.out_off[k] = outs;
+                arena += ((1ull << (2 * T.n)) + 15) & ~15ull;
+                outs += (uint32_t)T.n;
+                items.push_back(it);
+                cost.push_back((double)(T.plan.passes.size() + 1) * (double)(1ull << (2 * T.n)));
+                passes += T.plan.passes.size();
+            }
+        }
+    }
     // largest first
     std::vector<size_t> order(items.size());
     for (size_t k = 0; k < order.size(); ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t x, size_t y) { return b->inst[sel[x]].cost > b->inst[sel[y]].cost; });
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
     std::vector<BatchItem> queue;
     for (size_t k : order) queue.push_back(items[k]);
 
@@ -187,6 +274,55 @@ int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream)
     b->total_passes = passes;
     return VQD_OK;
 }
+
+}  // namespace
+
+int check_template(int n, int count, const int *kinds, const int *targets)
+{
+    if (!kinds || !targets || count < 1) return fail(VQD_E_ARG, "bad template arguments");
+    for (int i = 0; i < count; ++i) {
+        int nq = 0, np = 0;
+        if (kind_arity(kinds[i], &nq, &np) != 0) return fail(VQD_E_ARG, "unknown kind in template op " + std::to_string(i));
+        for (int j = 0; j < nq; ++j) {
+            const int q = targets[4 * i + j];
+            if (q < 0 || q >= n) return fail(VQD_E_ARG, "bad target in template op " + std::to_string(i));
+            for (int k = 0; k < j; ++k)
+                if (targets[4 * i + k] == q) return fail(VQD_E_ARG, "duplicate target in template op " + std::to_string(i));
+        }
+    }
+    return VQD_OK;
+}
+
+int plan_template(int n, const std::vector<int> &kinds, const std::vector<int> &targets, PlanOpts o, HostPlan &plan)
+{
+    o.record_recipes = true;
+    o.keep_identity = true;
+    std::vector<LOp> canon(kinds.size());
+    for (size_t j = 0; j < kinds.size(); ++j) {
+        double p[4];
+        canonical_params(kinds[j], p);
+        std::vector<cd> S;
+        int k = 0;
+        if (int rc = kind_superop(kinds[j], p, S, k)) return rc;
+        canon[j] = make_superop_op(k, &targets[4 * j], S.data());
+    }
+    return plan_program(n, canon, o, plan);
+}
+
+int template_mats(int n, const std::vector<int> &kinds, const std::vector<int> &targets, const HostPlan &plan,
+                  const double *params, std::vector<LOp> &lops, std::vector<cd> &mats)
+{
+    lops.resize(kinds.size());
+    std::vector<cd> S;
+    for (size_t j = 0; j < kinds.size(); ++j) {
+        int k = 0;
+        if (int rc = kind_superop(kinds[j], params + 4 * j, S, k)) return rc;
+        lops[j] = make_superop_op(k, &targets[4 * j], S.data());
+    }
+    return recompute_mats(n, plan, lops, mats);
+}
+
+namespace {
 
 std::string arch_name()
 {
@@ -265,8 +401,9 @@ int vqd_batch_add(vqd_batch *b, const vqd_prog *p, int *index)
     I.n = p->n;
     I.ops = p->ops;
     b->inst.push_back(std::move(I));
+    b->refs.emplace_back(-1, (uint32_t)b->inst.size() - 1);
     b->compiled = false;
-    if (index) *index = (int)b->inst.size() - 1;
+    if (index) *index = (int)b->refs.size() - 1;
     return VQD_OK;
 }
 
@@ -276,13 +413,7 @@ int vqd_batch_set_opts(vqd_batch *b, int n, const vqd_plan_opts *o)
     if (!b || !o) return fail(VQD_E_ARG, "null argument");
     if (n < 2 || n > VQD_MAX_QUBITS) return fail(VQD_E_SIZE, "n must be in [2, 16]");
     if (o->tile_bits < 4 || o->tile_bits > 12) return fail(VQD_E_ARG, "batched tile_bits must be in [4, 12]");
-    PlanOpts po;
-    po.tile_bits = o->tile_bits;
-    po.min_contig_bits = o->min_contig_bits;
-    po.max_ops_per_pass = o->max_ops_per_pass;
-    po.fuse_blocks = o->fuse_blocks != 0;
-    po.pad_coalesce = o->pad_coalesce != 0;
-    b->opts_by_n[n] = po;
+    b->opts_by_n[n] = to_plan_opts(*o);
     b->compiled = false;
     return VQD_OK;
 }
@@ -291,10 +422,17 @@ int vqd_batch_compile(vqd_batch *b, size_t *arena_bytes, size_t *n_outputs)
 {
     clear_error();
     if (!b) return fail(VQD_E_ARG, "null batch");
-    if (b->inst.empty()) return fail(VQD_E_STATE, "empty batch");
+    size_t n_tmpl = 0;
+    for (const auto &T : b->tmpl) n_tmpl += T.params.size();
+    if (b->inst.empty() && n_tmpl == 0) return fail(VQD_E_STATE, "empty batch");
     std::vector<int> all(b->inst.size());
     for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
     if (int rc = plan_all(b, all, b->opts_by_n)) return rc;
+    for (auto &T : b->tmpl) {
+        auto it = b->opts_by_n.find(T.n);
+        const PlanOpts o = (it != b->opts_by_n.end()) ? it->second : default_opts(T.n);
+        if (int rc = plan_template(T.n, T.kinds, T.targets, o, T.plan)) return rc;
+    }
     if (int rc = build_device(b, all, nullptr)) return rc;
     (void)hipGetDevice(&b->device);
     b->compiled = true;
@@ -307,9 +445,55 @@ int vqd_batch_offsets(const vqd_batch *b, int index, size_t *arena_offset_bytes,
 {
     clear_error();
     if (!b || !b->compiled) return fail(VQD_E_STATE, "batch not compiled");
-    if (index < 0 || index >= (int)b->inst.size()) return fail(VQD_E_ARG, "instance index out of range");
-    if (arena_offset_bytes) *arena_offset_bytes = (size_t)b->inst[index].arena_off * 16;
-    if (out_offset) *out_offset = b->inst[index].out_off;
+    if (index < 0 || index >= (int)b->refs.size()) return fail(VQD_E_ARG, "instance index out of range");
+    const auto ref = b->refs[index];
+    uint64_t a = 0;
+    uint32_t o = 0;
+    if (ref.first < 0) {
+        a = b->inst[ref.second].arena_off;
+        o = b->inst[ref.second].out_off;
+    } else {
+        a = b->tmpl[ref.first].arena_off[ref.second];
+        o = b->tmpl[ref.first].out_off[ref.second];
+    }
+    if (arena_offset_bytes) *arena_offset_bytes = (size_t)a * 16;
+    if (out_offset) *out_offset = o;
+    return VQD_OK;
+}
+
+int vqd_batch_add_template(vqd_batch *b, int n, int count, const int *kinds, const int *targets,
+                           int *template_id)
+{
+    clear_error();
+    if (!b || !kinds || !targets || count < 1) return fail(VQD_E_ARG, "bad template arguments");
+    if (n < 2 || n > VQD_MAX_QUBITS) return fail(VQD_E_SIZE, "batched instances need n in [2, 16]");
+    if (int rc = check_template(n, count, kinds, targets)) return rc;
+    vqd_batch::Template T;
+    T.n = n;
+    T.kinds.assign(kinds, kinds + count);
+    T.targets.assign(targets, targets + 4 * (size_t)count);
+    b->tmpl.push_back(std::move(T));
+    b->compiled = false;
+    if (template_id) *template_id = (int)b->tmpl.size() - 1;
+    return VQD_OK;
+}
+
+int vqd_batch_add_instances(vqd_batch *b, int template_id, int count, const double *params, int *first_index)
+{
+    clear_error();
+    if (!b || template_id < 0 || template_id >= (int)b->tmpl.size() || count < 0 || (count && !params))
+        return fail(VQD_E_ARG, "bad instance arguments");
+    auto &T = b->tmpl[template_id];
+    const size_t per = 4 * T.kinds.size();
+    for (size_t j = 0; j < per * (size_t)count; ++j)
+        if (!std::isfinite(params[j])) return fail(VQD_E_ARG, "non-finite parameter");
+    if (first_index) *first_index = (int)b->refs.size();
+    for (int i = 0; i < count; ++i) {
+        const double *p = params + per * (size_t)i;
+        T.params.emplace_back(p, p + per);
+        b->refs.emplace_back(template_id, (uint32_t)T.params.size() - 1);
+    }
+    b->compiled = false;
     return VQD_OK;
 }
 
@@ -358,13 +542,15 @@ int vqd_batch_autotune(vqd_batch *b, void *arena, size_t arena_bytes, double *ou
 {
     clear_error();
     if (!b || !arena || !out) return fail(VQD_E_ARG, "null argument");
-    if (b->inst.empty()) return fail(VQD_E_STATE, "empty batch");
+    if (b->refs.empty()) return fail(VQD_E_STATE, "empty batch");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     std::map<std::string, std::vector<double>> cache;
     if (cache_path) cache = read_cache(cache_path);
     const std::string arch = arch_name();
     std::map<int, std::vector<int>> by_n;
     for (size_t i = 0; i < b->inst.size(); ++i) by_n[b->inst[i].n].push_back((int)i);
+    for (const auto &T : b->tmpl)
+        if (!T.params.empty()) by_n[T.n];        // qubit counts with template instances only
     hipEvent_t e0, e1;
     VQD_HIP(hipEventCreate(&e0));
     VQD_HIP(hipEventCreate(&e1));
@@ -380,8 +566,10 @@ int vqd_batch_autotune(vqd_batch *b, void *arena, size_t arena_bytes, double *ou
             b->opts_by_n[n] = o;
             continue;
         }
-        std::vector<int> sel(kv.second.begin(),
-                             kv.second.begin() + std::min<size_t>(kv.second.size(), (size_t)std::max(1, max_per_n)));
+        const size_t cap = (size_t)std::max(1, max_per_n);
+        std::vector<int> sel(kv.second.begin(), kv.second.begin() + std::min<size_t>(kv.second.size(), cap));
+        // a sample of template instances only where no ordinary ones are
+        const bool use_tmpl = sel.empty();
         std::vector<PlanOpts> cands;
         for (int tb : {12, 11, 10, 9}) {
             const int t = std::min(tb, 2 * n);
@@ -399,7 +587,12 @@ int vqd_batch_autotune(vqd_batch *b, void *arena, size_t arena_bytes, double *ou
         for (const PlanOpts &o : cands) {
             std::map<int, PlanOpts> om{{n, o}};
             if ((rc = plan_all(b, sel, om))) break;
-            if ((rc = build_device(b, sel, st))) break;
+            if (use_tmpl)
+                for (auto &T : b->tmpl)
+                    if (T.n == n && !T.params.empty() && (rc = plan_template(T.n, T.kinds, T.targets, o, T.plan)))
+                        break;
+            if (rc) break;
+            if ((rc = build_device(b, sel, st, use_tmpl ? n : 0, cap))) break;
             if (arena_bytes < b->arena_amps * 16) { rc = fail(VQD_E_SIZE, "arena too small for tuning"); break; }
             if ((rc = launch_batch(static_cast<double2 *>(arena), b->dev, out, st))) break;
             VQD_HIP(hipEventRecord(e0, st));
@@ -431,7 +624,9 @@ int vqd_batch_info_get(const vqd_batch *b, vqd_batch_info *out)
 {
     clear_error();
     if (!b || !out) return fail(VQD_E_ARG, "null argument");
-    out->n_instances = (int)b->inst.size();
+    size_t n = b->inst.size();
+    for (const auto &T : b->tmpl) n += T.params.size();
+    out->n_instances = (int)n;
     out->total_passes = (long long)b->total_passes;
     out->arena_bytes = (size_t)b->arena_amps * 16;
     out->n_outputs = b->n_out;
@@ -454,3 +649,27 @@ int vqd_batch_plan_opts(const vqd_batch *b, int n, vqd_plan_opts *o)
 }
 
 }  // extern "C"
+
+int vqd_template_export(int n, int count, const int *kinds, const int *targets, const double *params,
+                        const vqd_plan_opts *opts, void *buf, size_t cap, size_t *needed)
+{
+    clear_error();
+    if (!needed) return fail(VQD_E_ARG, "null argument");
+    if (n < 1 || n > VQD_MAX_QUBITS) return fail(VQD_E_SIZE, "n out of range");
+    if (int rc = check_template(n, count, kinds, targets)) return rc;
+    vqd_plan_opts o;
+    vqd_plan_opts_default(&o);
+    if (opts) o = *opts;
+    const std::vector<int> kv(kinds, kinds + count), tv(targets, targets + 4 * (size_t)count);
+    HostPlan plan;
+    if (int rc = plan_template(n, kv, tv, to_plan_opts(o), plan)) return rc;
+    if (params) {
+        for (size_t j = 0; j < 4 * (size_t)count; ++j)
+            if (!std::isfinite(params[j])) return fail(VQD_E_ARG, "non-finite parameter");
+        std::vector<LOp> lops;
+        std::vector<cd> mats;
+        if (int rc = template_mats(n, kv, tv, plan, params, lops, mats)) return rc;
+        plan.mats = mats;
+    }
+    return export_plan(plan, n, o.tile_bits, buf, cap, needed);
+}

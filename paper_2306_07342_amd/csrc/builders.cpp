@@ -148,6 +148,19 @@ bool is_channel(int kind)
 
 }  // namespace
 
+void canonical_params(int kind, double *p)
+{
+    p[0] = p[1] = p[2] = p[3] = 0.0;
+    switch (kind) {
+    case VQD_K_SU2: p[0] = 0.31; p[1] = 0.52; p[2] = -0.73; p[3] = 0.44; break;
+    case VQD_K_GAMP: p[0] = 0.83; p[1] = 0.11; break;
+    case VQD_K_AMP_T1: case VQD_K_DEPH_T2: p[0] = 0.3; p[1] = 17.0; break;
+    case VQD_K_RX: case VQD_K_RY: case VQD_K_RZ: case VQD_K_CPHASE: case VQD_K_XX: case VQD_K_ZZ:
+        p[0] = 0.7371; break;
+    default: p[0] = 0.0123; break;        // channel probabilities
+    }
+}
+
 int kind_arity(int kind, int *nq, int *np)
 {
     static const int Q[VQD_K_COUNT] = {0, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2,

@@ -666,6 +666,7 @@ k_batch(double2 *__restrict__ arena, const BatchItem *__restrict__ items, uint32
         if (it >= n_items) break;
         const BatchItem *B = items + it;
         const uint32_t n = uni(B->n);
+        const double2 *M = mats + B->mat_base;     // this instance's coefficients
         double2 *amps = arena + B->arena_off;
         const uint64_t count = 1ull << (2 * n);
         for (uint64_t i = tid; i < count; i += blockDim.x) amps[i] = make_double2(i == 0 ? 1.0 : 0.0, 0.0);
@@ -677,13 +678,13 @@ k_batch(double2 *__restrict__ arena, const BatchItem *__restrict__ items, uint32
             const bool active = tid < (1u << nthr);
             const uint32_t rt_count = uni(P->rt_count);
             if (rt_count) {
-                const double2 *src = mats + uni(P->rt_mat);
+                const double2 *src = M + uni(P->rt_mat);
                 for (uint32_t i = tid; i < rt_count; i += blockDim.x) lds_rt[i] = src[i];
                 __syncthreads();
             }
             const uint64_t n_tiles = P->n_tiles;
             for (uint64_t t = 0; t < n_tiles; ++t)
-                batch_tile(amps, P, phases, ops, mats, lds, lds_rt, t, tid, nthr, active);
+                batch_tile(amps, P, phases, ops, M, lds, lds_rt, t, tid, nthr, active);
             wg_global_sync();
         }
         // <Z_q> = sum_r (-1)^{r_q} Re rho[r][r]

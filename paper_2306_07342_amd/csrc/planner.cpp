@@ -108,6 +108,8 @@ struct Block {
     uint32_t support = 0;       // register bits the block depends on
     bool diag = false;
     int op_index = -1;          // for rt blocks
+    std::vector<int> src;       // logical ops multiplied in, application order
+    int wide_half = -1;         // wide unitary row (0) or column (1) half
 };
 
 bool is_zero(cd x) { return x.real() == 0.0 && x.imag() == 0.0; }
@@ -334,7 +336,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         bool ident = true;
         for (const cd &f : op.D)
             if (f != cd(1)) { ident = false; break; }
-        if (ident) applied[i] = 1;
+        if (ident && !opt.keep_identity) applied[i] = 1;
     }
     size_t first = 0;
     SimResult sim, sim2;
@@ -488,15 +490,47 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                     ko.mat = (uint32_t)rt_tables.size();
                     rt_tables.insert(rt_tables.end(), table.begin(), table.end());
                     out.fma_per_amp += ko.real ? 2.0 : 4.0;
+                    if (opt.record_recipes) {
+                        Recipe r;
+                        r.rt = true;
+                        r.src = {bk.op_index};
+                        r.kind = KOP_DIAG_RT;
+                        r.real = ko.real != 0;
+                        r.mode = mode;
+                        r.row_j = row_j;
+                        r.col_j = col_j;
+                        r.rtj = rtj;
+                        r.mat_off = ko.mat;      // made absolute when the pass closes
+                        out.recipes.push_back(r);
+                    }
                 } else {
                     Encoded enc = encode(bk.m);
-                    if (enc.identity) continue;
+                    if (enc.identity) {
+                        if (!opt.keep_identity) continue;
+                        // a template keeps the slot: other parameters need not give 1
+                        enc.kind = KOP_DIAG;
+                        enc.mask = 15;
+                        enc.real = true;
+                        enc.data = pack(std::vector<cd>(16, cd(1)), true);
+                        enc.cost = 32.0;
+                    }
                     ko.kind = enc.kind;
                     ko.opmask = (uint32_t)enc.mask;
                     ko.real = enc.real ? 1u : 0u;
                     ko.mat = (uint32_t)out.mats.size();
                     out.mats.insert(out.mats.end(), enc.data.begin(), enc.data.end());
                     out.fma_per_amp += enc.cost / 16.0;
+                    if (opt.record_recipes) {
+                        Recipe r;
+                        r.src = bk.src;
+                        for (int b = 0; b < 4; ++b) r.reg_gpos[b] = reg_gpos[b];
+                        r.kind = enc.kind;
+                        r.mask = (uint32_t)enc.mask;
+                        r.real = enc.real;
+                        r.mat_off = ko.mat;
+                        if (bk.wide_half >= 0) r.mode = 100u + (uint32_t)bk.wide_half;
+                        out.recipes.push_back(r);
+                    }
                 }
                 out.ops.push_back(ko);
             }
@@ -597,6 +631,8 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                         }
                     Block bk;
                     bk.m = m;
+                    bk.src = {wide};
+                    bk.wide_half = half;
                     blocks.push_back(bk);
                     emit_phase(reg, blocks, {});
                 }
@@ -637,6 +673,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 Block nb;
                 nb.m = embed(op, n, reg, nb.support);
                 nb.diag = op.diag;
+                nb.src = {idx};
                 bool merged = false;
                 if (opt.fuse_blocks) {
                     for (int j = (int)blocks.size() - 1; j >= 0; --j) {
@@ -651,6 +688,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                             pb.m = prod;
                             pb.support |= nb.support;
                             pb.diag = pb.diag && nb.diag;
+                            pb.src.insert(pb.src.end(), nb.src.begin(), nb.src.end());
                             merged = true;
                         }
                         break;
@@ -695,8 +733,83 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         kp.phase_end = (uint32_t)out.phases.size();
         kp.rt_mat = (uint32_t)out.mats.size();
         kp.rt_count = (uint32_t)rt_tables.size();
+        if (opt.record_recipes)
+            for (uint32_t oi = out.phases[kp.phase_begin].op_begin; oi < out.ops.size(); ++oi)
+                if (out.recipes[oi].rt) out.recipes[oi].mat_off += kp.rt_mat;
         out.mats.insert(out.mats.end(), rt_tables.begin(), rt_tables.end());
         out.passes.push_back(kp);
+    }
+    return VQD_OK;
+}
+
+int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std::vector<cd> &mats)
+{
+    mats.assign(plan.mats.size(), cd(0));
+    if (plan.recipes.size() != plan.ops.size())
+        return fail(VQD_E_STATE, "plan has no coefficient recipes");
+    for (const Recipe &r : plan.recipes) {
+        for (int s : r.src)
+            if (s < 0 || s >= (int)ops.size()) return fail(VQD_E_ARG, "recipe refers to a missing op");
+        if (r.rt) {
+            const LOp &op = ops[r.src[0]];
+            if (!op.diag) return fail(VQD_E_ARG, "op structure differs from the template (diagonal expected)");
+            const int nb = 2 * op.k;
+            if (r.real && !all_real(op.D))
+                return fail(VQD_E_ARG, "op structure differs from the template (complex diagonal)");
+            if (r.mode == RT_GENERIC) {
+                for (int i = 0; i < (1 << nb); ++i) mats[r.mat_off + i] = op.D[i];
+            } else {
+                const int shift = (r.mode == RT_NONE) ? 0 : 2;
+                for (int idx = 0; idx < (1 << nb); ++idx) {
+                    int t = 0;
+                    for (size_t k = 0; k < r.rtj.size(); ++k) t |= ((idx >> r.rtj[k]) & 1) << k;
+                    int c = 0;
+                    if (r.mode != RT_NONE) c = ((idx >> r.row_j) & 1) | (((idx >> r.col_j) & 1) << 1);
+                    mats[r.mat_off + size_t(c) + (size_t(t) << shift)] = op.D[idx];
+                }
+            }
+            continue;
+        }
+        if (r.mode >= 100) return fail(VQD_E_ARG, "wide unitary blocks cannot be recomputed");
+        Mat16 m{};
+        for (int e = 0; e < 16; ++e) m[e * 16 + e] = 1.0;
+        for (int s : r.src) {
+            uint32_t sup = 0;
+            m = mul(embed(ops[s], n, r.reg_gpos, sup), m);
+        }
+        // the new coefficients must fit the form chosen for the template's
+        std::vector<cd> data;
+        if (r.kind == KOP_DIAG) {
+            data.resize(16);
+            for (int i = 0; i < 16; ++i)
+                for (int j = 0; j < 16; ++j)
+                    if (i != j && !is_zero(m[i * 16 + j]))
+                        return fail(VQD_E_ARG, "op structure differs from the template (not diagonal)");
+            for (int e = 0; e < 16; ++e) data[e] = m[e * 16 + e];
+        } else {
+            std::vector<cd> sub;
+            if (!restrict_to(m, (int)r.mask, sub))
+                return fail(VQD_E_ARG, "op structure differs from the template");
+            const int dim = 1 << popc(r.mask);
+            if (r.kind == KOP_MAT) {
+                data.resize(size_t(dim) * dim);
+                for (int j = 0; j < dim; ++j)
+                    for (int i = 0; i < dim; ++i) data[j * dim + i] = sub[i * dim + j];
+            } else {
+                const std::vector<int> fl = local_flips((int)r.mask);
+                for (int i = 0; i < dim; ++i)
+                    for (int j = 0; j < dim; ++j)
+                        if (!is_zero(sub[i * dim + j]) && std::find(fl.begin(), fl.end(), i ^ j) == fl.end())
+                            return fail(VQD_E_ARG, "op structure differs from the template (flip pattern)");
+                data.resize(fl.size() * dim);
+                for (size_t x = 0; x < fl.size(); ++x)
+                    for (int i = 0; i < dim; ++i) data[x * dim + i] = sub[i * dim + (i ^ fl[x])];
+            }
+        }
+        if (r.real && !all_real(data))
+            return fail(VQD_E_ARG, "op structure differs from the template (complex coefficients)");
+        const std::vector<cd> packed = pack(data, r.real);
+        for (size_t i = 0; i < packed.size(); ++i) mats[r.mat_off + i] = packed[i];
     }
     return VQD_OK;
 }

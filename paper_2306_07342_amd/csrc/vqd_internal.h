@@ -104,11 +104,27 @@ struct DevProgram {
 };
 
 // Host-side planned program.
+// How the coefficients of one kernel op were made from the logical ops, so
+// that they can be recomputed for other parameter values of the same op
+// kinds (parametric batch templates) without planning again.
+struct Recipe {
+    bool rt = false;
+    std::vector<int> src;       // logical ops multiplied into the block, application order
+    int reg_gpos[4] = {0, 0, 0, 0};
+    uint32_t kind = 0, mask = 0;
+    bool real = false;
+    uint32_t mode = 0;          // runtime diagonal: index mode and bit mapping
+    int row_j = -1, col_j = -1;
+    std::vector<int> rtj;
+    size_t mat_off = 0;         // where the coefficients live in HostPlan::mats
+};
+
 struct HostPlan {
     std::vector<KPass> passes;
     std::vector<KPhase> phases;
     std::vector<KOp> ops;
     std::vector<cd> mats;
+    std::vector<Recipe> recipes;    // one per kernel op when recorded
     double fma_per_amp = 0;
 };
 
@@ -134,8 +150,23 @@ struct PlanOpts {
     int max_ops_per_pass = 0;
     bool fuse_blocks = true;
     bool pad_coalesce = true;
+    bool record_recipes = false;    // fill HostPlan::recipes
+    bool keep_identity = false;     // do not drop ops that are exactly the identity
 };
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out);
+// Recompute a recorded plan's coefficients for new logical ops of the same
+// structure (same kinds and targets).  mats gets the plan's layout.
+int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std::vector<cd> &mats);
+// Serialise a plan (layout of vqd_prog_export).
+int export_plan(const HostPlan &plan, int n, int tile_bits, void *buf, size_t cap, size_t *needed);
+// Parametric templates: validate, plan with canonical parameters, and compute
+// one instance's coefficient block (`lops` is per-call scratch).
+int check_template(int n, int count, const int *kinds, const int *targets);
+int plan_template(int n, const std::vector<int> &kinds, const std::vector<int> &targets, PlanOpts o,
+                  HostPlan &plan);
+int template_mats(int n, const std::vector<int> &kinds, const std::vector<int> &targets, const HostPlan &plan,
+                  const double *params, std::vector<LOp> &lops, std::vector<cd> &mats);
+PlanOpts to_plan_opts(const vqd_plan_opts &o);
 
 // Upload a plan into a device program (re-using its buffer when large enough).
 int upload_plan(const HostPlan &plan, DevProgram &dev, hipStream_t stream);
@@ -145,10 +176,10 @@ void free_dev_program(DevProgram &dev);
 // One density matrix of a batch (queue order).
 struct alignas(16) BatchItem {
     uint64_t arena_off;       // first amplitude of the instance in the arena
+    uint64_t mat_base;        // added to every coefficient offset of its passes
     uint32_t n;
     uint32_t pass_begin, pass_end;
     uint32_t out_off;         // first of its n <Z_i> outputs
-    uint32_t pad[2];
 };
 
 struct BatchDev {
@@ -185,6 +216,9 @@ int reduce_pauli(const double2 *amps, int n, uint64_t xmask, uint64_t zmask, int
 
 // ------------------------------------------------------------- builders --
 int kind_arity(int kind, int *nq, int *np);
+// Parameters used to plan a parametric template: generic values for which no
+// matrix entry of the kind vanishes or turns real by accident.
+void canonical_params(int kind, double *p);
 int kind_matrix(int kind, const double *params, std::vector<cd> &U, int &k);
 int kind_superop(int kind, const double *params, std::vector<cd> &S, int &k);
 void kraus_to_superop(int k, int nk, const cd *K, std::vector<cd> &S);

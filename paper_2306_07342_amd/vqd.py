@@ -108,6 +108,10 @@ def load(path: str = LIB_PATH):
         "vqd_batch_run": ([vp, vp, ctypes.c_size_t, _dp, vp, ctypes.c_int], ctypes.c_int),
         "vqd_batch_autotune": ([vp, vp, ctypes.c_size_t, _dp, vp, ctypes.c_char_p, ctypes.c_int], ctypes.c_int),
         "vqd_batch_info_get": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
+        "vqd_batch_add_template": ([vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip], ctypes.c_int),
+        "vqd_batch_add_instances": ([vp, ctypes.c_int, ctypes.c_int, _dp, _ip], ctypes.c_int),
+        "vqd_template_export": ([ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, ctypes.POINTER(PlanOpts), vp,
+                                 ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_calc_purity": ([vp, _dp], ctypes.c_int),
         "vqd_calc_probs": ([vp, _dp], ctypes.c_int),
@@ -301,6 +305,34 @@ def plan_opts(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=T
                     1 if pad_coalesce else 0)
 
 
+def _structure(structure):
+    """(kind, qubits) pairs -> int32 kind codes and an (n_ops, 4) target array."""
+    k = np.fromiter((KINDS[s[0]] for s in structure), dtype=np.int32)
+    t = np.zeros((len(k), 4), dtype=np.int32)
+    for i, s in enumerate(structure):
+        t[i, :len(s[1])] = s[1]
+    return k, t
+
+
+def template_export(n: int, structure, params=None, opts: Optional[PlanOpts] = None) -> bytes:
+    """Host-only plan of a parametric template (see vqd_template_export),
+    with the coefficients of `params` ((n_ops, 4) array) or the generic ones."""
+    k, t = _structure(structure)
+    p = None
+    if params is not None:
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        assert p.shape == (len(k), 4), p.shape
+    L = lib()
+    need = ctypes.c_size_t()
+    o = ctypes.byref(opts) if opts is not None else None
+    check(L.vqd_template_export(n, len(k), _i(k), _i(t), _d(p) if p is not None else None, o, None, 0,
+                                ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    check(L.vqd_template_export(n, len(k), _i(k), _i(t), _d(p) if p is not None else None, o, buf,
+                                need.value, ctypes.byref(need)))
+    return buf.raw
+
+
 class Program:
     """An op program planned by the library into fused HBM passes."""
 
@@ -422,6 +454,27 @@ class Batch:
         p.close()
         self.ns.append(n)
         return idx.value
+
+    def add_template(self, n: int, structure) -> int:
+        """A parametric circuit: `structure` is a list of (kind, qubits) named
+        ops; instances supply only parameters (add_instances)."""
+        k, t = _structure(structure)
+        tid = ctypes.c_int()
+        check(lib().vqd_batch_add_template(self.handle, n, len(k), _i(k), _i(t), ctypes.byref(tid)))
+        self._tmpl = getattr(self, "_tmpl", {})
+        self._tmpl[tid.value] = (n, len(k))
+        return tid.value
+
+    def add_instances(self, template_id: int, params) -> range:
+        """Instances of a template; params has shape (count, n_ops, 4).
+        Returns their instance indices."""
+        n, n_ops = self._tmpl[template_id]
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        assert p.ndim == 3 and p.shape[1:] == (n_ops, 4), p.shape
+        first = ctypes.c_int()
+        check(lib().vqd_batch_add_instances(self.handle, template_id, p.shape[0], _d(p), ctypes.byref(first)))
+        self.ns.extend([n] * p.shape[0])
+        return range(first.value, first.value + p.shape[0])
 
     def set_opts(self, n: int, opts: PlanOpts):
         check(lib().vqd_batch_set_opts(self.handle, n, ctypes.byref(opts)))

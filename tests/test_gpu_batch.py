@@ -142,3 +142,68 @@ def test_full_batch_workload(gpu_lib):
         gpu_lib.Program(x["n"], x["ops"]).compile().run(dm)
         assert np.abs(b.state(int(i)) - dm.to_numpy()).max() <= TOL
         assert np.abs(b.expec_z(int(i)) - dm.expec_z()).max() <= TOL
+
+
+def test_template_instances_match_oracle(gpu_lib):
+    """Parametric templates (one planned structure, per-instance parameters)
+    mixed with ordinary instances in one batch; the instance indices follow
+    the order of addition."""
+    from workloads import c5_ansatz_circuit, c5_draw_samples, c5_params, c5_structure
+    say("template batch")
+    insts = mixed_instances(seed=3)[:4]
+    b = gpu_lib.Batch()
+    b.add(*insts[0])
+    st6 = c5_structure(n=6, layers=2)
+    dev6, ang6 = c5_draw_samples(5, seed=21, n_angles=8)
+    t6 = b.add_template(6, [(k, q) for k, q, _ in st6])
+    idx6 = b.add_instances(t6, c5_params(st6, dev6, ang6)[:3])
+    b.add(*insts[1])
+    st10 = c5_structure()
+    dev10, ang10 = c5_draw_samples(3, seed=22)
+    t10 = b.add_template(10, [(k, q) for k, q, _ in st10])
+    idx10 = b.add_instances(t10, c5_params(st10, dev10, ang10))
+    idx6b = b.add_instances(t6, c5_params(st6, dev6, ang6)[3:])
+    assert list(idx6) == [1, 2, 3] and list(idx10) == [5, 6, 7] and list(idx6b) == [8, 9]
+    b.compile()
+    assert b.info()["n_instances"] == 10
+    b.run()
+    for i, (n, ops) in zip((0, 4), insts[:2]):
+        ref = emulate(n, ops)
+        assert np.abs(b.state(i) - ref.to_vectorised()).max() <= TOL
+    for j, i in enumerate(list(idx6) + list(idx6b)):
+        ref = emulate(6, c5_ansatz_circuit(dev6[j], ang6[j], n=6, layers=2))
+        assert np.abs(b.state(i) - ref.to_vectorised()).max() <= TOL, i
+        assert np.abs(b.expec_z(i) - ref.expec_z()).max() <= TOL, i
+    for j, i in enumerate(idx10):
+        ref = emulate(10, c5_ansatz_circuit(dev10[j], ang10[j]))
+        assert np.abs(b.state(i) - ref.to_vectorised()).max() <= TOL, i
+        assert np.abs(b.expec_z(i) - ref.expec_z()).max() <= TOL, i
+
+
+def test_template_only_batch_graph_and_autotune(gpu_lib):
+    """A batch made only of template instances: autotuned (on a sample of
+    them), graph-replayed, and checked against the oracle on a sample."""
+    import torch
+    from workloads import c5_ansatz_circuit, c5_draw_samples, c5_params, c5_structure
+    say("template-only batch")
+    st = c5_structure()
+    dev, ang = c5_draw_samples(256, seed=23)
+    b = gpu_lib.Batch()
+    t = b.add_template(10, [(k, q) for k, q, _ in st])
+    idx = b.add_instances(t, c5_params(st, dev, ang))
+    b.compile()
+    with tempfile.TemporaryDirectory() as d:
+        b.autotune(os.path.join(d, "tune.json"), max_per_n=16)
+        assert ":n10" in open(os.path.join(d, "tune.json")).read()
+    b.compile()
+    b.run()
+    eager = b.out.clone()
+    for rep in range(3):
+        b.out.zero_()
+        torch.cuda.synchronize()
+        b.run(use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(b.out, eager), rep
+    for j in (0, 77, 255):
+        ref = emulate(10, c5_ansatz_circuit(dev[j], ang[j]))
+        assert np.abs(b.expec_z(idx[j]) - ref.expec_z()).max() <= TOL, j

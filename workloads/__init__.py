@@ -14,6 +14,10 @@ from .circuits import (  # noqa: F401
     c4_batch_instances,
     c5_ansatz_circuit,
     c5_draw_samples,
+    c5_params,
+    c5_structure,
+    C5_N,
+    C5_LAYERS,
     random_matrix_ops,
     count_gates,
     GATE_KINDS,

@@ -231,6 +231,54 @@ def c5_ansatz_circuit(dev: Sequence[float], angles: Sequence[float],
     return ops
 
 
+# slots of the concatenated parameter vector [dev (8), angles (4 * layers)]
+_C5_T1, _C5_T2, _C5_P1, _C5_P2, _C5_T1Q, _C5_T2Q, _C5_ALPHA, _C5_B = range(8)
+
+
+def c5_structure(n: int = C5_N, layers: int = C5_LAYERS):
+    """The op sequence of ``c5_ansatz_circuit`` as ``(kind, qubits, slots)``:
+    ``slots`` index the concatenated vector ``[dev (8), angles (4*layers)]``
+    for each of the op's parameters.  ZZ crosstalk ops are always present
+    (ZZ with alpha = 0 is the identity), so one structure serves every
+    parameter setting."""
+    out = []
+    edges = [(i, i + 1) for i in range(n - 1)]
+    for l in range(layers):
+        for k, kind in enumerate(("ry", "ry", "rz", "rz")):
+            for q in range(k % 2, n, 2):
+                out.append((kind, (q,), (8 + 4 * l + k,)))
+                out.append(("depol1", (q,), (_C5_P1,)))
+                out.append(("amp_t1", (q,), (_C5_T1Q, _C5_T1)))
+                out.append(("deph_t2", (q,), (_C5_T1Q, _C5_T2)))
+        for start in (0, 1):
+            brick = [(a, a + 1) for a in range(start, n - 1, 2)]
+            for (a, c) in brick:
+                out.append(("cz", (a, c), ()))
+                out.append(("depol2", (a, c), (_C5_P2,)))
+                for q in (a, c):
+                    out.append(("amp_t1", (q,), (_C5_T2Q, _C5_T1)))
+                    out.append(("deph_t2", (q,), (_C5_T2Q, _C5_T2)))
+            bs = set(brick)
+            for e in edges:
+                if e not in bs:
+                    out.append(("zz", e, (_C5_ALPHA,)))
+    for q in range(n):
+        out.append(("bitflip1", (q,), (_C5_B,)))
+    return out
+
+
+def c5_params(structure, dev: np.ndarray, angles: np.ndarray) -> np.ndarray:
+    """Per-op parameters ``[count, n_ops, 4]`` of ``count`` settings: each op's
+    slots gathered from ``[dev, angles]`` (unused entries 0)."""
+    v = np.concatenate([np.atleast_2d(dev), np.atleast_2d(angles)], axis=1)
+    idx = np.full((len(structure), 4), -1, dtype=np.int64)
+    for i, (_, _, slots) in enumerate(structure):
+        idx[i, :len(slots)] = slots
+    out = v[:, np.maximum(idx, 0)]
+    out[:, idx < 0] = 0.0
+    return out
+
+
 def c5_draw_samples(count: int, seed: int = SEED_BASE + 4, n_angles: int = 4 * C5_LAYERS):
     """Draw ``count`` (device parameters, circuit angles) pairs.
 
