@@ -159,6 +159,58 @@ def batched_leg(vqd, torch, steps):
             "tiles": "autotuned (%s)" % ("cached" if tuned else "fresh")}
 
 
+def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
+    """The learned surrogate of the 10-qubit, 4-layer ansatz (8 device
+    parameters + 16 angles -> 10 <Z_i>): training data from the batched
+    emulator, training by the library's kernels, then evals/s with fallback
+    (spread > 5e-3) against the emulator alone on a held-out set, judged by
+    the emulator at |dZ| < 1e-2.  A device-parameter sweep at fixed angles is
+    reported beside it."""
+    import numpy as np
+    from paper_2306_07342_amd.surrogate import SurrogateModel, TemplateEmulator, measure_gain
+    from workloads import SEED_BASE, c5_draw_samples, c5_params, c5_structure
+    from workloads.surrogate import c5_features, init_ensemble
+    st = c5_structure()
+    emu = TemplateEmulator(10, st)
+
+    def data(count, seed, fixed_angles=None):
+        dev, ang = c5_draw_samples(count, seed=seed)
+        if fixed_angles is not None:
+            ang[:] = fixed_angles
+        return c5_params(st, dev, ang), torch.as_tensor(c5_features(dev, ang), device="cuda")
+
+    def run(n_tr, n_te, ep, seeds, fixed=None):
+        P, x = data(n_tr, seeds[0], fixed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = emu.run(P).float().contiguous()
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        log("surrogate: %d training samples in %.1f s" % (n_tr, t_data))
+        model = SurrogateModel(init_ensemble(), max_batch=1024)
+        t0 = time.perf_counter()
+        model.fit(x, y, epochs=ep, batch=512, lr=1e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        log("surrogate: %d epochs in %.1f s, loss %s" % (ep, t_train, model.history[-1]))
+        Pt, xt = data(n_te, seeds[1], fixed)
+        res = measure_gain(model, emu, Pt, xt, threshold=5e-3, tol=1e-2)
+        res.update({"train_samples": n_tr, "data_gen_s": round(t_data, 2),
+                    "data_gen_evals_per_s": round(n_tr / t_data, 1), "epochs": ep, "batch": 512,
+                    "train_s": round(t_train, 2), "final_train_mse": [float(v) for v in model.history[-1]]})
+        return res
+
+    out = {"metric": "surrogate vs emulator evals/s at |dZ|<1e-2 (10-qubit 4-layer ansatz)",
+           "config": "8 device parameters + 16 angles drawn uniformly, 4 x MLP 24-256-256-256-10 GELU, "
+                     "bf16 operands / FP32 accumulate, fallback when spread > 5e-3"}
+    out["uniform_angles"] = run(n_train, n_test, epochs, (SEED_BASE + 4, SEED_BASE + 6))
+    fixed = c5_draw_samples(1, seed=SEED_BASE + 7)[1][0]
+    out["device_sweep_fixed_angles"] = run(max(4096, n_train // 8), max(1024, n_test // 4), 4 * epochs,
+                                           (SEED_BASE + 8, SEED_BASE + 9), fixed)
+    emu.release()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +219,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-every", type=int, default=782)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-emulation leg")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--surrogate-train", type=int, default=1 << 18, help="training samples (2^18)")
+    ap.add_argument("--surrogate-test", type=int, default=1 << 14, help="held-out samples (2^14)")
+    ap.add_argument("--surrogate-epochs", type=int, default=30)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device-to-device copy of the state buffer "
                          "(known size) for scaling HBM counters")
@@ -266,6 +322,10 @@ def main():
     if not args.no_batched:
         log("batched leg ...")
         out["batched"] = batched_leg(vqd, torch, args.steps)
+    if not args.no_surrogate:
+        log("surrogate leg ...")
+        out["surrogate"] = surrogate_leg(vqd, torch, args.surrogate_train, args.surrogate_test,
+                                         args.surrogate_epochs)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_sample_every)

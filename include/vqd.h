@@ -346,6 +346,65 @@ int vqd_calc_expec_zz(const vqd_dm *dm, const int *pairs, int npairs, double *ou
  * {0=I, 1=X, 2=Y, 3=Z} (Sec. 2: expectation values of Pauli strings). */
 int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, double *im);
 
+/* ------------------------------------------------------------- surrogate */
+
+/* Learned surrogate of the emulator: an ensemble of `members` MLPs mapping
+ * 24 scaled inputs (8 device parameters and 16 angles of a hardware-efficient
+ * ansatz, Sec. 2 and 3; the network itself is not in the paper) to the 10
+ * read-outs <Z_i>.  Each member: 24 -> 256 -> 256 -> 256 -> 10, GELU after
+ * each hidden layer (GELU(z) = z Phi(z)), linear output; loss = mean squared
+ * error over the batch and the 10 outputs; Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected).
+ *
+ * Number formats: FP32 master weights and Adam moments.  Every matrix product
+ * takes bfloat16 operands (round to nearest even) and accumulates in FP32;
+ * rounded are the input, the weights, the hidden activations after GELU and
+ * the back-propagated pre-activation gradients (which feed the weight, bias
+ * and input gradients alike).  Biases and pre-activations stay FP32.
+ *
+ * Parameter vector of a member (VQD_MLP_N_PARAMS floats): row-major
+ * W1[256][24], b1[256], W2[256][256], b2, W3[256][256], b3, W4[10][256],
+ * b4[10]; host arrays hold `members` such vectors back to back.
+ *
+ * Memory: the handle owns its parameters, Adam state and the training
+ * workspace (sized for max_batch) on the device current at creation; inputs
+ * and outputs of train/predict calls are caller-owned device arrays (x:
+ * [B][24] float, y: [B][10] float, idx: optional [B] int row indices into x
+ * and y, mean: [B][10], spread: [B], member_out: optional [members][B][10]).
+ * Calls on one handle must not overlap. */
+typedef struct vqd_mlp vqd_mlp;
+
+#define VQD_MLP_N_PARAMS 140554
+enum { VQD_MLP_PARAMS = 0, VQD_MLP_ADAM_M = 1, VQD_MLP_ADAM_V = 2, VQD_MLP_GRAD = 3 };
+
+int vqd_mlp_create(int members, int max_batch, vqd_mlp **out);   /* 1 <= members <= 8 */
+int vqd_mlp_destroy(vqd_mlp *h);
+int vqd_mlp_n_params(void);
+
+/* Host copies in and out (members x VQD_MLP_N_PARAMS floats).  set: PARAMS,
+ * ADAM_M or ADAM_V (setting PARAMS refreshes the bf16 copies); get: also
+ * GRAD, the gradient of the last grad/train call.  Both synchronise. */
+int vqd_mlp_set_state(vqd_mlp *h, int which, const float *host);
+int vqd_mlp_get_state(const vqd_mlp *h, int which, float *host);
+int vqd_mlp_set_step(vqd_mlp *h, long long step);   /* Adam step count t */
+long long vqd_mlp_get_step(const vqd_mlp *h);
+
+/* Loss (per member, device float[members], may be NULL) and gradient of
+ * every member on the same batch of B <= max_batch samples. */
+int vqd_mlp_grad(vqd_mlp *h, const float *x, const float *y, const int *idx, int B, float *loss_out,
+                 void *hip_stream);
+
+/* vqd_mlp_grad then one Adam step with learning rate lr (t incremented). */
+int vqd_mlp_train_step(vqd_mlp *h, const float *x, const float *y, const int *idx, int B, float lr,
+                       float *loss_out, void *hip_stream);
+
+/* Ensemble inference on B samples (any B >= 0): mean over members and
+ * spread = max over the 10 outputs of the population standard deviation
+ * across members.  A caller falls back to the emulator where spread exceeds
+ * its threshold. */
+int vqd_mlp_predict(const vqd_mlp *h, const float *x, int B, float *mean, float *spread, float *member_out,
+                    void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,9 +18,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvqd.so")
 ARCH = os.environ.get("VQD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "builders.cpp", "planner.cpp", "batch.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "builders.cpp", "planner.cpp", "batch.cpp", "kernels.hip", "mlp.hip"]
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-fcx-limited-range",
           "-I", os.path.join(HERE, "..", "include")]
 # packed FP32 instructions stay off in all device code
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH,

@@ -742,6 +742,56 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
     return VQD_OK;
 }
 
+namespace {
+
+bool same_targets(const LOp &x, const LOp &y)
+{
+    if (x.k != y.k || x.wide_unitary || y.wide_unitary) return false;
+    for (int j = 0; j < x.k; ++j)
+        if (x.q[j] != y.q[j]) return false;
+    return true;
+}
+
+// Product (application order) of ops[src[s..e)], all on the same targets.
+LOp local_product(const std::vector<LOp> &ops, const std::vector<int> &src, size_t s, size_t e)
+{
+    const LOp &a = ops[src[s]];
+    const int D = 1 << (2 * a.k);
+    LOp out;
+    out.k = a.k;
+    for (int j = 0; j < a.k; ++j) out.q[j] = a.q[j];
+    bool all_diag = true;
+    for (size_t i = s; i < e; ++i) all_diag &= ops[src[i]].diag;
+    if (all_diag) {
+        out.diag = true;
+        out.D.assign(D, cd(1));
+        for (size_t i = s; i < e; ++i)
+            for (int x = 0; x < D; ++x) out.D[x] *= ops[src[i]].D[x];
+        return out;
+    }
+    std::vector<cd> M(size_t(D) * D, cd(0)), T(size_t(D) * D);
+    for (int x = 0; x < D; ++x) M[size_t(x) * D + x] = 1.0;
+    for (size_t i = s; i < e; ++i) {
+        const LOp &o = ops[src[i]];
+        std::fill(T.begin(), T.end(), cd(0));
+        for (int r = 0; r < D; ++r)
+            if (o.diag) {
+                for (int c = 0; c < D; ++c) T[size_t(r) * D + c] = o.D[r] * M[size_t(r) * D + c];
+            } else {
+                for (int k = 0; k < D; ++k) {
+                    const cd v = o.S[size_t(r) * D + k];
+                    if (is_zero(v)) continue;
+                    for (int c = 0; c < D; ++c) T[size_t(r) * D + c] += v * M[size_t(k) * D + c];
+                }
+            }
+        M.swap(T);
+    }
+    out.S = std::move(M);
+    return out;
+}
+
+}  // namespace
+
 int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std::vector<cd> &mats)
 {
     mats.assign(plan.mats.size(), cd(0));
@@ -771,12 +821,23 @@ int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std
             continue;
         }
         if (r.mode >= 100) return fail(VQD_E_ARG, "wide unitary blocks cannot be recomputed");
+        // product in application order; a run of ops on the same targets is
+        // first multiplied in its own 4^k space, then embedded once
         Mat16 m{};
-        for (int e = 0; e < 16; ++e) m[e * 16 + e] = 1.0;
-        for (int s : r.src) {
+        bool first = true;
+        for (size_t s = 0; s < r.src.size();) {
+            const LOp &a = ops[r.src[s]];
+            size_t e = s + 1;
+            while (e < r.src.size() && same_targets(ops[r.src[e]], a)) ++e;
             uint32_t sup = 0;
-            m = mul(embed(ops[s], n, r.reg_gpos, sup), m);
+            Mat16 emb = (e - s == 1) ? embed(a, n, r.reg_gpos, sup)
+                                     : embed(local_product(ops, r.src, s, e), n, r.reg_gpos, sup);
+            m = first ? emb : mul(emb, m);
+            first = false;
+            s = e;
         }
+        if (first)
+            for (int e = 0; e < 16; ++e) m[e * 16 + e] = 1.0;
         // the new coefficients must fit the form chosen for the template's
         std::vector<cd> data;
         if (r.kind == KOP_DIAG) {

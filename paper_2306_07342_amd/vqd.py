@@ -29,6 +29,7 @@ BLOCK_SUPEROP = 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
+_fp = ctypes.POINTER(ctypes.c_float)
 
 
 class VQDError(RuntimeError):
@@ -110,6 +111,16 @@ def load(path: str = LIB_PATH):
         "vqd_batch_info_get": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
         "vqd_batch_add_template": ([vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip], ctypes.c_int),
         "vqd_batch_add_instances": ([vp, ctypes.c_int, ctypes.c_int, _dp, _ip], ctypes.c_int),
+        "vqd_mlp_create": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "vqd_mlp_destroy": ([vp], ctypes.c_int),
+        "vqd_mlp_n_params": ([], ctypes.c_int),
+        "vqd_mlp_set_state": ([vp, ctypes.c_int, _fp], ctypes.c_int),
+        "vqd_mlp_get_state": ([vp, ctypes.c_int, _fp], ctypes.c_int),
+        "vqd_mlp_set_step": ([vp, ctypes.c_longlong], ctypes.c_int),
+        "vqd_mlp_get_step": ([vp], ctypes.c_longlong),
+        "vqd_mlp_grad": ([vp, vp, vp, vp, ctypes.c_int, vp, vp], ctypes.c_int),
+        "vqd_mlp_train_step": ([vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp, vp], ctypes.c_int),
+        "vqd_mlp_predict": ([vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "vqd_template_export": ([ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, ctypes.POINTER(PlanOpts), vp,
                                  ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
@@ -537,3 +548,76 @@ class Batch:
         i = BatchInfo()
         check(lib().vqd_batch_info_get(self.handle, ctypes.byref(i)))
         return {f: getattr(i, f) for f, _ in BatchInfo._fields_}
+
+
+class Surrogate:
+    """Ensemble of MLPs (24 -> 256 -> 256 -> 256 -> 10, GELU) trained and run
+    by the library's bf16/FP32 kernels (see vqd_mlp_* in include/vqd.h).
+    Inputs and targets are device float32 tensors."""
+
+    PARAMS, ADAM_M, ADAM_V, GRAD = 0, 1, 2, 3
+
+    def __init__(self, members: int = 4, max_batch: int = 4096, params=None):
+        load()
+        h = ctypes.c_void_p()
+        check(lib().vqd_mlp_create(members, max_batch, ctypes.byref(h)))
+        self.handle = h
+        self.members = members
+        self.max_batch = max_batch
+        self.n_params = lib().vqd_mlp_n_params()
+        if params is not None:
+            self.set_state(self.PARAMS, params)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().vqd_mlp_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, which: int, values):
+        v = np.ascontiguousarray(values, dtype=np.float32).reshape(self.members, self.n_params)
+        check(lib().vqd_mlp_set_state(self.handle, which, v.ctypes.data_as(_fp)))
+
+    def get_state(self, which: int) -> np.ndarray:
+        v = np.empty((self.members, self.n_params), dtype=np.float32)
+        check(lib().vqd_mlp_get_state(self.handle, which, v.ctypes.data_as(_fp)))
+        return v
+
+    @property
+    def step(self) -> int:
+        return lib().vqd_mlp_get_step(self.handle)
+
+    @step.setter
+    def step(self, t: int):
+        check(lib().vqd_mlp_set_step(self.handle, int(t)))
+
+    @staticmethod
+    def _ptr(t, dtype=None):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    def grad(self, x, y, idx=None, B=None, loss=None, stream=None):
+        B = x.shape[0] if B is None and idx is None else (idx.shape[0] if B is None else B)
+        check(lib().vqd_mlp_grad(self.handle, self._ptr(x), self._ptr(y), self._ptr(idx), B, self._ptr(loss),
+                                 _stream_ptr(stream)))
+
+    def train_step(self, x, y, lr: float, idx=None, B=None, loss=None, stream=None):
+        B = x.shape[0] if B is None and idx is None else (idx.shape[0] if B is None else B)
+        check(lib().vqd_mlp_train_step(self.handle, self._ptr(x), self._ptr(y), self._ptr(idx), B, float(lr),
+                                       self._ptr(loss), _stream_ptr(stream)))
+
+    def predict(self, x, mean=None, spread=None, member_out=None, stream=None):
+        """Ensemble mean [B, 10] and spread [B] (device tensors)."""
+        import torch
+        B = x.shape[0]
+        if mean is None:
+            mean = torch.empty((B, 10), dtype=torch.float32, device=x.device)
+        if spread is None:
+            spread = torch.empty(B, dtype=torch.float32, device=x.device)
+        check(lib().vqd_mlp_predict(self.handle, self._ptr(x), B, self._ptr(mean), self._ptr(spread),
+                                    self._ptr(member_out), _stream_ptr(stream)))
+        return mean, spread

@@ -1,0 +1,221 @@
+"""The surrogate network's kernels against the FP64 oracle (oracle/mlp.py) on
+the same bf16-rounded weights, and its fallback to the emulator.
+
+Tolerances.  Both sides use identical bf16 operands; the GPU accumulates
+in FP32 and evaluates GELU in FP32.  Most elements therefore agree to FP32
+accuracy (the median tests), but where an FP32 pre-activation lies within
+FP32 error of a bf16 rounding midpoint the two sides round an activation (or
+a back-propagated gradient) to neighbouring bf16 values, one bf16 ulp
+(2^-8 relative) apart.  One such flip moves a downstream output by roughly
+|w| * 2^-8 * |a| ~ 1e-4; with a few flips per batch the bound on the largest
+difference is a few 1e-3 of the tensor's scale (the max tests)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from workloads.surrogate import c5_features, init_ensemble
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def t(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=dtype)
+
+
+def tensors_of(vec):
+    """Split a flat parameter vector into its eight tensors."""
+    out, off = [], 0
+    for i, o in zip(mlp.LAYERS[:-1], mlp.LAYERS[1:]):
+        out.append(vec[off:off + o * i])
+        off += o * i
+        out.append(vec[off:off + o])
+        off += o
+    return out
+
+
+@pytest.fixture(scope="module")
+def setup(gpu_lib):
+    params = init_ensemble(seed=77)
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0, 1, (200, 24)).astype(np.float32)
+    Y = rng.uniform(-1, 1, (200, 10)).astype(np.float32)
+    return params, X, Y
+
+
+def test_forward_members_mean_and_spread(gpu_lib, setup):
+    import torch
+    params, X, _ = setup
+    say("surrogate forward")
+    net = gpu_lib.Surrogate(members=4, max_batch=256, params=params)
+    x = t(X)
+    member = torch.empty((4, X.shape[0], 10), dtype=torch.float32, device="cuda")
+    mean, spread = net.predict(x, member_out=member)
+    got = member.cpu().numpy().astype(np.float64)
+    for m in range(4):
+        ref, _ = mlp.forward(params[m].astype(np.float64), X.astype(np.float64), mixed=True)
+        d = np.abs(got[m] - ref)
+        say("member", m, "max", d.max(), "median", np.median(d))
+        assert d.max() <= 3e-3 and np.median(d) <= 2e-5
+    rmean, rspread, _ = mlp.ensemble(params.astype(np.float64), X.astype(np.float64))
+    assert np.abs(mean.cpu().numpy() - rmean).max() <= 3e-3
+    assert np.abs(spread.cpu().numpy() - rspread).max() <= 3e-3
+    # the spread is computed from the member outputs the kernel itself produced
+    mem = got
+    sp = np.sqrt(((mem - mem.mean(0)) ** 2).mean(0)).max(1)
+    assert np.abs(spread.cpu().numpy() - sp).max() <= 1e-6
+
+
+@pytest.mark.parametrize("B", [200, 64, 1])
+def test_gradients_match_oracle(gpu_lib, setup, B):
+    import torch
+    params, X, Y = setup
+    say("surrogate gradients B=%d" % B)
+    net = gpu_lib.Surrogate(members=4, max_batch=256, params=params)
+    loss = torch.zeros(4, dtype=torch.float32, device="cuda")
+    net.grad(t(X[:B]), t(Y[:B]), loss=loss)
+    g = net.get_state(net.GRAD).astype(np.float64)
+    lg = loss.cpu().numpy()
+    for m in range(4):
+        rl, rg = mlp.loss_and_grad(params[m].astype(np.float64), X[:B].astype(np.float64),
+                                   Y[:B].astype(np.float64), mixed=True)
+        assert abs(lg[m] - rl) <= 1e-4 * rl, (m, lg[m], rl)
+        for k, (a, b) in enumerate(zip(tensors_of(g[m]), tensors_of(rg))):
+            scale = np.abs(b).max()
+            d = np.abs(a - b)
+            say("  member %d tensor %d scale %.3e max %.3e median %.3e" % (m, k, scale, d.max() / scale,
+                                                                          np.median(d) / scale))
+            assert d.max() <= 1e-2 * scale, (m, k)
+            assert np.median(d) <= 1e-4 * scale, (m, k)
+
+
+def test_gradients_with_row_indices(gpu_lib, setup):
+    """idx gathers the rows of x and y inside the kernel."""
+    params, X, Y = setup
+    net = gpu_lib.Surrogate(members=4, max_batch=256, params=params)
+    idx = np.random.default_rng(4).permutation(200)[:128].astype(np.int32)
+    net.grad(t(X), t(Y), idx=t(idx))
+    g1 = net.get_state(net.GRAD)
+    net.grad(t(X[idx]), t(Y[idx]))
+    g2 = net.get_state(net.GRAD)
+    assert np.array_equal(g1, g2)
+
+
+def test_adam_steps_match_oracle(gpu_lib, setup):
+    params, X, Y = setup
+    say("surrogate adam")
+    net = gpu_lib.Surrogate(members=4, max_batch=256, params=params)
+    theta = params.astype(np.float64)
+    m1 = np.zeros_like(theta)
+    m2 = np.zeros_like(theta)
+    for step, lr in ((1, 1e-3), (2, 5e-4)):
+        net.train_step(t(X), t(Y), lr)
+        g = net.get_state(net.GRAD).astype(np.float64)      # the gradient this step used
+        theta, m1, m2 = mlp.adam(theta, m1, m2, g, step, lr)
+        assert net.step == step
+        got = net.get_state(net.PARAMS).astype(np.float64)
+        assert np.abs(got - theta).max() <= 2e-6, step
+        assert np.abs(net.get_state(net.ADAM_M) - m1).max() <= 1e-6 * max(1e-12, np.abs(m1).max())
+        assert np.abs(net.get_state(net.ADAM_V) - m2).max() <= 1e-5 * max(1e-20, np.abs(m2).max())
+
+
+def test_state_round_trip_and_errors(gpu_lib, setup):
+    params, _, _ = setup
+    net = gpu_lib.Surrogate(members=4, max_batch=64, params=params)
+    assert np.array_equal(net.get_state(net.PARAMS), params)
+    bad = params.copy()
+    bad[1, 5] = np.nan
+    with pytest.raises(gpu_lib.VQDError):
+        net.set_state(net.PARAMS, bad)
+    with pytest.raises(gpu_lib.VQDError):
+        net.grad(t(np.zeros((65, 24), np.float32)), t(np.zeros((65, 10), np.float32)))
+
+
+def c5_setup(count, seed):
+    from workloads import c5_draw_samples, c5_params, c5_structure
+    st = c5_structure()
+    dev, ang = c5_draw_samples(count, seed=seed)
+    return st, c5_params(st, dev, ang), c5_features(dev, ang), dev, ang
+
+
+def test_template_emulator_and_fallback(gpu_lib):
+    """Exact values come from the batched emulator (checked against the
+    oracle); the fallback replaces exactly the samples whose spread exceeds
+    the threshold."""
+    import torch
+    from oracle.emulator import emulate
+    from paper_2306_07342_amd.surrogate import SurrogateModel, TemplateEmulator
+    from workloads import c5_ansatz_circuit
+    say("template emulator + fallback")
+    st, P, F, dev, ang = c5_setup(300, seed=31)
+    emu = TemplateEmulator(10, st, chunk=128)
+    Z = emu.run(P)
+    for j in (0, 129, 299):
+        ref = emulate(10, c5_ansatz_circuit(dev[j], ang[j])).expec_z()
+        assert np.abs(Z[j].cpu().numpy() - ref).max() <= 1e-10
+    model = SurrogateModel(init_ensemble(seed=5), max_batch=512)
+    x = t(F)
+    mean, spread = model.predict(x)
+    spread = spread.cpu().numpy()
+    exact = Z.float()
+
+    def fb(idx):
+        return exact[torch.as_tensor(idx, device="cuda")]
+
+    for thr in (0.0, float(np.median(spread)), np.inf):
+        val, fell = model.predict_with_fallback(x, fb, threshold=thr)
+        fell = fell.cpu().numpy()
+        assert np.array_equal(fell, spread > thr)
+        v = val.cpu().numpy()
+        assert np.array_equal(v[fell], exact.cpu().numpy()[fell])
+        assert np.array_equal(v[~fell], mean.cpu().numpy()[~fell])
+
+
+def test_training_reduces_loss(gpu_lib):
+    """A smooth regression target: the kernels' training loop must fit it."""
+    import torch
+    from paper_2306_07342_amd.surrogate import SurrogateModel
+    rng = np.random.default_rng(8)
+    X = rng.uniform(0, 1, (16384, 24)).astype(np.float32)
+    Y = (0.5 * np.sin(2 * np.pi * X[:, :10]) * np.cos(np.pi * X[:, 10:20])).astype(np.float32)
+    model = SurrogateModel(init_ensemble(seed=12), max_batch=1024)
+    model.fit(t(X), t(Y), epochs=20, batch=512, lr=2e-3)
+    first, last = model.history[0], model.history[-1]
+    say("loss", first, "->", last)
+    assert np.all(last < 0.1 * first)
+
+
+def test_surrogate_gain_on_device_parameter_sweep(gpu_lib):
+    """The gain test: a device-parameter sweep of the 10-qubit ansatz at
+    fixed circuit angles (the device sweeps of Sec. 3).  After training on
+    emulator data, the surrogate with fallback answers more samples per
+    second within |dZ| < 1e-2 than the emulator alone, which judges it."""
+    import torch
+    from paper_2306_07342_amd.surrogate import SurrogateModel, TemplateEmulator, measure_gain
+    from workloads import c5_draw_samples, c5_params, c5_structure
+    st = c5_structure()
+    emu = TemplateEmulator(10, st, chunk=8192)
+
+    def data(count, seed):
+        dev, ang = c5_draw_samples(count, seed=seed)
+        ang[:] = c5_draw_samples(1, seed=99)[1][0]
+        return c5_params(st, dev, ang), t(c5_features(dev, ang))
+
+    say("gain: generating training data")
+    P, x = data(16384, 41)
+    y = emu.run(P).float().contiguous()
+    model = SurrogateModel(init_ensemble(seed=13), max_batch=1024)
+    say("gain: training")
+    model.fit(x, y, epochs=120, batch=512, lr=1e-3)
+    Pt, xt = data(4096, 42)
+    res = measure_gain(model, emu, Pt, xt, threshold=5e-3, tol=1e-2)
+    say("gain:", res)
+    assert res["gain_at_tol"] > 1.0
+    assert res["accepted_within_tol_fraction"] >= 0.9
