@@ -183,10 +183,10 @@ def test_training_reduces_loss(gpu_lib):
     import torch
     from paper_2306_07342_amd.surrogate import SurrogateModel
     rng = np.random.default_rng(8)
-    X = rng.uniform(0, 1, (16384, 24)).astype(np.float32)
+    X = rng.uniform(0, 1, (32768, 24)).astype(np.float32)
     Y = (0.5 * np.sin(2 * np.pi * X[:, :10]) * np.cos(np.pi * X[:, 10:20])).astype(np.float32)
     model = SurrogateModel(init_ensemble(seed=12), max_batch=1024)
-    model.fit(t(X), t(Y), epochs=20, batch=512, lr=2e-3)
+    model.fit(t(X), t(Y), epochs=40, batch=512, lr=2e-3)
     first, last = model.history[0], model.history[-1]
     say("loss", first, "->", last)
     assert np.all(last < 0.1 * first)
