@@ -165,7 +165,7 @@ __device__ __forceinline__ void apply_diag(double2 (&a)[16], const double2 *__re
 
 // Per-phase, per-thread context of the op loop.
 struct Ctx {
-    uint64_t gb;        // global index bits of the tile (workgroup-uniform)
+    uint32_t gb;        // global index bits of the tile (workgroup-uniform)
     uint32_t tl;        // local index bits from the thread id
     uint32_t rl[4];     // local bit of register bit b
 };
@@ -177,7 +177,7 @@ __device__ __forceinline__ uint32_t slot_l(const uint32_t (&rl)[4], int e)
 
 // Table index of a runtime diagonal: gathered bit j comes from the tile's
 // group bits (uniform) or from local index bits of `loc`.
-__device__ __forceinline__ uint32_t rt_index(const KOp *__restrict__ op, uint32_t nb, uint64_t gb,
+__device__ __forceinline__ uint32_t rt_index(const KOp *__restrict__ op, uint32_t nb, uint32_t gb,
                                              uint32_t loc)
 {
     uint32_t r = 0;
@@ -185,7 +185,7 @@ __device__ __forceinline__ uint32_t rt_index(const KOp *__restrict__ op, uint32_
     for (int j = 0; j < 4; ++j) {
         if ((uint32_t)j < nb) {
             const uint32_t lp = uni(op->lpos[j]);
-            if (lp == kNotLocal) r |= (uint32_t)((gb >> uni(op->gpos[j])) & 1u) << j;
+            if (lp == kNotLocal) r |= ((gb >> uni(op->gpos[j])) & 1u) << j;
             else r |= ((loc >> lp) & 1u) << j;
         }
     }
@@ -217,48 +217,55 @@ __device__ __forceinline__ void apply_diag_rt(double2 (&a)[16], const KOp *__res
     }
 }
 
-// Global bits of tile t (workgroup-uniform).
-__device__ __forceinline__ uint64_t group_base(const KPass *__restrict__ P, uint64_t t, uint32_t ngb,
+// Global bits of tile t (workgroup-uniform).  Amplitude indices fit in 32
+// bits (2n <= 32); 32-bit index arithmetic keeps the per-slot offsets that
+// stay live across the tile loop in half as many scalar registers.
+__device__ __forceinline__ uint32_t group_base(const KPass *__restrict__ P, uint32_t t, uint32_t ngb,
                                                bool xcd)
 {
     if (xcd) {
         // workgroup b runs on XCD b % 8: the tiles that differ in the lowest
         // group bits (and share cache lines) are given to one XCD
-        const uint64_t x = t & 7u, s = t >> 3;
+        const uint32_t x = t & 7u, s = t >> 3;
         t = (s & 7u) | (x << 3) | ((s >> 3) << 6);
     }
-    uint64_t g = 0;
-    for (uint32_t i = 0; i < ngb; ++i) g |= ((t >> i) & 1ull) << uni(P->group_gpos[i]);
+    uint32_t g = 0;
+    for (uint32_t i = 0; i < ngb; ++i) g |= ((t >> i) & 1u) << uni(P->group_gpos[i]);
     return g;
 }
 
 // Local and global index bits contributed by the thread id in phase H.
 __device__ __forceinline__ void thread_bits(const KPhase *__restrict__ H, uint32_t tid, uint32_t nthr,
-                                            uint32_t &tl, uint64_t &tg)
+                                            uint32_t &tl, uint32_t &tg)
 {
     tl = 0;
     tg = 0;
     for (uint32_t i = 0; i < nthr; ++i) {
         const uint32_t b = (tid >> i) & 1u;
         tl |= b << uni(H->thr_local[i]);
-        tg |= (uint64_t)b << uni(H->thr_gpos[i]);
+        tg |= b << uni(H->thr_gpos[i]);
     }
 }
 
+// Fully unrolled over the fixed maximum so that the descriptor reads are
+// scalar loads: a vector load here would make the compiler wait for the
+// outstanding prefetch of the next tile.
 __device__ __forceinline__ uint32_t thread_local_bits(const KPhase *__restrict__ H, uint32_t tid,
                                                       uint32_t nthr)
 {
     uint32_t tl = 0;
-    for (uint32_t i = 0; i < nthr; ++i) tl |= ((tid >> i) & 1u) << uni(H->thr_local[i]);
+#pragma unroll
+    for (uint32_t i = 0; i < (uint32_t)kMaxThreadBits; ++i)
+        if (i < nthr) tl |= ((tid >> i) & 1u) << uni(H->thr_local[i]);
     return tl;
 }
 
-__device__ __forceinline__ uint64_t slot_g(const KPhase *__restrict__ H, int e)
+__device__ __forceinline__ uint32_t slot_g(const KPhase *__restrict__ H, int e)
 {
-    uint64_t g = 0;
+    uint32_t g = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-        if (e >> b & 1) g |= 1ull << uni(H->reg_gpos[b]);
+        if (e >> b & 1) g |= 1u << uni(H->reg_gpos[b]);
     return g;
 }
 
@@ -331,7 +338,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     const uint32_t nthr = L - 4;
     const uint32_t ngb = uni(P->n_group_bits);
     const bool xcd = uni(P->xcd_swizzle) != 0;
-    const uint64_t n_tiles = P->n_tiles;
+    const uint32_t n_tiles = (uint32_t)P->n_tiles;     // < 2^28
     const uint32_t tid = threadIdx.x;
     const uint32_t pb = uni(P->phase_begin), pe = uni(P->phase_end);
     const KPhase *H0 = phases + pb, *HL = phases + pe - 1;
@@ -347,39 +354,60 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
 
     // thread parts of the load (first phase) and store (last phase) addresses
     uint32_t tl0, tlL;
-    uint64_t tg0, tgL;
+    uint32_t tg0, tgL;
     thread_bits(H0, tid, nthr, tl0, tg0);
     thread_bits(HL, tid, nthr, tlL, tgL);
     const double2 *ld_lane = amps + tg0;
     double2 *st_lane = amps + tgL;
 
-    uint64_t t = blockIdx.x;
+    uint32_t t = blockIdx.x;
     double2 nxt[16];
     if (t < n_tiles) {
-        const uint64_t gb = group_base(P, t, ngb, xcd);
+        const uint32_t gb = group_base(P, t, ngb, xcd);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const uint64_t u = gb | slot_g(H0, e);
+            const uint32_t u = gb | slot_g(H0, e);
             nxt[e] = (PHANTOM && ((u | tg0) >> kPhantomPos)) ? make_double2(0.0, 0.0) : ld_lane[u];
         }
     }
 
+    // Software pipeline, per tile t: wait for t's prefetched data, issue
+    // the stores of the previous tile, issue the prefetch of the next tile,
+    // then compute t.  The wait comes before the stores because the memory
+    // counter retires in order: waiting for loads issued before fresh stores
+    // would wait for those stores too.
+    double2 a[16];
+    uint32_t gb_prev = 0;
+    bool have_prev = false;
     for (; t < n_tiles; t += gridDim.x) {
-        double2 a[16];
+        // vmcnt(0), other counters untouched (gfx9 encoding): the tile's
+        // prefetch and the stores issued a whole tile ago; also keeps the
+        // compiler from hoisting the stores below above this point
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        double2 cur[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) a[e] = nxt[e];
-        const uint64_t gb = group_base(P, t, ngb, xcd);
+        for (int e = 0; e < 16; ++e) cur[e] = nxt[e];
+        if (have_prev) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t u = gb_prev | slot_g(HL, e);
+                if (!(PHANTOM && ((u | tgL) >> kPhantomPos))) st_lane[u] = a[e];
+            }
+        }
+        const uint32_t gb = group_base(P, t, ngb, xcd);
         {
             // prefetch the next tile (the last iteration re-reads its own
             // tile, which keeps the loads unconditional)
-            const uint64_t t2 = (t + gridDim.x < n_tiles) ? t + gridDim.x : t;
-            const uint64_t gb2 = group_base(P, t2, ngb, xcd);
+            const uint32_t t2 = (t + gridDim.x < n_tiles) ? t + gridDim.x : t;
+            const uint32_t gb2 = group_base(P, t2, ngb, xcd);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const uint64_t u = gb2 | slot_g(H0, e);
+                const uint32_t u = gb2 | slot_g(H0, e);
                 nxt[e] = (PHANTOM && ((u | tg0) >> kPhantomPos)) ? make_double2(0.0, 0.0) : ld_lane[u];
             }
         }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a[e] = cur[e];
 
         for (uint32_t ph = pb; ph < pe; ++ph) {
             const KPhase *H = phases + ph;
@@ -405,13 +433,19 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
                     *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
                                                  (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
                 __syncthreads();
-            } else {
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const uint64_t u = gb | slot_g(HL, e);
-                    if (!(PHANTOM && ((u | tgL) >> kPhantomPos))) st_lane[u] = a[e];
-                }
             }
+        }
+        // the stores stay outside the phase loop: a loop holding global
+        // stores but no loads makes the compiler wait for every outstanding
+        // load (the prefetch) before entering it
+        gb_prev = gb;
+        have_prev = true;
+    }
+    if (have_prev) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t u = gb_prev | slot_g(HL, e);
+            if (!(PHANTOM && ((u | tgL) >> kPhantomPos))) st_lane[u] = a[e];
         }
     }
 }
@@ -579,55 +613,82 @@ k_pauli(const double2 *__restrict__ amps, int n, uint64_t xmask, uint64_t zmask,
 }
 
 // ------------------------------------------------------------- batched --
-// One tile of a pass for the batched kernel: load, register phases with LDS
-// exchanges, store.  Threads at or above 2^(L-4) hold no amplitudes but take
-// part in every barrier.
-__device__ __forceinline__ void batch_tile(double2 *__restrict__ amps, const KPass *__restrict__ P,
+// All tiles of one pass of one instance, software-pipelined as in k_pass:
+// wait for the prefetched tile, store the previous one, prefetch the next,
+// compute.  Inactive threads (tiles below 12 bits) only join the barriers.
+__device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPass *__restrict__ P,
                                            const KPhase *__restrict__ phases,
                                            const KOp *__restrict__ ops,
                                            const double2 *__restrict__ mats, double2 *lds,
-                                           const double2 *lds_rt, uint64_t t, uint32_t tid,
-                                           uint32_t nthr, bool active)
+                                           const double2 *lds_rt, uint32_t tid, uint32_t nthr, bool active)
 {
     const uint32_t pb = uni(P->phase_begin), pe = uni(P->phase_end);
-    const uint64_t gb = group_base(P, t, uni(P->n_group_bits), false);
-    double2 a[16];
-    for (uint32_t ph = pb; ph < pe; ++ph) {
-        const KPhase *H = phases + ph;
-        Ctx c;
-        c.gb = gb;
+    const KPhase *H0 = phases + pb, *HL = phases + pe - 1;
+    const uint32_t ngb = uni(P->n_group_bits);
+    const uint32_t n_tiles = (uint32_t)P->n_tiles;
+    uint32_t tl0, tlL;
+    uint32_t tg0, tgL;
+    thread_bits(H0, active ? tid : 0u, nthr, tl0, tg0);
+    thread_bits(HL, active ? tid : 0u, nthr, tlL, tgL);
+    const double2 *ld_lane = amps + tg0;
+    double2 *st_lane = amps + tgL;
+    double2 nxt[16], a[16];
+    if (active) {
+        const uint32_t gb = group_base(P, 0, ngb, false);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) c.rl[b] = 1u << uni(H->reg_local[b]);
-        uint64_t tg = 0;
-        thread_bits(H, active ? tid : 0u, nthr, c.tl, tg);
-        const uint32_t lds_thr = swz(c.tl) << 4;
-        if (ph == pb) {
-            if (active) {
+        for (int e = 0; e < 16; ++e) nxt[e] = ld_lane[gb | slot_g(H0, e)];
+    }
+    uint32_t gb_prev = 0;
+    for (uint32_t t = 0; t < n_tiles; ++t) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0) only (gfx9 encoding)
+        double2 cur[16];
 #pragma unroll
-                for (int e = 0; e < 16; ++e) a[e] = amps[gb | tg | slot_g(H, e)];
+        for (int e = 0; e < 16; ++e) cur[e] = nxt[e];
+        const uint32_t gb = group_base(P, t, ngb, false);
+        if (active) {
+            if (t > 0) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) st_lane[gb_prev | slot_g(HL, e)] = a[e];
             }
-        } else {
-            if (active) {
+            const uint32_t gb2 = group_base(P, (t + 1 < n_tiles) ? t + 1 : t, ngb, false);
 #pragma unroll
-                for (int e = 0; e < 16; ++e)
-                    a[e] = *reinterpret_cast<const double2 *>(
-                        reinterpret_cast<const char *>(lds) + (lds_thr ^ (swz(slot_l(c.rl, e)) << 4)));
-            }
-            __syncthreads();
+            for (int e = 0; e < 16; ++e) nxt[e] = ld_lane[gb2 | slot_g(H0, e)];
         }
-        if (active) apply_ops(a, H, ops, mats, lds_rt, c);
-        if (ph + 1 < pe) {
-            if (active) {
 #pragma unroll
-                for (int e = 0; e < 16; ++e)
-                    *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
-                                                 (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
+        for (int e = 0; e < 16; ++e) a[e] = cur[e];
+        for (uint32_t ph = pb; ph < pe; ++ph) {
+            const KPhase *H = phases + ph;
+            Ctx c;
+            c.gb = gb;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) c.rl[b] = 1u << uni(H->reg_local[b]);
+            c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL : thread_local_bits(H, active ? tid : 0u, nthr);
+            const uint32_t lds_thr = swz(c.tl) << 4;
+            if (ph != pb) {
+                if (active) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e)
+                        a[e] = *reinterpret_cast<const double2 *>(
+                            reinterpret_cast<const char *>(lds) + (lds_thr ^ (swz(slot_l(c.rl, e)) << 4)));
+                }
+                __syncthreads();
             }
-            __syncthreads();
-        } else if (active) {
+            if (active) apply_ops(a, H, ops, mats, lds_rt, c);
+            if (ph + 1 < pe) {
+                if (active) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) amps[gb | tg | slot_g(H, e)] = a[e];
+                    for (int e = 0; e < 16; ++e)
+                        *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
+                                                     (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
+                }
+                __syncthreads();
+            }
         }
+        gb_prev = gb;
+    }
+    if (active && n_tiles > 0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) st_lane[gb_prev | slot_g(HL, e)] = a[e];
     }
 }
 
@@ -682,9 +743,7 @@ k_batch(double2 *__restrict__ arena, const BatchItem *__restrict__ items, uint32
                 for (uint32_t i = tid; i < rt_count; i += blockDim.x) lds_rt[i] = src[i];
                 __syncthreads();
             }
-            const uint64_t n_tiles = P->n_tiles;
-            for (uint64_t t = 0; t < n_tiles; ++t)
-                batch_tile(amps, P, phases, ops, M, lds, lds_rt, t, tid, nthr, active);
+            batch_pass(amps, P, phases, ops, M, lds, lds_rt, tid, nthr, active);
             wg_global_sync();
         }
         // <Z_q> = sum_r (-1)^{r_q} Re rho[r][r]

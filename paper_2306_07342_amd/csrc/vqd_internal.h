@@ -39,7 +39,7 @@ constexpr int kMaxTileBits = 13;
 constexpr int kMaxThreadBits = kMaxTileBits - 4;
 constexpr int kRegBits = 4;
 constexpr int kSlots = 16;
-constexpr uint32_t kPhantomPos = 62;   // global position of a bit beyond 2n
+constexpr uint32_t kPhantomPos = 30;   // global position of a bit beyond 2n (only n = 1 has any)
 constexpr uint32_t kNotLocal = 0xffu;  // KOp::lpos of a group (non-tile) bit
 
 enum KOpKind : uint32_t {
