@@ -307,6 +307,27 @@ Mat16 embed(const LOp &op, int n, const int *reg_gpos, uint32_t &support)
 
 }  // namespace
 
+void rt_table(uint32_t mode, int ubits, const std::vector<RtPart> &parts, const std::vector<LOp> &ops,
+              std::vector<cd> &table)
+{
+    if (mode == RT_GENERIC) {            // one op, every index bit gathered in its own order
+        table = ops[parts[0].src].D;
+        return;
+    }
+    const int shift = (mode == RT_NONE) ? 0 : 2;
+    table.assign(size_t(1) << (shift + ubits), cd(1));
+    for (const RtPart &pt : parts) {
+        const std::vector<cd> &D = ops[pt.src].D;
+        for (int t = 0; t < (1 << ubits); ++t)
+            for (int c = 0; c < (1 << shift); ++c) {
+                int idx = 0;
+                for (size_t k = 0; k < pt.rtj.size(); ++k) idx |= ((t >> pt.upos[k]) & 1) << pt.rtj[k];
+                if (pt.mode != RT_NONE) idx |= ((c & 1) << pt.row_j) | (((c >> 1) & 1) << pt.col_j);
+                table[size_t(c) + (size_t(t) << shift)] *= D[idx];
+            }
+    }
+}
+
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out)
 {
     out = HostPlan{};
@@ -435,78 +456,134 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 H.thr_gpos[t] = (uint32_t)tb[tl_order[t]];
             }
             H.op_begin = (uint32_t)out.ops.size();
-            for (const Block &bk : blocks) {
+            // Runtime diagonals: a run of consecutive ones (all diagonal, so
+            // they commute) is regrouped by register pair and each group is
+            // tabulated as one op over the union of its gathered bits.
+            auto rt_part = [&](int op_index) {
+                const LOp &op = ops[op_index];
+                const int nb = 2 * op.k;
+                RtPart pt;
+                pt.src = op_index;
+                int sb[4];
+                for (int j = 0; j < nb; ++j) {
+                    pt.g[j] = (j < op.k) ? op.q[j] : op.q[j - op.k] + n;
+                    sb[j] = -1;
+                    for (int b = 0; b < 4; ++b)
+                        if (reg_gpos[b] == pt.g[j]) sb[j] = b;
+                }
+                pt.nb = nb;
+                std::vector<int> regj;
+                for (int j = 0; j < nb; ++j) (sb[j] >= 0 ? regj : pt.rtj).push_back(j);
+                pt.mode = RT_GENERIC;
+                if (regj.empty()) {
+                    pt.mode = RT_NONE;
+                } else if (regj.size() == 2) {
+                    for (int j : regj) {
+                        if (sb[j] == 0 || sb[j] == 1) pt.row_j = j;
+                        if (sb[j] == 2 || sb[j] == 3) pt.col_j = j;
+                    }
+                    if (pt.row_j >= 0 && pt.col_j >= 0 && sb[pt.col_j] == sb[pt.row_j] + 2)
+                        pt.mode = sb[pt.row_j] == 0 ? RT_PAIR_A : RT_PAIR_B;
+                }
+                if (pt.mode == RT_GENERIC) {
+                    pt.rtj.clear();
+                    for (int j = 0; j < nb; ++j) pt.rtj.push_back(j);
+                    pt.row_j = pt.col_j = -1;
+                }
+                return pt;
+            };
+            auto emit_rt = [&](uint32_t mode, std::vector<RtPart> parts) {
                 KOp ko{};
+                ko.kind = KOP_DIAG_RT;
+                ko.mode = mode;
+                std::vector<int> ubits;                  // union of gathered global bits
+                for (RtPart &pt : parts) {
+                    pt.upos.clear();
+                    for (int j : pt.rtj) {
+                        const int gg = pt.g[j];
+                        auto it = std::find(ubits.begin(), ubits.end(), gg);
+                        if (it == ubits.end()) {
+                            pt.upos.push_back((int)ubits.size());
+                            ubits.push_back(gg);
+                        } else {
+                            pt.upos.push_back((int)(it - ubits.begin()));
+                        }
+                    }
+                }
+                ko.nbits = (uint32_t)ubits.size();
+                for (size_t j = 0; j < ubits.size(); ++j) {
+                    ko.gpos[j] = (uint32_t)ubits[j];
+                    const int l = local_of(ubits[j]);
+                    ko.lpos[j] = (l >= 0) ? (uint32_t)l : kNotLocal;
+                }
+                std::vector<cd> table;
+                rt_table(mode, (int)ubits.size(), parts, ops, table);
+                ko.real = all_real(table) ? 1u : 0u;
+                ko.mat = (uint32_t)rt_tables.size();
+                rt_tables.insert(rt_tables.end(), table.begin(), table.end());
+                out.fma_per_amp += ko.real ? 2.0 : 4.0;
+                if (opt.record_recipes) {
+                    Recipe r;
+                    r.rt = true;
+                    for (const RtPart &pt : parts) r.src.push_back(pt.src);
+                    r.kind = KOP_DIAG_RT;
+                    r.real = ko.real != 0;
+                    r.mode = mode;
+                    r.rt_union = (int)ubits.size();
+                    r.rt_parts = parts;
+                    r.mat_off = ko.mat;      // made absolute when the pass closes
+                    out.recipes.push_back(r);
+                }
+                out.ops.push_back(ko);
+            };
+            for (size_t bi = 0; bi < blocks.size();) {
+                const Block &bk = blocks[bi];
                 if (bk.rt) {
-                    const LOp &op = ops[bk.op_index];
-                    const int nb = 2 * op.k;
-                    int g[4], sb[4];     // global position and register slot bit of index bit j
-                    for (int j = 0; j < nb; ++j) {
-                        g[j] = (j < op.k) ? op.q[j] : op.q[j - op.k] + n;
-                        sb[j] = -1;
-                        for (int b = 0; b < 4; ++b)
-                            if (reg_gpos[b] == g[j]) sb[j] = b;
+                    size_t be = bi;
+                    while (be < blocks.size() && blocks[be].rt) ++be;
+                    std::vector<RtPart> groups[3];     // pair A, pair B, none
+                    for (size_t k = bi; k < be; ++k) {
+                        RtPart pt = rt_part(blocks[k].op_index);
+                        if (pt.mode == RT_GENERIC) emit_rt(RT_GENERIC, {pt});
+                        else groups[pt.mode == RT_PAIR_A ? 0 : pt.mode == RT_PAIR_B ? 1 : 2].push_back(pt);
                     }
-                    // which index bits come from register slots
-                    std::vector<int> regj, rtj;
-                    for (int j = 0; j < nb; ++j) (sb[j] >= 0 ? regj : rtj).push_back(j);
-                    std::vector<cd> table;
-                    ko.kind = KOP_DIAG_RT;
-                    uint32_t mode = RT_GENERIC;
-                    int row_j = -1, col_j = -1;
-                    if (regj.empty()) {
-                        mode = RT_NONE;
-                    } else if (regj.size() == 2) {
-                        for (int j : regj) {
-                            if (sb[j] == 0 || sb[j] == 1) row_j = j;
-                            if (sb[j] == 2 || sb[j] == 3) col_j = j;
+                    // index-only factors join a pair group when there is one
+                    const int host = !groups[0].empty() ? 0 : !groups[1].empty() ? 1 : 2;
+                    if (host != 2) {
+                        groups[host].insert(groups[host].end(), groups[2].begin(), groups[2].end());
+                        groups[2].clear();
+                    }
+                    const uint32_t gmode[3] = {RT_PAIR_A, RT_PAIR_B, RT_NONE};
+                    for (int gi = 0; gi < 3; ++gi) {
+                        std::vector<RtPart> chunk;
+                        std::vector<int> cu;
+                        for (const RtPart &pt : groups[gi]) {
+                            std::vector<int> u2 = cu;
+                            for (int j : pt.rtj)
+                                if (std::find(u2.begin(), u2.end(), pt.g[j]) == u2.end()) u2.push_back(pt.g[j]);
+                            if (!chunk.empty() && ((int)u2.size() > kMaxRtBits || !opt.merge_rt)) {
+                                emit_rt(gmode[gi], chunk);
+                                chunk.clear();
+                                cu.clear();
+                                for (int j : pt.rtj) cu.push_back(pt.g[j]);
+                            } else {
+                                cu = u2;
+                            }
+                            chunk.push_back(pt);
                         }
-                        if (row_j >= 0 && col_j >= 0 && sb[col_j] == sb[row_j] + 2)
-                            mode = sb[row_j] == 0 ? RT_PAIR_A : RT_PAIR_B;
+                        if (!chunk.empty()) emit_rt(gmode[gi], chunk);
                     }
-                    ko.mode = mode;
-                    if (mode == RT_GENERIC) {
-                        ko.nbits = (uint32_t)nb;
-                        for (int j = 0; j < nb; ++j) ko.gpos[j] = (uint32_t)g[j];
-                        table = op.D;
-                    } else {
-                        ko.nbits = (uint32_t)rtj.size();
-                        for (size_t t = 0; t < rtj.size(); ++t) ko.gpos[t] = (uint32_t)g[rtj[t]];
-                        const int shift = (mode == RT_NONE) ? 0 : 2;
-                        table.assign(size_t(1) << (shift + rtj.size()), cd(0));
-                        for (int idx = 0; idx < (1 << nb); ++idx) {
-                            int t = 0;
-                            for (size_t r = 0; r < rtj.size(); ++r) t |= ((idx >> rtj[r]) & 1) << r;
-                            int c = 0;
-                            if (mode != RT_NONE) c = ((idx >> row_j) & 1) | (((idx >> col_j) & 1) << 1);
-                            table[size_t(c) + (size_t(t) << shift)] = op.D[idx];
-                        }
-                    }
-                    for (uint32_t j = 0; j < ko.nbits; ++j) {
-                        const int l = local_of((int)ko.gpos[j]);
-                        ko.lpos[j] = (l >= 0) ? (uint32_t)l : kNotLocal;
-                    }
-                    ko.real = all_real(table) ? 1u : 0u;
-                    ko.mat = (uint32_t)rt_tables.size();
-                    rt_tables.insert(rt_tables.end(), table.begin(), table.end());
-                    out.fma_per_amp += ko.real ? 2.0 : 4.0;
-                    if (opt.record_recipes) {
-                        Recipe r;
-                        r.rt = true;
-                        r.src = {bk.op_index};
-                        r.kind = KOP_DIAG_RT;
-                        r.real = ko.real != 0;
-                        r.mode = mode;
-                        r.row_j = row_j;
-                        r.col_j = col_j;
-                        r.rtj = rtj;
-                        r.mat_off = ko.mat;      // made absolute when the pass closes
-                        out.recipes.push_back(r);
-                    }
-                } else {
+                    bi = be;
+                    continue;
+                }
+                KOp ko{};
+                {
                     Encoded enc = encode(bk.m);
                     if (enc.identity) {
-                        if (!opt.keep_identity) continue;
+                        if (!opt.keep_identity) {
+                            ++bi;
+                            continue;
+                        }
                         // a template keeps the slot: other parameters need not give 1
                         enc.kind = KOP_DIAG;
                         enc.mask = 15;
@@ -533,6 +610,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                     }
                 }
                 out.ops.push_back(ko);
+                ++bi;
             }
             H.op_end = (uint32_t)out.ops.size();
             out.phases.push_back(H);
@@ -801,23 +879,14 @@ int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std
         for (int s : r.src)
             if (s < 0 || s >= (int)ops.size()) return fail(VQD_E_ARG, "recipe refers to a missing op");
         if (r.rt) {
-            const LOp &op = ops[r.src[0]];
-            if (!op.diag) return fail(VQD_E_ARG, "op structure differs from the template (diagonal expected)");
-            const int nb = 2 * op.k;
-            if (r.real && !all_real(op.D))
+            for (const RtPart &pt : r.rt_parts)
+                if (!ops[pt.src].diag)
+                    return fail(VQD_E_ARG, "op structure differs from the template (diagonal expected)");
+            std::vector<cd> table;
+            rt_table(r.mode, r.rt_union, r.rt_parts, ops, table);
+            if (r.real && !all_real(table))
                 return fail(VQD_E_ARG, "op structure differs from the template (complex diagonal)");
-            if (r.mode == RT_GENERIC) {
-                for (int i = 0; i < (1 << nb); ++i) mats[r.mat_off + i] = op.D[i];
-            } else {
-                const int shift = (r.mode == RT_NONE) ? 0 : 2;
-                for (int idx = 0; idx < (1 << nb); ++idx) {
-                    int t = 0;
-                    for (size_t k = 0; k < r.rtj.size(); ++k) t |= ((idx >> r.rtj[k]) & 1) << k;
-                    int c = 0;
-                    if (r.mode != RT_NONE) c = ((idx >> r.row_j) & 1) | (((idx >> r.col_j) & 1) << 1);
-                    mats[r.mat_off + size_t(c) + (size_t(t) << shift)] = op.D[idx];
-                }
-            }
+            for (size_t i = 0; i < table.size(); ++i) mats[r.mat_off + i] = table[i];
             continue;
         }
         if (r.mode >= 100) return fail(VQD_E_ARG, "wide unitary blocks cannot be recomputed");

@@ -107,6 +107,19 @@ struct DevProgram {
 // How the coefficients of one kernel op were made from the logical ops, so
 // that they can be recomputed for other parameter values of the same op
 // kinds (parametric batch templates) without planning again.
+// One diagonal op's share of a runtime-diagonal table: which of its index
+// bits come from register slots (row_j, col_j in the pair modes) and which are
+// gathered (rtj, at union positions upos of the merged op's index).
+struct RtPart {
+    int src = -1;
+    int nb = 0;
+    int g[4] = {0, 0, 0, 0};      // global position of each op index bit
+    uint32_t mode = 0;
+    int row_j = -1, col_j = -1;
+    std::vector<int> rtj, upos;
+};
+constexpr int kMaxRtBits = 4;     // gathered bits of one runtime-diagonal op
+
 struct Recipe {
     bool rt = false;
     std::vector<int> src;       // logical ops multiplied into the block, application order
@@ -114,8 +127,8 @@ struct Recipe {
     uint32_t kind = 0, mask = 0;
     bool real = false;
     uint32_t mode = 0;          // runtime diagonal: index mode and bit mapping
-    int row_j = -1, col_j = -1;
-    std::vector<int> rtj;
+    int rt_union = 0;           // runtime diagonal: gathered bits and the ops multiplied in
+    std::vector<RtPart> rt_parts;
     size_t mat_off = 0;         // where the coefficients live in HostPlan::mats
 };
 
@@ -152,11 +165,15 @@ struct PlanOpts {
     bool pad_coalesce = true;
     bool record_recipes = false;    // fill HostPlan::recipes
     bool keep_identity = false;     // do not drop ops that are exactly the identity
+    bool merge_rt = true;           // tabulate runs of runtime diagonals together
 };
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out);
 // Recompute a recorded plan's coefficients for new logical ops of the same
 // structure (same kinds and targets).  mats gets the plan's layout.
 int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std::vector<cd> &mats);
+// Table of a (merged) runtime-diagonal op, layout as in RtMode.
+void rt_table(uint32_t mode, int ubits, const std::vector<RtPart> &parts, const std::vector<LOp> &ops,
+              std::vector<cd> &table);
 // Serialise a plan (layout of vqd_prog_export).
 int export_plan(const HostPlan &plan, int n, int tile_bits, void *buf, size_t cap, size_t *needed);
 // Parametric templates: validate, plan with canonical parameters, and compute
