@@ -73,10 +73,9 @@ __device__ __forceinline__ void cmac(double2 &y, const double2 m, const double2 
 // coefficient column feeds DIM * NG independent accumulators; the first
 // column initialises them.
 template <int MASK, bool REAL>
-__device__ __forceinline__ void apply_mat(double2 (&a)[16], const double2 *__restrict__ M)
+__device__ __forceinline__ void apply_mat(const double2 (&a)[16], double2 (&y)[16], const double2 *__restrict__ M)
 {
     constexpr int NB = popc4(MASK), DIM = 1 << NB, NG = 16 >> NB, REST = (~MASK) & 15;
-    double2 y[16];
 #pragma unroll
     for (int j = 0; j < DIM; ++j) {
         double2 col[DIM];
@@ -99,8 +98,6 @@ __device__ __forceinline__ void apply_mat(double2 (&a)[16], const double2 *__res
                 }
             }
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) a[e] = y[e];
 }
 
 // Flip-pattern matrix: y[i] = sum_x W[x][i] a[i ^ flip(x)], flip(x) flipping
@@ -113,11 +110,10 @@ __host__ __device__ constexpr int slot_flip(int x)
 }
 
 template <int MASK, bool REAL>
-__device__ __forceinline__ void apply_xor(double2 (&a)[16], const double2 *__restrict__ M)
+__device__ __forceinline__ void apply_xor(const double2 (&a)[16], double2 (&y)[16], const double2 *__restrict__ M)
 {
     constexpr int NB = popc4(MASK), DIM = 1 << NB, NG = 16 >> NB, REST = (~MASK) & 15;
     constexpr int NX = (MASK == 15) ? 4 : 2;
-    double2 y[16];
 #pragma unroll
     for (int x = 0; x < NX; ++x) {
         double2 w[DIM];
@@ -140,8 +136,6 @@ __device__ __forceinline__ void apply_xor(double2 (&a)[16], const double2 *__res
                 }
             }
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) a[e] = y[e];
 }
 
 __device__ __forceinline__ double2 cmul(const double2 m, const double2 x)
@@ -157,10 +151,10 @@ __device__ __forceinline__ double2 fmul(const double2 m, const double2 x)
 
 // Element-wise factors indexed by the register slot.
 template <bool REAL>
-__device__ __forceinline__ void apply_diag(double2 (&a)[16], const double2 *__restrict__ M)
+__device__ __forceinline__ void apply_diag(const double2 (&a)[16], double2 (&y)[16], const double2 *__restrict__ M)
 {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) a[e] = fmul<REAL>(coef<REAL>(M, e), a[e]);
+    for (int e = 0; e < 16; ++e) y[e] = fmul<REAL>(coef<REAL>(M, e), a[e]);
 }
 
 // Per-phase, per-thread context of the op loop.
@@ -194,14 +188,14 @@ __device__ __forceinline__ uint32_t rt_index(const KOp *__restrict__ op, uint32_
 
 // Element-wise factors from an LDS table indexed by global bits (see RtMode).
 template <uint32_t MODE, bool REAL>
-__device__ __forceinline__ void apply_diag_rt(double2 (&a)[16], const KOp *__restrict__ op,
+__device__ __forceinline__ void apply_diag_rt(const double2 (&a)[16], double2 (&y)[16], const KOp *__restrict__ op,
                                               const double2 *T, const Ctx &c)
 {
     const uint32_t nb = uni(op->nbits);
     if (MODE == RT_NONE) {
         const double2 f = T[rt_index(op, nb, c.gb, c.tl)];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) a[e] = fmul<REAL>(f, a[e]);
+        for (int e = 0; e < 16; ++e) y[e] = fmul<REAL>(f, a[e]);
     } else if (MODE == RT_PAIR_A || MODE == RT_PAIR_B) {
         constexpr int R = (MODE == RT_PAIR_A) ? 0 : 1;
         const uint32_t base = 4 * rt_index(op, nb, c.gb, c.tl);
@@ -209,11 +203,11 @@ __device__ __forceinline__ void apply_diag_rt(double2 (&a)[16], const KOp *__res
 #pragma unroll
         for (int k = 0; k < 4; ++k) f[k] = T[base + k];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) a[e] = fmul<REAL>(f[((e >> R) & 1) | (((e >> (R + 2)) & 1) << 1)], a[e]);
+        for (int e = 0; e < 16; ++e) y[e] = fmul<REAL>(f[((e >> R) & 1) | (((e >> (R + 2)) & 1) << 1)], a[e]);
     } else {
 #pragma unroll
         for (int e = 0; e < 16; ++e)
-            a[e] = fmul<REAL>(T[rt_index(op, nb, c.gb, c.tl | slot_l(c.rl, e))], a[e]);
+            y[e] = fmul<REAL>(T[rt_index(op, nb, c.gb, c.tl | slot_l(c.rl, e))], a[e]);
     }
 }
 
@@ -269,54 +263,67 @@ __device__ __forceinline__ uint32_t slot_g(const KPhase *__restrict__ H, int e)
     return g;
 }
 
+// One op: y = op(x).
+__device__ __forceinline__ void apply_op(const double2 (&x)[16], double2 (&y)[16], const KOp *__restrict__ op,
+                                         const double2 *__restrict__ mats, const double2 *lds_rt, const Ctx &c)
+{
+    const uint32_t kind = uni(op->kind);
+    const uint32_t sel = uni(op->opmask) | (uni(op->real) << 4);
+    const double2 *M = mats + uni(op->mat);
+    if (kind == KOP_MAT) {
+        switch (sel) {
+        case 5: apply_mat<5, false>(x, y, M); break;
+        case 10: apply_mat<10, false>(x, y, M); break;
+        case 15: apply_mat<15, false>(x, y, M); break;
+        case 7: apply_mat<7, false>(x, y, M); break;
+        case 16 | 5: apply_mat<5, true>(x, y, M); break;
+        case 16 | 10: apply_mat<10, true>(x, y, M); break;
+        case 16 | 15: apply_mat<15, true>(x, y, M); break;
+        default: apply_mat<7, true>(x, y, M); break;
+        }
+    } else if (kind == KOP_XOR) {
+        switch (sel) {
+        case 5: apply_xor<5, false>(x, y, M); break;
+        case 10: apply_xor<10, false>(x, y, M); break;
+        case 15: apply_xor<15, false>(x, y, M); break;
+        case 16 | 5: apply_xor<5, true>(x, y, M); break;
+        case 16 | 10: apply_xor<10, true>(x, y, M); break;
+        default: apply_xor<15, true>(x, y, M); break;
+        }
+    } else if (kind == KOP_DIAG) {
+        if (sel & 16) apply_diag<true>(x, y, M);
+        else apply_diag<false>(x, y, M);
+    } else {
+        const double2 *T = lds_rt + uni(op->mat);
+        switch (uni(op->mode) | (sel & 16)) {
+        case RT_NONE: apply_diag_rt<RT_NONE, false>(x, y, op, T, c); break;
+        case RT_PAIR_A: apply_diag_rt<RT_PAIR_A, false>(x, y, op, T, c); break;
+        case RT_PAIR_B: apply_diag_rt<RT_PAIR_B, false>(x, y, op, T, c); break;
+        case RT_GENERIC: apply_diag_rt<RT_GENERIC, false>(x, y, op, T, c); break;
+        case 16 | RT_NONE: apply_diag_rt<RT_NONE, true>(x, y, op, T, c); break;
+        case 16 | RT_PAIR_A: apply_diag_rt<RT_PAIR_A, true>(x, y, op, T, c); break;
+        case 16 | RT_PAIR_B: apply_diag_rt<RT_PAIR_B, true>(x, y, op, T, c); break;
+        default: apply_diag_rt<RT_GENERIC, true>(x, y, op, T, c); break;
+        }
+    }
+}
+
+// The phase's ops, two at a time between a and b so that no op copies its
+// results back into its input registers; an odd count ends with one copy.
 __device__ __forceinline__ void apply_ops(double2 (&a)[16], const KPhase *__restrict__ H,
                                           const KOp *__restrict__ ops,
                                           const double2 *__restrict__ mats, const double2 *lds_rt,
                                           const Ctx &c)
 {
     const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
-    for (uint32_t oi = ob; oi < oe; ++oi) {
-        const KOp *op = ops + oi;
-        const uint32_t kind = uni(op->kind);
-        const uint32_t sel = uni(op->opmask) | (uni(op->real) << 4);
-        const double2 *M = mats + uni(op->mat);
-        if (kind == KOP_MAT) {
-            switch (sel) {
-            case 5: apply_mat<5, false>(a, M); break;
-            case 10: apply_mat<10, false>(a, M); break;
-            case 15: apply_mat<15, false>(a, M); break;
-            case 7: apply_mat<7, false>(a, M); break;
-            case 16 | 5: apply_mat<5, true>(a, M); break;
-            case 16 | 10: apply_mat<10, true>(a, M); break;
-            case 16 | 15: apply_mat<15, true>(a, M); break;
-            case 16 | 7: apply_mat<7, true>(a, M); break;
-            default: break;
-            }
-        } else if (kind == KOP_XOR) {
-            switch (sel) {
-            case 5: apply_xor<5, false>(a, M); break;
-            case 10: apply_xor<10, false>(a, M); break;
-            case 15: apply_xor<15, false>(a, M); break;
-            case 16 | 5: apply_xor<5, true>(a, M); break;
-            case 16 | 10: apply_xor<10, true>(a, M); break;
-            case 16 | 15: apply_xor<15, true>(a, M); break;
-            default: break;
-            }
-        } else if (kind == KOP_DIAG) {
-            if (sel & 16) apply_diag<true>(a, M);
-            else apply_diag<false>(a, M);
+    double2 b[16];
+    for (uint32_t oi = ob; oi < oe; oi += 2) {
+        apply_op(a, b, ops + oi, mats, lds_rt, c);
+        if (oi + 1 < oe) {
+            apply_op(b, a, ops + oi + 1, mats, lds_rt, c);
         } else {
-            const double2 *T = lds_rt + uni(op->mat);
-            switch (uni(op->mode) | (sel & 16)) {
-            case RT_NONE: apply_diag_rt<RT_NONE, false>(a, op, T, c); break;
-            case RT_PAIR_A: apply_diag_rt<RT_PAIR_A, false>(a, op, T, c); break;
-            case RT_PAIR_B: apply_diag_rt<RT_PAIR_B, false>(a, op, T, c); break;
-            case RT_GENERIC: apply_diag_rt<RT_GENERIC, false>(a, op, T, c); break;
-            case 16 | RT_NONE: apply_diag_rt<RT_NONE, true>(a, op, T, c); break;
-            case 16 | RT_PAIR_A: apply_diag_rt<RT_PAIR_A, true>(a, op, T, c); break;
-            case 16 | RT_PAIR_B: apply_diag_rt<RT_PAIR_B, true>(a, op, T, c); break;
-            default: apply_diag_rt<RT_GENERIC, true>(a, op, T, c); break;
-            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) a[e] = b[e];
         }
     }
 }
