@@ -241,6 +241,12 @@ __device__ __forceinline__ void thread_bits(const KPhase *__restrict__ H, uint32
     }
 }
 
+// Thread id of this lane within the workgroup, from the wave's base.
+__device__ __forceinline__ uint32_t lane_tid(uint32_t wave_base)
+{
+    return wave_base + __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
 // Fully unrolled over the fixed maximum so that the descriptor reads are
 // scalar loads: a vector load here would make the compiler wait for the
 // outstanding prefetch of the next tile.
@@ -347,6 +353,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     const bool xcd = uni(P->xcd_swizzle) != 0;
     const uint32_t n_tiles = (uint32_t)P->n_tiles;     // < 2^28
     const uint32_t tid = threadIdx.x;
+    const uint32_t wave_base = uni(tid & ~63u);
     const uint32_t pb = uni(P->phase_begin), pe = uni(P->phase_end);
     const KPhase *H0 = phases + pb, *HL = phases + pe - 1;
 
@@ -422,7 +429,9 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
             c.gb = gb;
 #pragma unroll
             for (int b = 0; b < 4; ++b) c.rl[b] = 1u << uni(H->reg_local[b]);
-            c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL : thread_local_bits(H, tid, nthr);
+            // the thread id is rebuilt from the lane id (mbcnt) and the
+            // wave's uniform base rather than kept live in a register
+            c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL : thread_local_bits(H, lane_tid(wave_base), nthr);
             // LDS byte address of slot e: swizzle is xor-linear, so it splits
             // into a per-thread part and a uniform per-slot part
             const uint32_t lds_thr = swz(c.tl) << 4;
@@ -639,12 +648,16 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
     thread_bits(HL, active ? tid : 0u, nthr, tlL, tgL);
     const double2 *ld_lane = amps + tg0;
     double2 *st_lane = amps + tgL;
+    // loads are unconditional (inactive threads read thread 0's addresses
+    // and ignore the data): a conditional load would need register copies
+    // right after it, which wait for the load
     double2 nxt[16], a[16];
-    if (active) {
+    {
         const uint32_t gb = group_base(P, 0, ngb, false);
 #pragma unroll
         for (int e = 0; e < 16; ++e) nxt[e] = ld_lane[gb | slot_g(H0, e)];
     }
+    const uint32_t wave_base = uni(tid & ~63u);
     uint32_t gb_prev = 0;
     for (uint32_t t = 0; t < n_tiles; ++t) {
         __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0) only (gfx9 encoding)
@@ -652,11 +665,11 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
 #pragma unroll
         for (int e = 0; e < 16; ++e) cur[e] = nxt[e];
         const uint32_t gb = group_base(P, t, ngb, false);
-        if (active) {
-            if (t > 0) {
+        if (active && t > 0) {
 #pragma unroll
-                for (int e = 0; e < 16; ++e) st_lane[gb_prev | slot_g(HL, e)] = a[e];
-            }
+            for (int e = 0; e < 16; ++e) st_lane[gb_prev | slot_g(HL, e)] = a[e];
+        }
+        {
             const uint32_t gb2 = group_base(P, (t + 1 < n_tiles) ? t + 1 : t, ngb, false);
 #pragma unroll
             for (int e = 0; e < 16; ++e) nxt[e] = ld_lane[gb2 | slot_g(H0, e)];
@@ -669,7 +682,8 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
             c.gb = gb;
 #pragma unroll
             for (int b = 0; b < 4; ++b) c.rl[b] = 1u << uni(H->reg_local[b]);
-            c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL : thread_local_bits(H, active ? tid : 0u, nthr);
+            c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL
+                 : thread_local_bits(H, active ? lane_tid(wave_base) : 0u, nthr);
             const uint32_t lds_thr = swz(c.tl) << 4;
             if (ph != pb) {
                 if (active) {
