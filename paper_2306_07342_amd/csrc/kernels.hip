@@ -171,17 +171,17 @@ __device__ __forceinline__ uint32_t slot_l(const uint32_t (&rl)[4], int e)
 
 // Table index of a runtime diagonal: gathered bit j comes from the tile's
 // group bits (uniform) or from local index bits of `loc`.
+// Branch-free over the four entries, so that the descriptor fields arrive in
+// one batch of scalar loads rather than one load-and-wait per bit.
 __device__ __forceinline__ uint32_t rt_index(const KOp *__restrict__ op, uint32_t nb, uint32_t gb,
                                              uint32_t loc)
 {
     uint32_t r = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        if ((uint32_t)j < nb) {
-            const uint32_t lp = uni(op->lpos[j]);
-            if (lp == kNotLocal) r |= ((gb >> uni(op->gpos[j])) & 1u) << j;
-            else r |= ((loc >> lp) & 1u) << j;
-        }
+        const uint32_t lp = uni(op->lpos[j]), gp = uni(op->gpos[j]);
+        const uint32_t b = (lp == kNotLocal) ? ((gb >> (gp & 31u)) & 1u) : ((loc >> (lp & 31u)) & 1u);
+        r |= (((uint32_t)j < nb) ? b : 0u) << j;
     }
     return r;
 }
@@ -229,15 +229,20 @@ __device__ __forceinline__ uint32_t group_base(const KPass *__restrict__ P, uint
 }
 
 // Local and global index bits contributed by the thread id in phase H.
+// Thread-id bits at or above nthr are zero (tid < 2^nthr) and the unused
+// descriptor entries are zero-filled, so the loops run over the fixed
+// maximum without branches.
 __device__ __forceinline__ void thread_bits(const KPhase *__restrict__ H, uint32_t tid, uint32_t nthr,
                                             uint32_t &tl, uint32_t &tg)
 {
+    (void)nthr;
     tl = 0;
     tg = 0;
-    for (uint32_t i = 0; i < nthr; ++i) {
+#pragma unroll
+    for (uint32_t i = 0; i < (uint32_t)kMaxThreadBits; ++i) {
         const uint32_t b = (tid >> i) & 1u;
-        tl |= b << uni(H->thr_local[i]);
-        tg |= b << uni(H->thr_gpos[i]);
+        tl |= b << (uni(H->thr_local[i]) & 31u);
+        tg |= b << (uni(H->thr_gpos[i]) & 31u);
     }
 }
 
@@ -253,10 +258,10 @@ __device__ __forceinline__ uint32_t lane_tid(uint32_t wave_base)
 __device__ __forceinline__ uint32_t thread_local_bits(const KPhase *__restrict__ H, uint32_t tid,
                                                       uint32_t nthr)
 {
+    (void)nthr;
     uint32_t tl = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < (uint32_t)kMaxThreadBits; ++i)
-        if (i < nthr) tl |= ((tid >> i) & 1u) << uni(H->thr_local[i]);
+    for (uint32_t i = 0; i < (uint32_t)kMaxThreadBits; ++i) tl |= ((tid >> i) & 1u) << (uni(H->thr_local[i]) & 31u);
     return tl;
 }
 

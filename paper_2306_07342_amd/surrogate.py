@@ -57,12 +57,15 @@ class TemplateEmulator:
             b.arena, b.out = self._arena, self._out
             b.compile(device=self.device)
             self._arena, self._out = b.arena, b.out
+            # freeing the previous chunk's plan synchronises the device: do it
+            # only now, after this chunk's host work, so that work overlapped
+            # the previous launch
+            if prev is not None:
+                prev.close()
             b.run()
             outs = np.fromiter((b.offsets(i)[1] for i in idx), dtype=np.int64, count=hi - lo)
             sel = torch.as_tensor(outs, device=self.device)[:, None] + torch.arange(self.n, device=self.device)
             res[lo:hi] = self._out[sel]
-            if prev is not None:
-                prev.close()
             prev = b
         if prev is not None:
             prev.close()
