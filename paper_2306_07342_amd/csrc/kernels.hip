@@ -634,9 +634,51 @@ k_pauli(const double2 *__restrict__ amps, int n, uint64_t xmask, uint64_t zmask,
 }
 
 // ------------------------------------------------------------- batched --
-// All tiles of one pass of one instance, software-pipelined as in k_pass:
-// wait for the prefetched tile, store the previous one, prefetch the next,
-// compute.  Inactive threads (tiles below 12 bits) only join the barriers.
+// The register phases of one tile of the batched kernel (data in a).
+__device__ __forceinline__ void batch_phases(double2 (&a)[16], const KPhase *__restrict__ phases,
+                                             const KOp *__restrict__ ops, const double2 *__restrict__ mats,
+                                             double2 *lds, const double2 *lds_rt, uint32_t pb, uint32_t pe,
+                                             uint32_t gb, uint32_t tl0, uint32_t tlL, uint32_t wave_base,
+                                             uint32_t nthr, bool active)
+{
+    for (uint32_t ph = pb; ph < pe; ++ph) {
+        const KPhase *H = phases + ph;
+        Ctx c;
+        c.gb = gb;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c.rl[b] = 1u << uni(H->reg_local[b]);
+        c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL
+             : thread_local_bits(H, active ? lane_tid(wave_base) : 0u, nthr);
+        const uint32_t lds_thr = swz(c.tl) << 4;
+        if (ph != pb) {
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    a[e] = *reinterpret_cast<const double2 *>(
+                        reinterpret_cast<const char *>(lds) + (lds_thr ^ (swz(slot_l(c.rl, e)) << 4)));
+            }
+            __syncthreads();
+        }
+        if (active) apply_ops(a, H, ops, mats, lds_rt, c);
+        if (ph + 1 < pe) {
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
+                                                 (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// All tiles of one pass of one instance, software-pipelined: while tile t is
+// computed in one register buffer, tile t+1 is loaded into the other (the
+// loop is unrolled by two so that no loaded buffer is copied, which would
+// wait for the load).  Per step: wait for the loads, issue the stores of the
+// previous tile from the other buffer, prefetch into it, compute.  Loads are
+// unconditional (inactive threads read thread 0's addresses and ignore the
+// data); stores are not.
 __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPass *__restrict__ P,
                                            const KPhase *__restrict__ phases,
                                            const KOp *__restrict__ ops,
@@ -653,68 +695,53 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
     thread_bits(HL, active ? tid : 0u, nthr, tlL, tgL);
     const double2 *ld_lane = amps + tg0;
     double2 *st_lane = amps + tgL;
-    // loads are unconditional (inactive threads read thread 0's addresses
-    // and ignore the data): a conditional load would need register copies
-    // right after it, which wait for the load
-    double2 nxt[16], a[16];
+    const uint32_t wave_base = uni(tid & ~63u);
+    double2 A[16], B[16];
     {
         const uint32_t gb = group_base(P, 0, ngb, false);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) nxt[e] = ld_lane[gb | slot_g(H0, e)];
+        for (int e = 0; e < 16; ++e) A[e] = ld_lane[gb | slot_g(H0, e)];
     }
-    const uint32_t wave_base = uni(tid & ~63u);
-    uint32_t gb_prev = 0;
-    for (uint32_t t = 0; t < n_tiles; ++t) {
+    for (uint32_t t = 0; t < n_tiles; t += 2) {
+        // tile t in A; the previous tile's results are in B
         __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0) only (gfx9 encoding)
-        double2 cur[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) cur[e] = nxt[e];
         const uint32_t gb = group_base(P, t, ngb, false);
         if (active && t > 0) {
+            const uint32_t gbp = group_base(P, t - 1, ngb, false);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) st_lane[gb_prev | slot_g(HL, e)] = a[e];
+            for (int e = 0; e < 16; ++e) st_lane[gbp | slot_g(HL, e)] = B[e];
         }
         {
             const uint32_t gb2 = group_base(P, (t + 1 < n_tiles) ? t + 1 : t, ngb, false);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) nxt[e] = ld_lane[gb2 | slot_g(H0, e)];
+            for (int e = 0; e < 16; ++e) B[e] = ld_lane[gb2 | slot_g(H0, e)];
         }
+        batch_phases(A, phases, ops, mats, lds, lds_rt, pb, pe, gb, tl0, tlL, wave_base, nthr, active);
+        if (t + 1 >= n_tiles) break;
+        // tile t + 1 in B; tile t's results in A
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        const uint32_t gb1 = group_base(P, t + 1, ngb, false);
+        if (active) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) a[e] = cur[e];
-        for (uint32_t ph = pb; ph < pe; ++ph) {
-            const KPhase *H = phases + ph;
-            Ctx c;
-            c.gb = gb;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) c.rl[b] = 1u << uni(H->reg_local[b]);
-            c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL
-                 : thread_local_bits(H, active ? lane_tid(wave_base) : 0u, nthr);
-            const uint32_t lds_thr = swz(c.tl) << 4;
-            if (ph != pb) {
-                if (active) {
-#pragma unroll
-                    for (int e = 0; e < 16; ++e)
-                        a[e] = *reinterpret_cast<const double2 *>(
-                            reinterpret_cast<const char *>(lds) + (lds_thr ^ (swz(slot_l(c.rl, e)) << 4)));
-                }
-                __syncthreads();
-            }
-            if (active) apply_ops(a, H, ops, mats, lds_rt, c);
-            if (ph + 1 < pe) {
-                if (active) {
-#pragma unroll
-                    for (int e = 0; e < 16; ++e)
-                        *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
-                                                     (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
-                }
-                __syncthreads();
-            }
+            for (int e = 0; e < 16; ++e) st_lane[gb | slot_g(HL, e)] = A[e];
         }
-        gb_prev = gb;
+        {
+            const uint32_t gb2 = group_base(P, (t + 2 < n_tiles) ? t + 2 : t + 1, ngb, false);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) A[e] = ld_lane[gb2 | slot_g(H0, e)];
+        }
+        batch_phases(B, phases, ops, mats, lds, lds_rt, pb, pe, gb1, tl0, tlL, wave_base, nthr, active);
     }
+    // the last tile's results: in A when n_tiles is odd, else in B
     if (active && n_tiles > 0) {
+        const uint32_t gbl = group_base(P, n_tiles - 1, ngb, false);
+        if (n_tiles & 1u) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) st_lane[gb_prev | slot_g(HL, e)] = a[e];
+            for (int e = 0; e < 16; ++e) st_lane[gbl | slot_g(HL, e)] = A[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) st_lane[gbl | slot_g(HL, e)] = B[e];
+        }
     }
 }
 
