@@ -87,6 +87,7 @@ def cpu_baseline(ops, n, sample_every):
 
 
 BATCH_TUNE_FILE = os.path.join(ROOT, "paper_2306_07342_amd", "tune", "batch_tiles.json")
+C5_TUNE_FILE = os.path.join(ROOT, "paper_2306_07342_amd", "tune", "c5_template_tiles.json")
 
 
 def batched_leg(vqd, torch, steps):
@@ -172,6 +173,10 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
     from workloads.surrogate import c5_features, init_ensemble
     st = c5_structure()
     emu = TemplateEmulator(10, st)
+    # tile shape of the ansatz template from the batched autotuner (cached)
+    tuned = os.path.exists(C5_TUNE_FILE)
+    d0, a0 = c5_draw_samples(1024, seed=SEED_BASE + 10)
+    emu.autotune(c5_params(st, d0, a0), C5_TUNE_FILE if tuned else os.path.join("/tmp", "vqd_c5_tiles.json"))
 
     def data(count, seed, fixed_angles=None):
         dev, ang = c5_draw_samples(count, seed=seed)
@@ -203,6 +208,8 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
     out = {"metric": "surrogate vs emulator evals/s at |dZ|<1e-2 (10-qubit 4-layer ansatz)",
            "config": "8 device parameters + 16 angles drawn uniformly, 4 x MLP 24-256-256-256-10 GELU, "
                      "bf16 operands / FP32 accumulate, fallback when spread > 5e-3"}
+    out["template_tiles"] = {"tile_bits": emu.opts.tile_bits, "min_contig_bits": emu.opts.min_contig_bits,
+                             "source": "autotuned (%s)" % ("cached" if tuned else "fresh")}
     out["uniform_angles"] = run(n_train, n_test, epochs, (SEED_BASE + 4, SEED_BASE + 6))
     fixed = c5_draw_samples(1, seed=SEED_BASE + 7)[1][0]
     out["device_sweep_fixed_angles"] = run(max(4096, n_train // 8), max(1024, n_test // 4), 4 * epochs,

@@ -71,6 +71,22 @@ class TemplateEmulator:
             prev.close()
         return res
 
+    def autotune(self, params: np.ndarray, cache_path: str, sample: int = 1024):
+        """Pick the template's tile shape with the batched autotuner (timed
+        on ``sample`` instances, result cached in ``cache_path``)."""
+        P = np.ascontiguousarray(params[:sample], dtype=np.float64)
+        b = vqd.Batch()
+        tid = b.add_template(self.n, self.structure)
+        b.add_instances(tid, P)
+        b.compile(device=self.device)
+        b.autotune(cache_path, max_per_n=sample)
+        o = b.plan_opts(self.n)
+        self.opts = vqd.plan_opts(tile_bits=o["tile_bits"], min_contig_bits=o["min_contig_bits"],
+                                  max_ops_per_pass=o["max_ops_per_pass"], fuse_blocks=bool(o["fuse_blocks"]),
+                                  pad_coalesce=bool(o["pad_coalesce"]))
+        b.close()
+        return o
+
     def release(self):
         self._arena = None
         self._out = None

@@ -63,6 +63,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libvqd.so is not built (%s); run `python -m paper_2306_07342_amd.build`" % path)
+    # PyTorch (which provides device memory and streams) must bring up the GPU
+    # before the library's HIP runtime does: loading the library registers
+    # its kernels, and a device first opened by that runtime cannot then be
+    # initialised by PyTorch's
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
     L = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     sig = {
