@@ -200,6 +200,14 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
         log("surrogate: %d epochs in %.1f s, loss %s" % (ep, t_train, model.history[-1]))
         Pt, xt = data(n_te, seeds[1], fixed)
         res = measure_gain(model, emu, Pt, xt, threshold=5e-3, tol=1e-2)
+        # the emulator as judge: calibrate the spread threshold on a held-out
+        # validation set so that accepted answers stay within |dZ| < 1e-2
+        Pv, xv = data(max(1024, n_te // 4), seeds[2], fixed)
+        thr = model.calibrate(xv, emu.run(Pv), tol=1e-2)
+        cal = measure_gain(model, emu, Pt, xt, threshold=thr, tol=1e-2)
+        res["calibrated"] = {k: cal[k] for k in ("threshold", "surrogate_evals_per_s", "surrogate_good_evals_per_s",
+                                                  "gain_at_tol", "fallback_fraction", "accepted_within_tol_fraction",
+                                                  "max_abs_dz_accepted")}
         res.update({"train_samples": n_tr, "data_gen_s": round(t_data, 2),
                     "data_gen_evals_per_s": round(n_tr / t_data, 1), "epochs": ep, "batch": 512,
                     "train_s": round(t_train, 2), "final_train_mse": [float(v) for v in model.history[-1]]})
@@ -210,10 +218,10 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
                      "bf16 operands / FP32 accumulate, fallback when spread > 5e-3"}
     out["template_tiles"] = {"tile_bits": emu.opts.tile_bits, "min_contig_bits": emu.opts.min_contig_bits,
                              "source": "autotuned (%s)" % ("cached" if tuned else "fresh")}
-    out["uniform_angles"] = run(n_train, n_test, epochs, (SEED_BASE + 4, SEED_BASE + 6))
+    out["uniform_angles"] = run(n_train, n_test, epochs, (SEED_BASE + 4, SEED_BASE + 6, SEED_BASE + 11))
     fixed = c5_draw_samples(1, seed=SEED_BASE + 7)[1][0]
     out["device_sweep_fixed_angles"] = run(max(4096, n_train // 8), max(1024, n_test // 4), 4 * epochs,
-                                           (SEED_BASE + 8, SEED_BASE + 9), fixed)
+                                           (SEED_BASE + 8, SEED_BASE + 9, SEED_BASE + 12), fixed)
     emu.release()
     return out
 

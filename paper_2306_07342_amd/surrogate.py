@@ -130,6 +130,28 @@ class SurrogateModel:
     def predict(self, x):
         return self.net.predict(x)
 
+    def calibrate(self, x, exact, tol: float = 1e-2, quantile: float = 1.0) -> float:
+        """The largest spread threshold under which the accepted samples of a
+        held-out set (inputs x, exact values from the emulator, the judge)
+        stay within max_i |dZ_i| < tol; with quantile < 1 that fraction of
+        them must.  Returns 0 when even the lowest-spread sample misses."""
+        import torch
+        mean, spread = self.net.predict(x)
+        err = (mean.double() - exact).abs().max(dim=1).values.cpu().numpy()
+        sp = spread.cpu().numpy()
+        order = np.argsort(sp, kind="stable")
+        bad = err[order] >= tol
+        # accepted set {spread <= thr} grows along `order`; keep the longest
+        # prefix whose miss fraction stays within 1 - quantile
+        misses = np.cumsum(bad)
+        ok = misses <= (1.0 - quantile) * np.arange(1, len(order) + 1)
+        if not ok[0]:
+            return 0.0
+        last = int(np.nonzero(~ok)[0][0]) - 1 if (~ok).any() else len(order) - 1
+        thr = float(sp[order[last]])
+        # thresholds are compared with "spread > thr" for fallback
+        return thr
+
     def predict_with_fallback(self, x, fallback: Callable[[np.ndarray], "object"], threshold: float = 5e-3):
         """Ensemble mean where the spread is at most ``threshold``; elsewhere
         ``fallback(indices)`` (exact values, device [k, 10]) is used.  Returns

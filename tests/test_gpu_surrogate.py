@@ -219,3 +219,29 @@ def test_surrogate_gain_on_device_parameter_sweep(gpu_lib):
     say("gain:", res)
     assert res["gain_at_tol"] > 1.0
     assert res["accepted_within_tol_fraction"] >= 0.9
+
+
+def test_calibrated_threshold_keeps_accepted_answers_within_tolerance(gpu_lib):
+    """The judge sets the fallback threshold: on the validation set the
+    accepted answers meet the tolerance, and every lower-spread sample is
+    accepted too."""
+    import torch
+    from paper_2306_07342_amd.surrogate import SurrogateModel
+    rng = np.random.default_rng(21)
+    X = rng.uniform(0, 1, (4096, 24)).astype(np.float32)
+    Y = (0.5 * np.sin(2 * np.pi * X[:, :10]) * np.cos(np.pi * X[:, 10:20])).astype(np.float32)
+    model = SurrogateModel(init_ensemble(seed=14), max_batch=1024)
+    model.fit(t(X), t(Y), epochs=5, batch=512, lr=2e-3)
+    exact = t(Y).double()
+    thr = model.calibrate(t(X), exact, tol=1e-2)
+    mean, spread = model.predict(t(X))
+    err = (mean.double() - exact).abs().max(dim=1).values.cpu().numpy()
+    sp = spread.cpu().numpy()
+    acc = sp <= thr
+    say("calibrated threshold", thr, "accepted", acc.mean())
+    assert np.all(err[acc] < 1e-2)
+    # a threshold just above would accept a miss (or accept nothing more)
+    nxt = sp[sp > thr]
+    if nxt.size:
+        first = np.argmin(nxt)
+        assert err[sp > thr][first] >= 1e-2
