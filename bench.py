@@ -243,8 +243,8 @@ def main():
                          "(known size) for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(how it would shard is documented with the design); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,7 +1,7 @@
 """GPU parity: every C-ABI call of libvqd against the CPU oracle.
 
 Tolerance: 1e-10 max-abs per amplitude (real and imaginary parts) and per
-observable, the bar the spec requirement fixes for FP64.  States are
+observable, the FP64 bar of the emulator.  States are
 normalised (trace 1 or, for random non-trace-preserving maps, entries of
 order one), so the absolute bar is meaningful.
 """

@@ -222,7 +222,7 @@ def test_surrogate_gain_on_device_parameter_sweep(gpu_lib):
 
 
 def test_calibrated_threshold_keeps_accepted_answers_within_tolerance(gpu_lib):
-    """The judge sets the fallback threshold: on the validation set the
+    """The emulator, as judge, sets the fallback threshold: on the validation set the
     accepted answers meet the tolerance, and every lower-spread sample is
     accepted too."""
     import torch
