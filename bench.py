@@ -160,6 +160,50 @@ def batched_leg(vqd, torch, steps):
             "tiles": "autotuned (%s)" % ("cached" if tuned else "fresh")}
 
 
+def c3_leg(vqd, torch, steps: int):
+    """Context beside the 14-qubit metric: the seeded 16-qubit all-to-all
+    circuit (500 XX/Ry/Rz gates with depol2 and dephasing) on a 64 GiB
+    density matrix, one warm-up and `steps` timed steps."""
+    from workloads import c3_all_to_all_circuit
+    n = 16
+    ops = c3_all_to_all_circuit(n=n, n_gates=500)
+    n_gates = sum(1 for k, _, _ in ops if k in ("xx", "ry", "rz"))
+    prog = vqd.Program(n, ops).compile(vqd.plan_opts(**PLAN_OPTS))
+    info = prog.info()
+    dm = vqd.DensityMatrix(n)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        dm.init_zero()
+        prog.run(dm)
+        return dm.expec_z(), dm.purity()
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        z, pur = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    amps = 4 ** n
+    t_pass = e0.elapsed_time(e1) / 1e3 / steps       # includes init and read-outs
+    gbs = 32.0 * amps * info["n_passes"] / t_pass / 1e9
+    tf = 2.0 * info["fma_per_amp"] * amps / t_pass / 1e12
+    out = {"workload": "16-qubit density matrix (complex128, 4^16 amps, 68.7 GB), all-to-all circuit, "
+                       "500 XX/Ry/Rz gates with depol2(1e-2) and deph(1e-3)",
+           "dm_ops_per_s": round(len(ops) / wall, 1), "gates_per_s": round(n_gates / wall, 1),
+           "ms_per_step": round(wall * 1e3, 2), "dm_ops": len(ops), "passes": info["n_passes"],
+           "hbm_gbs_of_passes": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "fp64_tflops": round(tf, 2), "alu_frac": round(tf / FP64_PEAK_TFLOPS, 4),
+           "check": {"purity": float(pur), "z0": float(z[0])}}
+    del dm
+    torch.cuda.empty_cache()
+    return out
+
+
 def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
     """The learned surrogate of the 10-qubit, 4-layer ansatz (8 device
     parameters + 16 angles -> 10 <Z_i>): training data from the batched
@@ -235,6 +279,7 @@ def main():
     ap.add_argument("--cpu-sample-every", type=int, default=782)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-emulation leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-16q", action="store_true", help="skip the 16-qubit context leg")
     ap.add_argument("--surrogate-train", type=int, default=1 << 18, help="training samples (2^18)")
     ap.add_argument("--surrogate-test", type=int, default=1 << 14, help="held-out samples (2^14)")
     ap.add_argument("--surrogate-epochs", type=int, default=30)
@@ -337,6 +382,11 @@ def main():
     if not args.no_batched:
         log("batched leg ...")
         out["batched"] = batched_leg(vqd, torch, args.steps)
+    if not args.no_16q and torch.cuda.get_device_properties(0).total_memory > 100 * 2 ** 30:
+        log("16-qubit leg ...")
+        del dm
+        torch.cuda.empty_cache()
+        out["c3_16q"] = c3_leg(vqd, torch, 1)
     if not args.no_surrogate:
         log("surrogate leg ...")
         out["surrogate"] = surrogate_leg(vqd, torch, args.surrogate_train, args.surrogate_test,
