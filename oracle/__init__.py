@@ -10,6 +10,8 @@ import it.
   Kraus maps from ``(kind, params)``, written from the paper's definitions.
 * :mod:`oracle.emulator` -- runs an op stream and computes the read-outs.
 * :mod:`oracle.mlp`      -- FP64 reference of the surrogate network.
+* :mod:`oracle.trajectories` -- Monte Carlo state-vector trajectories (one
+  Kraus operator drawn per channel per sample), in numpy.
 
 Parity status of each function is stated in its docstring; a function without
 an independent pin says "parity unpinned".
