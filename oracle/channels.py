@@ -85,13 +85,14 @@ def depol1(p):
 
 def depol2(p):
     """eq. (depol2): (1-p) rho + p/15 sum over the 15 non-identity two-qubit
-    Pauli products sigma_i sigma'_j."""
-    Ks = []
-    for a in range(4):
-        for b in range(4):
-            w = (1 - p) if (a == 0 and b == 0) else p / 15
-            Ks.append(math.sqrt(w) * on2(PAULIS[a], PAULIS[b]))
-    return Ks
+    Pauli products.  The operators follow the order in which the equation
+    writes its terms (which fixes which operator a trajectory's uniform
+    draws): the identity, sigma_i for sigma = X, Y, Z, then sigma_j, then
+    sigma_i sigma'_j with sigma the outer index."""
+    terms = ([(0, 0)] + [(a, 0) for a in (1, 2, 3)] + [(0, b) for b in (1, 2, 3)]
+             + [(a, b) for a in (1, 2, 3) for b in (1, 2, 3)])
+    return [math.sqrt((1 - p) if (a, b) == (0, 0) else p / 15) * on2(PAULIS[a], PAULIS[b])
+            for a, b in terms]
 
 
 def deph1(p):

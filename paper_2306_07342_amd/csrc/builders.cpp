@@ -69,11 +69,14 @@ int channel_kraus(int kind, const double *p, int &k, std::vector<std::vector<cd>
     case VQD_K_DEPOL2: {
         if (!need_prob(p[0], 1.0)) return fail(VQD_E_ARG, "depol2: p outside [0, 1]");
         k = 2;
-        for (int b = 0; b < 4; ++b)
-            for (int a = 0; a < 4; ++a) {
-                double w = (a == 0 && b == 0) ? 1 - p[0] : p[0] / 15;
-                Ks.push_back(scaled(kron2(pauli(a), pauli(b)), std::sqrt(w)));
-            }
+        // operators in the order of the equation's terms (a trajectory's draw
+        // depends on it): identity, sigma on the first target, sigma on the
+        // second, then the products with the first target's Pauli outer
+        Ks.push_back(scaled(kron2(pauli(0), pauli(0)), std::sqrt(1 - p[0])));
+        for (int a = 1; a < 4; ++a) Ks.push_back(scaled(kron2(pauli(a), pauli(0)), std::sqrt(p[0] / 15)));
+        for (int b = 1; b < 4; ++b) Ks.push_back(scaled(kron2(pauli(0), pauli(b)), std::sqrt(p[0] / 15)));
+        for (int a = 1; a < 4; ++a)
+            for (int b = 1; b < 4; ++b) Ks.push_back(scaled(kron2(pauli(a), pauli(b)), std::sqrt(p[0] / 15)));
         return VQD_OK;
     }
     case VQD_K_DEPH1: case VQD_K_DEPH_T2: {
@@ -240,6 +243,18 @@ int kind_matrix(int kind, const double *p, std::vector<cd> &U, int &k)
     }
     return VQD_OK;
 }
+
+int kind_kraus(int kind, const double *p, std::vector<std::vector<cd>> &Ks, int &k)
+{
+    int nq = 0, np = 0;
+    if (kind_arity(kind, &nq, &np) != 0 || !is_channel(kind))
+        return fail(VQD_E_ARG, "not a channel kind: " + std::to_string(kind));
+    for (int i = 0; i < np; ++i)
+        if (!std::isfinite(p[i])) return fail(VQD_E_ARG, "non-finite channel parameter");
+    return channel_kraus(kind, p, k, Ks);
+}
+
+bool kind_is_channel(int kind) { return is_channel(kind); }
 
 void unitary_to_superop(int k, const cd *U, std::vector<cd> &S)
 {
