@@ -348,6 +348,84 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
 
 /* ------------------------------------------------------------- surrogate */
 
+/* Monte Carlo trajectories on state vectors: the paper's alternative to the
+ * density matrix (Sec. 2, where QuESTlink replaces each channel by one
+ * operator drawn from its Kraus map and averages expected values over many
+ * sampled state vectors).  Memory per sample is 2^n amplitudes instead of 4^n.
+ *
+ * A trajectory program holds n qubits (1 <= n <= 13) and an ordered list of
+ * unitary gates and channels.  Each trajectory starts in |0...0> and, in op
+ * order, applies every gate as psi -> U psi and every channel {K_i} by
+ * drawing one operator: with the trajectory's next uniform variate u in
+ * [0, 1) and weights w_i = ||K_i psi||^2, the drawn index is the smallest i
+ * whose running sum w_0 + ... + w_i (left to right) exceeds u W, W the sum
+ * of all weights (the last positive weight if rounding leaves none), and the
+ * state becomes K_i psi / sqrt(w_i).  For a mixed-unitary channel (every
+ * K_i^dagger K_i = q_i I, as for the depolarising, dephasing and bit-flip
+ * maps of Sec. 3) the weights are the constants q_i.  The same uniform
+ * always gives the same draw, so runs are reproducible and comparable
+ * sample by sample; a draw can differ between two implementations only
+ * when u lies within rounding of an interval boundary.
+ *
+ * The whole state of a trajectory stays on the chip (registers and LDS of
+ * one workgroup); only the outputs go to memory.  Gates must be unitary
+ * (|U^dagger U - I| <= 1e-10, else VQD_E_ARG); channels may be any Kraus set
+ * of 1 to 16 operators on 1 or 2 qubits, trace preserving or not. */
+typedef struct vqd_traj vqd_traj;
+
+typedef struct vqd_traj_info {
+    int n;
+    int n_ops;            /* gates and channels added */
+    int n_channels;       /* uniforms one trajectory consumes */
+    int n_phases;         /* register layouts of the plan */
+    int n_kernel_ops;     /* ops after fusion */
+    int n_mixed;          /* channels drawn from constant weights */
+    int n_general;        /* channels whose weights come from the state */
+    double fma_per_amp;   /* planned FP64 FMA per amplitude per trajectory */
+} vqd_traj_info;
+
+int vqd_traj_create(int n, vqd_traj **out);
+int vqd_traj_destroy(vqd_traj *t);
+/* Same kinds, targets and parameters as vqd_prog_add_named (gates and
+ * channels of Sec. 3); named_many takes 4 targets and 4 parameters per op
+ * and adds all or nothing. */
+int vqd_traj_add_named(vqd_traj *t, int kind, const int *targets, const double *params);
+int vqd_traj_add_named_many(vqd_traj *t, int count, const int *kinds, const int *targets,
+                            const double *params);
+/* Host matrices as for vqd_prog_add_unitary / vqd_prog_add_kraus (row-major
+ * interleaved complex; k in [1, 4] for gates, [1, 2] for Kraus maps of
+ * nk in [1, 16] operators). */
+int vqd_traj_add_unitary(vqd_traj *t, int k, const int *targets, const double *u);
+int vqd_traj_add_kraus(vqd_traj *t, int k, const int *targets, int nk, const double *kraus);
+
+/* Plan the program and copy its descriptors to the current device (which
+ * later runs must use).  Ops added afterwards need another compile. */
+int vqd_traj_compile(vqd_traj *t);
+int vqd_traj_info_get(const vqd_traj *t, vqd_traj_info *out);
+
+/* Host-only planning (no device) and a copy of the planned descriptors:
+ * ten uint32 (magic 0x54445156, version 1, n, n_eff = max(n, 4), channels,
+ * phases, ops, pool entries, sizeof(TPhase), sizeof(TOp)), then the phases,
+ * the ops and the coefficient pool (complex doubles); layouts as in the
+ * library's internal header.  With buf = NULL only *needed is set. */
+int vqd_traj_plan(vqd_traj *t);
+int vqd_traj_export(const vqd_traj *t, void *buf, size_t cap, size_t *needed);
+
+/* Run `count` trajectories, asynchronously on hip_stream.  Device arrays:
+ *   uniforms   [count][n_channels] doubles in [0, 1), trajectory-major
+ *              (may be NULL when the program has no channel);
+ *   z_out      [count][n]   <Z_q> = sum_x |psi_x|^2 (1 - 2 x_q) of each final state;
+ *   norm_out   [count]      sum_x |psi_x|^2 (may be NULL);
+ *   state_out  [count][2^n] final states, interleaved complex (may be NULL).
+ * All are caller-owned.  count = 0 does nothing. */
+int vqd_traj_run(vqd_traj *t, const double *uniforms, long long count, double *z_out, double *norm_out,
+                 double *state_out, void *hip_stream);
+
+/* Mean over the rows of x ([count][m] device doubles) and its standard error
+ * sqrt(sum (x - mean)^2 / (count - 1)) / sqrt(count) (infinity for count = 1),
+ * into device arrays mean[m], sem[m]; asynchronous on hip_stream. */
+int vqd_traj_stats(const double *x, long long count, int m, double *mean, double *sem, void *hip_stream);
+
 /* Learned surrogate of the emulator: an ensemble of `members` MLPs mapping
  * 24 scaled inputs (8 device parameters and 16 angles of a hardware-efficient
  * ansatz, Sec. 2 and 3; the network itself is not in the paper) to the 10

@@ -24,8 +24,6 @@ int hip_fail(hipError_t e, const char *what)
     return fail(VQD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-namespace {
-
 std::vector<cd> read_complex(const double *p, size_t count)
 {
     std::vector<cd> v(count);
@@ -52,6 +50,8 @@ int check_targets(int n, int k, const int *t)
     }
     return VQD_OK;
 }
+
+namespace {
 
 int check_dm(const vqd_dm *dm)
 {

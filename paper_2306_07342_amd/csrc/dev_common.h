@@ -1,0 +1,109 @@
+// Device helpers shared by the gfx950 kernels of the vqd library: bit
+// deposit, LDS swizzle, uniform values, coefficient access and the dense
+// small-matrix application on the 16 register slots of a thread.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vqd_internal.h"
+
+namespace vqd {
+namespace {
+
+// Deposit the low bits of v into the set bits of mask (ascending order).
+__host__ __device__ constexpr int dep4(int v, int mask)
+{
+    int out = 0, k = 0;
+    for (int b = 0; b < 4; ++b)
+        if (mask >> b & 1) {
+            if (v >> k & 1) out |= 1 << b;
+            ++k;
+        }
+    return out;
+}
+
+__host__ __device__ constexpr int popc4(int m)
+{
+    return (m & 1) + (m >> 1 & 1) + (m >> 2 & 1) + (m >> 3 & 1);
+}
+
+// LDS index swizzle: xor the low 3 bits of the local index with a hash of
+// the higher bits so that strided register phases spread over the banks.
+__device__ __forceinline__ uint32_t swz(uint32_t l)
+{
+    return l ^ (((l >> 3) ^ (l >> 6) ^ (l >> 9)) & 7u);
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t x)
+{
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
+// Coefficient c of an op: complex entries as stored, real ones packed two
+// per pool entry.
+template <bool REAL>
+__device__ __forceinline__ double2 coef(const double2 *__restrict__ M, int c)
+{
+    if (REAL) {
+        const double2 p = M[c >> 1];
+        return make_double2((c & 1) ? p.y : p.x, 0.0);
+    }
+    return M[c];
+}
+
+template <bool REAL>
+__device__ __forceinline__ void cmac(double2 &y, const double2 m, const double2 x)
+{
+    y.x = fma(m.x, x.x, y.x);
+    y.y = fma(m.x, x.y, y.y);
+    if (!REAL) {
+        y.x = fma(-m.y, x.y, y.x);
+        y.y = fma(m.y, x.x, y.y);
+    }
+}
+
+// Dense matrix on the register bits in MASK (column-major coefficients), for
+// every setting of the other register bits.  Column-outer order: each
+// coefficient column feeds DIM * NG independent accumulators; the first
+// column initialises them.
+template <int MASK, bool REAL>
+__device__ __forceinline__ void apply_mat(const double2 (&a)[16], double2 (&y)[16], const double2 *__restrict__ M)
+{
+    constexpr int NB = popc4(MASK), DIM = 1 << NB, NG = 16 >> NB, REST = (~MASK) & 15;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+        double2 col[DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) col[i] = coef<REAL>(M, j * DIM + i);
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int so = dep4(i, MASK) | dep4(g, REST), si = dep4(j, MASK) | dep4(g, REST);
+                if (j == 0) {
+                    y[so].x = col[i].x * a[si].x;
+                    y[so].y = col[i].x * a[si].y;
+                    if (!REAL) {
+                        y[so].x = fma(-col[i].y, a[si].y, y[so].x);
+                        y[so].y = fma(col[i].y, a[si].x, y[so].y);
+                    }
+                } else {
+                    cmac<REAL>(y[so], col[i], a[si]);
+                }
+            }
+    }
+}
+
+__device__ __forceinline__ double2 cmul(const double2 m, const double2 x)
+{
+    return make_double2(fma(m.x, x.x, -m.y * x.y), fma(m.x, x.y, m.y * x.x));
+}
+
+// Local index bits of register slot e (rl[b] = local bit of register bit b).
+__device__ __forceinline__ uint32_t slot_l(const uint32_t (&rl)[4], int e)
+{
+    return ((e & 1) ? rl[0] : 0) | ((e & 2) ? rl[1] : 0) | ((e & 4) ? rl[2] : 0) | ((e & 8) ? rl[3] : 0);
+}
+
+}  // namespace
+}  // namespace vqd

@@ -1,0 +1,442 @@
+// gfx950 kernels of the Monte Carlo trajectory mode (state-vector samples,
+// one Kraus operator drawn per channel; the paper's Sec. 2 alternative to the
+// density matrix).
+//
+// * k_traj       -- a batch of trajectories.  A trajectory of n_eff qubits is
+//                   held by 2^(n_eff-4) threads, 16 register slots each, and
+//                   never leaves the chip: it starts as |0...0> in registers,
+//                   every phase applies its ops to the register slots and
+//                   moves the state through LDS to the next phase's layout,
+//                   and only <Z_q>, the squared norm and (optionally) the
+//                   final state are written to memory.  A channel's operator
+//                   is drawn from the trajectory's uniform variate; for a
+//                   general channel the weights ||K_i psi||^2 = Tr(K_i^dagger
+//                   K_i rho_T) come from the reduced density matrix rho_T of
+//                   the target qubits, summed over the trajectory's threads.
+// * k_traj_stats -- mean and standard error over trajectories.
+//
+// Every sum over threads has a fixed order, so results are deterministic and
+// all threads of a trajectory draw the same operator.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dev_common.h"
+#include "vqd_internal.h"
+
+namespace vqd {
+
+namespace {
+
+constexpr int kTrajRed = 16;          // values in one group reduction
+constexpr int kTrajMaxWaves = 8;      // waves of the largest workgroup (512 threads)
+
+struct TCtx {
+    uint32_t tl;      // amplitude-index bits from the thread id
+    uint32_t rl[4];   // amplitude-index bit of register bit b
+};
+
+// Amplitude-index bits of thread tt of a trajectory in phase H (thread bit i
+// carries qubit thr_q[i]; unused entries are zero and tt has no bit there).
+__device__ __forceinline__ uint32_t traj_thread_bits(const TPhase *__restrict__ H, uint32_t tt)
+{
+    uint32_t tl = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < (uint32_t)kTrajMaxThreadBits; ++i) tl |= ((tt >> i) & 1u) << (uni(H->thr_q[i]) & 31u);
+    return tl;
+}
+
+// Sum of v over the threads of one trajectory, bitwise identical in all of
+// them: a butterfly over the lane bits inside the wave (each pairwise sum is
+// formed from the same two operands on both lanes), then, when a trajectory
+// spans several waves, the per-wave sums added in wave order through LDS.
+template <int CNT, bool WIDE>
+__device__ __forceinline__ void group_sum(double (&v)[CNT], uint32_t log_tt, double *red, uint32_t wave,
+                                          uint32_t wpt)
+{
+    const uint32_t steps = WIDE ? 6u : log_tt;
+    for (uint32_t s = 0; s < steps; ++s) {
+#pragma unroll
+        for (int i = 0; i < CNT; ++i) v[i] += __shfl_xor(v[i], 1 << s);
+    }
+    if (WIDE && wpt > 1) {
+        if ((threadIdx.x & 63u) == 0) {
+#pragma unroll
+            for (int i = 0; i < CNT; ++i) red[wave * kTrajRed + i] = v[i];
+        }
+        __syncthreads();
+        const uint32_t w0 = wave & ~(wpt - 1u);
+#pragma unroll
+        for (int i = 0; i < CNT; ++i) {
+            double s = red[w0 * kTrajRed + i];
+            for (uint32_t w = 1; w < wpt; ++w) s += red[(w0 + w) * kTrajRed + i];
+            v[i] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// This thread's part of the reduced density matrix of the register bits in
+// MASK: rho_xy = sum over the other bits of psi_x conj(psi_y).  Packed as the
+// DIM real diagonal entries, then (re, im) of rho_xy for x < y in row order.
+template <int MASK>
+__device__ __forceinline__ void rho_partial(const double2 (&a)[16], double (&r)[kTrajRed])
+{
+    constexpr int NB = popc4(MASK), DIM = 1 << NB, NG = 16 >> NB, REST = (~MASK) & 15;
+#pragma unroll
+    for (int i = 0; i < kTrajRed; ++i) r[i] = 0.0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        int p = 0;
+#pragma unroll
+        for (int x = 0; x < DIM; ++x) {
+            const double2 ax = a[dep4(x, MASK) | dep4(g, REST)];
+            r[x] = fma(ax.x, ax.x, fma(ax.y, ax.y, r[x]));
+#pragma unroll
+            for (int y = x + 1; y < DIM; ++y, ++p) {
+                const double2 ay = a[dep4(y, MASK) | dep4(g, REST)];
+                r[DIM + 2 * p] = fma(ax.x, ay.x, fma(ax.y, ay.y, r[DIM + 2 * p]));
+                r[DIM + 2 * p + 1] = fma(ax.y, ay.x, fma(-ax.x, ay.y, r[DIM + 2 * p + 1]));
+            }
+        }
+    }
+}
+
+// Tr(G rho) for Hermitian G (row-major) and rho packed as by rho_partial:
+// sum_x G_xx rho_xx + 2 sum_{x<y} Re(G_xy conj(rho_xy)).
+template <int DIM>
+__device__ __forceinline__ double gram_weight(const double2 *__restrict__ G, const double (&r)[kTrajRed])
+{
+    double w = 0.0;
+#pragma unroll
+    for (int x = 0; x < DIM; ++x) w = fma(G[x * DIM + x].x, r[x], w);
+    int p = 0;
+#pragma unroll
+    for (int x = 0; x < DIM; ++x)
+#pragma unroll
+        for (int y = x + 1; y < DIM; ++y, ++p) {
+            const double2 g = G[x * DIM + y];
+            w = fma(2.0 * g.x, r[DIM + 2 * p], w);
+            w = fma(2.0 * g.y, r[DIM + 2 * p + 1], w);
+        }
+    return w;
+}
+
+// The drawn index: the smallest i whose running sum of weights exceeds u W
+// (W the sum of all nk weights, both sums taken in index order), or the last
+// positive weight if rounding leaves none.  Also returns that weight.
+__device__ __forceinline__ uint32_t draw_index(const double (&w)[kTrajMaxKraus], uint32_t nk, double u,
+                                               double &wj)
+{
+    double W = 0.0;
+#pragma unroll
+    for (uint32_t i = 0; i < (uint32_t)kTrajMaxKraus; ++i)
+        if (i < nk) W += w[i];
+    const double thr = u * W;
+    double cum = 0.0, w_found = 0.0, w_last = 0.0;
+    uint32_t j = kTrajMaxKraus, last = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < (uint32_t)kTrajMaxKraus; ++i) {
+        if (i < nk) {
+            cum += w[i];
+            const bool take = (j == (uint32_t)kTrajMaxKraus) && (cum > thr);
+            j = take ? i : j;
+            w_found = take ? w[i] : w_found;
+            const bool pos = w[i] > 0.0;
+            last = pos ? i : last;
+            w_last = pos ? w[i] : w_last;
+        }
+    }
+    const bool found = j < (uint32_t)kTrajMaxKraus;
+    wj = found ? w_found : w_last;
+    return found ? j : last;
+}
+
+// A channel on the register bits in MASK: draw, then apply the drawn
+// operator (a mixed-unitary channel's unitary as stored; a general Kraus
+// operator divided by the square root of its weight).
+template <int MASK, bool WIDE>
+__device__ __forceinline__ void traj_channel(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+                                             const double2 *__restrict__ M, double u, uint32_t log_tt,
+                                             double *red, uint32_t wave, uint32_t wpt)
+{
+    constexpr int DIM = 1 << popc4(MASK), D2 = DIM * DIM;
+    const uint32_t nk = uni(op->nk);
+    const bool mixed = uni(op->kind) == TOP_MIX;
+    double w[kTrajMaxKraus];
+    const double2 *mats;
+    if (mixed) {
+#pragma unroll
+        for (int i = 0; i < kTrajMaxKraus; ++i) w[i] = ((uint32_t)i < nk) ? M[i].x : 0.0;
+        mats = M + nk;
+    } else {
+        double r[kTrajRed];
+        rho_partial<MASK>(x, r);
+        group_sum<kTrajRed, WIDE>(r, log_tt, red, wave, wpt);
+#pragma unroll
+        for (int i = 0; i < kTrajMaxKraus; ++i) w[i] = ((uint32_t)i < nk) ? gram_weight<DIM>(M + i * D2, r) : 0.0;
+        mats = M + nk * D2;
+    }
+    double wj;
+    uint32_t j = draw_index(w, nk, u, wj);
+    if (WIDE) j = uni(j);        // one trajectory per wave: the operator's loads are scalar
+    apply_mat<MASK, false>(x, y, mats + j * D2);
+    if (!mixed) {
+        const double s = 1.0 / sqrt(wj);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            y[e].x *= s;
+            y[e].y *= s;
+        }
+    }
+}
+
+// Diagonal gate on one or two qubits anywhere in the index: factor index
+// bit j is bit dq[j] of the amplitude index.
+__device__ __forceinline__ void traj_diag(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+                                          const double2 *__restrict__ M, const TCtx &c)
+{
+    const uint32_t nd = uni(op->nd), q0 = uni(op->dq[0]) & 31u, q1 = uni(op->dq[1]) & 31u;
+    const double2 d0 = M[0], d1 = M[1];
+    double2 d2 = d0, d3 = d1;
+    if (nd > 1) {
+        d2 = M[2];
+        d3 = M[3];
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const uint32_t xi = c.tl | slot_l(c.rl, e);
+        const uint32_t b0 = (xi >> q0) & 1u, b1 = (nd > 1) ? ((xi >> q1) & 1u) : 0u;
+        const double2 f = b1 ? (b0 ? d3 : d2) : (b0 ? d1 : d0);
+        y[e] = cmul(f, x[e]);
+    }
+}
+
+template <bool WIDE>
+__device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+                                        const double2 *__restrict__ pool, const TCtx &c, double u, uint32_t log_tt,
+                                        double *red, uint32_t wave, uint32_t wpt)
+{
+    const uint32_t kind = uni(op->kind);
+    const uint32_t mask = uni(op->mask);
+    const double2 *M = pool + uni(op->mat);
+    if (kind == TOP_MAT) {
+        switch (mask | (uni(op->real) << 4)) {
+#define VQD_TMAT(m)                                             \
+    case m: apply_mat<m, false>(x, y, M); break;                \
+    case 16 | m: apply_mat<m, true>(x, y, M); break;
+        VQD_TMAT(1) VQD_TMAT(2) VQD_TMAT(3) VQD_TMAT(4) VQD_TMAT(5) VQD_TMAT(6) VQD_TMAT(7)
+        VQD_TMAT(8) VQD_TMAT(9) VQD_TMAT(10) VQD_TMAT(11) VQD_TMAT(12) VQD_TMAT(13) VQD_TMAT(14)
+        VQD_TMAT(15)
+#undef VQD_TMAT
+        default: break;
+        }
+    } else if (kind == TOP_DIAG) {
+        traj_diag(x, y, op, M, c);
+    } else {
+        switch (mask) {
+#define VQD_TCH(m) \
+    case m: traj_channel<m, WIDE>(x, y, op, M, u, log_tt, red, wave, wpt); break;
+        VQD_TCH(1) VQD_TCH(2) VQD_TCH(4) VQD_TCH(8) VQD_TCH(3) VQD_TCH(5) VQD_TCH(6) VQD_TCH(9)
+        VQD_TCH(10) VQD_TCH(12)
+#undef VQD_TCH
+        default: break;
+        }
+    }
+}
+
+// One batch of trajectories.  Workgroup g of the persistent loop holds
+// blockDim / 2^log_tt trajectories; group grp's threads are tid >> log_tt.
+// Channels are met in increasing channel order, so the uniform of the next
+// channel is prefetched while the ops before it run.
+template <bool WIDE>
+__global__ void __launch_bounds__(512)
+k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restrict__ ops,
+       const double2 *__restrict__ pool, uint32_t n, uint32_t log_tt, uint32_t n_ch,
+       const double *__restrict__ U, uint64_t T, double *__restrict__ z_out, double *__restrict__ norm_out,
+       double *__restrict__ state_out)
+{
+    extern __shared__ double2 lds[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t TT = 1u << log_tt;
+    const uint32_t tpw = blockDim.x >> log_tt;
+    const uint32_t grp = tid >> log_tt, tt = tid & (TT - 1u);
+    const uint32_t wave = tid >> 6, wpt = WIDE ? (TT >> 6) : 1u;
+    double *red = reinterpret_cast<double *>(lds + (size_t)blockDim.x * 16);
+    double2 *xl = lds + (size_t)grp * TT * 16;
+    const uint64_t n_groups = (T + tpw - 1) / tpw;
+    const uint32_t dim = 1u << n;
+
+    for (uint64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+        const uint64_t traj = g * tpw + grp;
+        const bool active = traj < T;
+        const double *Urow = U + (active ? traj : T - 1) * (uint64_t)n_ch;
+        uint32_t next_ch = 0;
+        double u_next = (n_ch > 0) ? Urow[0] : 0.0;
+        double2 a[16], b[16];
+        TCtx c;
+        for (uint32_t ph = 0; ph < n_phases; ++ph) {
+            const TPhase *H = phases + ph;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c.rl[r] = 1u << (uni(H->reg_q[r]) & 31u);
+            c.tl = traj_thread_bits(H, tt);
+            if (ph == 0) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    a[e] = make_double2(((c.tl | slot_l(c.rl, e)) == 0u) ? 1.0 : 0.0, 0.0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) a[e] = xl[swz(c.tl | slot_l(c.rl, e))];
+                __syncthreads();
+            }
+            const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
+            for (uint32_t oi = ob; oi < oe; oi += 2) {
+                double u = 0.0;
+                if (uni(ops[oi].kind) >= TOP_MIX) {
+                    u = u_next;
+                    ++next_ch;
+                    u_next = (next_ch < n_ch) ? Urow[next_ch] : 0.0;
+                }
+                traj_op<WIDE>(a, b, ops + oi, pool, c, u, log_tt, red, wave, wpt);
+                if (oi + 1 < oe) {
+                    u = 0.0;
+                    if (uni(ops[oi + 1].kind) >= TOP_MIX) {
+                        u = u_next;
+                        ++next_ch;
+                        u_next = (next_ch < n_ch) ? Urow[next_ch] : 0.0;
+                    }
+                    traj_op<WIDE>(b, a, ops + oi + 1, pool, c, u, log_tt, red, wave, wpt);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) a[e] = b[e];
+                }
+            }
+            if (ph + 1 < n_phases) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) xl[swz(c.tl | slot_l(c.rl, e))] = a[e];
+                __syncthreads();
+            }
+        }
+
+        // read-out: <Z_q> for q < n in r[q], the squared norm in r[15]
+        double r[kTrajRed];
+#pragma unroll
+        for (int i = 0; i < kTrajRed; ++i) r[i] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t xi = c.tl | slot_l(c.rl, e);
+            const double p = fma(a[e].x, a[e].x, a[e].y * a[e].y);
+            r[15] += p;
+#pragma unroll
+            for (int q = 0; q < kTrajMaxQubits; ++q) r[q] += ((xi >> q) & 1u) ? -p : p;
+        }
+        group_sum<kTrajRed, WIDE>(r, log_tt, red, wave, wpt);
+        if (active) {
+            if (tt == 0) {
+                for (uint32_t q = 0; q < n; ++q) z_out[traj * n + q] = r[q];
+                if (norm_out) norm_out[traj] = r[15];
+            }
+            if (state_out) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const uint32_t xi = c.tl | slot_l(c.rl, e);
+                    if (xi < dim) {
+                        state_out[2 * (traj * dim + xi)] = a[e].x;
+                        state_out[2 * (traj * dim + xi) + 1] = a[e].y;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Column j of the T x m row-major samples: mean, then the sum of squared
+// deviations from it, each summed per thread in row order and then over the
+// threads in a fixed tree.
+constexpr int kStatThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kStatThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double out = sh[0];
+    __syncthreads();
+    return out;
+}
+
+__global__ void __launch_bounds__(kStatThreads)
+k_traj_stats(const double *__restrict__ x, uint64_t T, uint32_t m, double *__restrict__ mean,
+             double *__restrict__ sem)
+{
+    __shared__ double sh[kStatThreads];
+    const uint32_t j = blockIdx.x;
+    double s = 0.0;
+    for (uint64_t t = threadIdx.x; t < T; t += kStatThreads) s += x[t * m + j];
+    const double mu = block_sum(s, sh) / (double)T;
+    double q = 0.0;
+    for (uint64_t t = threadIdx.x; t < T; t += kStatThreads) {
+        const double d = x[t * m + j] - mu;
+        q = fma(d, d, q);
+    }
+    const double Q = block_sum(q, sh);
+    if (threadIdx.x == 0) {
+        mean[j] = mu;
+        sem[j] = (T > 1) ? sqrt(Q / (double)(T - 1)) / sqrt((double)T) : INFINITY;
+    }
+}
+
+}  // namespace
+
+int launch_traj(const TPhase *phases, uint32_t n_phases, const TOp *ops, const double2 *pool, int n,
+                int n_eff, uint32_t n_ch, const double *U, uint64_t T, double *z_out, double *norm_out,
+                double *state_out, hipStream_t stream)
+{
+    if (T == 0) return VQD_OK;
+    const uint32_t log_tt = (uint32_t)(n_eff - 4);
+    const uint32_t threads = (log_tt == 9) ? 512u : 256u;
+    const size_t lds = size_t(threads) * 16 * sizeof(double2) + size_t(kTrajMaxWaves) * kTrajRed * sizeof(double);
+    const bool wide = log_tt >= 6;
+    const void *kfn = wide ? (const void *)k_traj<true> : (const void *)k_traj<false>;
+    static bool attr_set = false;
+    static int n_cu = 0;
+    if (!attr_set) {
+        VQD_HIP(hipFuncSetAttribute((const void *)k_traj<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024));
+        VQD_HIP(hipFuncSetAttribute((const void *)k_traj<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024));
+        int dev_id = 0;
+        VQD_HIP(hipGetDevice(&dev_id));
+        VQD_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id));
+        attr_set = true;
+    }
+    int per_cu = 0;
+    VQD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, (int)threads, lds));
+    if (per_cu < 1) per_cu = 1;
+    const uint32_t tpw = threads >> log_tt;
+    const uint64_t n_groups = (T + tpw - 1) / tpw;
+    uint64_t grid = (uint64_t)per_cu * (uint64_t)n_cu;
+    if (grid > n_groups) grid = n_groups;
+    if (wide)
+        hipLaunchKernelGGL(k_traj<true>, dim3((uint32_t)grid), dim3(threads), lds, stream, phases, n_phases, ops,
+                           pool, (uint32_t)n, log_tt, n_ch, U, T, z_out, norm_out, state_out);
+    else
+        hipLaunchKernelGGL(k_traj<false>, dim3((uint32_t)grid), dim3(threads), lds, stream, phases, n_phases, ops,
+                           pool, (uint32_t)n, log_tt, n_ch, U, T, z_out, norm_out, state_out);
+    VQD_HIP(hipGetLastError());
+    return VQD_OK;
+}
+
+int launch_traj_stats(const double *x, uint64_t T, int m, double *mean, double *sem, hipStream_t stream)
+{
+    if (m <= 0) return VQD_OK;
+    hipLaunchKernelGGL(k_traj_stats, dim3((uint32_t)m), dim3(kStatThreads), 0, stream, x, T, (uint32_t)m, mean,
+                       sem);
+    VQD_HIP(hipGetLastError());
+    return VQD_OK;
+}
+
+}  // namespace vqd

@@ -21,6 +21,11 @@ void clear_error();
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
+// Argument helpers of the C ABI.
+std::vector<cd> read_complex(const double *p, size_t count);
+bool all_finite(const double *p, size_t count);
+int check_targets(int n, int k, const int *t);
+
 #define VQD_HIP(call)                                   \
     do {                                                \
         hipError_t e_ = (call);                         \
@@ -189,6 +194,49 @@ PlanOpts to_plan_opts(const vqd_plan_opts &o);
 int upload_plan(const HostPlan &plan, DevProgram &dev, hipStream_t stream);
 void free_dev_program(DevProgram &dev);
 
+// --------------------------------------------------------- trajectories --
+// Monte Carlo state-vector trajectories.  One trajectory of n_eff = max(n, 4)
+// qubits is held by 2^(n_eff-4) threads with 16 register slots each: in every
+// phase four qubits are the register bits and the others the thread bits; the
+// state moves between phases through LDS.  A workgroup holds several
+// trajectories when n_eff < 12.
+constexpr int kTrajMaxQubits = 13;
+constexpr int kTrajMaxThreadBits = kTrajMaxQubits - 4;
+constexpr int kTrajMaxKraus = 16;
+
+enum TOpKind : uint32_t {
+    TOP_MAT = 1,      // dense matrix on register bits `mask` (column-major; real ones packed)
+    TOP_DIAG = 2,     // diagonal factors, index bit j = bit dq[j] of the amplitude index
+    TOP_MIX = 3,      // mixed-unitary channel: nk weights (in .x), then nk unitaries
+    TOP_KRAUS = 4,    // general channel: nk Gram matrices K^dagger K (row-major), then nk
+                      // Kraus matrices (column-major)
+};
+
+struct alignas(16) TOp {
+    uint32_t kind;
+    uint32_t mask;    // TOP_MAT / TOP_MIX / TOP_KRAUS: register bits acted on
+    uint32_t mat;     // offset of the coefficients in the pool (complex entries)
+    uint32_t real;    // TOP_MAT: real coefficients, packed two per entry
+    uint32_t nk;      // TOP_MIX / TOP_KRAUS: number of operators
+    uint32_t chan;    // TOP_MIX / TOP_KRAUS: channel index (column of the uniforms)
+    uint32_t nd;      // TOP_DIAG: number of qubits (1 or 2)
+    uint32_t pad0;
+    uint32_t dq[2];   // TOP_DIAG: the qubits, dq[0] the low bit of the factor index
+    uint32_t pad1[2];
+};
+
+struct alignas(16) TPhase {
+    uint32_t op_begin, op_end;
+    uint32_t reg_q[4];                      // qubit of register bit b
+    uint32_t thr_q[kTrajMaxThreadBits];     // qubit of thread bit i (zero-filled past n_eff - 4)
+    uint32_t pad;
+};
+
+int launch_traj(const TPhase *phases, uint32_t n_phases, const TOp *ops, const double2 *pool, int n,
+                int n_eff, uint32_t n_ch, const double *U, uint64_t T, double *z_out, double *norm_out,
+                double *state_out, hipStream_t stream);
+int launch_traj_stats(const double *x, uint64_t T, int m, double *mean, double *sem, hipStream_t stream);
+
 // ------------------------------------------------------------- batched --
 // One density matrix of a batch (queue order).
 struct alignas(16) BatchItem {
@@ -238,6 +286,9 @@ int kind_arity(int kind, int *nq, int *np);
 void canonical_params(int kind, double *p);
 int kind_matrix(int kind, const double *params, std::vector<cd> &U, int &k);
 int kind_superop(int kind, const double *params, std::vector<cd> &S, int &k);
+// Kraus set of a named channel (each a 2^k x 2^k row-major matrix).
+int kind_kraus(int kind, const double *params, std::vector<std::vector<cd>> &Ks, int &k);
+bool kind_is_channel(int kind);
 void kraus_to_superop(int k, int nk, const cd *K, std::vector<cd> &S);
 void unitary_to_superop(int k, const cd *U, std::vector<cd> &S);
 

@@ -56,6 +56,12 @@ class ProgInfo(ctypes.Structure):
                 ("fma_per_amp", ctypes.c_double)]
 
 
+class TrajInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("n_ops", ctypes.c_int), ("n_channels", ctypes.c_int),
+                ("n_phases", ctypes.c_int), ("n_kernel_ops", ctypes.c_int), ("n_mixed", ctypes.c_int),
+                ("n_general", ctypes.c_int), ("fma_per_amp", ctypes.c_double)]
+
+
 def load(path: str = LIB_PATH):
     """Load libvqd.so (raises if it has not been built)."""
     global _lib
@@ -130,6 +136,18 @@ def load(path: str = LIB_PATH):
         "vqd_mlp_predict": ([vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "vqd_template_export": ([ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, ctypes.POINTER(PlanOpts), vp,
                                  ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "vqd_traj_create": ([ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "vqd_traj_destroy": ([vp], ctypes.c_int),
+        "vqd_traj_add_named": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+        "vqd_traj_add_named_many": ([vp, ctypes.c_int, _ip, _ip, _dp], ctypes.c_int),
+        "vqd_traj_add_unitary": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+        "vqd_traj_add_kraus": ([vp, ctypes.c_int, _ip, ctypes.c_int, _dp], ctypes.c_int),
+        "vqd_traj_plan": ([vp], ctypes.c_int),
+        "vqd_traj_export": ([vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "vqd_traj_compile": ([vp], ctypes.c_int),
+        "vqd_traj_info_get": ([vp, ctypes.POINTER(TrajInfo)], ctypes.c_int),
+        "vqd_traj_run": ([vp, vp, ctypes.c_longlong, vp, vp, vp, vp], ctypes.c_int),
+        "vqd_traj_stats": ([vp, ctypes.c_longlong, ctypes.c_int, vp, vp, vp], ctypes.c_int),
         "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_calc_purity": ([vp, _dp], ctypes.c_int),
         "vqd_calc_probs": ([vp, _dp], ctypes.c_int),
@@ -436,6 +454,131 @@ class Program:
         i = ProgInfo()
         check(lib().vqd_prog_info_get(self.handle, ctypes.byref(i)))
         return {f: getattr(i, f) for f, _ in ProgInfo._fields_}
+
+
+class Trajectories:
+    """Monte Carlo state-vector trajectories (vqd_traj_* in include/vqd.h):
+    one Kraus operator drawn per channel and trajectory from caller-supplied
+    uniforms, the whole state held on the chip."""
+
+    def __init__(self, n: int, ops: Optional[Iterable] = None):
+        load()
+        self.n = n
+        h = ctypes.c_void_p()
+        check(lib().vqd_traj_create(n, ctypes.byref(h)))
+        self.handle = h
+        if ops is not None:
+            self.extend(ops)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().vqd_traj_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, op):
+        kind, qubits, params = op
+        t = np.ascontiguousarray(qubits, dtype=np.int32)
+        if kind == "matrix":
+            check(lib().vqd_traj_add_unitary(self.handle, len(t), _i(t), _d(_cplx(params[0]))))
+        elif kind == "kraus":
+            K = np.stack([np.asarray(x, dtype=np.complex128) for x in params])
+            check(lib().vqd_traj_add_kraus(self.handle, len(t), _i(t), K.shape[0], _d(_cplx(K))))
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float64) if len(params) else np.zeros(1)
+            check(lib().vqd_traj_add_named(self.handle, KINDS[kind], _i(t), _d(p)))
+
+    def extend(self, ops: Iterable):
+        """Append ops; runs of named ops are passed in one call."""
+        run = []
+
+        def flush():
+            if not run:
+                return
+            k = np.fromiter((KINDS[o[0]] for o in run), dtype=np.int32, count=len(run))
+            t = np.zeros((len(run), 4), dtype=np.int32)
+            pr = np.zeros((len(run), 4), dtype=np.float64)
+            for i, (_, q, par) in enumerate(run):
+                t[i, :len(q)] = q
+                pr[i, :len(par)] = par
+            check(lib().vqd_traj_add_named_many(self.handle, len(run), _i(k), _i(t), _d(pr)))
+            run.clear()
+
+        for op in ops:
+            if op[0] in KINDS:
+                run.append(op)
+            else:
+                flush()
+                self.add(op)
+        flush()
+        return self
+
+    def plan(self):
+        """Plan on the host only (no device needed)."""
+        check(lib().vqd_traj_plan(self.handle))
+        return self
+
+    def export(self) -> bytes:
+        need = ctypes.c_size_t()
+        check(lib().vqd_traj_export(self.handle, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        check(lib().vqd_traj_export(self.handle, buf, need.value, ctypes.byref(need)))
+        return buf.raw
+
+    def compile(self):
+        check(lib().vqd_traj_compile(self.handle))
+        return self
+
+    def info(self) -> dict:
+        i = TrajInfo()
+        check(lib().vqd_traj_info_get(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in TrajInfo._fields_}
+
+    def run(self, uniforms, count: Optional[int] = None, z_out=None, norm: bool = True, state: bool = False,
+            stream=None) -> dict:
+        """Run trajectories for the rows of ``uniforms`` (a CUDA float64 tensor
+        [count, n_channels]); returns CUDA tensors z [count, n] and, when
+        asked for, norm [count] and state [count, 2^n] (complex128)."""
+        import torch
+        nch = self.info()["n_channels"]
+        if count is None:
+            count = int(uniforms.shape[0]) if uniforms is not None else 0
+        if nch:
+            if (uniforms is None or not uniforms.is_cuda or uniforms.dtype != torch.float64
+                    or not uniforms.is_contiguous() or uniforms.numel() != count * nch):
+                raise ValueError("uniforms must be a contiguous CUDA float64 tensor [count, %d]" % nch)
+        dev = uniforms.device if uniforms is not None else torch.device("cuda")
+        z = z_out if z_out is not None else torch.empty((count, self.n), dtype=torch.float64, device=dev)
+        nrm = torch.empty(count, dtype=torch.float64, device=dev) if norm else None
+        st = torch.empty((count, 1 << self.n), dtype=torch.complex128, device=dev) if state else None
+        ptr = (lambda x: ctypes.c_void_p(x.data_ptr()) if x is not None else None)
+        check(lib().vqd_traj_run(self.handle, ptr(uniforms) if nch else None, count, ptr(z), ptr(nrm), ptr(st),
+                                 _stream_ptr(stream)))
+        out = {"z": z}
+        if norm:
+            out["norm"] = nrm
+        if state:
+            out["state"] = st
+        return out
+
+    @staticmethod
+    def stats(x, stream=None):
+        """Mean over the rows of a CUDA float64 tensor [count, m] and its
+        standard error (vqd_traj_stats)."""
+        import torch
+        x = x.contiguous()
+        m = int(x.shape[1]) if x.dim() == 2 else 1
+        mean = torch.empty(m, dtype=torch.float64, device=x.device)
+        sem = torch.empty(m, dtype=torch.float64, device=x.device)
+        check(lib().vqd_traj_stats(ctypes.c_void_p(x.data_ptr()), int(x.shape[0]), m,
+                                   ctypes.c_void_p(mean.data_ptr()), ctypes.c_void_p(sem.data_ptr()),
+                                   _stream_ptr(stream)))
+        return mean, sem
 
 
 class Batch:

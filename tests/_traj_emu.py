@@ -1,0 +1,125 @@
+"""CPU execution of exported trajectory plans (vqd_traj_export).
+
+Test infrastructure: decodes the library's phase/op descriptors and runs
+them on full state vectors with numpy, op by op, with the kernel's rules
+(mixed-unitary channels drawn from their stored weights, general ones from
+Tr(K^dagger K rho_T) of the reduced density matrix of the targets).  It
+checks the host planner's encoding (register masks, bit orders, packing,
+channel order) without a GPU; the register and LDS mechanics of the kernel
+are left to the GPU tests.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle.trajectories import apply_matrix
+
+MAGIC = 0x54445156
+TOP_MAT, TOP_DIAG, TOP_MIX, TOP_KRAUS = 1, 2, 3, 4
+
+PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4", 9), ("pad", "<u4")])
+OP = np.dtype([("kind", "<u4"), ("mask", "<u4"), ("mat", "<u4"), ("real", "<u4"), ("nk", "<u4"),
+               ("chan", "<u4"), ("nd", "<u4"), ("pad0", "<u4"), ("dq", "<u4", 2), ("pad1", "<u4", 2)])
+
+
+def parse(blob: bytes) -> dict:
+    h = np.frombuffer(blob, dtype="<u4", count=10)
+    assert h[0] == MAGIC and h[1] == 1
+    n, ne, nch, nph, nop, npool, szp, szo = (int(x) for x in h[2:10])
+    assert szp == PHASE.itemsize and szo == OP.itemsize
+    off = 40
+    phases = np.frombuffer(blob, dtype=PHASE, count=nph, offset=off)
+    off += nph * szp
+    ops = np.frombuffer(blob, dtype=OP, count=nop, offset=off)
+    off += nop * szo
+    pool = np.frombuffer(blob, dtype="<f8", count=2 * npool, offset=off).view(np.complex128)
+    return {"n": n, "n_eff": ne, "n_channels": nch, "phases": phases, "ops": ops, "pool": pool}
+
+
+def _qubits(mask, reg):
+    return [int(reg[b]) for b in range(4) if (int(mask) >> b) & 1]
+
+
+def _colmajor(pool, off, d):
+    return pool[off:off + d * d].reshape(d, d).T
+
+
+def _mat(pool, op, d):
+    off = int(op["mat"])
+    if op["real"]:
+        packed = pool[off:off + (d * d + 1) // 2]
+        c = np.stack([packed.real, packed.imag], axis=1).reshape(-1)[:d * d].astype(complex)
+        return c.reshape(d, d).T
+    return _colmajor(pool, off, d)
+
+
+def _reduced(psi, qs):
+    n = int(psi.size).bit_length() - 1
+    mask = sum(1 << q for q in qs)
+    x = np.arange(psi.size)
+    base = x[(x & mask) == 0]
+    off = np.array([sum(((l >> j) & 1) << q for j, q in enumerate(qs)) for l in range(1 << len(qs))])
+    A = psi[base[:, None] | off[None, :]]
+    del n
+    return A.T @ A.conj()
+
+
+def _draw(w, u):
+    W = 0.0
+    for x in w:
+        W += x
+    thr = u * W
+    cum = 0.0
+    for i, x in enumerate(w):
+        cum += x
+        if cum > thr:
+            return i
+    return max(i for i, x in enumerate(w) if x > 0)
+
+
+def run(plan: dict, U: np.ndarray):
+    """Per-trajectory <Z_q> (T x n), squared norms (T) and the channel order
+    met (one list of channel indices)."""
+    n, ne, pool = plan["n"], plan["n_eff"], plan["pool"]
+    T = U.shape[0]
+    Z = np.empty((T, n))
+    N = np.empty(T)
+    order = []
+    for t in range(T):
+        psi = np.zeros(1 << ne, dtype=complex)
+        psi[0] = 1
+        for ph in plan["phases"]:
+            for op in plan["ops"][int(ph["ob"]):int(ph["oe"])]:
+                kind = int(op["kind"])
+                if kind == TOP_DIAG:
+                    qs = [int(q) for q in op["dq"][:int(op["nd"])]]
+                    f = pool[int(op["mat"]):int(op["mat"]) + (1 << len(qs))]
+                    psi = apply_matrix(psi, qs, np.diag(f))
+                    continue
+                qs = _qubits(op["mask"], ph["reg"])
+                d = 1 << len(qs)
+                if kind == TOP_MAT:
+                    psi = apply_matrix(psi, qs, _mat(pool, op, d))
+                    continue
+                nk, off = int(op["nk"]), int(op["mat"])
+                if t == 0:
+                    order.append(int(op["chan"]))
+                if kind == TOP_MIX:
+                    w = list(pool[off:off + nk].real)
+                    mats = off + nk
+                else:
+                    rho = _reduced(psi, qs)
+                    w = [float(np.sum(pool[off + i * d * d: off + (i + 1) * d * d].reshape(d, d) * rho.T).real)
+                         for i in range(nk)]
+                    mats = off + nk * d * d
+                j = _draw(w, float(U[t, int(op["chan"])]))
+                psi = apply_matrix(psi, qs, _colmajor(pool, mats + j * d * d, d))
+                if kind == TOP_KRAUS:
+                    psi = psi / math.sqrt(w[j])
+        p = np.abs(psi) ** 2
+        x = np.arange(psi.size)
+        Z[t] = [np.sum(p * (1 - 2 * ((x >> q) & 1))) for q in range(n)]
+        N[t] = p.sum()
+    return Z, N, order

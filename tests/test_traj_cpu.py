@@ -1,0 +1,110 @@
+"""Trajectory planner on the CPU: plans exported by the library
+(vqd_traj_export) are executed by tests/_traj_emu.py and compared, trajectory
+by trajectory, with the trajectory oracle on the same uniforms."""
+import numpy as np
+import pytest
+
+from oracle import trajectories as tj
+from tests import _traj_emu as emu
+from workloads import (c1_line_circuit, c2_grid_circuit, c3_all_to_all_circuit, random_tp_ops,
+                       uniforms)
+
+
+def check_plan(vqd, n, ops, T=8, seed=0, tol=1e-12):
+    t = vqd.Trajectories(n, ops).plan()
+    plan = emu.parse(t.export())
+    nch = tj.n_channels(ops)
+    info = t.info()
+    assert info["n_channels"] == nch == plan["n_channels"]
+    assert info["n_mixed"] + info["n_general"] == nch
+    U = uniforms(T, nch, seed=seed)
+    Z, N, order = emu.run(plan, U)
+    assert order == list(range(nch))          # channels met in channel order
+    Zr, Nr = tj.run_many(n, ops, U)
+    assert np.abs(Z - Zr).max() <= tol, np.abs(Z - Zr).max()
+    assert np.abs(N - Nr).max() <= tol
+    return t, plan
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_random_unitaries_and_kraus_maps(vqd_host, n):
+    ops = random_tp_ops(n, 40, seed=200 + n, max_k=min(2, n))
+    check_plan(vqd_host, n, ops)
+
+
+@pytest.mark.parametrize("n", [2, 5])
+def test_three_and_four_qubit_gates(vqd_host, n):
+    """Gates on up to four qubits (k <= n) among channels."""
+    rng = np.random.default_rng(n)
+    ops = []
+    for i in range(12):
+        k = int(rng.integers(1, min(4, n) + 1))
+        ops += random_tp_ops(n, 1, seed=300 + i, max_k=min(2, n), p_channel=1.0)
+        tg = tuple(int(x) for x in rng.choice(n, size=k, replace=False))
+        Q, _ = np.linalg.qr(rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k)))
+        ops.append(("matrix", tg, (Q,)))
+    check_plan(vqd_host, n, ops)
+
+
+def test_named_gates_and_channels(vqd_host):
+    n = 5
+    ops = [("h", (0,), ()), ("x", (1,), ()), ("y", (2,), ()), ("z", (3,), ()), ("rx", (4,), (0.3,)),
+           ("ry", (0,), (1.1,)), ("rz", (1,), (2.2,)), ("su2", (2,), (0.1, -0.7, 0.4, 0.2)),
+           ("cz", (0, 3), ()), ("cphase", (4, 1), (0.6,)), ("xx", (2, 0), (0.9,)), ("zz", (3, 4), (0.05,)),
+           ("depol1", (0,), (0.2,)), ("depol2", (1, 3), (0.3,)), ("deph1", (2,), (0.25,)),
+           ("deph2", (4, 0), (0.1,)), ("amp", (1,), (0.4,)), ("gamp", (3,), (0.6, 0.3)),
+           ("bitflip1", (4,), (0.2,)), ("bitflip2", (2, 1), (0.3,)), ("amp_t1", (0,), (0.5, 2.0)),
+           ("deph_t2", (3,), (0.5, 1.0))]
+    _, plan = check_plan(vqd_host, n, ops * 3, T=24)
+    kinds = set(int(k) for k in plan["ops"]["kind"])
+    assert kinds == {emu.TOP_MAT, emu.TOP_DIAG, emu.TOP_MIX, emu.TOP_KRAUS}
+
+
+def test_workload_circuits(vqd_host):
+    check_plan(vqd_host, 6, c1_line_circuit(), T=3)
+    check_plan(vqd_host, 6, c2_grid_circuit(rows=2, cols=3, n_gates=60), T=3)
+    check_plan(vqd_host, 7, c3_all_to_all_circuit(n=7, n_gates=40), T=3)
+
+
+def test_gate_only_and_empty_programs(vqd_host):
+    ops = [op for op in c1_line_circuit(n=4, n_gates=20) if not tj.is_channel(op)]
+    check_plan(vqd_host, 4, ops, T=1)
+    t = vqd_host.Trajectories(3).plan()
+    plan = emu.parse(t.export())
+    Z, N, _ = emu.run(plan, np.zeros((2, 0)))
+    assert np.array_equal(Z, np.ones((2, 3))) and np.array_equal(N, np.ones(2))
+
+
+def test_phase_layouts_are_permutations(vqd_host):
+    n = 9
+    t = vqd_host.Trajectories(n, c2_grid_circuit(rows=3, cols=3, n_gates=200)).plan()
+    plan = emu.parse(t.export())
+    for ph in plan["phases"]:
+        qs = list(ph["reg"]) + list(ph["thr"][:n - 4])
+        assert sorted(int(q) for q in qs) == list(range(n))
+    # fusion and reordering keep the plan well below one phase per op
+    assert len(plan["phases"]) < len(plan["ops"])
+
+
+def test_errors(vqd_host):
+    v = vqd_host
+    with pytest.raises(v.VQDError):
+        v.Trajectories(0)
+    with pytest.raises(v.VQDError):
+        v.Trajectories(14)
+    t = v.Trajectories(3)
+    with pytest.raises(v.VQDError):                # not unitary
+        t.add(("matrix", (0,), (np.array([[1, 0], [0, 2]]),)))
+    with pytest.raises(v.VQDError):                # too many Kraus operators
+        t.add(("kraus", (0,), tuple(np.eye(2) / np.sqrt(17) for _ in range(17))))
+    with pytest.raises(v.VQDError):                # Kraus maps on at most two qubits
+        t.add(("kraus", (0, 1, 2), (np.eye(8),)))
+    with pytest.raises(v.VQDError):                # duplicate target
+        t.add(("cz", (1, 1), ()))
+    with pytest.raises(v.VQDError):                # bad probability
+        t.add(("depol1", (0,), (1.5,)))
+    with pytest.raises(v.VQDError):                # bad op inside a batch of named ops: all or nothing
+        t.extend([("h", (0,), ()), ("depol1", (5,), (0.1,))])
+    assert t.info()["n_ops"] == 0
+    with pytest.raises(v.VQDError):                # not planned yet
+        t.export()
