@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -204,6 +205,77 @@ def c3_leg(vqd, torch, steps: int):
     return out
 
 
+def traj_leg(vqd, torch, n_traj: int, steps: int, oracle_sample: bool):
+    """Monte Carlo trajectories of the 12-qubit grid circuit (2x6 grid, 2000
+    gates, the same noise as the 14-qubit workload), all trajectories in one
+    launch with their uniforms resident in HBM, against the exact density
+    matrix of the same circuit on the same GPU."""
+    import numpy as np
+    from workloads import traj_grid_circuit, uniforms
+    n = 12
+    ops = traj_grid_circuit()
+    n_gates = sum(1 for k, _, _ in ops if k in ("su2", "cz"))
+    t0 = time.perf_counter()
+    prog = vqd.Trajectories(n, ops).compile()
+    info = prog.info()
+    nch = info["n_channels"]
+    U = torch.as_tensor(uniforms(n_traj, nch), device="cuda")
+    z = torch.empty((n_traj, n), dtype=torch.float64, device="cuda")
+    log("trajectories: setup %.1f s, %s" % (time.perf_counter() - t0, info))
+    stream = torch.cuda.current_stream()
+    prog.run(U, z_out=z, norm=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        prog.run(U, z_out=z, norm=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_run = e0.elapsed_time(e1) / 1e3 / steps
+    mean, sem = vqd.Trajectories.stats(z)
+    mean, sem = mean.cpu().numpy(), sem.cpu().numpy()
+    # the exact answer: the density-matrix path on the same circuit
+    dprog = vqd.Program(n, ops).compile(vqd.plan_opts(**PLAN_OPTS))
+    dm = vqd.DensityMatrix(n)
+    dm.init_zero()
+    dprog.run(dm)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        dm.init_zero()
+        dprog.run(dm)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_dm = e0.elapsed_time(e1) / 1e3 / steps
+    exact = dm.expec_z()
+    err = float(np.abs(mean - exact).max())
+    sigma = float(sem.max() * math.sqrt(n_traj))          # per-trajectory standard deviation
+    need = int(math.ceil((3.0 * sigma / 1e-2) ** 2))       # 3 standard errors below 1e-2
+    rate = n_traj / t_run
+    tflops = 2.0 * info["fma_per_amp"] * (1 << n) * n_traj / t_run / 1e12
+    out = {"metric": "noisy trajectories per second (12-qubit state vectors, one launch)",
+           "workload": "2x6 grid, 2000 SU(2)/CZ gates with depol2, ZZ crosstalk and T1/T2 noise "
+                       "(%d ops, %d channels); %d trajectories" % (len(ops), nch, n_traj),
+           "trajectories_per_s": round(rate, 1), "ms_per_launch": round(t_run * 1e3, 3),
+           "gates_per_s": round(n_gates * rate, 1), "ops_per_s": round(len(ops) * rate, 1),
+           "phases": info["n_phases"], "kernel_ops": info["n_kernel_ops"],
+           "planned_fp64_fma_per_amp": round(info["fma_per_amp"], 1),
+           "alu": {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(tflops / FP64_PEAK_TFLOPS, 4)},
+           "max_abs_dz_vs_density_matrix": err, "max_standard_error": float(sem.max()),
+           "trajectories_for_3sigma_below_1e-2": need,
+           "time_to_1e-2_s": round(need / rate, 4), "density_matrix_s": round(t_dm, 5),
+           "memory_per_sample_bytes": {"trajectory": 16 << n, "density_matrix": 16 << (2 * n)}}
+    if oracle_sample:
+        from oracle import trajectories as tj
+        t0 = time.perf_counter()
+        tj.run(n, ops, uniforms(1, nch)[0])
+        out["oracle_trajectories_per_s"] = round(1.0 / (time.perf_counter() - t0), 3)
+    del U, z, dm
+    torch.cuda.empty_cache()
+    return out
+
+
 def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
     """The learned surrogate of the 10-qubit, 4-layer ansatz (8 device
     parameters + 16 angles -> 10 <Z_i>): training data from the batched
@@ -280,6 +352,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-emulation leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-16q", action="store_true", help="skip the 16-qubit context leg")
+    ap.add_argument("--no-traj", action="store_true", help="skip the trajectory leg")
+    ap.add_argument("--trajectories", type=int, default=1 << 16, help="trajectories per launch")
     ap.add_argument("--surrogate-train", type=int, default=1 << 18, help="training samples (2^18)")
     ap.add_argument("--surrogate-test", type=int, default=1 << 14, help="held-out samples (2^14)")
     ap.add_argument("--surrogate-epochs", type=int, default=30)
@@ -382,6 +456,9 @@ def main():
     if not args.no_batched:
         log("batched leg ...")
         out["batched"] = batched_leg(vqd, torch, args.steps)
+    if not args.no_traj:
+        log("trajectory leg ...")
+        out["trajectories"] = traj_leg(vqd, torch, args.trajectories, args.steps, not args.no_cpu_baseline)
     if not args.no_16q and torch.cuda.get_device_properties(0).total_memory > 100 * 2 ** 30:
         log("16-qubit leg ...")
         del dm

@@ -254,7 +254,13 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                     if (q[i] > 0.0) keep.push_back(i);
                 if (keep.empty()) return fail(VQD_E_ARG, "channel with all-zero Kraus operators");
                 k.nk = (uint32_t)keep.size();
-                for (size_t i : keep) t->pool.push_back(cd(q[i], 0.0));
+                // (running sum of the weights in index order, weight): the
+                // kernel draws by comparing u W with the running sums
+                double cum = 0.0;
+                for (size_t i : keep) {
+                    cum += q[i];
+                    t->pool.push_back(cd(cum, q[i]));
+                }
                 for (size_t i : keep) {
                     std::vector<cd> U = Ks[i];
                     const double s = 1.0 / std::sqrt(q[i]);

@@ -50,9 +50,13 @@ __device__ __forceinline__ uint32_t traj_thread_bits(const TPhase *__restrict__ 
 // them: a butterfly over the lane bits inside the wave (each pairwise sum is
 // formed from the same two operands on both lanes), then, when a trajectory
 // spans several waves, the per-wave sums added in wave order through LDS.
+// The cross-wave sums alternate between two LDS buffers (`flip`), so one
+// barrier per reduction suffices: a buffer is written again only after every
+// wave has passed the barrier of the reduction in between, which follows its
+// reads of that buffer.
 template <int CNT, bool WIDE>
 __device__ __forceinline__ void group_sum(double (&v)[CNT], uint32_t log_tt, double *red, uint32_t wave,
-                                          uint32_t wpt)
+                                          uint32_t wpt, uint32_t &flip)
 {
     const uint32_t steps = WIDE ? 6u : log_tt;
     for (uint32_t s = 0; s < steps; ++s) {
@@ -60,19 +64,20 @@ __device__ __forceinline__ void group_sum(double (&v)[CNT], uint32_t log_tt, dou
         for (int i = 0; i < CNT; ++i) v[i] += __shfl_xor(v[i], 1 << s);
     }
     if (WIDE && wpt > 1) {
+        double *buf = red + flip * (kTrajMaxWaves * kTrajRed);
+        flip ^= 1u;
         if ((threadIdx.x & 63u) == 0) {
 #pragma unroll
-            for (int i = 0; i < CNT; ++i) red[wave * kTrajRed + i] = v[i];
+            for (int i = 0; i < CNT; ++i) buf[wave * kTrajRed + i] = v[i];
         }
         __syncthreads();
         const uint32_t w0 = wave & ~(wpt - 1u);
 #pragma unroll
         for (int i = 0; i < CNT; ++i) {
-            double s = red[w0 * kTrajRed + i];
-            for (uint32_t w = 1; w < wpt; ++w) s += red[(w0 + w) * kTrajRed + i];
+            double s = buf[w0 * kTrajRed + i];
+            for (uint32_t w = 1; w < wpt; ++w) s += buf[(w0 + w) * kTrajRed + i];
             v[i] = s;
         }
-        __syncthreads();
     }
 }
 
@@ -80,11 +85,11 @@ __device__ __forceinline__ void group_sum(double (&v)[CNT], uint32_t log_tt, dou
 // MASK: rho_xy = sum over the other bits of psi_x conj(psi_y).  Packed as the
 // DIM real diagonal entries, then (re, im) of rho_xy for x < y in row order.
 template <int MASK>
-__device__ __forceinline__ void rho_partial(const double2 (&a)[16], double (&r)[kTrajRed])
+__device__ __forceinline__ void rho_partial(const double2 (&a)[16], double (&r)[1 << (2 * popc4(MASK))])
 {
     constexpr int NB = popc4(MASK), DIM = 1 << NB, NG = 16 >> NB, REST = (~MASK) & 15;
 #pragma unroll
-    for (int i = 0; i < kTrajRed; ++i) r[i] = 0.0;
+    for (int i = 0; i < DIM * DIM; ++i) r[i] = 0.0;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         int p = 0;
@@ -105,7 +110,7 @@ __device__ __forceinline__ void rho_partial(const double2 (&a)[16], double (&r)[
 // Tr(G rho) for Hermitian G (row-major) and rho packed as by rho_partial:
 // sum_x G_xx rho_xx + 2 sum_{x<y} Re(G_xy conj(rho_xy)).
 template <int DIM>
-__device__ __forceinline__ double gram_weight(const double2 *__restrict__ G, const double (&r)[kTrajRed])
+__device__ __forceinline__ double gram_weight(const double2 *__restrict__ G, const double (&r)[DIM * DIM])
 {
     double w = 0.0;
 #pragma unroll
@@ -122,63 +127,56 @@ __device__ __forceinline__ double gram_weight(const double2 *__restrict__ G, con
     return w;
 }
 
-// The drawn index: the smallest i whose running sum of weights exceeds u W
-// (W the sum of all nk weights, both sums taken in index order), or the last
-// positive weight if rounding leaves none.  Also returns that weight.
-__device__ __forceinline__ uint32_t draw_index(const double (&w)[kTrajMaxKraus], uint32_t nk, double u,
-                                               double &wj)
-{
-    double W = 0.0;
-#pragma unroll
-    for (uint32_t i = 0; i < (uint32_t)kTrajMaxKraus; ++i)
-        if (i < nk) W += w[i];
-    const double thr = u * W;
-    double cum = 0.0, w_found = 0.0, w_last = 0.0;
-    uint32_t j = kTrajMaxKraus, last = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < (uint32_t)kTrajMaxKraus; ++i) {
-        if (i < nk) {
-            cum += w[i];
-            const bool take = (j == (uint32_t)kTrajMaxKraus) && (cum > thr);
-            j = take ? i : j;
-            w_found = take ? w[i] : w_found;
-            const bool pos = w[i] > 0.0;
-            last = pos ? i : last;
-            w_last = pos ? w[i] : w_last;
-        }
-    }
-    const bool found = j < (uint32_t)kTrajMaxKraus;
-    wj = found ? w_found : w_last;
-    return found ? j : last;
-}
-
-// A channel on the register bits in MASK: draw, then apply the drawn
-// operator (a mixed-unitary channel's unitary as stored; a general Kraus
-// operator divided by the square root of its weight).
+// A channel on the register bits in MASK.  The drawn operator is the
+// smallest index i whose running sum of weights (taken in index order)
+// exceeds u W, W the sum of all weights, or the last positive weight if
+// rounding leaves none; a mixed-unitary channel's unitary is applied as
+// stored, a general Kraus operator is divided by the square root of its
+// weight.  A mixed-unitary channel stores the running sums themselves (the
+// same sums, formed on the host), so its draw is a count of the sums not
+// above u W; a general channel's weights Tr(K_i^dagger K_i rho_T) are formed
+// twice (for W, then for the running sum) rather than kept in registers.
 template <int MASK, bool WIDE>
 __device__ __forceinline__ void traj_channel(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
                                              const double2 *__restrict__ M, double u, uint32_t log_tt,
-                                             double *red, uint32_t wave, uint32_t wpt)
+                                             double *red, uint32_t wave, uint32_t wpt, uint32_t &flip)
 {
     constexpr int DIM = 1 << popc4(MASK), D2 = DIM * DIM;
     const uint32_t nk = uni(op->nk);
     const bool mixed = uni(op->kind) == TOP_MIX;
-    double w[kTrajMaxKraus];
+    uint32_t j = 0;
+    double wj = 1.0;
     const double2 *mats;
     if (mixed) {
-#pragma unroll
-        for (int i = 0; i < kTrajMaxKraus; ++i) w[i] = ((uint32_t)i < nk) ? M[i].x : 0.0;
+        const double thr = u * M[nk - 1].x;
+        for (uint32_t i = 0; i + 1 < nk; ++i) j += (M[i].x <= thr) ? 1u : 0u;
         mats = M + nk;
     } else {
-        double r[kTrajRed];
+        double r[D2];
         rho_partial<MASK>(x, r);
-        group_sum<kTrajRed, WIDE>(r, log_tt, red, wave, wpt);
-#pragma unroll
-        for (int i = 0; i < kTrajMaxKraus; ++i) w[i] = ((uint32_t)i < nk) ? gram_weight<DIM>(M + i * D2, r) : 0.0;
+        group_sum<D2, WIDE>(r, log_tt, red, wave, wpt, flip);
+        double W = 0.0;
+        for (uint32_t i = 0; i < nk; ++i) W += gram_weight<DIM>(M + i * D2, r);
+        const double thr = u * W;
+        double cum = 0.0, w_last = 0.0;
+        bool found = false;
+        uint32_t last = 0;
+        for (uint32_t i = 0; i < nk; ++i) {
+            const double wi = gram_weight<DIM>(M + i * D2, r);
+            cum += wi;
+            const bool take = !found && cum > thr;
+            j = take ? i : j;
+            wj = take ? wi : wj;
+            found = found || take;
+            last = (wi > 0.0) ? i : last;
+            w_last = (wi > 0.0) ? wi : w_last;
+        }
+        if (!found) {
+            j = last;
+            wj = w_last;
+        }
         mats = M + nk * D2;
     }
-    double wj;
-    uint32_t j = draw_index(w, nk, u, wj);
     if (WIDE) j = uni(j);        // one trajectory per wave: the operator's loads are scalar
     apply_mat<MASK, false>(x, y, mats + j * D2);
     if (!mixed) {
@@ -215,7 +213,7 @@ __device__ __forceinline__ void traj_diag(const double2 (&x)[16], double2 (&y)[1
 template <bool WIDE>
 __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
                                         const double2 *__restrict__ pool, const TCtx &c, double u, uint32_t log_tt,
-                                        double *red, uint32_t wave, uint32_t wpt)
+                                        double *red, uint32_t wave, uint32_t wpt, uint32_t &flip)
 {
     const uint32_t kind = uni(op->kind);
     const uint32_t mask = uni(op->mask);
@@ -236,7 +234,7 @@ __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16]
     } else {
         switch (mask) {
 #define VQD_TCH(m) \
-    case m: traj_channel<m, WIDE>(x, y, op, M, u, log_tt, red, wave, wpt); break;
+    case m: traj_channel<m, WIDE>(x, y, op, M, u, log_tt, red, wave, wpt, flip); break;
         VQD_TCH(1) VQD_TCH(2) VQD_TCH(4) VQD_TCH(8) VQD_TCH(3) VQD_TCH(5) VQD_TCH(6) VQD_TCH(9)
         VQD_TCH(10) VQD_TCH(12)
 #undef VQD_TCH
@@ -245,10 +243,44 @@ __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16]
     }
 }
 
+// The uniforms of one trajectory, fetched in blocks: the LG = min(2^log_tt,
+// 64) lanes of a trajectory inside a wave hold one block of LG consecutive
+// channels (lane j channel base + j) and the next block is loaded one block
+// ahead.  Channels are met in increasing order (the same order in every
+// trajectory of the workgroup), so a channel's uniform is a lane shuffle.
+struct UBlock {
+    const double *row;   // this trajectory's uniforms
+    uint32_t n_ch, lg, gl0, LG;
+    uint32_t base;       // first channel of the current block
+    double cur, nxt;
+
+    __device__ __forceinline__ void start(const double *r, uint32_t nch, uint32_t log_tt)
+    {
+        row = r;
+        n_ch = nch;
+        LG = 1u << (log_tt < 6 ? log_tt : 6);
+        const uint32_t lane = threadIdx.x & 63u;
+        lg = lane & (LG - 1u);
+        gl0 = lane & ~(LG - 1u);
+        base = 0;
+        cur = (lg < n_ch) ? row[lg] : 0.0;
+        nxt = (LG + lg < n_ch) ? row[LG + lg] : 0.0;
+    }
+
+    __device__ __forceinline__ double take(uint32_t ch)
+    {
+        if (ch >= base + LG) {           // workgroup-uniform
+            cur = nxt;
+            base += LG;
+            const uint32_t k = base + LG + lg;
+            nxt = (k < n_ch) ? row[k] : 0.0;
+        }
+        return __shfl(cur, (int)(gl0 + (ch - base)));
+    }
+};
+
 // One batch of trajectories.  Workgroup g of the persistent loop holds
 // blockDim / 2^log_tt trajectories; group grp's threads are tid >> log_tt.
-// Channels are met in increasing channel order, so the uniform of the next
-// channel is prefetched while the ops before it run.
 template <bool WIDE>
 __global__ void __launch_bounds__(512)
 k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restrict__ ops,
@@ -266,13 +298,14 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
     double2 *xl = lds + (size_t)grp * TT * 16;
     const uint64_t n_groups = (T + tpw - 1) / tpw;
     const uint32_t dim = 1u << n;
+    uint32_t flip = 0;
 
     for (uint64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
         const uint64_t traj = g * tpw + grp;
         const bool active = traj < T;
-        const double *Urow = U + (active ? traj : T - 1) * (uint64_t)n_ch;
+        UBlock ub;
+        ub.start(U + (active ? traj : T - 1) * (uint64_t)n_ch, n_ch, log_tt);
         uint32_t next_ch = 0;
-        double u_next = (n_ch > 0) ? Urow[0] : 0.0;
         double2 a[16], b[16];
         TCtx c;
         for (uint32_t ph = 0; ph < n_phases; ++ph) {
@@ -292,20 +325,12 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
             const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
             for (uint32_t oi = ob; oi < oe; oi += 2) {
                 double u = 0.0;
-                if (uni(ops[oi].kind) >= TOP_MIX) {
-                    u = u_next;
-                    ++next_ch;
-                    u_next = (next_ch < n_ch) ? Urow[next_ch] : 0.0;
-                }
-                traj_op<WIDE>(a, b, ops + oi, pool, c, u, log_tt, red, wave, wpt);
+                if (uni(ops[oi].kind) >= TOP_MIX) u = ub.take(next_ch++);
+                traj_op<WIDE>(a, b, ops + oi, pool, c, u, log_tt, red, wave, wpt, flip);
                 if (oi + 1 < oe) {
                     u = 0.0;
-                    if (uni(ops[oi + 1].kind) >= TOP_MIX) {
-                        u = u_next;
-                        ++next_ch;
-                        u_next = (next_ch < n_ch) ? Urow[next_ch] : 0.0;
-                    }
-                    traj_op<WIDE>(b, a, ops + oi + 1, pool, c, u, log_tt, red, wave, wpt);
+                    if (uni(ops[oi + 1].kind) >= TOP_MIX) u = ub.take(next_ch++);
+                    traj_op<WIDE>(b, a, ops + oi + 1, pool, c, u, log_tt, red, wave, wpt, flip);
                 } else {
 #pragma unroll
                     for (int e = 0; e < 16; ++e) a[e] = b[e];
@@ -330,7 +355,7 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
 #pragma unroll
             for (int q = 0; q < kTrajMaxQubits; ++q) r[q] += ((xi >> q) & 1u) ? -p : p;
         }
-        group_sum<kTrajRed, WIDE>(r, log_tt, red, wave, wpt);
+        group_sum<kTrajRed, WIDE>(r, log_tt, red, wave, wpt, flip);
         if (active) {
             if (tt == 0) {
                 for (uint32_t q = 0; q < n; ++q) z_out[traj * n + q] = r[q];
@@ -398,7 +423,7 @@ int launch_traj(const TPhase *phases, uint32_t n_phases, const TOp *ops, const d
     if (T == 0) return VQD_OK;
     const uint32_t log_tt = (uint32_t)(n_eff - 4);
     const uint32_t threads = (log_tt == 9) ? 512u : 256u;
-    const size_t lds = size_t(threads) * 16 * sizeof(double2) + size_t(kTrajMaxWaves) * kTrajRed * sizeof(double);
+    const size_t lds = size_t(threads) * 16 * sizeof(double2) + size_t(2 * kTrajMaxWaves) * kTrajRed * sizeof(double);
     const bool wide = log_tt >= 6;
     const void *kfn = wide ? (const void *)k_traj<true> : (const void *)k_traj<false>;
     static bool attr_set = false;

@@ -207,7 +207,7 @@ constexpr int kTrajMaxKraus = 16;
 enum TOpKind : uint32_t {
     TOP_MAT = 1,      // dense matrix on register bits `mask` (column-major; real ones packed)
     TOP_DIAG = 2,     // diagonal factors, index bit j = bit dq[j] of the amplitude index
-    TOP_MIX = 3,      // mixed-unitary channel: nk weights (in .x), then nk unitaries
+    TOP_MIX = 3,      // mixed-unitary channel: nk (running sum of weights, weight), then nk unitaries
     TOP_KRAUS = 4,    // general channel: nk Gram matrices K^dagger K (row-major), then nk
                       // Kraus matrices (column-major)
 };

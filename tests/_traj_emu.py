@@ -107,7 +107,8 @@ def run(plan: dict, U: np.ndarray):
                 if t == 0:
                     order.append(int(op["chan"]))
                 if kind == TOP_MIX:
-                    w = list(pool[off:off + nk].real)
+                    w = list(pool[off:off + nk].imag)
+                    assert np.array_equal(pool[off:off + nk].real, np.cumsum(w))
                     mats = off + nk
                 else:
                     rho = _reduced(psi, qs)
