@@ -105,5 +105,13 @@ __device__ __forceinline__ uint32_t slot_l(const uint32_t (&rl)[4], int e)
     return ((e & 1) ? rl[0] : 0) | ((e & 2) ? rl[1] : 0) | ((e & 4) ? rl[2] : 0) | ((e & 8) ? rl[3] : 0);
 }
 
+// Thread id of this lane within the workgroup, from the wave's base (the
+// lane count is opaque to the compiler, so values derived from it are
+// recomputed rather than kept live).
+__device__ __forceinline__ uint32_t lane_tid(uint32_t wave_base)
+{
+    return wave_base + __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
 }  // namespace
 }  // namespace vqd

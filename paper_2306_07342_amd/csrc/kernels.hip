@@ -153,12 +153,6 @@ __device__ __forceinline__ void thread_bits(const KPhase *__restrict__ H, uint32
     }
 }
 
-// Thread id of this lane within the workgroup, from the wave's base.
-__device__ __forceinline__ uint32_t lane_tid(uint32_t wave_base)
-{
-    return wave_base + __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
 // Fully unrolled over the fixed maximum so that the descriptor reads are
 // scalar loads: a vector load here would make the compiler wait for the
 // outstanding prefetch of the next tile.

@@ -38,8 +38,12 @@ struct TCtx {
 
 // Amplitude-index bits of thread tt of a trajectory in phase H (thread bit i
 // carries qubit thr_q[i]; unused entries are zero and tt has no bit there).
+// The empty asm hides tt's value from the compiler, so the per-bit values are
+// recomputed in every phase instead of being hoisted out of the phase loop
+// and kept live (or spilled) across it.
 __device__ __forceinline__ uint32_t traj_thread_bits(const TPhase *__restrict__ H, uint32_t tt)
 {
+    asm volatile("" : "+v"(tt));
     uint32_t tl = 0;
 #pragma unroll
     for (uint32_t i = 0; i < (uint32_t)kTrajMaxThreadBits; ++i) tl |= ((tt >> i) & 1u) << (uni(H->thr_q[i]) & 31u);
@@ -71,12 +75,14 @@ __device__ __forceinline__ void group_sum(double (&v)[CNT], uint32_t log_tt, dou
             for (int i = 0; i < CNT; ++i) buf[wave * kTrajRed + i] = v[i];
         }
         __syncthreads();
-        const uint32_t w0 = wave & ~(wpt - 1u);
+        // the trajectory's first wave and the wave count are wave-uniform
+        const double *p = buf + uni((wave & ~(wpt - 1u)) * kTrajRed);
 #pragma unroll
-        for (int i = 0; i < CNT; ++i) {
-            double s = buf[w0 * kTrajRed + i];
-            for (uint32_t w = 1; w < wpt; ++w) s += buf[(w0 + w) * kTrajRed + i];
-            v[i] = s;
+        for (int i = 0; i < CNT; ++i) v[i] = p[i];
+        for (uint32_t w = 1; w < wpt; ++w) {
+            p += kTrajRed;
+#pragma unroll
+            for (int i = 0; i < CNT; ++i) v[i] += p[i];
         }
     }
 }
@@ -201,11 +207,14 @@ __device__ __forceinline__ void traj_diag(const double2 (&x)[16], double2 (&y)[1
         d2 = M[2];
         d3 = M[3];
     }
+    // a qubit is either a thread bit or a register bit: the thread's part of
+    // the factor index once, the slot's part (workgroup-uniform) per slot
+    const uint32_t tb = ((c.tl >> q0) & 1u) | ((nd > 1) ? (((c.tl >> q1) & 1u) << 1) : 0u);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const uint32_t xi = c.tl | slot_l(c.rl, e);
-        const uint32_t b0 = (xi >> q0) & 1u, b1 = (nd > 1) ? ((xi >> q1) & 1u) : 0u;
-        const double2 f = b1 ? (b0 ? d3 : d2) : (b0 ? d1 : d0);
+        const uint32_t sl = slot_l(c.rl, e);
+        const uint32_t idx = tb | ((sl >> q0) & 1u) | ((nd > 1) ? (((sl >> q1) & 1u) << 1) : 0u);
+        const double2 f = (idx & 2u) ? ((idx & 1u) ? d3 : d2) : ((idx & 1u) ? d1 : d0);
         y[e] = cmul(f, x[e]);
     }
 }
@@ -267,6 +276,7 @@ struct UBlock {
         nxt = (LG + lg < n_ch) ? row[LG + lg] : 0.0;
     }
 
+    template <bool WIDE>
     __device__ __forceinline__ double take(uint32_t ch)
     {
         if (ch >= base + LG) {           // workgroup-uniform
@@ -274,6 +284,13 @@ struct UBlock {
             base += LG;
             const uint32_t k = base + LG + lg;
             nxt = (k < n_ch) ? row[k] : 0.0;
+        }
+        if (WIDE) {                      // one trajectory per wave: the lane is uniform
+            const int src = (int)(ch - base);
+            const uint64_t bits = __double_as_longlong(cur);
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)bits, src);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(bits >> 32), src);
+            return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
         }
         return __shfl(cur, (int)(gl0 + (ch - base)));
     }
@@ -293,7 +310,7 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
     const uint32_t TT = 1u << log_tt;
     const uint32_t tpw = blockDim.x >> log_tt;
     const uint32_t grp = tid >> log_tt, tt = tid & (TT - 1u);
-    const uint32_t wave = tid >> 6, wpt = WIDE ? (TT >> 6) : 1u;
+    const uint32_t wave = uni(tid >> 6), wpt = WIDE ? (TT >> 6) : 1u;
     double *red = reinterpret_cast<double *>(lds + (size_t)blockDim.x * 16);
     double2 *xl = lds + (size_t)grp * TT * 16;
     const uint64_t n_groups = (T + tpw - 1) / tpw;
@@ -325,11 +342,11 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
             const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
             for (uint32_t oi = ob; oi < oe; oi += 2) {
                 double u = 0.0;
-                if (uni(ops[oi].kind) >= TOP_MIX) u = ub.take(next_ch++);
+                if (uni(ops[oi].kind) >= TOP_MIX) u = ub.take<WIDE>(next_ch++);
                 traj_op<WIDE>(a, b, ops + oi, pool, c, u, log_tt, red, wave, wpt, flip);
                 if (oi + 1 < oe) {
                     u = 0.0;
-                    if (uni(ops[oi + 1].kind) >= TOP_MIX) u = ub.take(next_ch++);
+                    if (uni(ops[oi + 1].kind) >= TOP_MIX) u = ub.take<WIDE>(next_ch++);
                     traj_op<WIDE>(b, a, ops + oi + 1, pool, c, u, log_tt, red, wave, wpt, flip);
                 } else {
 #pragma unroll
@@ -337,8 +354,11 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
                 }
             }
             if (ph + 1 < n_phases) {
+                // the thread bits formed again rather than kept (with the
+                // 16 slot addresses) live across the ops
+                const uint32_t tlw = traj_thread_bits(H, tt);
 #pragma unroll
-                for (int e = 0; e < 16; ++e) xl[swz(c.tl | slot_l(c.rl, e))] = a[e];
+                for (int e = 0; e < 16; ++e) xl[swz(tlw | slot_l(c.rl, e))] = a[e];
                 __syncthreads();
             }
         }
