@@ -202,13 +202,43 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
         const int nq = (int)o.qs.size(), d = 1 << nq;
         if (!o.chan) {
             if (o.diag && nq <= 2) {
-                k.kind = TOP_DIAG;
-                k.nd = (uint32_t)nq;
-                k.dq[0] = (uint32_t)o.qs[0];
-                k.dq[1] = nq > 1 ? (uint32_t)o.qs[1] : 0u;
+                // where the qubits are: register bit or -1 (a thread qubit)
+                int rb[2] = {-1, -1};
+                for (int j = 0; j < nq; ++j)
+                    for (int b = 0; b < 4; ++b)
+                        if (R[b] == o.qs[j]) rb[j] = b;
+                const int n_reg = (rb[0] >= 0) + (nq > 1 && rb[1] >= 0);
+                bool real = true;
+                for (int x = 0; x < d; ++x) real = real && o.M[size_t(x) * d + x].imag() == 0.0;
                 k.mat = (uint32_t)t->pool.size();
-                for (int x = 0; x < d; ++x) t->pool.push_back(o.M[size_t(x) * d + x]);
-                t->fma_per_amp += 4.0;
+                k.real = real ? 1u : 0u;
+                if (n_reg == nq) {
+                    // factor of register slot e: matrix index bit j = slot bit rb[j]
+                    k.kind = TOP_DREG;
+                    for (int e = 0; e < 16; ++e) {
+                        int x = 0;
+                        for (int j = 0; j < nq; ++j) x |= ((e >> rb[j]) & 1) << j;
+                        t->pool.push_back(o.M[size_t(x) * d + x]);
+                    }
+                } else if (n_reg == 0) {
+                    k.kind = TOP_DTHR;
+                    k.nd = (uint32_t)nq;
+                    k.dq[0] = (uint32_t)o.qs[0];
+                    k.dq[1] = nq > 1 ? (uint32_t)o.qs[1] : 0u;
+                    for (int x = 0; x < d; ++x) t->pool.push_back(o.M[size_t(x) * d + x]);
+                } else {
+                    // one register qubit jr, one thread qubit jt
+                    const int jr = rb[0] >= 0 ? 0 : 1, jt = 1 - jr;
+                    k.kind = TOP_DMIX;
+                    k.mask = 1u << rb[jr];
+                    k.dq[0] = (uint32_t)o.qs[jt];
+                    for (int tb = 0; tb < 2; ++tb)
+                        for (int r = 0; r < 2; ++r) {
+                            const int x = (tb << jt) | (r << jr);
+                            t->pool.push_back(o.M[size_t(x) * d + x]);
+                        }
+                }
+                t->fma_per_amp += real ? 2.0 : 4.0;
             } else {
                 bool real = true;
                 for (const cd &z : o.M) real = real && z.imag() == 0.0;
@@ -384,9 +414,20 @@ int plan(vqd_traj *t)
         TPhase ph{};
         ph.op_begin = (uint32_t)t->kops.size();
         for (int b = 0; b < 4; ++b) ph.reg_q[b] = (uint32_t)R[b];
-        int ti = 0;
+        // thread qubits: the first three (lane bits 0-2) at index positions of
+        // residue 0, 1, 2 mod 3 where possible, which the LDS index swizzle
+        // spreads over distinct 16-byte bank groups; the rest ascending
+        std::vector<int> rest;
         for (int q = 0; q < ne; ++q)
-            if (std::find(R.begin(), R.end(), q) == R.end()) ph.thr_q[ti++] = (uint32_t)q;
+            if (std::find(R.begin(), R.end(), q) == R.end()) rest.push_back(q);
+        int ti = 0;
+        for (int i = 0; i < 3 && !rest.empty(); ++i) {
+            auto it = std::find_if(rest.begin(), rest.end(), [&](int q) { return q % 3 == i && q < 12; });
+            if (it == rest.end()) it = rest.begin();
+            ph.thr_q[ti++] = (uint32_t)*it;
+            rest.erase(it);
+        }
+        for (int q : rest) ph.thr_q[ti++] = (uint32_t)q;
         if (int rc = encode_phase(t, R.data(), fused)) return rc;
         ph.op_end = (uint32_t)t->kops.size();
         t->phases.push_back(ph);

@@ -31,6 +31,8 @@ namespace {
 constexpr int kTrajRed = 16;          // values in one group reduction
 constexpr int kTrajMaxWaves = 8;      // waves of the largest workgroup (512 threads)
 
+__device__ __forceinline__ bool is_channel(uint32_t kind) { return kind == TOP_MIX || kind == TOP_KRAUS; }
+
 struct TCtx {
     uint32_t tl;      // amplitude-index bits from the thread id
     uint32_t rl[4];   // amplitude-index bit of register bit b
@@ -195,28 +197,44 @@ __device__ __forceinline__ void traj_channel(const double2 (&x)[16], double2 (&y
     }
 }
 
-// Diagonal gate on one or two qubits anywhere in the index: factor index
-// bit j is bit dq[j] of the amplitude index.
-__device__ __forceinline__ void traj_diag(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+// Diagonal gates.  On register qubits only: one uniform factor per slot.
+template <bool REAL>
+__device__ __forceinline__ void traj_dreg(const double2 (&x)[16], double2 (&y)[16], const double2 *__restrict__ M)
+{
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const double2 f = M[e];
+        y[e] = REAL ? make_double2(f.x * x[e].x, f.x * x[e].y) : cmul(f, x[e]);
+    }
+}
+
+// On thread qubits only: one factor per thread, from its thread bits.
+__device__ __forceinline__ void traj_dthr(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
                                           const double2 *__restrict__ M, const TCtx &c)
 {
     const uint32_t nd = uni(op->nd), q0 = uni(op->dq[0]) & 31u, q1 = uni(op->dq[1]) & 31u;
+    const uint32_t tb = ((c.tl >> q0) & 1u) | ((nd > 1) ? (((c.tl >> q1) & 1u) << 1) : 0u);
     const double2 d0 = M[0], d1 = M[1];
     double2 d2 = d0, d3 = d1;
     if (nd > 1) {
         d2 = M[2];
         d3 = M[3];
     }
-    // a qubit is either a thread bit or a register bit: the thread's part of
-    // the factor index once, the slot's part (workgroup-uniform) per slot
-    const uint32_t tb = ((c.tl >> q0) & 1u) | ((nd > 1) ? (((c.tl >> q1) & 1u) << 1) : 0u);
+    const double2 f = (tb & 2u) ? ((tb & 1u) ? d3 : d2) : ((tb & 1u) ? d1 : d0);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const uint32_t sl = slot_l(c.rl, e);
-        const uint32_t idx = tb | ((sl >> q0) & 1u) | ((nd > 1) ? (((sl >> q1) & 1u) << 1) : 0u);
-        const double2 f = (idx & 2u) ? ((idx & 1u) ? d3 : d2) : ((idx & 1u) ? d1 : d0);
-        y[e] = cmul(f, x[e]);
-    }
+    for (int e = 0; e < 16; ++e) y[e] = cmul(f, x[e]);
+}
+
+// One register qubit (bit MASK) and one thread qubit: two factors per thread,
+// the slot's register bit picks one.
+template <int MASK>
+__device__ __forceinline__ void traj_dmix(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+                                          const double2 *__restrict__ M, const TCtx &c)
+{
+    const uint32_t tb = (c.tl >> (uni(op->dq[0]) & 31u)) & 1u;
+    const double2 f0 = tb ? M[2] : M[0], f1 = tb ? M[3] : M[1];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) y[e] = cmul((e & MASK) ? f1 : f0, x[e]);
 }
 
 template <bool WIDE>
@@ -238,8 +256,18 @@ __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16]
 #undef VQD_TMAT
         default: break;
         }
-    } else if (kind == TOP_DIAG) {
-        traj_diag(x, y, op, M, c);
+    } else if (kind == TOP_DREG) {
+        if (uni(op->real)) traj_dreg<true>(x, y, M);
+        else traj_dreg<false>(x, y, M);
+    } else if (kind == TOP_DTHR) {
+        traj_dthr(x, y, op, M, c);
+    } else if (kind == TOP_DMIX) {
+        switch (mask) {
+        case 1: traj_dmix<1>(x, y, op, M, c); break;
+        case 2: traj_dmix<2>(x, y, op, M, c); break;
+        case 4: traj_dmix<4>(x, y, op, M, c); break;
+        default: traj_dmix<8>(x, y, op, M, c); break;
+        }
     } else {
         switch (mask) {
 #define VQD_TCH(m) \
@@ -313,6 +341,11 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
     const uint32_t wave = uni(tid >> 6), wpt = WIDE ? (TT >> 6) : 1u;
     double *red = reinterpret_cast<double *>(lds + (size_t)blockDim.x * 16);
     double2 *xl = lds + (size_t)grp * TT * 16;
+    // LDS index of amplitude t | s (thread part t, slot part s) is
+    // swz(t) ^ swz(s) ^ gx: the swizzle is xor-linear, so the slot part is
+    // workgroup-uniform.  gx permutes the low index bits by trajectory so
+    // that lanes of different trajectories in one wave spread over the banks.
+    const uint32_t gx = (grp << log_tt) & 7u;
     const uint64_t n_groups = (T + tpw - 1) / tpw;
     const uint32_t dim = 1u << n;
     uint32_t flip = 0;
@@ -335,18 +368,19 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
                 for (int e = 0; e < 16; ++e)
                     a[e] = make_double2(((c.tl | slot_l(c.rl, e)) == 0u) ? 1.0 : 0.0, 0.0);
             } else {
+                const uint32_t lt = swz(c.tl) ^ gx;
 #pragma unroll
-                for (int e = 0; e < 16; ++e) a[e] = xl[swz(c.tl | slot_l(c.rl, e))];
+                for (int e = 0; e < 16; ++e) a[e] = xl[lt ^ swz(slot_l(c.rl, e))];
                 __syncthreads();
             }
             const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
             for (uint32_t oi = ob; oi < oe; oi += 2) {
                 double u = 0.0;
-                if (uni(ops[oi].kind) >= TOP_MIX) u = ub.take<WIDE>(next_ch++);
+                if (is_channel(uni(ops[oi].kind))) u = ub.take<WIDE>(next_ch++);
                 traj_op<WIDE>(a, b, ops + oi, pool, c, u, log_tt, red, wave, wpt, flip);
                 if (oi + 1 < oe) {
                     u = 0.0;
-                    if (uni(ops[oi + 1].kind) >= TOP_MIX) u = ub.take<WIDE>(next_ch++);
+                    if (is_channel(uni(ops[oi + 1].kind))) u = ub.take<WIDE>(next_ch++);
                     traj_op<WIDE>(b, a, ops + oi + 1, pool, c, u, log_tt, red, wave, wpt, flip);
                 } else {
 #pragma unroll
@@ -354,11 +388,9 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
                 }
             }
             if (ph + 1 < n_phases) {
-                // the thread bits formed again rather than kept (with the
-                // 16 slot addresses) live across the ops
-                const uint32_t tlw = traj_thread_bits(H, tt);
+                const uint32_t lt = swz(traj_thread_bits(H, tt)) ^ gx;
 #pragma unroll
-                for (int e = 0; e < 16; ++e) xl[swz(tlw | slot_l(c.rl, e))] = a[e];
+                for (int e = 0; e < 16; ++e) xl[lt ^ swz(slot_l(c.rl, e))] = a[e];
                 __syncthreads();
             }
         }

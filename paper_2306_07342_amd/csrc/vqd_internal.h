@@ -206,10 +206,14 @@ constexpr int kTrajMaxKraus = 16;
 
 enum TOpKind : uint32_t {
     TOP_MAT = 1,      // dense matrix on register bits `mask` (column-major; real ones packed)
-    TOP_DIAG = 2,     // diagonal factors, index bit j = bit dq[j] of the amplitude index
+    TOP_DTHR = 2,     // diagonal gate on thread qubits only: 2^nd factors, index bit j = bit dq[j]
+                      // of the amplitude index (one factor per thread)
     TOP_MIX = 3,      // mixed-unitary channel: nk (running sum of weights, weight), then nk unitaries
     TOP_KRAUS = 4,    // general channel: nk Gram matrices K^dagger K (row-major), then nk
                       // Kraus matrices (column-major)
+    TOP_DREG = 5,     // diagonal gate on register qubits only: 16 factors, one per register slot
+    TOP_DMIX = 6,     // two-qubit diagonal gate, one register qubit (bit `mask`) and one thread
+                      // qubit dq[0]: factors (thread bit, register bit) = 00, 01, 10, 11
 };
 
 struct alignas(16) TOp {
@@ -219,9 +223,9 @@ struct alignas(16) TOp {
     uint32_t real;    // TOP_MAT: real coefficients, packed two per entry
     uint32_t nk;      // TOP_MIX / TOP_KRAUS: number of operators
     uint32_t chan;    // TOP_MIX / TOP_KRAUS: channel index (column of the uniforms)
-    uint32_t nd;      // TOP_DIAG: number of qubits (1 or 2)
+    uint32_t nd;      // TOP_DTHR: number of qubits (1 or 2)
     uint32_t pad0;
-    uint32_t dq[2];   // TOP_DIAG: the qubits, dq[0] the low bit of the factor index
+    uint32_t dq[2];   // TOP_DTHR / TOP_DMIX: thread qubits, dq[0] the low bit of the factor index
     uint32_t pad1[2];
 };
 

@@ -17,7 +17,7 @@ import numpy as np
 from oracle.trajectories import apply_matrix
 
 MAGIC = 0x54445156
-TOP_MAT, TOP_DIAG, TOP_MIX, TOP_KRAUS = 1, 2, 3, 4
+TOP_MAT, TOP_DTHR, TOP_MIX, TOP_KRAUS, TOP_DREG, TOP_DMIX = 1, 2, 3, 4, 5, 6
 
 PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4", 9), ("pad", "<u4")])
 OP = np.dtype([("kind", "<u4"), ("mask", "<u4"), ("mat", "<u4"), ("real", "<u4"), ("nk", "<u4"),
@@ -93,10 +93,26 @@ def run(plan: dict, U: np.ndarray):
         for ph in plan["phases"]:
             for op in plan["ops"][int(ph["ob"]):int(ph["oe"])]:
                 kind = int(op["kind"])
-                if kind == TOP_DIAG:
+                if kind == TOP_DTHR:
                     qs = [int(q) for q in op["dq"][:int(op["nd"])]]
+                    assert not set(qs) & set(int(q) for q in ph["reg"])
                     f = pool[int(op["mat"]):int(op["mat"]) + (1 << len(qs))]
                     psi = apply_matrix(psi, qs, np.diag(f))
+                    continue
+                if kind == TOP_DREG:
+                    # 16 factors by register slot: the diagonal on the four register qubits
+                    f = pool[int(op["mat"]):int(op["mat"]) + 16]
+                    if op["real"]:
+                        assert np.all(f.imag == 0)
+                    psi = apply_matrix(psi, [int(q) for q in ph["reg"]], np.diag(f))
+                    continue
+                if kind == TOP_DMIX:
+                    # factor index: register qubit the low bit, thread qubit the high bit
+                    qr = _qubits(op["mask"], ph["reg"])
+                    assert len(qr) == 1
+                    qt = int(op["dq"][0])
+                    f = pool[int(op["mat"]):int(op["mat"]) + 4]
+                    psi = apply_matrix(psi, [qr[0], qt], np.diag(f))
                     continue
                 qs = _qubits(op["mask"], ph["reg"])
                 d = 1 << len(qs)

@@ -57,7 +57,7 @@ def test_named_gates_and_channels(vqd_host):
            ("deph_t2", (3,), (0.5, 1.0))]
     _, plan = check_plan(vqd_host, n, ops * 3, T=24)
     kinds = set(int(k) for k in plan["ops"]["kind"])
-    assert kinds == {emu.TOP_MAT, emu.TOP_DIAG, emu.TOP_MIX, emu.TOP_KRAUS}
+    assert kinds == {emu.TOP_MAT, emu.TOP_DTHR, emu.TOP_DREG, emu.TOP_DMIX, emu.TOP_MIX, emu.TOP_KRAUS}
 
 
 def test_workload_circuits(vqd_host):
