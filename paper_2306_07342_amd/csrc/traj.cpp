@@ -346,32 +346,26 @@ int plan(vqd_traj *t)
     auto needs_regs = [&](const TIn &o) { return o.chan || !o.diag || o.k > 2; };
     uint32_t expect_chan = 0;
     while (head < pending.size()) {
-        // register qubits: those of the first movable ops that need them
+        // the register qubits and the phase's ops together: walk the pending
+        // ops in order and take each op that commutes with every earlier
+        // pending op and whose qubits fit the register set (which grows up
+        // to four qubits), until a walk takes nothing
         std::vector<int> R;
-        const size_t lim = std::min(pending.size(), head + kWindow);
-        for (size_t p = head; p < lim && R.size() < 4; ++p) {
-            const TIn &o = ops[pending[p]];
-            if (!needs_regs(o) || !movable(p)) continue;
-            std::vector<int> u = R;
-            for (int j = 0; j < o.k; ++j)
-                if (std::find(u.begin(), u.end(), o.q[j]) == u.end()) u.push_back(o.q[j]);
-            if (u.size() <= 4) R = u;
-        }
-        for (int q = 0; q < ne && R.size() < 4; ++q)
-            if (std::find(R.begin(), R.end(), q) == R.end()) R.push_back(q);
-        std::sort(R.begin(), R.end());
-        // take every movable op that fits, until none does
         std::vector<POp> taken;
         bool progress = true;
         while (progress) {
             progress = false;
-            const size_t lim2 = std::min(pending.size(), head + kWindow);
-            for (size_t p = head; p < lim2; ++p) {
+            const size_t lim = std::min(pending.size(), head + kWindow);
+            for (size_t p = head; p < lim; ++p) {
                 const TIn &o = ops[pending[p]];
-                bool fits = true;
-                if (needs_regs(o))
-                    for (int j = 0; j < o.k; ++j) fits = fits && std::find(R.begin(), R.end(), o.q[j]) != R.end();
-                if (!fits || !movable(p)) continue;
+                if (!movable(p)) continue;
+                if (needs_regs(o)) {
+                    std::vector<int> u = R;
+                    for (int j = 0; j < o.k; ++j)
+                        if (std::find(u.begin(), u.end(), o.q[j]) == u.end()) u.push_back(o.q[j]);
+                    if (u.size() > 4) continue;
+                    R = u;
+                }
                 POp po;
                 po.chan = o.chan;
                 po.diag = o.diag;
@@ -388,6 +382,9 @@ int plan(vqd_traj *t)
                 progress = true;
             }
         }
+        for (int q = 0; q < ne && R.size() < 4; ++q)
+            if (std::find(R.begin(), R.end(), q) == R.end()) R.push_back(q);
+        std::sort(R.begin(), R.end());
         if (taken.empty()) return fail(VQD_E_STATE, "internal: planner made no progress");
         // fuse consecutive gates whose qubit sets nest
         std::vector<POp> fused;
