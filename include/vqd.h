@@ -348,6 +348,30 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
 
 /* ------------------------------------------------------------- surrogate */
 
+/* Measurement (the read-out of the devices of Secs. 4-6; the parity
+ * measurement of eq. (m); the simulated shots of Sec. 6).
+ *
+ * vqd_measure_z: projective measurement of qubit q in the computational
+ * basis.  The outcome weights are w_m = Re Tr(P_m rho), P_m = |m><m| on q;
+ * with the caller's uniform u in [0, 1) the outcome is 0 if w_0 > u (w_0 +
+ * w_1), else 1 (the draw rule of the trajectory calls).  rho becomes
+ * P_m rho P_m / w_m in place.  *outcome gets m, *weight (may be NULL) w_m.
+ * Synchronises the handle's stream (the weights come back to the host), then
+ * enqueues the collapse.  VQD_E_STATE if both weights are <= 0.
+ *
+ * vqd_measure_parity: eq. (m) on (q0, q1): outcome 0 for the odd-parity
+ * projector |01><01| + |10><10|, 1 for the even one; otherwise as above.
+ *
+ * vqd_sample: `shots` basis states from the diagonal probabilities
+ * p_x = max(0, Re rho[x][x]): for shot s the smallest x whose running sum
+ * p_0 + ... + p_x (formed left to right) exceeds uniforms[s] W, W the sum
+ * of all p_x; the last x with p_x > 0 if rounding leaves none.  uniforms
+ * ([shots] doubles in [0, 1)) and out ([shots] uint32, bit q = qubit q) are
+ * caller-owned device arrays; asynchronous on the handle's stream. */
+int vqd_measure_z(vqd_dm *dm, int q, double u, int *outcome, double *weight);
+int vqd_measure_parity(vqd_dm *dm, int q0, int q1, double u, int *outcome, double *weight);
+int vqd_sample(vqd_dm *dm, const double *uniforms, long long shots, uint32_t *out);
+
 /* Monte Carlo trajectories on state vectors: the paper's alternative to the
  * density matrix (Sec. 2, where QuESTlink replaces each channel by one
  * operator drawn from its Kraus map and averages expected values over many

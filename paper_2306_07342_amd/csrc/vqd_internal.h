@@ -241,6 +241,13 @@ int launch_traj(const TPhase *phases, uint32_t n_phases, const TOp *ops, const d
                 double *state_out, hipStream_t stream);
 int launch_traj_stats(const double *x, uint64_t T, int m, double *mean, double *sem, hipStream_t stream);
 
+// ----------------------------------------------------------- measurement --
+enum MeasKind : uint32_t { MEAS_Z = 0, MEAS_PARITY = 1 };
+int launch_project(double2 *amps, int n, int kind, int q0, int q1, int m, double scale, hipStream_t stream);
+// scratch: 2^(n+1) + 1 doubles of device memory
+int launch_sample(const double2 *amps, int n, double *scratch, const double *U, uint64_t shots, uint32_t *out,
+                  hipStream_t stream);
+
 // ------------------------------------------------------------- batched --
 // One density matrix of a batch (queue order).
 struct alignas(16) BatchItem {

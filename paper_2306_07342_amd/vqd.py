@@ -148,6 +148,9 @@ def load(path: str = LIB_PATH):
         "vqd_traj_info_get": ([vp, ctypes.POINTER(TrajInfo)], ctypes.c_int),
         "vqd_traj_run": ([vp, vp, ctypes.c_longlong, vp, vp, vp, vp], ctypes.c_int),
         "vqd_traj_stats": ([vp, ctypes.c_longlong, ctypes.c_int, vp, vp, vp], ctypes.c_int),
+        "vqd_measure_z": ([vp, ctypes.c_int, ctypes.c_double, _ip, _dp], ctypes.c_int),
+        "vqd_measure_parity": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip, _dp], ctypes.c_int),
+        "vqd_sample": ([vp, vp, ctypes.c_longlong, vp], ctypes.c_int),
         "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_calc_purity": ([vp, _dp], ctypes.c_int),
         "vqd_calc_probs": ([vp, _dp], ctypes.c_int),
@@ -325,6 +328,33 @@ class DensityMatrix:
         p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
         out = np.empty(p.shape[0])
         check(lib().vqd_calc_expec_zz(self.handle, _i(p), p.shape[0], _d(out)))
+        return out
+
+    def measure_z(self, q: int, u: float):
+        """Projective Z measurement of qubit q with uniform u (vqd_measure_z);
+        collapses the state, returns (outcome, weight)."""
+        m, w = ctypes.c_int(), ctypes.c_double()
+        check(lib().vqd_measure_z(self.handle, q, float(u), ctypes.byref(m), ctypes.byref(w)))
+        return m.value, w.value
+
+    def measure_parity(self, q0: int, q1: int, u: float):
+        """Parity measurement of eq. (m) (outcome 0 odd, 1 even); collapses the
+        state, returns (outcome, weight)."""
+        m, w = ctypes.c_int(), ctypes.c_double()
+        check(lib().vqd_measure_parity(self.handle, q0, q1, float(u), ctypes.byref(m), ctypes.byref(w)))
+        return m.value, w.value
+
+    def sample(self, uniforms, out=None):
+        """One basis state per uniform (a CUDA float64 tensor) from the diagonal
+        probabilities (vqd_sample); returns a CUDA int32 tensor of bit strings."""
+        import torch
+        if not (uniforms.is_cuda and uniforms.dtype == torch.float64 and uniforms.is_contiguous()):
+            raise ValueError("uniforms must be a contiguous CUDA float64 tensor")
+        shots = uniforms.numel()
+        if out is None:
+            out = torch.empty(shots, dtype=torch.int32, device=uniforms.device)
+        check(lib().vqd_sample(self.handle, ctypes.c_void_p(uniforms.data_ptr()), shots,
+                               ctypes.c_void_p(out.data_ptr())))
         return out
 
     def expec_pauli(self, codes) -> complex:
