@@ -276,6 +276,47 @@ def traj_leg(vqd, torch, n_traj: int, steps: int, oracle_sample: bool):
     return out
 
 
+def measure_leg(vqd, torch, dm, steps: int):
+    """Measurement on the 14-qubit state the main leg leaves: projective Z
+    measurement (weights, draw, collapse) and 2^20 shots from the diagonal."""
+    import numpy as np
+    n = dm.n
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    saved = dm.buffer.clone()
+    q = n // 2
+    # collapse alone: the kernel time of one measurement, from the library's
+    # own launch (the weights are reduced first and come back to the host)
+    t_meas = []
+    for _ in range(max(1, steps)):
+        dm.buffer.copy_(saved)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m, w = dm.measure_z(q, 0.25)
+        torch.cuda.synchronize()
+        t_meas.append(time.perf_counter() - t0)
+    shots = 1 << 20
+    U = torch.as_tensor(np.random.default_rng(7).random(shots), device="cuda")
+    out = torch.empty(shots, dtype=torch.int32, device="cuda")
+    dm.sample(U, out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(max(1, steps)):
+        dm.sample(U, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_shots = e0.elapsed_time(e1) / 1e3 / max(1, steps)
+    dm.buffer.copy_(saved)
+    amps = 4 ** n
+    # algorithmic bytes of the collapse: the quarter of the elements in the
+    # support read, every element written (16 B each)
+    coll_bytes = 16.0 * amps * (0.25 + 1.0)
+    return {"workload": "14-qubit grid-circuit state: measure_z(q=%d) and %d shots" % (q, shots),
+            "measure_z_ms": round(min(t_meas) * 1e3, 3), "outcome": m, "weight": w,
+            "collapse_algorithmic_bytes": coll_bytes,
+            "shots_per_s": round(shots / t_shots, 1), "sample_ms": round(t_shots * 1e3, 3)}
+
+
 def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
     """The learned surrogate of the 10-qubit, 4-layer ansatz (8 device
     parameters + 16 angles -> 10 <Z_i>): training data from the batched
@@ -453,6 +494,8 @@ def main():
         "roofline_other": alu if roof is hbm else hbm,
         "check": {"trace_re": tr.real, "purity": pur, "z0": float(z[0])},
     }
+    log("measurement leg ...")
+    out["measurement"] = measure_leg(vqd, torch, dm, args.steps)
     if not args.no_batched:
         log("batched leg ...")
         out["batched"] = batched_leg(vqd, torch, args.steps)

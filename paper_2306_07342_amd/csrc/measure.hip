@@ -7,7 +7,7 @@
 //                   written without being read.
 // * k_diag_probs -- the diagonal probabilities max(0, Re rho[x][x]) into a
 //                   contiguous array.
-// * k_cdf        -- their running sums, left to right in one thread (the
+// * k_cdf        -- their running sums, left to right in one wave (the
 //                   order the draw rule fixes; 2^n <= 65536 terms).
 // * k_sample     -- one basis state per uniform: binary search of the
 //                   running sums for the first one above u W.
@@ -57,20 +57,49 @@ k_diag_probs(const double2 *__restrict__ amps, uint32_t n, double *__restrict__ 
 }
 
 // cum[x] = p[0] + ... + p[x] formed left to right; cum[D] holds the last x
-// with p[x] > 0 (or 0), as a double.
-__global__ void k_cdf(const double *__restrict__ p, uint32_t n, double *__restrict__ cum)
+// with p[x] > 0 (or 0), as a double.  One wave: each block of 64 terms
+// arrives in one coalesced load (the next block is loaded while this one is
+// summed), the sum runs through the block term by term in every lane alike,
+// and lane j keeps the running sum at term j for one coalesced store.
+__device__ __forceinline__ double lane_value(double v, uint32_t j)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const uint32_t D = 1u << n;
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, (int)j);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), (int)j);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__global__ void __launch_bounds__(64) k_cdf(const double *__restrict__ p, uint32_t n, double *__restrict__ cum)
+{
+    const uint32_t lane = threadIdx.x, D = 1u << n;
     double s = 0.0;
     uint32_t last = 0;
-    for (uint32_t x = 0; x < D; ++x) {
-        const double v = p[x];
-        s += v;
-        cum[x] = s;
-        last = (v > 0.0) ? x : last;
+    double nxt = (lane < D) ? p[lane] : 0.0;
+    for (uint32_t base = 0; base < D; base += 64) {
+        const double v = nxt;
+        nxt = (base + 64 + lane < D) ? p[base + 64 + lane] : 0.0;
+        const uint32_t cnt = (D - base < 64u) ? D - base : 64u;
+        double mine = 0.0;
+        if (cnt == 64u) {
+            // unrolled: the lane reads do not depend on the sum and issue ahead
+#pragma unroll
+            for (uint32_t j = 0; j < 64u; ++j) {
+                const double x = lane_value(v, j);
+                s += x;
+                mine = (lane == j) ? s : mine;
+                last = (x > 0.0) ? base + j : last;
+            }
+        } else {
+            for (uint32_t j = 0; j < cnt; ++j) {
+                const double x = lane_value(v, j);
+                s += x;
+                mine = (lane == j) ? s : mine;
+                last = (x > 0.0) ? base + j : last;
+            }
+        }
+        if (lane < cnt) cum[base + lane] = mine;
     }
-    cum[D] = (double)last;
+    if (lane == 0) cum[D] = (double)last;
 }
 
 __global__ void __launch_bounds__(kMeasThreads)
