@@ -35,7 +35,7 @@ PLAN_OPTS = dict(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_block
 # WRITE_SIZE) on this workload; valid only for the kernel source it was taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_grid14_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_07342_amd", "csrc", f)
-                  for f in ("kernels.hip", "planner.cpp")]
+                  for f in ("kernels.hip", "dev_common.h", "planner.cpp")]
 
 
 def kernel_source_hash() -> str:
