@@ -394,6 +394,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-16q", action="store_true", help="skip the 16-qubit context leg")
     ap.add_argument("--no-traj", action="store_true", help="skip the trajectory leg")
+    ap.add_argument("--no-measure", action="store_true", help="skip the measurement leg")
     ap.add_argument("--trajectories", type=int, default=1 << 16, help="trajectories per launch")
     ap.add_argument("--surrogate-train", type=int, default=1 << 18, help="training samples (2^18)")
     ap.add_argument("--surrogate-test", type=int, default=1 << 14, help="held-out samples (2^14)")
@@ -494,8 +495,9 @@ def main():
         "roofline_other": alu if roof is hbm else hbm,
         "check": {"trace_re": tr.real, "purity": pur, "z0": float(z[0])},
     }
-    log("measurement leg ...")
-    out["measurement"] = measure_leg(vqd, torch, dm, args.steps)
+    if not args.no_measure:
+        log("measurement leg ...")
+        out["measurement"] = measure_leg(vqd, torch, dm, args.steps)
     if not args.no_batched:
         log("batched leg ...")
         out["batched"] = batched_leg(vqd, torch, args.steps)
