@@ -168,6 +168,18 @@ int vqd_kind_arity(int kind, int *n_qubits, int *n_params);
 int vqd_kind_matrix(int kind, const double *params, double *out);
 int vqd_kind_superop(int kind, const double *params, double *out);
 
+/* Error parameters from reported gate fidelities (App. B).  Entanglement
+ * fidelity of depolarising p_depol followed by dephasing p_deph on an
+ * nq-qubit gate (nq = 1: eq. fe1, 1 - p - q + 4/3 p q; nq = 2: 1 - p - q +
+ * 16/15 p q).  vqd_fidelity_to_errors splits a reported average fidelity
+ * fbar (converted by eq. fidelities_relation, F_e = ((d+1) fbar - 1)/d) into
+ * p_depol = x eps and p_deph = (1 - x) eps, x in [0, 1] the depolarising
+ * share, eps the smaller root in [0, 1]; VQD_E_ARG if there is none.
+ * vqd_angle_scaled_error: eps |theta| / pi (App. C, rotation-angle scaling). */
+int vqd_entanglement_fidelity(int nq, double p_depol, double p_deph, double *fe);
+int vqd_fidelity_to_errors(int nq, double fbar, double x, double *p_depol, double *p_deph);
+double vqd_angle_scaled_error(double eps, double theta);
+
 /* Superoperator of a Kraus set: nk matrices of 2^k x 2^k, k in [1, 2]. */
 int vqd_kraus_to_superop(int k, int nk, const double *kraus, double *out);
 

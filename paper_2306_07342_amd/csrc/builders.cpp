@@ -336,3 +336,50 @@ LOp make_unitary_op(int k, const int *targets, const cd *U)
 }
 
 }  // namespace vqd
+
+// ------------------------------------------------------- error parameters --
+// App. B: average and entanglement fidelity, eq. (fidelities_relation); the
+// depolarising + dephasing entanglement fidelity 1 - p - q + c p q, c = 4/3
+// for one qubit (eq. fe1) and 16/15 for two; the split of a reported average
+// fidelity into depolarising x eps and dephasing (1 - x) eps.
+extern "C" {
+
+int vqd_entanglement_fidelity(int nq, double p_depol, double p_deph, double *fe)
+{
+    vqd::clear_error();
+    if (nq != 1 && nq != 2) return vqd::fail(VQD_E_ARG, "only one- and two-qubit gates");
+    if (!fe) return vqd::fail(VQD_E_ARG, "null output");
+    if (!std::isfinite(p_depol) || !std::isfinite(p_deph)) return vqd::fail(VQD_E_ARG, "non-finite parameter");
+    const double c = nq == 1 ? 4.0 / 3.0 : 16.0 / 15.0;
+    *fe = 1.0 - p_depol - p_deph + c * p_depol * p_deph;
+    return VQD_OK;
+}
+
+int vqd_fidelity_to_errors(int nq, double fbar, double x, double *p_depol, double *p_deph)
+{
+    vqd::clear_error();
+    if (nq != 1 && nq != 2) return vqd::fail(VQD_E_ARG, "only one- and two-qubit gates");
+    if (!p_depol || !p_deph) return vqd::fail(VQD_E_ARG, "null output");
+    if (!(x >= 0.0 && x <= 1.0)) return vqd::fail(VQD_E_ARG, "x outside [0, 1]");
+    if (!(fbar <= 1.0) || !std::isfinite(fbar)) return vqd::fail(VQD_E_ARG, "fidelity above 1");
+    const double d = nq == 1 ? 2.0 : 4.0;
+    const double c = nq == 1 ? 4.0 / 3.0 : 16.0 / 15.0;
+    const double fe = ((d + 1.0) * fbar - 1.0) / d;
+    // 1 - eps + a eps^2 = fe with a = c x (1 - x): the smaller root, written
+    // without cancellation
+    const double a = c * x * (1.0 - x), delta = 1.0 - fe;
+    const double disc = 1.0 - 4.0 * a * delta;
+    if (delta < 0.0 || disc < 0.0) return vqd::fail(VQD_E_ARG, "no error parameters reach this fidelity");
+    const double eps = 2.0 * delta / (1.0 + std::sqrt(disc));
+    if (eps > 1.0) return vqd::fail(VQD_E_ARG, "no error parameters in [0, 1] reach this fidelity");
+    *p_depol = x * eps;
+    *p_deph = (1.0 - x) * eps;
+    return VQD_OK;
+}
+
+double vqd_angle_scaled_error(double eps, double theta)
+{
+    return eps * std::fabs(theta) / 3.14159265358979323846;
+}
+
+}  // extern "C"

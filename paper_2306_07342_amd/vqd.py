@@ -151,6 +151,9 @@ def load(path: str = LIB_PATH):
         "vqd_measure_z": ([vp, ctypes.c_int, ctypes.c_double, _ip, _dp], ctypes.c_int),
         "vqd_measure_parity": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip, _dp], ctypes.c_int),
         "vqd_sample": ([vp, vp, ctypes.c_longlong, vp], ctypes.c_int),
+        "vqd_entanglement_fidelity": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp], ctypes.c_int),
+        "vqd_fidelity_to_errors": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp], ctypes.c_int),
+        "vqd_angle_scaled_error": ([ctypes.c_double, ctypes.c_double], ctypes.c_double),
         "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_calc_purity": ([vp, _dp], ctypes.c_int),
         "vqd_calc_probs": ([vp, _dp], ctypes.c_int),
@@ -223,6 +226,25 @@ def kraus_to_superop(Ks) -> np.ndarray:
     out = np.empty(2 * d ** 4)
     check(lib().vqd_kraus_to_superop(k, K.shape[0], _d(_cplx(K)), _d(out)))
     return out.view(np.complex128).reshape(d * d, d * d)
+
+
+def entanglement_fidelity(nq: int, p_depol: float, p_deph: float) -> float:
+    """App. B: entanglement fidelity of depolarising then dephasing noise."""
+    out = ctypes.c_double()
+    check(lib().vqd_entanglement_fidelity(nq, p_depol, p_deph, ctypes.byref(out)))
+    return out.value
+
+
+def fidelity_to_errors(nq: int, fbar: float, x: float):
+    """App. B: (p_depol, p_deph) = (x eps, (1 - x) eps) reproducing average
+    gate fidelity fbar."""
+    p, q = ctypes.c_double(), ctypes.c_double()
+    check(lib().vqd_fidelity_to_errors(nq, fbar, x, ctypes.byref(p), ctypes.byref(q)))
+    return p.value, q.value
+
+
+def angle_scaled_error(eps: float, theta: float) -> float:
+    return lib().vqd_angle_scaled_error(eps, theta)
 
 
 class DensityMatrix:
