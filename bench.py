@@ -276,6 +276,26 @@ def traj_leg(vqd, torch, n_traj: int, steps: int, oracle_sample: bool):
     return out
 
 
+def device_leg(vqd):
+    """Host-side noise insertion: the 2000 ideal gates of the 14-qubit grid
+    circuit through a superconducting-like device specification."""
+    ops, _ = workload()
+    ideal = [op for op in ops if op[0] in ("su2", "cz")]
+    dev = vqd.Device(N_QUBITS)
+    dev.set_gate("su2", 0.05, 1e-3, 5e-4)
+    dev.set_gate("cz", 0.5, 5e-3, 1e-3)
+    dev.set_passive([100.0] * N_QUBITS, [50.0] * N_QUBITS)
+    dev.set_crosstalk([(a, a + 1) for a in range(13) if a != 6] + [(a, a + 7) for a in range(7)], 0.01)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        noisy = dev.insert_noise(ideal)
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": "2000 ideal SU(2)/CZ gates of the 14-qubit grid circuit -> %d noisy ops" % len(noisy),
+            "ms_per_circuit": round(dt * 1e3, 3), "gates_per_s": round(len(ideal) / dt, 1),
+            "note": "host only, including the binding's argument marshalling"}
+
+
 def measure_leg(vqd, torch, dm, steps: int):
     """Measurement on the 14-qubit state the main leg leaves: projective Z
     measurement (weights, draw, collapse) and 2^20 shots from the diagonal."""
@@ -495,6 +515,7 @@ def main():
         "roofline_other": alu if roof is hbm else hbm,
         "check": {"trace_re": tr.real, "purity": pur, "z0": float(z[0])},
     }
+    out["device_layer"] = device_leg(vqd)
     if not args.no_measure:
         log("measurement leg ...")
         out["measurement"] = measure_leg(vqd, torch, dm, args.steps)

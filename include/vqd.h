@@ -360,6 +360,36 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
 
 /* ------------------------------------------------------------- surrogate */
 
+/* Virtual-device noise insertion (Sec. 2: a device specification maps an
+ * ideal circuit to the channels a noisy device realises; Secs. 3.4, 3.5:
+ * crosstalk and passive T1/T2 decay).  A device holds, per named gate kind,
+ * a duration and active noise (depolarising p_depol then dephasing p_deph on
+ * the gate's qubits after the gate; one- or two-qubit forms by the gate's
+ * size), per-qubit T1 and T2 (<= 0 disables), and crosstalk edges with a ZZ
+ * phase alpha (eq. weak_dephasing_zz).
+ *
+ * vqd_device_insert_noise schedules the ideal gates (named gate kinds, 4
+ * targets and 4 parameters per gate as for vqd_prog_add_named_many) as soon
+ * as possible into parallel batches (a gate joins the batch after the last
+ * one that uses any of its qubits; a batch lasts as long as its slowest
+ * gate) and emits, per batch: its gates in input order, each followed by its
+ * active noise; ZZ(alpha) on every edge whose qubits are both idle, if the
+ * batch holds a two-qubit gate; then for every qubit in ascending order
+ * amp_t1(dt, T1) and deph_t2(dt, T2) for the time dt it is idle in the
+ * batch.  Operations with no effect are left out.  Output arrays hold cap
+ * ops (kinds, 4 targets and 4 parameters each, as for named_many); with all
+ * three NULL only *out_count is set.  Unspecified gate kinds take no time
+ * and add no noise.  Host only. */
+typedef struct vqd_device vqd_device;
+int vqd_device_create(int n, vqd_device **out);      /* 1 <= n <= 64 */
+int vqd_device_destroy(vqd_device *d);
+int vqd_device_set_gate(vqd_device *d, int kind, double duration, double p_depol, double p_deph);
+int vqd_device_set_passive(vqd_device *d, const double *T1, const double *T2);   /* n each */
+int vqd_device_set_crosstalk(vqd_device *d, int n_edges, const int *edges, double alpha);
+int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, const int *targets,
+                            const double *params, int cap, int *out_count, int *out_kinds,
+                            int *out_targets, double *out_params);
+
 /* Measurement (the read-out of the devices of Secs. 4-6; the parity
  * measurement of eq. (m); the simulated shots of Sec. 6).
  *

@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvqd.so")
 ARCH = os.environ.get("VQD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "builders.cpp", "planner.cpp", "batch.cpp", "traj.cpp", "measure.cpp", "kernels.hip",
+SOURCES = ["api.cpp", "builders.cpp", "planner.cpp", "batch.cpp", "traj.cpp", "measure.cpp", "device.cpp",
+           "kernels.hip",
            "mlp.hip", "traj.hip", "measure.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-fcx-limited-range",

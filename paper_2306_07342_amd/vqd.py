@@ -154,6 +154,14 @@ def load(path: str = LIB_PATH):
         "vqd_entanglement_fidelity": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp], ctypes.c_int),
         "vqd_fidelity_to_errors": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp], ctypes.c_int),
         "vqd_angle_scaled_error": ([ctypes.c_double, ctypes.c_double], ctypes.c_double),
+        "vqd_device_create": ([ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "vqd_device_destroy": ([vp], ctypes.c_int),
+        "vqd_device_set_gate": ([vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+                                ctypes.c_int),
+        "vqd_device_set_passive": ([vp, _dp, _dp], ctypes.c_int),
+        "vqd_device_set_crosstalk": ([vp, ctypes.c_int, _ip, ctypes.c_double], ctypes.c_int),
+        "vqd_device_insert_noise": ([vp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int, _ip, _ip, _ip, _dp],
+                                    ctypes.c_int),
         "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_calc_purity": ([vp, _dp], ctypes.c_int),
         "vqd_calc_probs": ([vp, _dp], ctypes.c_int),
@@ -506,6 +514,73 @@ class Program:
         i = ProgInfo()
         check(lib().vqd_prog_info_get(self.handle, ctypes.byref(i)))
         return {f: getattr(i, f) for f, _ in ProgInfo._fields_}
+
+
+KIND_NAMES = {v: k for k, v in KINDS.items()}
+
+
+class Device:
+    """Virtual-device noise insertion (vqd_device_* in include/vqd.h): ideal
+    gates in, the device's noisy op stream out (host only)."""
+
+    def __init__(self, n: int):
+        load()
+        self.n = n
+        h = ctypes.c_void_p()
+        check(lib().vqd_device_create(n, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().vqd_device_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_gate(self, kind: str, duration: float, p_depol: float = 0.0, p_deph: float = 0.0):
+        check(lib().vqd_device_set_gate(self.handle, KINDS[kind], duration, p_depol, p_deph))
+
+    def set_passive(self, T1, T2):
+        a = np.ascontiguousarray(T1, dtype=np.float64)
+        b = np.ascontiguousarray(T2, dtype=np.float64)
+        if a.shape != (self.n,) or b.shape != (self.n,):
+            raise ValueError("T1 and T2 need one value per qubit")
+        check(lib().vqd_device_set_passive(self.handle, _d(a), _d(b)))
+
+    def set_crosstalk(self, edges, alpha: float):
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        check(lib().vqd_device_set_crosstalk(self.handle, e.shape[0], _i(e), alpha))
+
+    def insert_noise(self, gates) -> list:
+        """Noisy op stream (kind, qubits, params) for a list of named gates."""
+        m = len(gates)
+        k = np.zeros(max(m, 1), dtype=np.int32)
+        t = np.zeros((max(m, 1), 4), dtype=np.int32)
+        p = np.zeros((max(m, 1), 4), dtype=np.float64)
+        for i, (kind, q, par) in enumerate(gates):
+            k[i] = KINDS[kind]
+            t[i, :len(q)] = q
+            p[i, :len(par)] = par
+        cnt = ctypes.c_int()
+        check(lib().vqd_device_insert_noise(self.handle, m, _i(k), _i(t), _d(p), 0, ctypes.byref(cnt),
+                                            None, None, None))
+        c = cnt.value
+        ok = np.zeros(max(c, 1), dtype=np.int32)
+        ot = np.zeros((max(c, 1), 4), dtype=np.int32)
+        opr = np.zeros((max(c, 1), 4), dtype=np.float64)
+        check(lib().vqd_device_insert_noise(self.handle, m, _i(k), _i(t), _d(p), c, ctypes.byref(cnt),
+                                            _i(ok), _i(ot), _d(opr)))
+        out = []
+        for i in range(c):
+            name = KIND_NAMES[int(ok[i])]
+            nq, npar = ctypes.c_int(), ctypes.c_int()
+            lib().vqd_kind_arity(int(ok[i]), ctypes.byref(nq), ctypes.byref(npar))
+            out.append((name, tuple(int(x) for x in ot[i, :nq.value]), tuple(float(x) for x in opr[i, :npar.value])))
+        return out
 
 
 class Trajectories:

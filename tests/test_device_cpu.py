@@ -1,0 +1,73 @@
+"""The library's noise insertion (vqd_device_*) against the oracle
+(oracle/device.py): identical op streams for hand-made and random circuits
+and device specifications."""
+import numpy as np
+import pytest
+
+from oracle import device as dv
+from tests.test_device_oracle import random_gates, spec4
+from workloads import c1_line_circuit, c2_grid_circuit
+
+
+def same_stream(a, b):
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        assert x[0] == y[0] and tuple(x[1]) == tuple(y[1]), (x, y)
+        assert np.allclose(x[2], y[2], rtol=0, atol=1e-15), (x, y)
+
+
+def lib_device(vqd, ref: dv.Device):
+    d = vqd.Device(ref.n)
+    for k, (t, p, q) in ref.gates.items():
+        d.set_gate(k, t, p, q)
+    d.set_passive(ref.T1, ref.T2)
+    d.set_crosstalk(ref.edges, ref.alpha)
+    return d
+
+
+def test_hand_example(vqd_host):
+    ref = spec4()
+    gates = [("h", (0,), ()), ("cz", (0, 1), ()), ("x", (2,), ())]
+    same_stream(lib_device(vqd_host, ref).insert_noise(gates), dv.insert_noise(ref, gates))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_circuits_and_devices(vqd_host, seed):
+    rng = np.random.default_rng(seed)
+    n = 7
+    ref = dv.Device(n)
+    for k in ("rx", "ry", "rz", "h", "cz"):
+        if rng.random() < 0.9:
+            ref.set_gate(k, float(rng.choice([0.0, 0.02, 0.05, 0.3])), float(rng.choice([0.0, 1e-3])),
+                         float(rng.choice([0.0, 2e-3])))
+    T1 = rng.uniform(20, 200, n) * (rng.random(n) < 0.8)
+    ref.set_passive(list(T1), list(rng.uniform(10, 100, n) * (rng.random(n) < 0.8)))
+    ref.set_crosstalk([(i, i + 1) for i in range(n - 1)], float(rng.choice([0.0, 0.01])))
+    gates = random_gates(n, 80, seed)
+    same_stream(lib_device(vqd_host, ref).insert_noise(gates), dv.insert_noise(ref, gates))
+
+
+def test_grid_gates_with_a_superconducting_like_device(vqd_host):
+    ideal = [op for op in c2_grid_circuit(rows=2, cols=4, n_gates=120) if op[0] in ("su2", "cz")]
+    ref = dv.Device(8)
+    ref.set_gate("su2", 0.05, 1e-3, 5e-4)
+    ref.set_gate("cz", 0.5, 5e-3, 1e-3)
+    ref.set_passive([100.0] * 8, [50.0] * 8)
+    ref.set_crosstalk([(a, a + 1) for a in range(7) if a != 3] + [(a, a + 4) for a in range(4)], 0.01)
+    same_stream(lib_device(vqd_host, ref).insert_noise(ideal), dv.insert_noise(ref, ideal))
+
+
+def test_errors(vqd_host):
+    v = vqd_host
+    with pytest.raises(v.VQDError):
+        v.Device(0)
+    d = v.Device(3)
+    with pytest.raises(v.VQDError):
+        d.set_gate("depol1", 0.1)                # a channel is not a gate
+    with pytest.raises(v.VQDError):
+        d.set_gate("cz", -1.0)
+    with pytest.raises(v.VQDError):
+        d.set_crosstalk([(0, 3)], 0.1)
+    with pytest.raises(v.VQDError):
+        d.insert_noise([("cz", (0, 0), ())])
+    assert d.insert_noise([]) == []
