@@ -156,6 +156,8 @@ enum vqd_kind {
     VQD_K_BITFLIP2,     /* b   (eq. bf2)                                      */
     VQD_K_AMP_T1,       /* dt, T1: amp(1 - exp(-dt/T1))          (eq. ampt1)  */
     VQD_K_DEPH_T2,      /* dt, T2: deph((1 - exp(-dt/T2)) / 2)   (eq. depht2) */
+    VQD_K_DEPH_T2S,     /* dt, T2*: deph((1 - exp(-(dt/T2*)^2)) / 2) (eq. depht2s) */
+    VQD_K_DEPOL_T1,     /* dt, T1: depol1(3/4 (1 - exp(-dt/T1)))  (eq. depolt1) */
     VQD_K_COUNT
 };
 

@@ -143,10 +143,20 @@ def deph_t2(dt, T2):
     return deph1(0.5 * (1.0 - math.exp(-dt / T2)))
 
 
+def deph_t2s(dt, T2s):
+    """eq. (depht2s): deph(1/2 (1 - exp(-(dt/T2*)^2))), the Gaussian T2* decay."""
+    return deph1(0.5 * (1.0 - math.exp(-(dt / T2s) ** 2)))
+
+
+def depol_t1(dt, T1):
+    """eq. (depolt1): depol(3/4 (1 - exp(-dt/T1)))."""
+    return depol1(0.75 * (1.0 - math.exp(-dt / T1)))
+
+
 CHANNELS = {
     "depol1": depol1, "depol2": depol2, "deph1": deph1, "deph2": deph2,
     "amp": amp, "gamp": gamp, "bitflip1": bitflip1, "bitflip2": bitflip2,
-    "amp_t1": amp_t1, "deph_t2": deph_t2,
+    "amp_t1": amp_t1, "deph_t2": deph_t2, "deph_t2s": deph_t2s, "depol_t1": depol_t1,
 }
 
 

@@ -59,11 +59,16 @@ int channel_kraus(int kind, const double *p, int &k, std::vector<std::vector<cd>
         return std::isfinite(x) && x >= 0.0 && x <= hi;
     };
     switch (kind) {
-    case VQD_K_DEPOL1: {
-        if (!need_prob(p[0], 1.0)) return fail(VQD_E_ARG, "depol1: p outside [0, 1]");
+    case VQD_K_DEPOL1: case VQD_K_DEPOL_T1: {
+        double q = p[0];
+        if (kind == VQD_K_DEPOL_T1) {
+            if (!(p[1] > 0) || !(p[0] >= 0)) return fail(VQD_E_ARG, "depol_t1: need dt >= 0, T1 > 0");
+            q = 0.75 * (1.0 - std::exp(-p[0] / p[1]));
+        }
+        if (!need_prob(q, 1.0)) return fail(VQD_E_ARG, "depol1: p outside [0, 1]");
         k = 1;
-        Ks.push_back(scaled(m2v(pauli(0)), std::sqrt(1 - p[0])));
-        for (int a = 1; a < 4; ++a) Ks.push_back(scaled(m2v(pauli(a)), std::sqrt(p[0] / 3)));
+        Ks.push_back(scaled(m2v(pauli(0)), std::sqrt(1 - q)));
+        for (int a = 1; a < 4; ++a) Ks.push_back(scaled(m2v(pauli(a)), std::sqrt(q / 3)));
         return VQD_OK;
     }
     case VQD_K_DEPOL2: {
@@ -79,11 +84,15 @@ int channel_kraus(int kind, const double *p, int &k, std::vector<std::vector<cd>
             for (int b = 1; b < 4; ++b) Ks.push_back(scaled(kron2(pauli(a), pauli(b)), std::sqrt(p[0] / 15)));
         return VQD_OK;
     }
-    case VQD_K_DEPH1: case VQD_K_DEPH_T2: {
+    case VQD_K_DEPH1: case VQD_K_DEPH_T2: case VQD_K_DEPH_T2S: {
         double q = p[0];
         if (kind == VQD_K_DEPH_T2) {
             if (!(p[1] > 0) || !(p[0] >= 0)) return fail(VQD_E_ARG, "deph_t2: need dt >= 0, T2 > 0");
             q = 0.5 * (1.0 - std::exp(-p[0] / p[1]));
+        } else if (kind == VQD_K_DEPH_T2S) {
+            if (!(p[1] > 0) || !(p[0] >= 0)) return fail(VQD_E_ARG, "deph_t2s: need dt >= 0, T2* > 0");
+            const double r = p[0] / p[1];
+            q = 0.5 * (1.0 - std::exp(-r * r));
         }
         if (!need_prob(q, 1.0)) return fail(VQD_E_ARG, "deph1: p outside [0, 1]");
         k = 1;
@@ -157,7 +166,8 @@ void canonical_params(int kind, double *p)
     switch (kind) {
     case VQD_K_SU2: p[0] = 0.31; p[1] = 0.52; p[2] = -0.73; p[3] = 0.44; break;
     case VQD_K_GAMP: p[0] = 0.83; p[1] = 0.11; break;
-    case VQD_K_AMP_T1: case VQD_K_DEPH_T2: p[0] = 0.3; p[1] = 17.0; break;
+    case VQD_K_AMP_T1: case VQD_K_DEPH_T2: case VQD_K_DEPH_T2S: case VQD_K_DEPOL_T1:
+        p[0] = 0.3; p[1] = 17.0; break;
     case VQD_K_RX: case VQD_K_RY: case VQD_K_RZ: case VQD_K_CPHASE: case VQD_K_XX: case VQD_K_ZZ:
         p[0] = 0.7371; break;
     default: p[0] = 0.0123; break;        // channel probabilities
@@ -167,9 +177,9 @@ void canonical_params(int kind, double *p)
 int kind_arity(int kind, int *nq, int *np)
 {
     static const int Q[VQD_K_COUNT] = {0, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2,
-                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1};
+                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1};
     static const int P[VQD_K_COUNT] = {0, 1, 1, 1, 0, 0, 0, 0, 4, 0, 1, 1, 1,
-                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2};
+                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2};
     if (kind <= 0 || kind >= VQD_K_COUNT) return -1;
     if (nq) *nq = Q[kind];
     if (np) *np = P[kind];

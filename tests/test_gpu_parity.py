@@ -207,3 +207,26 @@ def test_random_program_nonhermitian_start(gpu_lib, n):
     dm.from_numpy(to_vec(R))
     gpu_lib.Program(n, ops).compile().run(dm)
     assert max_err(dm.to_numpy(), ref.to_vectorised()) <= TOL * max(1.0, np.abs(ref.R).max())
+
+
+def test_every_named_kind_in_a_program(gpu_lib):
+    """Every named gate and channel kind of the library, in one planned
+    program on 5 qubits, against the oracle's own builders."""
+    from paper_2306_07342_amd.vqd import KINDS
+    n = 5
+    params = {"rx": (0.3,), "ry": (1.1,), "rz": (2.2,), "su2": (0.1, -0.7, 0.4, 0.2), "cphase": (0.6,),
+              "xx": (0.9,), "zz": (0.05,), "depol1": (0.2,), "depol2": (0.3,), "deph1": (0.25,), "deph2": (0.1,),
+              "amp": (0.4,), "gamp": (0.6, 0.3), "bitflip1": (0.2,), "bitflip2": (0.3,), "amp_t1": (0.5, 2.0),
+              "deph_t2": (0.5, 1.0), "deph_t2s": (0.7, 1.5), "depol_t1": (0.6, 2.5)}
+    two = {"cz", "cphase", "xx", "zz", "depol2", "deph2", "bitflip2"}
+    ops = []
+    for i, kind in enumerate(sorted(KINDS, key=KINDS.get)):
+        q = i % n
+        tg = (q, (q + 2) % n) if kind in two else (q,)
+        ops.append((kind, tg, params.get(kind, ())))
+    ops = [("h", (q,), ()) for q in range(n)] + ops + ops[::-1]
+    say("every named kind: %d ops" % len(ops))
+    dm = gpu_lib.DensityMatrix(n)
+    gpu_lib.Program(n, ops).compile().run(dm)
+    ref = emulate(n, ops)
+    assert np.abs(dm.to_numpy() - ref.to_vectorised()).max() <= 1e-10
