@@ -277,6 +277,24 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
             }
             k.chan = o.chan_idx;
             k.mat = (uint32_t)t->pool.size();
+            // operators that are diagonal (and real) take the kernel's
+            // per-slot path when drawn; channels are counted at the cost of
+            // their most probable operator (for a general channel: largest
+            // Tr(K^dagger K), its weight on the maximally mixed state)
+            auto diag_of = [&](const std::vector<cd> &K, bool &real) {
+                real = true;
+                for (int x = 0; x < d; ++x)
+                    for (int y = 0; y < d; ++y) {
+                        const cd z = K[size_t(x) * d + y];
+                        if (x != y && z != cd(0)) return false;
+                        if (x == y) real = real && z.imag() == 0.0;
+                    }
+                return true;
+            };
+            auto op_cost = [&](const std::vector<cd> &K) {
+                bool real = false;
+                return diag_of(K, real) ? (real ? 2.0 : 4.0) : 4.0 * d;
+            };
             if (mixed) {
                 k.kind = TOP_MIX;
                 std::vector<size_t> keep;
@@ -291,21 +309,46 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                     cum += q[i];
                     t->pool.push_back(cd(cum, q[i]));
                 }
-                for (size_t i : keep) {
+                size_t mode = keep[0];
+                for (size_t j = 0; j < keep.size(); ++j) {
+                    const size_t i = keep[j];
                     std::vector<cd> U = Ks[i];
                     const double s = 1.0 / std::sqrt(q[i]);
                     for (cd &z : U) z *= s;
+                    bool real = false;
+                    if (diag_of(U, real)) {
+                        k.dmask |= 1u << j;
+                        if (real) k.rmask |= 1u << j;
+                    }
+                    if (q[i] > q[mode]) mode = i;
                     k.mask = put_matrix(t->pool, U, o.qs, R, true);
                 }
                 ++t->n_mixed;
-                t->fma_per_amp += 4.0 * d;
+                std::vector<cd> Um = Ks[mode];
+                for (cd &z : Um) z /= std::sqrt(q[mode]);
+                t->fma_per_amp += op_cost(Um);
             } else {
                 k.kind = TOP_KRAUS;
                 k.nk = (uint32_t)Ks.size();
-                for (const auto &G : Gs) put_matrix(t->pool, G, o.qs, R, false);
-                for (const auto &K : Ks) k.mask = put_matrix(t->pool, K, o.qs, R, true);
+                k.gdiag = 1;
+                for (const auto &G : Gs) {
+                    bool real = false;
+                    if (!diag_of(G, real)) k.gdiag = 0;
+                    put_matrix(t->pool, G, o.qs, R, false);
+                }
+                size_t mode = 0;
+                for (size_t i = 0; i < Ks.size(); ++i) {
+                    bool real = false;
+                    if (diag_of(Ks[i], real)) {
+                        k.dmask |= 1u << i;
+                        if (real) k.rmask |= 1u << i;
+                    }
+                    if (q[i] > q[mode]) mode = i;
+                    k.mask = put_matrix(t->pool, Ks[i], o.qs, R, true);
+                }
                 ++t->n_general;
-                t->fma_per_amp += 4.0 * d + 2.0 + 2.0 * d;
+                // drawn operator, its scaling, and this thread's part of rho_T
+                t->fma_per_amp += op_cost(Ks[mode]) + 2.0 + (k.gdiag ? 2.0 : 2.0 * d);
             }
         }
         t->kops.push_back(k);

@@ -115,6 +115,54 @@ __device__ __forceinline__ void rho_partial(const double2 (&a)[16], double (&r)[
     }
 }
 
+// Only the diagonal of the reduced density matrix: rho_xx = sum |psi_x|^2.
+template <int MASK>
+__device__ __forceinline__ void rho_diag_partial(const double2 (&a)[16], double (&r)[1 << popc4(MASK)])
+{
+    constexpr int NB = popc4(MASK), DIM = 1 << NB, NG = 16 >> NB, REST = (~MASK) & 15;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) r[i] = 0.0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int x = 0; x < DIM; ++x) {
+            const double2 ax = a[dep4(x, MASK) | dep4(g, REST)];
+            r[x] = fma(ax.x, ax.x, fma(ax.y, ax.y, r[x]));
+        }
+}
+
+// Index bits of register slot e on the register bits in MASK (the inverse of
+// dep4): bit j of the result is the j-th set bit of MASK in e.
+__host__ __device__ constexpr int ext4(int e, int mask)
+{
+    int out = 0, k = 0;
+    for (int b = 0; b < 4; ++b)
+        if (mask >> b & 1) {
+            if (e >> b & 1) out |= 1 << k;
+            ++k;
+        }
+    return out;
+}
+
+// A diagonal operator on the register bits in MASK (its diagonal read from
+// the column-major matrix M): one factor per slot, real or complex.
+template <int MASK>
+__device__ __forceinline__ void apply_diag_op(const double2 (&a)[16], double2 (&y)[16], const double2 *__restrict__ M,
+                                              bool real)
+{
+    constexpr int DIM = 1 << popc4(MASK);
+    if (real) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const double f = M[ext4(e, MASK) * (DIM + 1)].x;
+            y[e] = make_double2(f * a[e].x, f * a[e].y);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) y[e] = cmul(M[ext4(e, MASK) * (DIM + 1)], a[e]);
+    }
+}
+
 // Tr(G rho) for Hermitian G (row-major) and rho packed as by rho_partial:
 // sum_x G_xx rho_xx + 2 sum_{x<y} Re(G_xy conj(rho_xy)).
 template <int DIM>
@@ -160,9 +208,19 @@ __device__ __forceinline__ void traj_channel(const double2 (&x)[16], double2 (&y
         for (uint32_t i = 0; i + 1 < nk; ++i) j += (M[i].x <= thr) ? 1u : 0u;
         mats = M + nk;
     } else {
+        // weights Tr(G_i rho_T): from the diagonal of rho_T alone when every
+        // Gram matrix is diagonal (amplitude damping), else from all of it
         double r[D2];
-        rho_partial<MASK>(x, r);
-        group_sum<D2, WIDE>(r, log_tt, red, wave, wpt, flip);
+        if (uni(op->gdiag)) {
+            double rd[DIM];
+            rho_diag_partial<MASK>(x, rd);
+            group_sum<DIM, WIDE>(rd, log_tt, red, wave, wpt, flip);
+#pragma unroll
+            for (int i = 0; i < D2; ++i) r[i] = (i < DIM) ? rd[i] : 0.0;
+        } else {
+            rho_partial<MASK>(x, r);
+            group_sum<D2, WIDE>(r, log_tt, red, wave, wpt, flip);
+        }
         double W = 0.0;
         for (uint32_t i = 0; i < nk; ++i) W += gram_weight<DIM>(M + i * D2, r);
         const double thr = u * W;
@@ -185,8 +243,18 @@ __device__ __forceinline__ void traj_channel(const double2 (&x)[16], double2 (&y
         }
         mats = M + nk * D2;
     }
-    if (WIDE) j = uni(j);        // one trajectory per wave: the operator's loads are scalar
-    apply_mat<MASK, false>(x, y, mats + j * D2);
+    // the drawn operator: per-slot factors when it is diagonal (the identity
+    // of a mixed-unitary channel, the no-jump operator of damping), else the
+    // dense product
+    const uint32_t dmask = uni(op->dmask), rmask = uni(op->rmask);
+    if (WIDE) {
+        j = uni(j);              // one trajectory per wave: the operator's loads are scalar
+        if ((dmask >> j) & 1u) apply_diag_op<MASK>(x, y, mats + j * D2, (rmask >> j) & 1u);
+        else apply_mat<MASK, false>(x, y, mats + j * D2);
+    } else {
+        if (__all((dmask >> j) & 1u)) apply_diag_op<MASK>(x, y, mats + j * D2, __all((rmask >> j) & 1u));
+        else apply_mat<MASK, false>(x, y, mats + j * D2);
+    }
     if (!mixed) {
         const double s = 1.0 / sqrt(wj);
 #pragma unroll

@@ -224,9 +224,10 @@ struct alignas(16) TOp {
     uint32_t nk;      // TOP_MIX / TOP_KRAUS: number of operators
     uint32_t chan;    // TOP_MIX / TOP_KRAUS: channel index (column of the uniforms)
     uint32_t nd;      // TOP_DTHR: number of qubits (1 or 2)
-    uint32_t pad0;
+    uint32_t dmask;   // TOP_MIX / TOP_KRAUS: bit i set if operator i is diagonal
     uint32_t dq[2];   // TOP_DTHR / TOP_DMIX: thread qubits, dq[0] the low bit of the factor index
-    uint32_t pad1[2];
+    uint32_t rmask;   // TOP_MIX / TOP_KRAUS: bit i set if operator i is diagonal and real
+    uint32_t gdiag;   // TOP_KRAUS: every K_i^dagger K_i is diagonal (only rho_T's diagonal is needed)
 };
 
 struct alignas(16) TPhase {

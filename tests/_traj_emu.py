@@ -21,7 +21,8 @@ TOP_MAT, TOP_DTHR, TOP_MIX, TOP_KRAUS, TOP_DREG, TOP_DMIX = 1, 2, 3, 4, 5, 6
 
 PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4", 9), ("pad", "<u4")])
 OP = np.dtype([("kind", "<u4"), ("mask", "<u4"), ("mat", "<u4"), ("real", "<u4"), ("nk", "<u4"),
-               ("chan", "<u4"), ("nd", "<u4"), ("pad0", "<u4"), ("dq", "<u4", 2), ("pad1", "<u4", 2)])
+               ("chan", "<u4"), ("nd", "<u4"), ("dmask", "<u4"), ("dq", "<u4", 2), ("rmask", "<u4"),
+               ("gdiag", "<u4")])
 
 
 def parse(blob: bytes) -> dict:
@@ -131,6 +132,16 @@ def run(plan: dict, U: np.ndarray):
                     w = [float(np.sum(pool[off + i * d * d: off + (i + 1) * d * d].reshape(d, d) * rho.T).real)
                          for i in range(nk)]
                     mats = off + nk * d * d
+                if t == 0:
+                    # the per-operator flags the kernel's fast paths rely on
+                    for i in range(nk):
+                        K = _colmajor(pool, mats + i * d * d, d)
+                        isdiag = np.count_nonzero(K - np.diag(np.diag(K))) == 0
+                        assert bool((int(op["dmask"]) >> i) & 1) == isdiag
+                        assert bool((int(op["rmask"]) >> i) & 1) == (isdiag and np.all(np.diag(K).imag == 0))
+                    if kind == TOP_KRAUS:
+                        G = [pool[off + i * d * d: off + (i + 1) * d * d].reshape(d, d) for i in range(nk)]
+                        assert bool(op["gdiag"]) == all(np.count_nonzero(g - np.diag(np.diag(g))) == 0 for g in G)
                 j = _draw(w, float(U[t, int(op["chan"])]))
                 psi = apply_matrix(psi, qs, _colmajor(pool, mats + j * d * d, d))
                 if kind == TOP_KRAUS:
