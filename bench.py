@@ -513,6 +513,9 @@ def main():
         "pass_kernel_avg_launch_us": round(avg_launch_s * 1e6, 2),
         "roofline": roof,
         "roofline_other": alu if roof is hbm else hbm,
+        # context, not a roofline: the bytes an op-by-op path (one HBM pass
+        # per density-matrix op) would move, per second of the fused path
+        "unfused_equivalent_gbs": round(32.0 * amps * len(ops) * args.steps / wall / 1e9, 1),
         "check": {"trace_re": tr.real, "purity": pur, "z0": float(z[0])},
     }
     out["device_layer"] = device_leg(vqd)
