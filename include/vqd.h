@@ -158,6 +158,8 @@ enum vqd_kind {
     VQD_K_DEPH_T2,      /* dt, T2: deph((1 - exp(-dt/T2)) / 2)   (eq. depht2) */
     VQD_K_DEPH_T2S,     /* dt, T2*: deph((1 - exp(-(dt/T2*)^2)) / 2) (eq. depht2s) */
     VQD_K_DEPOL_T1,     /* dt, T1: depol1(3/4 (1 - exp(-dt/T1)))  (eq. depolt1) */
+    VQD_K_GAMP_T1,      /* p, dt, T1: gamp(p, 1 - exp(-dt/T1)), T1 relaxation
+                           towards p|0><0| + (1-p)|1><1|      (eq. gdamp)     */
     VQD_K_COUNT
 };
 
@@ -177,10 +179,17 @@ int vqd_kind_superop(int kind, const double *params, double *out);
  * fbar (converted by eq. fidelities_relation, F_e = ((d+1) fbar - 1)/d) into
  * p_depol = x eps and p_deph = (1 - x) eps, x in [0, 1] the depolarising
  * share, eps the smaller root in [0, 1]; VQD_E_ARG if there is none.
- * vqd_angle_scaled_error: eps |theta| / pi (App. C, rotation-angle scaling). */
+ * vqd_angle_scaled_error: eps |theta| / pi (App. C, rotation-angle scaling).
+ * vqd_zz_crosstalk_strength: the static ZZ coupling of two transmons (Sec.
+ * 7), beta = J^2 (1/(delta_ct - alpha_t) - 1/(delta_ct + alpha_c)) from the
+ * coupling strength J, the frequency difference delta_ct = f_c - f_t and
+ * the anharmonicities alpha_c, alpha_t, all in one frequency unit; the
+ * result is in that unit.  VQD_E_ARG for a non-finite input or a zero
+ * denominator. */
 int vqd_entanglement_fidelity(int nq, double p_depol, double p_deph, double *fe);
 int vqd_fidelity_to_errors(int nq, double fbar, double x, double *p_depol, double *p_deph);
 double vqd_angle_scaled_error(double eps, double theta);
+int vqd_zz_crosstalk_strength(double J, double delta_ct, double alpha_c, double alpha_t, double *beta);
 
 /* Superoperator of a Kraus set: nk matrices of 2^k x 2^k, k in [1, 2]. */
 int vqd_kraus_to_superop(int k, int nk, const double *kraus, double *out);
@@ -363,31 +372,89 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
 /* ------------------------------------------------------------- surrogate */
 
 /* Virtual-device noise insertion (Sec. 2: a device specification maps an
- * ideal circuit to the channels a noisy device realises; Secs. 3.4, 3.5:
- * crosstalk and passive T1/T2 decay).  A device holds, per named gate kind,
- * a duration and active noise (depolarising p_depol then dephasing p_deph on
- * the gate's qubits after the gate; one- or two-qubit forms by the gate's
- * size), per-qubit T1 and T2 (<= 0 disables), and crosstalk edges with a ZZ
- * phase alpha (eq. weak_dephasing_zz).
+ * ideal circuit to the channels a noisy device realises; Secs. 3.4, 3.5 and
+ * 8: crosstalk, passive T1/T2 decay, thermal relaxation, read-out).  A
+ * device holds, per named gate kind, a duration and active noise
+ * (depolarising p_depol then dephasing p_deph on the gate's qubits after
+ * the gate; one- or two-qubit forms by the gate's size), per-qubit T1 and T2
+ * (<= 0 disables), crosstalk edges with a ZZ phase alpha (eq.
+ * weak_dephasing_zz), static ZZ couplings, and read-out noise.
  *
  * vqd_device_insert_noise schedules the ideal gates (named gate kinds, 4
  * targets and 4 parameters per gate as for vqd_prog_add_named_many) as soon
  * as possible into parallel batches (a gate joins the batch after the last
  * one that uses any of its qubits; a batch lasts as long as its slowest
  * gate) and emits, per batch: its gates in input order, each followed by its
- * active noise; ZZ(alpha) on every edge whose qubits are both idle, if the
- * batch holds a two-qubit gate; then for every qubit in ascending order
- * amp_t1(dt, T1) and deph_t2(dt, T2) for the time dt it is idle in the
- * batch.  Operations with no effect are left out.  Output arrays hold cap
- * ops (kinds, 4 targets and 4 parameters each, as for named_many); with all
- * three NULL only *out_count is set.  Unspecified gate kinds take no time
- * and add no noise.  Host only. */
+ * active noise; ZZ(alpha) on every crosstalk edge whose qubits are both
+ * idle, if the batch holds a two-qubit gate; ZZ(beta_e dt) on every static
+ * coupling e whose pair carries no two-qubit gate of the batch, dt the
+ * batch's duration; then for every qubit in ascending order its T1 decay and
+ * its T2 decay for the time dt it is idle in the batch.  Operations with no
+ * effect are left out.  Output arrays hold cap ops (kinds, 4 targets and 4
+ * parameters each, as for named_many); with all three NULL only *out_count
+ * is set.  Unspecified gate kinds take no time and add no noise.  Host only.
+ *
+ * vqd_device_set_angle_scaling: for a parameterised gate kind, multiply its
+ * active noise probabilities (scale_noise) and/or its duration
+ * (scale_duration) by |theta| / pi, theta the gate's first parameter (App.
+ * C); a scaled probability above 1 makes insert_noise fail with VQD_E_ARG.
+ * vqd_device_set_thermal: per-qubit ground population p0 of the thermal
+ * state (eq. thermalstate; default 1); with p0 < 1 amplitude-damping T1
+ * decay becomes gamp_t1(p0, dt, T1), relaxation towards that state (eq.
+ * gdamp).  vqd_device_set_passive_forms: the T1 decay kind (VQD_K_AMP_T1,
+ * the default, or VQD_K_DEPOL_T1, eq. depolt1) and the T2 decay kind
+ * (VQD_K_DEPH_T2, the default, or VQD_K_DEPH_T2S, eq. depht2s).
+ * vqd_device_set_static_zz: couplings beta[e] (radians of ZZ phase, as in
+ * exp(-i a Z(x)Z), per unit time) on the pairs edges[2e], edges[2e+1].
+ *
+ * vqd_device_set_readout / vqd_device_readout_noise: the read-out model of
+ * Sec. 8, T1 decay for the measurement time t_meas, then depolarising
+ * noise eps[q], then the projective measurement, then depolarising noise
+ * eps[q] again.  readout_noise emits, for the listed qubits in list order,
+ * stage 0 (before the measurement): T1 decay for t_meas and depol1(eps[q]),
+ * then T1 and T2 decay for t_meas on every unlisted qubit in ascending
+ * order; stage 1 (after): depol1(eps[q]).  Output arrays as for
+ * insert_noise.  VQD_E_ARG for a duplicate or out-of-range qubit. */
 typedef struct vqd_device vqd_device;
 int vqd_device_create(int n, vqd_device **out);      /* 1 <= n <= 64 */
 int vqd_device_destroy(vqd_device *d);
 int vqd_device_set_gate(vqd_device *d, int kind, double duration, double p_depol, double p_deph);
+int vqd_device_set_angle_scaling(vqd_device *d, int kind, int scale_noise, int scale_duration);
 int vqd_device_set_passive(vqd_device *d, const double *T1, const double *T2);   /* n each */
+int vqd_device_set_thermal(vqd_device *d, const double *p0);                     /* n */
+int vqd_device_set_passive_forms(vqd_device *d, int t1_kind, int t2_kind);
 int vqd_device_set_crosstalk(vqd_device *d, int n_edges, const int *edges, double alpha);
+int vqd_device_set_static_zz(vqd_device *d, int n_edges, const int *edges, const double *beta);
+int vqd_device_set_readout(vqd_device *d, double t_meas, const double *eps);     /* eps: n */
+int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int stage, int cap,
+                             int *out_count, int *out_kinds, int *out_targets, double *out_params);
+
+/* Device presets: the parameter tables of the paper's virtual devices (App.
+ * C) as device specifications; times in microseconds.
+ *
+ * VQD_PRESET_SUPERCONDUCTING (Sec. 8, table conf:scq), 6 qubits: ideal
+ * gates, 0.05 us for one-qubit gates other than Rz and Z (no time), 0.5 us
+ * for two-qubit gates; per-qubit T1 relaxation towards the thermal state
+ * and T2 dephasing; static ZZ coupling 2 pi beta per microsecond on the 7
+ * coupled pairs, beta from vqd_zz_crosstalk_strength with the tabulated
+ * couplings, qubit frequencies (control minus target, the pair's lower
+ * qubit the control) and anharmonicities in MHz; read-out: 5 us and
+ * eps = 1 - the read-out fidelity.  p0 receives 1 - the excited
+ * initialisation probabilities (for vqd_dm_init_product_diag).
+ *
+ * VQD_PRESET_TRAPPED_ION (Sec. 4, table conf:trapped_ions), 8 qubits (two
+ * nodes of four ions): Rx, Ry with depolarising noise of average fidelity
+ * 0.99999 (vqd_fidelity_to_errors, x = 1), 0.05 us per pi, noise and time
+ * scaled by |theta| / pi; H, X, Y as pi rotations; CZ of fidelity 0.999 split
+ * 0.1 : 0.9, 5 us; T1 amplitude damping and Gaussian T2* dephasing
+ * (3e9 us, 1e6 us).  p0 receives the initialisation fidelity 0.9999.
+ *
+ * vqd_device_preset creates *out (destroy with vqd_device_destroy); p0 is
+ * NULL or holds vqd_device_preset_qubits(preset) doubles.  VQD_E_ARG for an
+ * unknown preset. */
+enum vqd_preset { VQD_PRESET_SUPERCONDUCTING = 1, VQD_PRESET_TRAPPED_ION = 2 };
+int vqd_device_preset(int preset, vqd_device **out, double *p0);
+int vqd_device_preset_qubits(int preset, int *n);
 int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, const int *targets,
                             const double *params, int cap, int *out_count, int *out_kinds,
                             int *out_targets, double *out_params);

@@ -153,10 +153,17 @@ def depol_t1(dt, T1):
     return depol1(0.75 * (1.0 - math.exp(-dt / T1)))
 
 
+def gamp_t1(p, dt, T1):
+    """eq. (gdamp) with gamma(dt) = 1 - exp(-dt/T1): T1 relaxation for a time dt
+    towards the thermal state p|0><0| + (1-p)|1><1|."""
+    return gamp(p, 1.0 - math.exp(-dt / T1))
+
+
 CHANNELS = {
     "depol1": depol1, "depol2": depol2, "deph1": deph1, "deph2": deph2,
     "amp": amp, "gamp": gamp, "bitflip1": bitflip1, "bitflip2": bitflip2,
     "amp_t1": amp_t1, "deph_t2": deph_t2, "deph_t2s": deph_t2s, "depol_t1": depol_t1,
+    "gamp_t1": gamp_t1,
 }
 
 

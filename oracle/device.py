@@ -4,7 +4,10 @@ Only tests use this module.  It maps an ideal gate list to the noisy op
 stream a device specification prescribes (Sec. 2: active noise after each
 gate, passive noise on idle qubits for the duration of the slowest operation
 of their automatically scheduled parallel batch; Sec. 3.4 crosstalk; Sec. 3.5
-passive T1/T2 decay, eqs. ampt1 and depht2).
+passive T1/T2 decay, eqs. ampt1, depolt1, depht2 and depht2s; Sec. 8: T1
+relaxation towards the thermal state, eq. gdamp, the static ZZ coupling of
+transmons, and the read-out model; App. C: errors scaled by the rotation
+angle).
 
 Readings (the paper describes the behaviour, not a procedure):
 
@@ -21,9 +24,23 @@ Readings (the paper describes the behaviour, not a procedure):
 * Operations with no effect are left out: zero probabilities, zero idle
   time, a disabled T1 or T2 (<= 0), zero crosstalk phase.
 * Gate kinds without a specification take no time and add no noise.
+* T1 decay is amp_t1, or gamp_t1(p0, dt, T1) when the qubit's thermal ground
+  population p0 is below 1 (relaxation towards the state it is initialised
+  in, eq. thermalstate), or depol_t1 when that form is chosen; T2 decay is
+  deph_t2 or, when chosen, the Gaussian deph_t2s.
+* Static ZZ coupling beta (phase per unit time) acts on its pair for the
+  whole duration of every batch, as one ZZ(beta dt) emitted after the
+  idle-edge crosstalk, except in batches with a two-qubit gate on that very
+  pair (the paper: a driven coupler gate removes it).
+* Angle scaling (App. C) multiplies a gate's active noise probabilities,
+  and if asked its duration, by |theta|/pi for its first parameter theta.
+* Read-out (Sec. 8): T1 decay for the measurement time, then
+  depolarising noise eps, before the projection; depolarising noise eps
+  after it.  Qubits not measured idle for the measurement time (T1, T2).
 """
 from __future__ import annotations
 
+import math
 from typing import Dict, List, Sequence, Tuple
 
 
@@ -31,10 +48,31 @@ class Device:
     def __init__(self, n: int):
         self.n = n
         self.gates: Dict[str, Tuple[float, float, float]] = {}   # kind -> (duration, p_depol, p_deph)
+        self.scaling: Dict[str, Tuple[bool, bool]] = {}          # kind -> (noise, duration)
         self.T1 = [0.0] * n
         self.T2 = [0.0] * n
+        self.p0 = [1.0] * n
+        self.t1_form, self.t2_form = "amp_t1", "deph_t2"
         self.edges: List[Tuple[int, int]] = []
         self.alpha = 0.0
+        self.static_zz: List[Tuple[int, int, float]] = []
+        self.t_meas = 0.0
+        self.eps = [0.0] * n
+
+    def set_angle_scaling(self, kind: str, noise: bool = True, duration: bool = False):
+        self.scaling[kind] = (noise, duration)
+
+    def set_thermal(self, p0: Sequence[float]):
+        self.p0 = list(p0)
+
+    def set_passive_forms(self, t1: str = "amp_t1", t2: str = "deph_t2"):
+        self.t1_form, self.t2_form = t1, t2
+
+    def set_static_zz(self, edges, beta):
+        self.static_zz = [(int(a), int(b), float(x)) for (a, b), x in zip(edges, beta)]
+
+    def set_readout(self, t_meas: float, eps: Sequence[float]):
+        self.t_meas, self.eps = t_meas, list(eps)
 
     def set_gate(self, kind: str, duration: float, p_depol: float = 0.0, p_deph: float = 0.0):
         self.gates[kind] = (duration, p_depol, p_deph)
@@ -60,33 +98,81 @@ def schedule(n: int, gates: Sequence) -> List[List[int]]:
     return batches
 
 
+def _t1(dev: Device, q: int, dt: float) -> List[tuple]:
+    if dev.T1[q] <= 0 or dt <= 0:
+        return []
+    if dev.t1_form == "depol_t1":
+        return [("depol_t1", (q,), (dt, dev.T1[q]))]
+    if dev.p0[q] < 1:
+        return [("gamp_t1", (q,), (dev.p0[q], dt, dev.T1[q]))]
+    return [("amp_t1", (q,), (dt, dev.T1[q]))]
+
+
+def _t2(dev: Device, q: int, dt: float) -> List[tuple]:
+    if dev.T2[q] <= 0 or dt <= 0:
+        return []
+    return [(dev.t2_form, (q,), (dt, dev.T2[q]))]
+
+
 def insert_noise(dev: Device, gates: Sequence) -> List[tuple]:
     out: List[tuple] = []
     for batch in schedule(dev.n, gates):
-        spec = [dev.gates.get(gates[i][0], (0.0, 0.0, 0.0)) for i in batch]
+        spec = []
+        for i in batch:
+            kind, _, params = gates[i]
+            d, pd, pq = dev.gates.get(kind, (0.0, 0.0, 0.0))
+            scale_noise, scale_dur = dev.scaling.get(kind, (False, False))
+            f = abs(params[0]) / math.pi if (scale_noise or scale_dur) else 1.0
+            if scale_noise:
+                pd, pq = pd * f, pq * f
+                if pd > 1 or pq > 1:
+                    raise ValueError("angle-scaled noise probability above 1")
+            if scale_dur:
+                d = d * f
+            spec.append((d, pd, pq))
         dur = max(s[0] for s in spec)
         busy = {}
-        two_qubit = False
+        pairs = set()
         for i, (d, pd, pq) in zip(batch, spec):
             kind, qs, params = gates[i]
             out.append((kind, tuple(qs), tuple(params)))
             k = len(qs)
-            two_qubit = two_qubit or k == 2
+            if k == 2:
+                pairs.add(frozenset(qs))
             if pd > 0:
                 out.append(("depol1" if k == 1 else "depol2", tuple(qs), (pd,)))
             if pq > 0:
                 out.append(("deph1" if k == 1 else "deph2", tuple(qs), (pq,)))
             for q in qs:
                 busy[q] = d
-        if two_qubit and dev.alpha != 0:
+        if pairs and dev.alpha != 0:
             for a, b in dev.edges:
                 if a not in busy and b not in busy:
                     out.append(("zz", (a, b), (dev.alpha,)))
+        if dur > 0:
+            for a, b, beta in dev.static_zz:
+                if beta != 0 and frozenset((a, b)) not in pairs:
+                    out.append(("zz", (a, b), (beta * dur,)))
         for q in range(dev.n):
             idle = dur - busy.get(q, 0.0)
             if idle > 0:
-                if dev.T1[q] > 0:
-                    out.append(("amp_t1", (q,), (idle, dev.T1[q])))
-                if dev.T2[q] > 0:
-                    out.append(("deph_t2", (q,), (idle, dev.T2[q])))
+                out += _t1(dev, q, idle) + _t2(dev, q, idle)
+    return out
+
+
+def readout_noise(dev: Device, qubits: Sequence[int], stage: int) -> List[tuple]:
+    """Noise of the read-out model around a projective measurement of
+    ``qubits``: stage 0 before it, stage 1 after it."""
+    if len(set(qubits)) != len(qubits):
+        raise ValueError("duplicate qubit")
+    out: List[tuple] = []
+    for q in qubits:
+        if stage == 0:
+            out += _t1(dev, q, dev.t_meas)
+        if dev.eps[q] > 0:
+            out.append(("depol1", (q,), (dev.eps[q],)))
+    if stage == 0:
+        for q in range(dev.n):
+            if q not in qubits:
+                out += _t1(dev, q, dev.t_meas) + _t2(dev, q, dev.t_meas)
     return out

@@ -47,3 +47,9 @@ def severity(F: float, nq: int, x: float):
 
 def angle_scaled(eps: float, theta: float) -> float:
     return eps * abs(theta) / math.pi
+
+
+def zz_strength(J: float, delta_ct: float, alpha_c: float, alpha_t: float) -> float:
+    """Sec. 8: static ZZ coupling of two transmons, J^2 (1/(Delta_ct - alpha_t)
+    - 1/(Delta_ct + alpha_c)), in the unit of its inputs."""
+    return J * J * (1.0 / (delta_ct - alpha_t) - 1.0 / (delta_ct + alpha_c))

@@ -19,6 +19,7 @@ LIB = os.path.join(HERE, "libvqd.so")
 ARCH = os.environ.get("VQD_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "builders.cpp", "planner.cpp", "batch.cpp", "traj.cpp", "measure.cpp", "device.cpp",
+           "presets.cpp",
            "kernels.hip",
            "mlp.hip", "traj.hip", "measure.hip"]
 
@@ -44,7 +45,9 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd[1:1] = DEVICE
     else:
-        cmd[1:1] = ["-D__HIP_PLATFORM_AMD__"]
+        # host sources: hipcc still runs a device pass over them, so name the
+        # target rather than take its default
+        cmd[1:1] = ["-D__HIP_PLATFORM_AMD__", "--offload-arch=" + ARCH]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

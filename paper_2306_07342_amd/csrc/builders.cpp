@@ -3,7 +3,8 @@
 // Gates follow the conventions R_sigma(theta) = exp(-i theta sigma / 2)
 // (Rx is eq. u of Sec. 6 at zero detuning), the Rydberg/ZZ/exchange forms of
 // Secs. 3.4 and 6, and the Kraus maps of Sec. 3 (eqs. depol1, depol2, deph1,
-// deph2, damp, gdamp, bf, bf2, ampt1, depht2).  A two-qubit operator A on
+// deph2, damp, gdamp, bf, bf2, ampt1, depht2, depht2s, depolt1; gdamp with
+// gamma(dt) = 1 - exp(-dt/T1)).  A two-qubit operator A on
 // targets[0] and B on targets[1] has matrix kron(B, A) (targets[0] is the
 // least significant bit of the index).
 #include <array>
@@ -121,8 +122,12 @@ int channel_kraus(int kind, const double *p, int &k, std::vector<std::vector<cd>
         Ks.push_back({cd(0), cd(std::sqrt(g)), cd(0), cd(0)});
         return VQD_OK;
     }
-    case VQD_K_GAMP: {
+    case VQD_K_GAMP: case VQD_K_GAMP_T1: {
         double pp = p[0], g = p[1];
+        if (kind == VQD_K_GAMP_T1) {
+            if (!(p[2] > 0) || !(p[1] >= 0)) return fail(VQD_E_ARG, "gamp_t1: need dt >= 0, T1 > 0");
+            g = 1.0 - std::exp(-p[1] / p[2]);
+        }
         if (!need_prob(pp, 1.0) || !need_prob(g, 1.0)) return fail(VQD_E_ARG, "gamp: p, gamma outside [0, 1]");
         k = 1;
         double a = std::sqrt(pp), b = std::sqrt(1 - pp);
@@ -166,6 +171,7 @@ void canonical_params(int kind, double *p)
     switch (kind) {
     case VQD_K_SU2: p[0] = 0.31; p[1] = 0.52; p[2] = -0.73; p[3] = 0.44; break;
     case VQD_K_GAMP: p[0] = 0.83; p[1] = 0.11; break;
+    case VQD_K_GAMP_T1: p[0] = 0.83; p[1] = 0.3; p[2] = 17.0; break;
     case VQD_K_AMP_T1: case VQD_K_DEPH_T2: case VQD_K_DEPH_T2S: case VQD_K_DEPOL_T1:
         p[0] = 0.3; p[1] = 17.0; break;
     case VQD_K_RX: case VQD_K_RY: case VQD_K_RZ: case VQD_K_CPHASE: case VQD_K_XX: case VQD_K_ZZ:
@@ -177,9 +183,9 @@ void canonical_params(int kind, double *p)
 int kind_arity(int kind, int *nq, int *np)
 {
     static const int Q[VQD_K_COUNT] = {0, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2,
-                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1};
+                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1, 1};
     static const int P[VQD_K_COUNT] = {0, 1, 1, 1, 0, 0, 0, 0, 4, 0, 1, 1, 1,
-                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2};
+                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2, 3};
     if (kind <= 0 || kind >= VQD_K_COUNT) return -1;
     if (nq) *nq = Q[kind];
     if (np) *np = P[kind];
@@ -390,6 +396,18 @@ int vqd_fidelity_to_errors(int nq, double fbar, double x, double *p_depol, doubl
 double vqd_angle_scaled_error(double eps, double theta)
 {
     return eps * std::fabs(theta) / 3.14159265358979323846;
+}
+
+int vqd_zz_crosstalk_strength(double J, double delta_ct, double alpha_c, double alpha_t, double *beta)
+{
+    vqd::clear_error();
+    if (!beta) return vqd::fail(VQD_E_ARG, "null output");
+    if (!std::isfinite(J) || !std::isfinite(delta_ct) || !std::isfinite(alpha_c) || !std::isfinite(alpha_t))
+        return vqd::fail(VQD_E_ARG, "non-finite parameter");
+    const double a = delta_ct - alpha_t, b = delta_ct + alpha_c;
+    if (a == 0.0 || b == 0.0) return vqd::fail(VQD_E_ARG, "zero denominator");
+    *beta = J * J * (1.0 / a - 1.0 / b);
+    return VQD_OK;
 }
 
 }  // extern "C"

@@ -4,10 +4,14 @@
 // batches (a gate joins the batch after the last one that uses any of its
 // qubits); a batch lasts as long as its slowest gate.  Each batch is
 // emitted as its gates in input order, each followed by its active noise
-// (depolarising, then dephasing), then ZZ crosstalk on the listed edges
-// whose qubits are both idle (when the batch holds a two-qubit gate), then
-// passive amp(1 - exp(-dt/T1)) and deph((1 - exp(-dt/T2))/2) for every
-// qubit's idle time dt (Secs. 2, 3.4, 3.5; eqs. ampt1, depht2).
+// (depolarising, then dephasing; optionally scaled by the rotation angle,
+// App. C), then ZZ crosstalk on the listed edges whose qubits are both idle
+// (when the batch holds a two-qubit gate), then the static ZZ coupling of
+// every coupled pair that carries no two-qubit gate (Sec. 8), then passive
+// T1 and T2 decay for every qubit's idle time dt (Secs. 2, 3.4, 3.5, 8; eqs.
+// ampt1, depolt1, gdamp, depht2, depht2s).  Read-out noise (Sec. 8: T1 decay
+// for the measurement time and depolarising noise on either side of the
+// projection) comes from its own call.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -19,6 +23,7 @@ namespace {
 
 struct GateSpec {
     double duration = 0.0, p_depol = 0.0, p_deph = 0.0;
+    bool scale_noise = false, scale_duration = false;     // by |theta| / pi
 };
 
 struct Op {
@@ -33,9 +38,60 @@ struct vqd_device {
     int n = 0;
     GateSpec gate[VQD_K_COUNT];
     std::vector<double> T1, T2;
+    std::vector<double> p0;                    // thermal ground populations
+    int t1_kind = VQD_K_AMP_T1, t2_kind = VQD_K_DEPH_T2;
     std::vector<std::pair<int, int>> edges;
     double alpha = 0.0;
+    std::vector<std::pair<int, int>> zz_edges;  // static coupling
+    std::vector<double> zz_beta;
+    double t_meas = 0.0;
+    std::vector<double> eps;                   // read-out infidelities
 };
+
+namespace {
+
+using OpList = std::vector<Op>;
+
+void emit(OpList &out, int kind, int a, int b, double p0, double p1 = 0.0, double p2 = 0.0)
+{
+    out.push_back(Op{kind, {a, b, 0, 0}, {p0, p1, p2, 0.0}});
+}
+
+// T1 decay of qubit q over a time dt: amplitude damping (towards the thermal
+// state under a thermal population) or depolarising decay.
+void t1_decay(const vqd_device *d, OpList &out, int q, double dt)
+{
+    if (!(d->T1[q] > 0.0) || !(dt > 0.0)) return;
+    if (d->t1_kind == VQD_K_DEPOL_T1) emit(out, VQD_K_DEPOL_T1, q, 0, dt, d->T1[q]);
+    else if (d->p0[q] < 1.0) emit(out, VQD_K_GAMP_T1, q, 0, d->p0[q], dt, d->T1[q]);
+    else emit(out, VQD_K_AMP_T1, q, 0, dt, d->T1[q]);
+}
+
+void t2_decay(const vqd_device *d, OpList &out, int q, double dt)
+{
+    if (!(d->T2[q] > 0.0) || !(dt > 0.0)) return;
+    emit(out, d->t2_kind, q, 0, dt, d->T2[q]);
+}
+
+int write_ops(const OpList &out, int cap, int *out_count, int *out_kinds, int *out_targets, double *out_params)
+{
+    *out_count = (int)out.size();
+    if (!out_kinds && !out_targets && !out_params) return VQD_OK;      // size query
+    if (!out_kinds || !out_targets || !out_params) return vqd::fail(VQD_E_ARG, "null output array");
+    if (cap < (int)out.size()) return vqd::fail(VQD_E_SIZE, "output arrays too small");
+    for (size_t i = 0; i < out.size(); ++i) {
+        out_kinds[i] = out[i].kind;
+        for (int j = 0; j < 4; ++j) {
+            out_targets[4 * i + j] = out[i].t[j];
+            out_params[4 * i + j] = out[i].p[j];
+        }
+    }
+    return VQD_OK;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+}  // namespace
 
 using namespace vqd;
 
@@ -52,6 +108,8 @@ int vqd_device_create(int n, vqd_device **out)
     d->n = n;
     d->T1.assign(n, 0.0);
     d->T2.assign(n, 0.0);
+    d->p0.assign(n, 1.0);
+    d->eps.assign(n, 0.0);
     *out = d;
     return VQD_OK;
 }
@@ -104,6 +162,99 @@ int vqd_device_set_crosstalk(vqd_device *d, int n_edges, const int *edges, doubl
     return VQD_OK;
 }
 
+int vqd_device_set_angle_scaling(vqd_device *d, int kind, int scale_noise, int scale_duration)
+{
+    clear_error();
+    if (!d) return fail(VQD_E_ARG, "null device");
+    int nq = 0, np = 0;
+    if (kind_arity(kind, &nq, &np) != 0 || kind_is_channel(kind) || np < 1)
+        return fail(VQD_E_ARG, "not a parameterised gate kind: " + std::to_string(kind));
+    d->gate[kind].scale_noise = scale_noise != 0;
+    d->gate[kind].scale_duration = scale_duration != 0;
+    return VQD_OK;
+}
+
+int vqd_device_set_thermal(vqd_device *d, const double *p0)
+{
+    clear_error();
+    if (!d || !p0) return fail(VQD_E_ARG, "null argument");
+    for (int q = 0; q < d->n; ++q)
+        if (!(p0[q] >= 0.0 && p0[q] <= 1.0)) return fail(VQD_E_ARG, "thermal population outside [0, 1]");
+    d->p0.assign(p0, p0 + d->n);
+    return VQD_OK;
+}
+
+int vqd_device_set_passive_forms(vqd_device *d, int t1_kind, int t2_kind)
+{
+    clear_error();
+    if (!d) return fail(VQD_E_ARG, "null device");
+    if (t1_kind != VQD_K_AMP_T1 && t1_kind != VQD_K_DEPOL_T1)
+        return fail(VQD_E_ARG, "T1 decay must be VQD_K_AMP_T1 or VQD_K_DEPOL_T1");
+    if (t2_kind != VQD_K_DEPH_T2 && t2_kind != VQD_K_DEPH_T2S)
+        return fail(VQD_E_ARG, "T2 decay must be VQD_K_DEPH_T2 or VQD_K_DEPH_T2S");
+    d->t1_kind = t1_kind;
+    d->t2_kind = t2_kind;
+    return VQD_OK;
+}
+
+int vqd_device_set_static_zz(vqd_device *d, int n_edges, const int *edges, const double *beta)
+{
+    clear_error();
+    if (!d) return fail(VQD_E_ARG, "null device");
+    if (n_edges < 0 || (n_edges > 0 && (!edges || !beta))) return fail(VQD_E_ARG, "bad edge list");
+    std::vector<std::pair<int, int>> e;
+    std::vector<double> b;
+    for (int i = 0; i < n_edges; ++i) {
+        if (int rc = check_targets(d->n, 2, edges + 2 * i)) return rc;
+        if (!std::isfinite(beta[i])) return fail(VQD_E_ARG, "non-finite coupling");
+        e.emplace_back(edges[2 * i], edges[2 * i + 1]);
+        b.push_back(beta[i]);
+    }
+    d->zz_edges = std::move(e);
+    d->zz_beta = std::move(b);
+    return VQD_OK;
+}
+
+int vqd_device_set_readout(vqd_device *d, double t_meas, const double *eps)
+{
+    clear_error();
+    if (!d || !eps) return fail(VQD_E_ARG, "null argument");
+    if (!finite_nonneg(t_meas)) return fail(VQD_E_ARG, "measurement time must be finite and >= 0");
+    for (int q = 0; q < d->n; ++q)
+        if (!(eps[q] >= 0.0 && eps[q] <= 1.0)) return fail(VQD_E_ARG, "read-out infidelity outside [0, 1]");
+    d->t_meas = t_meas;
+    d->eps.assign(eps, eps + d->n);
+    return VQD_OK;
+}
+
+int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int stage, int cap, int *out_count,
+                             int *out_kinds, int *out_targets, double *out_params)
+{
+    clear_error();
+    if (!d || !out_count) return fail(VQD_E_ARG, "null argument");
+    if (stage != 0 && stage != 1) return fail(VQD_E_ARG, "stage must be 0 (before) or 1 (after)");
+    if (nq < 0 || nq > d->n || (nq > 0 && !qubits)) return fail(VQD_E_ARG, "bad qubit list");
+    std::vector<char> measured(d->n, 0);
+    for (int i = 0; i < nq; ++i) {
+        if (qubits[i] < 0 || qubits[i] >= d->n) return fail(VQD_E_ARG, "qubit out of range");
+        if (measured[qubits[i]]) return fail(VQD_E_ARG, "duplicate qubit");
+        measured[qubits[i]] = 1;
+    }
+    OpList out;
+    for (int i = 0; i < nq; ++i) {
+        const int q = qubits[i];
+        if (stage == 0) t1_decay(d, out, q, d->t_meas);
+        if (d->eps[q] > 0.0) emit(out, VQD_K_DEPOL1, q, 0, d->eps[q]);
+    }
+    if (stage == 0)
+        for (int q = 0; q < d->n; ++q)
+            if (!measured[q]) {
+                t1_decay(d, out, q, d->t_meas);
+                t2_decay(d, out, q, d->t_meas);
+            }
+    return write_ops(out, cap, out_count, out_kinds, out_targets, out_params);
+}
+
 int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, const int *targets, const double *params,
                             int cap, int *out_count, int *out_kinds, int *out_targets, double *out_params)
 {
@@ -128,60 +279,62 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
     std::vector<std::vector<int>> batches(n_batches);
     for (int i = 0; i < count; ++i) batches[batch_of[i]].push_back(i);
 
-    std::vector<Op> out;
-    auto emit = [&](int kind, int a, int b, double p0, double p1) {
-        Op o{kind, {a, b, 0, 0}, {p0, p1, 0.0, 0.0}};
-        out.push_back(o);
-    };
+    OpList out;
     std::vector<double> busy(n);
     std::vector<char> active(n);
+    std::vector<std::pair<int, int>> pairs;      // two-qubit gates of the batch
     for (const auto &batch : batches) {
         double dur = 0.0;
         bool two = false;
         std::fill(busy.begin(), busy.end(), 0.0);
         std::fill(active.begin(), active.end(), 0);
+        pairs.clear();
         for (int i : batch) {
             const GateSpec &g = d->gate[kinds[i]];
-            dur = std::max(dur, g.duration);
             int nq = 0;
             kind_arity(kinds[i], &nq, nullptr);
             const int *t = targets + 4 * (size_t)i;
+            const double *par = params + 4 * (size_t)i;
+            const double s = std::fabs(par[0]) / 3.14159265358979323846;
+            const double gd = g.scale_duration ? g.duration * s : g.duration;
+            const double pd = g.scale_noise ? g.p_depol * s : g.p_depol;
+            const double pq = g.scale_noise ? g.p_deph * s : g.p_deph;
+            if (!(pd <= 1.0) || !(pq <= 1.0))
+                return fail(VQD_E_ARG, "gate " + std::to_string(i) + ": angle-scaled noise probability above 1");
+            dur = std::max(dur, gd);
             Op o{kinds[i], {0, 0, 0, 0}, {0.0, 0.0, 0.0, 0.0}};
             for (int j = 0; j < 4; ++j) {
                 o.t[j] = t[j];
-                o.p[j] = params[4 * (size_t)i + j];
+                o.p[j] = par[j];
             }
             out.push_back(o);
-            if (g.p_depol > 0.0) emit(nq == 1 ? VQD_K_DEPOL1 : VQD_K_DEPOL2, t[0], nq > 1 ? t[1] : 0, g.p_depol, 0.0);
-            if (g.p_deph > 0.0) emit(nq == 1 ? VQD_K_DEPH1 : VQD_K_DEPH2, t[0], nq > 1 ? t[1] : 0, g.p_deph, 0.0);
+            if (pd > 0.0) emit(out, nq == 1 ? VQD_K_DEPOL1 : VQD_K_DEPOL2, t[0], nq > 1 ? t[1] : 0, pd);
+            if (pq > 0.0) emit(out, nq == 1 ? VQD_K_DEPH1 : VQD_K_DEPH2, t[0], nq > 1 ? t[1] : 0, pq);
             two = two || nq == 2;
+            if (nq == 2) pairs.emplace_back(std::min(t[0], t[1]), std::max(t[0], t[1]));
             for (int j = 0; j < nq; ++j) {
-                busy[t[j]] = g.duration;
+                busy[t[j]] = gd;
                 active[t[j]] = 1;
             }
         }
         if (two && d->alpha != 0.0)
             for (const auto &e : d->edges)
-                if (!active[e.first] && !active[e.second]) emit(VQD_K_ZZ, e.first, e.second, d->alpha, 0.0);
+                if (!active[e.first] && !active[e.second]) emit(out, VQD_K_ZZ, e.first, e.second, d->alpha);
+        if (dur > 0.0)
+            for (size_t k = 0; k < d->zz_edges.size(); ++k) {
+                const auto &e = d->zz_edges[k];
+                const std::pair<int, int> key(std::min(e.first, e.second), std::max(e.first, e.second));
+                if (d->zz_beta[k] == 0.0 || std::find(pairs.begin(), pairs.end(), key) != pairs.end()) continue;
+                emit(out, VQD_K_ZZ, e.first, e.second, d->zz_beta[k] * dur);
+            }
         for (int q = 0; q < n; ++q) {
             const double idle = dur - busy[q];
             if (!(idle > 0.0)) continue;
-            if (d->T1[q] > 0.0) emit(VQD_K_AMP_T1, q, 0, idle, d->T1[q]);
-            if (d->T2[q] > 0.0) emit(VQD_K_DEPH_T2, q, 0, idle, d->T2[q]);
+            t1_decay(d, out, q, idle);
+            t2_decay(d, out, q, idle);
         }
     }
-    *out_count = (int)out.size();
-    if (!out_kinds && !out_targets && !out_params) return VQD_OK;      // size query
-    if (!out_kinds || !out_targets || !out_params) return fail(VQD_E_ARG, "null output array");
-    if (cap < (int)out.size()) return fail(VQD_E_SIZE, "output arrays too small");
-    for (size_t i = 0; i < out.size(); ++i) {
-        out_kinds[i] = out[i].kind;
-        for (int j = 0; j < 4; ++j) {
-            out_targets[4 * i + j] = out[i].t[j];
-            out_params[4 * i + j] = out[i].p[j];
-        }
-    }
-    return VQD_OK;
+    return write_ops(out, cap, out_count, out_kinds, out_targets, out_params);
 }
 
 }  // extern "C"

@@ -1,0 +1,154 @@
+// Device presets: the parameter tables of the paper's virtual devices (App.
+// C) turned into device-layer specifications (declarations and contract in
+// include/vqd.h).  Units as in App. C: microseconds and megahertz.
+//
+// Superconducting (Sec. 8, table conf:scq): six transmons.  Gates are ideal
+// (the model's errors are all passive); Rx and Ry (and the other one-qubit
+// rotations, which the device realises with them) take 0.05 us, Z rotations
+// are frame changes and take no time, two-qubit gates (cross-resonance ZX,
+// siZZle ZZ) take 0.5 us.  Passive noise: T1 relaxation towards the thermal
+// state the qubits are initialised in (eqs. thermalstate, gdamp), T2
+// dephasing (eq. depht2), and the static ZZ coupling of every capacitively
+// coupled pair, beta = J^2 (1/(Delta - alpha_t) - 1/(Delta + alpha_c)) in
+// MHz, applied as a phase of 2 pi beta per microsecond except while a
+// two-qubit gate drives that pair.  Read-out: T1 decay for the 5 us
+// measurement and depolarising noise of the read-out infidelity 1 - F on
+// either side of the projection.
+//
+// Trapped ions (Sec. 4, table conf:trapped_ions): two nodes of four ions in
+// one register (qubits 0-3 and 4-7).  Passive noise: T1 amplitude damping
+// and Gaussian T2* dephasing (eq. depht2s).  x and y rotations: depolarising
+// noise from the reported fidelity (App. B), scaled with the duration by
+// |theta| / pi (App. C); a pi rotation takes 1 / (2 x Rabi frequency).  CZ:
+// the reported fidelity split 0.1 : 0.9 into depolarising and dephasing
+// noise, duration 1 / (2 x its gate frequency).  Ion transport, remote
+// entanglement and the ions' bit-flip read-out are not part of the preset.
+#include <cmath>
+#include <string>
+
+#include "vqd_internal.h"
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+int superconducting(vqd_device **out, double *p0)
+{
+    constexpr int n = 6;
+    const double T1[n] = {63, 93, 109, 115, 68, 125};
+    const double T2[n] = {113, 149, 185, 161, 122, 200};
+    const double excited[n] = {3.2e-2, 2.1e-2, 0.8e-2, 0.9e-2, 2.5e-2, 0.7e-2};
+    const double freq[n] = {4.5e3, 4.9e3, 4.7e3, 5.1e3, 4.9e3, 5.3e3};
+    const double anharm[n] = {296.7, 298.6, 297.4, 298.3, 297.2, 299.1};
+    const double fid_read[n] = {0.9, 0.92, 0.96, 0.97, 0.93, 0.97};
+    const int pairs[7][2] = {{0, 1}, {0, 2}, {1, 3}, {2, 3}, {2, 4}, {3, 5}, {4, 5}};
+    const double J[7] = {4, 1.5, 1.5, 4, 1.5, 1.5, 4};
+    const double t_meas = 5.0, t_1q = 0.05, t_2q = 0.5;
+
+    vqd_device *d = nullptr;
+    if (int rc = vqd_device_create(n, &d)) return rc;
+    double ground[n], eps[n], beta[7];
+    int edges[14];
+    for (int q = 0; q < n; ++q) {
+        ground[q] = 1.0 - excited[q];
+        eps[q] = 1.0 - fid_read[q];
+    }
+    for (int e = 0; e < 7; ++e) {
+        const int c = pairs[e][0], t = pairs[e][1];
+        edges[2 * e] = c;
+        edges[2 * e + 1] = t;
+        double b = 0.0;
+        if (int rc = vqd_zz_crosstalk_strength(J[e], freq[c] - freq[t], anharm[c], anharm[t], &b)) {
+            vqd_device_destroy(d);
+            return rc;
+        }
+        beta[e] = kTwoPi * b;
+    }
+    int rc = VQD_OK;
+    for (int k : {VQD_K_RX, VQD_K_RY, VQD_K_H, VQD_K_X, VQD_K_Y, VQD_K_SU2})
+        if (!rc) rc = vqd_device_set_gate(d, k, t_1q, 0.0, 0.0);
+    for (int k : {VQD_K_CZ, VQD_K_CPHASE, VQD_K_XX, VQD_K_ZZ})
+        if (!rc) rc = vqd_device_set_gate(d, k, t_2q, 0.0, 0.0);
+    if (!rc) rc = vqd_device_set_passive(d, T1, T2);
+    if (!rc) rc = vqd_device_set_thermal(d, ground);
+    if (!rc) rc = vqd_device_set_static_zz(d, 7, edges, beta);
+    if (!rc) rc = vqd_device_set_readout(d, t_meas, eps);
+    if (rc) {
+        vqd_device_destroy(d);
+        return rc;
+    }
+    if (p0)
+        for (int q = 0; q < n; ++q) p0[q] = ground[q];
+    *out = d;
+    return VQD_OK;
+}
+
+int trapped_ion(vqd_device **out, double *p0)
+{
+    constexpr int n = 8;
+    const double T1 = 3e9, T2s = 10e5, fid_init = 0.9999;
+    const double fid_xy = 0.99999, x_xy = 1.0, rabi = 10.0;
+    const double fid_cz = 0.999, x_cz = 0.1, freq_cz = 0.1;
+
+    vqd_device *d = nullptr;
+    if (int rc = vqd_device_create(n, &d)) return rc;
+    double t1[n], t2[n];
+    for (int q = 0; q < n; ++q) {
+        t1[q] = T1;
+        t2[q] = T2s;
+    }
+    double pd1 = 0, pq1 = 0, pd2 = 0, pq2 = 0;
+    int rc = vqd_fidelity_to_errors(1, fid_xy, x_xy, &pd1, &pq1);
+    if (!rc) rc = vqd_fidelity_to_errors(2, fid_cz, x_cz, &pd2, &pq2);
+    const double t_pi = 1.0 / (2.0 * rabi), t_cz = 1.0 / (2.0 * freq_cz);
+    for (int k : {VQD_K_RX, VQD_K_RY}) {
+        if (!rc) rc = vqd_device_set_gate(d, k, t_pi, pd1, pq1);
+        if (!rc) rc = vqd_device_set_angle_scaling(d, k, 1, 1);
+    }
+    for (int k : {VQD_K_H, VQD_K_X, VQD_K_Y})     // pi rotations
+        if (!rc) rc = vqd_device_set_gate(d, k, t_pi, pd1, pq1);
+    if (!rc) rc = vqd_device_set_gate(d, VQD_K_CZ, t_cz, pd2, pq2);
+    if (!rc) rc = vqd_device_set_passive(d, t1, t2);
+    if (!rc) rc = vqd_device_set_passive_forms(d, VQD_K_AMP_T1, VQD_K_DEPH_T2S);
+    if (rc) {
+        vqd_device_destroy(d);
+        return rc;
+    }
+    if (p0)
+        for (int q = 0; q < n; ++q) p0[q] = fid_init;
+    *out = d;
+    return VQD_OK;
+}
+
+}  // namespace
+
+using namespace vqd;
+
+extern "C" {
+
+int vqd_device_preset(int preset, vqd_device **out, double *p0)
+{
+    clear_error();
+    if (!out) return fail(VQD_E_ARG, "null output pointer");
+    *out = nullptr;
+    int rc;
+    switch (preset) {
+    case VQD_PRESET_SUPERCONDUCTING: rc = superconducting(out, p0); break;
+    case VQD_PRESET_TRAPPED_ION: rc = trapped_ion(out, p0); break;
+    default: return fail(VQD_E_ARG, "unknown preset " + std::to_string(preset));
+    }
+    return rc;
+}
+
+int vqd_device_preset_qubits(int preset, int *n)
+{
+    clear_error();
+    if (!n) return fail(VQD_E_ARG, "null output pointer");
+    switch (preset) {
+    case VQD_PRESET_SUPERCONDUCTING: *n = 6; return VQD_OK;
+    case VQD_PRESET_TRAPPED_ION: *n = 8; return VQD_OK;
+    default: return fail(VQD_E_ARG, "unknown preset " + std::to_string(preset));
+    }
+}
+
+}  // extern "C"

@@ -23,6 +23,7 @@ KINDS = {
     "cz": 9, "cphase": 10, "xx": 11, "zz": 12,
     "depol1": 13, "depol2": 14, "deph1": 15, "deph2": 16, "amp": 17, "gamp": 18,
     "bitflip1": 19, "bitflip2": 20, "amp_t1": 21, "deph_t2": 22, "deph_t2s": 23, "depol_t1": 24,
+    "gamp_t1": 25,
 }
 BLOCK_UNITARY = 0
 BLOCK_SUPEROP = 1
@@ -154,12 +155,23 @@ def load(path: str = LIB_PATH):
         "vqd_entanglement_fidelity": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp], ctypes.c_int),
         "vqd_fidelity_to_errors": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp], ctypes.c_int),
         "vqd_angle_scaled_error": ([ctypes.c_double, ctypes.c_double], ctypes.c_double),
+        "vqd_zz_crosstalk_strength": ([ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp],
+                                      ctypes.c_int),
         "vqd_device_create": ([ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "vqd_device_destroy": ([vp], ctypes.c_int),
         "vqd_device_set_gate": ([vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double],
                                 ctypes.c_int),
         "vqd_device_set_passive": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_device_set_crosstalk": ([vp, ctypes.c_int, _ip, ctypes.c_double], ctypes.c_int),
+        "vqd_device_preset": ([ctypes.c_int, ctypes.POINTER(vp), _dp], ctypes.c_int),
+        "vqd_device_preset_qubits": ([ctypes.c_int, _ip], ctypes.c_int),
+        "vqd_device_set_angle_scaling": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "vqd_device_set_thermal": ([vp, _dp], ctypes.c_int),
+        "vqd_device_set_passive_forms": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "vqd_device_set_static_zz": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+        "vqd_device_set_readout": ([vp, ctypes.c_double, _dp], ctypes.c_int),
+        "vqd_device_readout_noise": ([vp, ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip, _dp],
+                                     ctypes.c_int),
         "vqd_device_insert_noise": ([vp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int, _ip, _ip, _ip, _dp],
                                     ctypes.c_int),
         "vqd_calc_trace": ([vp, _dp, _dp], ctypes.c_int),
@@ -253,6 +265,13 @@ def fidelity_to_errors(nq: int, fbar: float, x: float):
 
 def angle_scaled_error(eps: float, theta: float) -> float:
     return lib().vqd_angle_scaled_error(eps, theta)
+
+
+def zz_crosstalk_strength(J: float, delta_ct: float, alpha_c: float, alpha_t: float) -> float:
+    """Sec. 8: static ZZ coupling of two transmons (same frequency unit in and out)."""
+    out = ctypes.c_double()
+    check(lib().vqd_zz_crosstalk_strength(J, delta_ct, alpha_c, alpha_t, ctypes.byref(out)))
+    return out.value
 
 
 class DensityMatrix:
@@ -519,6 +538,9 @@ class Program:
 KIND_NAMES = {v: k for k, v in KINDS.items()}
 
 
+PRESETS = {"superconducting": 1, "trapped_ion": 2}
+
+
 class Device:
     """Virtual-device noise insertion (vqd_device_* in include/vqd.h): ideal
     gates in, the device's noisy op stream out (host only)."""
@@ -529,6 +551,20 @@ class Device:
         h = ctypes.c_void_p()
         check(lib().vqd_device_create(n, ctypes.byref(h)))
         self.handle = h
+
+    @classmethod
+    def preset(cls, name: str):
+        """(device, p0): a device of the paper's parameter tables and the
+        ground populations of its initial state."""
+        load()
+        n = ctypes.c_int()
+        check(lib().vqd_device_preset_qubits(PRESETS[name], ctypes.byref(n)))
+        p0 = np.zeros(n.value)
+        h = ctypes.c_void_p()
+        check(lib().vqd_device_preset(PRESETS[name], ctypes.byref(h), _d(p0)))
+        d = cls.__new__(cls)
+        d.n, d.handle = n.value, h
+        return d, p0
 
     def close(self):
         if getattr(self, "handle", None):
@@ -555,6 +591,50 @@ class Device:
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         check(lib().vqd_device_set_crosstalk(self.handle, e.shape[0], _i(e), alpha))
 
+    def set_angle_scaling(self, kind: str, noise: bool = True, duration: bool = False):
+        check(lib().vqd_device_set_angle_scaling(self.handle, KINDS[kind], int(noise), int(duration)))
+
+    def _per_qubit(self, v, what):
+        a = np.ascontiguousarray(v, dtype=np.float64)
+        if a.shape != (self.n,):
+            raise ValueError("%s needs one value per qubit" % what)
+        return a
+
+    def set_thermal(self, p0):
+        a = self._per_qubit(p0, "p0")
+        check(lib().vqd_device_set_thermal(self.handle, _d(a)))
+
+    def set_passive_forms(self, t1: str = "amp_t1", t2: str = "deph_t2"):
+        check(lib().vqd_device_set_passive_forms(self.handle, KINDS[t1], KINDS[t2]))
+
+    def set_static_zz(self, edges, beta):
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        b = np.ascontiguousarray(beta, dtype=np.float64).reshape(-1)
+        if b.shape[0] != e.shape[0]:
+            raise ValueError("one coupling per edge")
+        check(lib().vqd_device_set_static_zz(self.handle, e.shape[0], _i(e), _d(b) if b.size else None))
+
+    def set_readout(self, t_meas: float, eps):
+        a = self._per_qubit(eps, "eps")
+        check(lib().vqd_device_set_readout(self.handle, t_meas, _d(a)))
+
+    @staticmethod
+    def _decode(fill) -> list:
+        cnt = ctypes.c_int()
+        check(fill(0, ctypes.byref(cnt), None, None, None))
+        c = cnt.value
+        ok = np.zeros(max(c, 1), dtype=np.int32)
+        ot = np.zeros((max(c, 1), 4), dtype=np.int32)
+        opr = np.zeros((max(c, 1), 4), dtype=np.float64)
+        check(fill(c, ctypes.byref(cnt), _i(ok), _i(ot), _d(opr)))
+        out = []
+        for i in range(c):
+            name = KIND_NAMES[int(ok[i])]
+            nq, npar = ctypes.c_int(), ctypes.c_int()
+            lib().vqd_kind_arity(int(ok[i]), ctypes.byref(nq), ctypes.byref(npar))
+            out.append((name, tuple(int(x) for x in ot[i, :nq.value]), tuple(float(x) for x in opr[i, :npar.value])))
+        return out
+
     def insert_noise(self, gates) -> list:
         """Noisy op stream (kind, qubits, params) for a list of named gates."""
         m = len(gates)
@@ -565,22 +645,16 @@ class Device:
             k[i] = KINDS[kind]
             t[i, :len(q)] = q
             p[i, :len(par)] = par
-        cnt = ctypes.c_int()
-        check(lib().vqd_device_insert_noise(self.handle, m, _i(k), _i(t), _d(p), 0, ctypes.byref(cnt),
-                                            None, None, None))
-        c = cnt.value
-        ok = np.zeros(max(c, 1), dtype=np.int32)
-        ot = np.zeros((max(c, 1), 4), dtype=np.int32)
-        opr = np.zeros((max(c, 1), 4), dtype=np.float64)
-        check(lib().vqd_device_insert_noise(self.handle, m, _i(k), _i(t), _d(p), c, ctypes.byref(cnt),
-                                            _i(ok), _i(ot), _d(opr)))
-        out = []
-        for i in range(c):
-            name = KIND_NAMES[int(ok[i])]
-            nq, npar = ctypes.c_int(), ctypes.c_int()
-            lib().vqd_kind_arity(int(ok[i]), ctypes.byref(nq), ctypes.byref(npar))
-            out.append((name, tuple(int(x) for x in ot[i, :nq.value]), tuple(float(x) for x in opr[i, :npar.value])))
-        return out
+        return self._decode(lambda cap, cnt, a, b, c: lib().vqd_device_insert_noise(
+            self.handle, m, _i(k), _i(t), _d(p), cap, cnt, a, b, c))
+
+    def readout_noise(self, qubits, stage: int) -> list:
+        """Read-out noise ops of the measured ``qubits``: stage 0 before the
+        projective measurement, stage 1 after it."""
+        q = np.ascontiguousarray(list(qubits) or [0], dtype=np.int32)
+        nq = len(qubits)
+        return self._decode(lambda cap, cnt, a, b, c: lib().vqd_device_readout_noise(
+            self.handle, nq, _i(q), stage, cap, cnt, a, b, c))
 
 
 class Trajectories:

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import device as dv
-from tests.test_device_oracle import random_gates, spec4
+from tests.test_device_oracle import random_gates, spec4, spec_sc
 from workloads import c1_line_circuit, c2_grid_circuit
 
 
@@ -22,6 +22,12 @@ def lib_device(vqd, ref: dv.Device):
         d.set_gate(k, t, p, q)
     d.set_passive(ref.T1, ref.T2)
     d.set_crosstalk(ref.edges, ref.alpha)
+    for k, (noise, dur) in ref.scaling.items():
+        d.set_angle_scaling(k, noise, dur)
+    d.set_thermal(ref.p0)
+    d.set_passive_forms(ref.t1_form, ref.t2_form)
+    d.set_static_zz([(a, b) for a, b, _ in ref.static_zz], [x for _, _, x in ref.static_zz])
+    d.set_readout(ref.t_meas, ref.eps)
     return d
 
 
@@ -57,6 +63,45 @@ def test_grid_gates_with_a_superconducting_like_device(vqd_host):
     same_stream(lib_device(vqd_host, ref).insert_noise(ideal), dv.insert_noise(ref, ideal))
 
 
+def test_hand_example_with_every_rule(vqd_host):
+    ref = spec_sc()
+    gates = [("rx", (0,), (np.pi / 2,)), ("cz", (1, 2), ())]
+    same_stream(lib_device(vqd_host, ref).insert_noise(gates), dv.insert_noise(ref, gates))
+
+
+@pytest.mark.parametrize("seed", [4, 5, 6])
+def test_random_devices_with_every_rule(vqd_host, seed):
+    rng = np.random.default_rng(seed)
+    n = 6
+    ref = dv.Device(n)
+    for k in ("rx", "ry", "rz", "h", "cz"):
+        ref.set_gate(k, float(rng.choice([0.0, 0.05, 0.3])), float(rng.choice([0.0, 1e-3])),
+                     float(rng.choice([0.0, 2e-3])))
+    for k in ("rx", "ry"):
+        ref.set_angle_scaling(k, bool(rng.integers(2)), bool(rng.integers(2)))
+    ref.set_passive(list(rng.uniform(20, 200, n) * (rng.random(n) < 0.8)),
+                    list(rng.uniform(10, 100, n) * (rng.random(n) < 0.8)))
+    ref.set_thermal(list(np.where(rng.random(n) < 0.5, 1.0, rng.uniform(0.9, 1.0, n))))
+    ref.set_passive_forms(str(rng.choice(["amp_t1", "depol_t1"])), str(rng.choice(["deph_t2", "deph_t2s"])))
+    ref.set_crosstalk([(i, i + 1) for i in range(n - 1)], 0.01)
+    ref.set_static_zz([(i, i + 1) for i in range(n - 1)] + [(0, n - 1)], list(rng.uniform(-0.05, 0.05, n)))
+    ref.set_readout(float(rng.uniform(1, 5)), list(rng.uniform(0, 0.05, n) * (rng.random(n) < 0.7)))
+    gates = random_gates(n, 80, seed)
+    lib = lib_device(vqd_host, ref)
+    same_stream(lib.insert_noise(gates), dv.insert_noise(ref, gates))
+    for qs in ([0], [3, 1], list(range(n)), []):
+        for stage in (0, 1):
+            same_stream(lib.readout_noise(qs, stage), dv.readout_noise(ref, qs, stage))
+
+
+def test_zz_strength(vqd_host):
+    from oracle.params import zz_strength
+    for args in ((4.0, -400.0, 296.7, 298.6), (1.5, 200.0, 297.4, 297.2), (0.0, 10.0, 1.0, 2.0)):
+        assert abs(vqd_host.zz_crosstalk_strength(*args) - zz_strength(*args)) <= 1e-15
+    with pytest.raises(vqd_host.VQDError):
+        vqd_host.zz_crosstalk_strength(1.0, 5.0, 1.0, 5.0)        # Delta - alpha_t = 0
+
+
 def test_errors(vqd_host):
     v = vqd_host
     with pytest.raises(v.VQDError):
@@ -71,3 +116,22 @@ def test_errors(vqd_host):
     with pytest.raises(v.VQDError):
         d.insert_noise([("cz", (0, 0), ())])
     assert d.insert_noise([]) == []
+    with pytest.raises(v.VQDError):
+        d.set_angle_scaling("h")                     # no angle
+    with pytest.raises(v.VQDError):
+        d.set_thermal([1.0, 1.2, 0.5])
+    with pytest.raises(v.VQDError):
+        d.set_passive_forms("deph_t2", "deph_t2")
+    with pytest.raises(v.VQDError):
+        d.set_static_zz([(0, 0)], [0.1])
+    with pytest.raises(v.VQDError):
+        d.set_readout(-1.0, [0.0] * 3)
+    d.set_readout(1.0, [0.1] * 3)
+    with pytest.raises(v.VQDError):
+        d.readout_noise([1, 1], 0)
+    with pytest.raises(v.VQDError):
+        d.readout_noise([0], 2)
+    d.set_gate("rx", 0.1, 0.5)
+    d.set_angle_scaling("rx")
+    with pytest.raises(v.VQDError):                  # 0.5 * 3 > 1
+        d.insert_noise([("rx", (0,), (3 * np.pi,))])

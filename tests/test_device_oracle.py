@@ -81,3 +81,96 @@ def test_noise_free_device_reproduces_the_ideal_state():
     out = dv.insert_noise(d, gates)
     assert sorted(map(str, out)) == sorted(map(str, gates))
     assert np.abs(emulate(n, out).R - emulate(n, gates).R).max() <= 1e-13
+
+
+def spec_sc():
+    """A device with every optional rule on: thermal relaxation, Gaussian
+    dephasing, static ZZ coupling, angle-scaled noise and durations."""
+    d = dv.Device(3)
+    d.set_gate("rx", 0.1, p_depol=0.02, p_deph=0.01)
+    d.set_gate("cz", 0.4)
+    d.set_angle_scaling("rx", noise=True, duration=True)
+    d.set_passive([60.0, 80.0, 0.0], [30.0, 40.0, 20.0])
+    d.set_thermal([0.97, 1.0, 0.9])
+    d.set_passive_forms("amp_t1", "deph_t2s")
+    d.set_static_zz([(0, 1), (1, 2)], [0.03, -0.02])
+    return d
+
+
+def test_hand_example_with_every_rule():
+    pi = np.pi
+    gates = [("rx", (0,), (pi / 2,)), ("cz", (1, 2), ())]
+    got = dv.insert_noise(spec_sc(), gates)
+    expect = [
+        # one batch: Rx(pi/2) on 0 (0.05 us, noise halved), CZ on (1, 2) (0.4 us)
+        ("rx", (0,), (pi / 2,)), ("depol1", (0,), (0.01,)), ("deph1", (0,), (0.005,)),
+        ("cz", (1, 2), ()),
+        ("zz", (0, 1), (0.03 * 0.4,)),                    # (1, 2) carries the CZ
+        ("gamp_t1", (0,), (0.97, 0.35, 60.0)), ("deph_t2s", (0,), (0.35, 30.0)),
+    ]
+    assert len(got) == len(expect), got
+    for g, e in zip(got, expect):
+        assert g[0] == e[0] and g[1] == e[1] and np.allclose(g[2], e[2], rtol=0, atol=1e-15), (g, e)
+    with pytest.raises(ValueError):                   # |theta|/pi = 60 pushes 0.02 above 1
+        dv.insert_noise(spec_sc(), [("rx", (0,), (60 * pi,))])
+
+
+def test_idle_qubit_relaxes_towards_its_thermal_state():
+    """Qubit 1 is flipped and then idles while qubit 0 runs 39 more X gates:
+    its excited population decays as e^{-t/T1} towards 1 - p0, t the idle
+    time (the first batch holds both qubits' X)."""
+    d = dv.Device(2)
+    d.set_gate("x", 0.25)
+    d.set_passive([0.0, 3.0], [0.0, 0.0])
+    d.set_thermal([1.0, 0.8])
+    gates = [("x", (1,), ())] + [("x", (0,), ())] * 40
+    dm = emulate(2, dv.insert_noise(d, gates))
+    t = 39 * 0.25
+    p1 = dm.R[2, 2].real + dm.R[3, 3].real           # qubit 1 excited
+    assert abs(p1 - ((1 - 0.8) + 0.8 * np.exp(-t / 3.0))) <= 1e-13
+
+
+@pytest.mark.parametrize("b", [0, 1])
+def test_static_coupling_accumulates_phase(b):
+    """|+> on qubit 0, |b> on qubit 1, gates only on qubit 2: the coupling
+    beta on (0, 1) rotates qubit 0 by exp(-i (-1)^b beta t Z), so <X_0> =
+    cos(2 beta t) and <Y_0> = (-1)^b sin(2 beta t)."""
+    d = dv.Device(3)
+    d.set_gate("h", 0.1)
+    d.set_gate("z", 0.3)
+    beta = 0.37
+    d.set_static_zz([(0, 1)], [beta])
+    prep = [("h", (0,), ())] + ([("x", (1,), ())] if b else [])
+    gates = [("z", (2,), ())] * 7
+    dm = emulate(3, prep + dv.insert_noise(d, gates))
+    t = 7 * 0.3
+    assert abs(dm.expec_pauli([1, 0, 0]).real - np.cos(2 * beta * t)) <= 1e-13
+    assert abs(dm.expec_pauli([2, 0, 0]).real - (-1) ** b * np.sin(2 * beta * t)) <= 1e-13
+
+
+def test_readout_flip_probability():
+    """|1> read out after T1 decay for t_M and depolarising eps: the outcome
+    is 1 with probability e^{-t/T1} (1 - 2eps/3) + (1 - e^{-t/T1}) 2eps/3."""
+    d = dv.Device(2)
+    d.set_passive([25.0, 40.0], [10.0, 10.0])
+    d.set_readout(5.0, [0.06, 0.0])
+    pre = dv.readout_noise(d, [0], 0)
+    assert [k for k, _, _ in pre] == ["amp_t1", "depol1", "amp_t1", "deph_t2"]
+    dm = emulate(2, [("x", (0,), ())] + pre)
+    e = np.exp(-5.0 / 25.0)
+    p1 = dm.R[1, 1].real + dm.R[3, 3].real
+    assert abs(p1 - (e * (1 - 0.04) + (1 - e) * 0.04)) <= 1e-14
+    assert dv.readout_noise(d, [0], 1) == [("depol1", (0,), (0.06,))]
+    assert dv.readout_noise(d, [1], 1) == []
+
+
+def test_zz_strength_closed_forms():
+    """Sec. 8's coupling: zero without coupling, the same whichever transmon
+    is called control, and 2 alpha J^2 / (Delta^2 - alpha^2) for equal
+    anharmonicities."""
+    from oracle.params import zz_strength
+    J, fc, ft, ac, at = 4.0, 4500.0, 4900.0, 296.7, 298.6
+    assert zz_strength(0.0, fc - ft, ac, at) == 0.0
+    assert abs(zz_strength(J, fc - ft, ac, at) - zz_strength(J, ft - fc, at, ac)) <= 1e-15
+    D, a = -400.0, 297.0
+    assert abs(zz_strength(J, D, a, a) - 2 * a * J * J / (D * D - a * a)) <= 1e-15

@@ -29,3 +29,35 @@ def test_device_stream_on_the_density_matrix(gpu_lib):
     want = emulate(n, dv.insert_noise(ref, ideal))
     assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
     assert abs(dm.purity() - want.purity()) <= 1e-10
+
+
+def test_superconducting_preset_with_readout(gpu_lib):
+    """The superconducting preset end to end on the GPU: thermal initial
+    state, the noisy circuit, read-out noise, a projective measurement of
+    every qubit and the noise after it, against the oracle."""
+    from oracle import measure as om
+    from tests.test_presets import oracle_superconducting, sc_gates
+    n = 6
+    dev, p0 = gpu_lib.Device.preset("superconducting")
+    ref, rp0 = oracle_superconducting()
+    gates = sc_gates(n, 150, 21)
+    noisy = dev.insert_noise(gates) + dev.readout_noise(list(range(n)), 0)
+    want_ops = dv.insert_noise(ref, gates) + dv.readout_noise(ref, list(range(n)), 0)
+    print("superconducting preset: %d ops" % len(noisy), flush=True)
+    dm = gpu_lib.DensityMatrix(n)
+    dm.init_product_diag(p0)
+    gpu_lib.Program(n, noisy).compile().run(dm)
+    from oracle.core import OracleDM
+    want = OracleDM(n)
+    want.init_product_diag(rp0)
+    emulate(n, want_ops, want)
+    assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
+    U = np.random.default_rng(5).random(n)
+    for q in range(n):
+        m, w = dm.measure_z(q, float(U[q]))
+        mr, wr = om.measure_z(want, q, float(U[q]))
+        assert m == mr and abs(w - wr[mr]) <= 1e-10
+    post = dev.readout_noise(list(range(n)), 1)
+    gpu_lib.Program(n, post).compile().run(dm)
+    emulate(n, dv.readout_noise(ref, list(range(n)), 1), want)
+    assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
