@@ -72,6 +72,8 @@ PlanOpts default_opts(int n)
     o.tile_bits = std::min(kBatchTile, 2 * n);
     o.min_contig_bits = 3;
     o.pad_coalesce = false;
+    // k_batch stages a full 2^12 tile and keeps 1 KiB of its own beside it
+    o.rt_budget = (160 * 1024 - 1024 - (16 << kBatchTile)) / 16;
     return o;
 }
 

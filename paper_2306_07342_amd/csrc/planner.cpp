@@ -339,6 +339,9 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
     const int L = std::max(4, std::min(opt.tile_bits, n2));
     const int contig = std::max(0, std::min(opt.min_contig_bits, std::min(L, n2)));
     const int max_take = opt.max_ops_per_pass;
+    // LDS left for the runtime-diagonal tables beside the staged tile
+    const size_t rt_budget = opt.rt_budget > 0 ? (size_t)opt.rt_budget
+                                               : (size_t(160 * 1024) - 1024 - (size_t(16) << L)) / 16;
 
     std::vector<uint32_t> qm(ops.size());
     for (size_t i = 0; i < ops.size(); ++i) {
@@ -361,16 +364,18 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
     }
     size_t first = 0;
     SimResult sim, sim2;
+    int retry_take = 0;     // > 0: the last attempt at this pass overflowed LDS
     while (true) {
         while (first < ops.size() && applied[first]) ++first;
         if (first >= ops.size()) break;
+        const int take_cap = retry_take > 0 ? retry_take : max_take;
 
         // ---- choose the pass qubit set
         uint32_t Q = 0;
         while (true) {
-            simulate(ops, qm, applied, first, Q, n, max_take, sim, true);
+            simulate(ops, qm, applied, first, Q, n, take_cap, sim, true);
             const size_t base = sim.taken.size();
-            if (max_take > 0 && (int)base >= max_take) break;
+            if (take_cap > 0 && (int)base >= take_cap) break;
             uint32_t bestQ = Q;
             size_t bestc = base;
             for (uint32_t c : sim.cands) {
@@ -380,7 +385,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 const bool fits = (int)tile_bits_for(Q2, n, contig).size() <= L ||
                                   (Q == 0 && (int)tile_bits_for(Q2, n, 0).size() <= L);
                 if (!fits) continue;
-                simulate(ops, qm, applied, first, Q2, n, max_take, sim2, false);
+                simulate(ops, qm, applied, first, Q2, n, take_cap, sim2, false);
                 if (sim2.taken.size() > bestc) {
                     bestc = sim2.taken.size();
                     bestQ = Q2;
@@ -389,9 +394,11 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             if (bestQ == Q) break;
             Q = bestQ;
         }
-        simulate(ops, qm, applied, first, Q, n, max_take, sim, false);
+        simulate(ops, qm, applied, first, Q, n, take_cap, sim, false);
         if (sim.taken.empty()) return fail(VQD_E_STATE, "planner made no progress");
         for (int i : sim.taken) applied[i] = 1;
+        const size_t ops_before = out.ops.size(), mats_before = out.mats.size(),
+                     recipes_before = out.recipes.size();
 
         // ---- tile bits
         std::vector<int> tb = tile_bits_for(Q, n, contig);
@@ -808,6 +815,19 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 }
             }
         }
+        if (rt_tables.size() > rt_budget) {
+            // too many tables to stage: undo the pass and take half the ops
+            if (sim.taken.size() <= 1) return fail(VQD_E_SIZE, "a diagonal op's table exceeds the LDS budget");
+            out.phases.resize(kp.phase_begin);
+            out.ops.resize(ops_before);
+            out.mats.resize(mats_before);
+            out.recipes.resize(recipes_before);
+            out.fma_per_amp = fma_before;
+            for (int i : sim.taken) applied[i] = 0;
+            retry_take = (int)sim.taken.size() / 2;
+            continue;
+        }
+        retry_take = 0;
         kp.phase_end = (uint32_t)out.phases.size();
         kp.rt_mat = (uint32_t)out.mats.size();
         kp.rt_count = (uint32_t)rt_tables.size();

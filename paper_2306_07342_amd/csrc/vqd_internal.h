@@ -171,6 +171,8 @@ struct PlanOpts {
     bool record_recipes = false;    // fill HostPlan::recipes
     bool keep_identity = false;     // do not drop ops that are exactly the identity
     bool merge_rt = true;           // tabulate runs of runtime diagonals together
+    int rt_budget = 0;              // runtime-diagonal table entries a pass may stage in
+                                    // LDS (0: what 160 KiB leaves beside the tile)
 };
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out);
 // Recompute a recorded plan's coefficients for new logical ops of the same

@@ -113,3 +113,23 @@ def test_named_channels_and_gates(vqd_host):
     for tb in (4, 8, 12):
         got, ref, _ = run_both(vqd_host, n, ops, seed=4, tile_bits=tb, min_contig_bits=0)
         assert_close(got, ref)
+
+
+def test_many_runtime_diagonals_fit_lds(vqd_host):
+    """A long stream of diagonal ops on qubits outside the register slots (the
+    static ZZ coupling and read-out of a device preset) needs more table
+    entries than one pass can stage: the planner splits the pass so that the
+    tables and the tile fit the 160 KiB of LDS, and the result is unchanged."""
+    from tests.test_presets import sc_gates
+    n = 6
+    dev, _ = vqd_host.Device.preset("superconducting")
+    ops = dev.insert_noise(sc_gates(n, 150, 21)) + dev.readout_noise(list(range(n)), 0)
+    got, ref, info = run_both(vqd_host, n, ops, seed=3)
+    assert_close(got, ref, 1e-11)
+    prog = vqd_host.Program(n, ops)
+    prog.plan(vqd_host.plan_opts())
+    plan = emu.parse(prog.export())
+    for p in plan["passes"]:
+        L = int(p["L"])
+        assert (16 << L) + 16 * int(p["rt_count"]) + 1024 <= 160 * 1024
+    assert len(plan["passes"]) > 1
