@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-every", type=int, default=782)
+    ap.add_argument("--cpu-sample-every", type=int, default=180)   # ~52 ops, 10-15 s of oracle work
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-emulation leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-16q", action="store_true", help="skip the 16-qubit context leg")
