@@ -470,6 +470,8 @@ int plan(vqd_traj *t)
         for (int q : rest) ph.thr_q[ti++] = (uint32_t)q;
         if (int rc = encode_phase(t, R.data(), fused)) return rc;
         ph.op_end = (uint32_t)t->kops.size();
+        for (uint32_t i = ph.op_begin; i < ph.op_end; ++i)
+            if (t->kops[i].kind == TOP_KRAUS) ph.flags |= kTPhaseReduces;
         t->phases.push_back(ph);
     }
     if (t->phases.empty()) {

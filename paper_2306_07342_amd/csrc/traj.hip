@@ -392,6 +392,14 @@ struct UBlock {
     }
 };
 
+// Orders one wave's LDS accesses for the compiler; the hardware executes a
+// wave's LDS instructions in issue order.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // One batch of trajectories.  Workgroup g of the persistent loop holds
 // blockDim / 2^log_tt trajectories; group grp's threads are tid >> log_tt.
 template <bool WIDE>
@@ -417,6 +425,9 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
     const uint64_t n_groups = (T + tpw - 1) / tpw;
     const uint32_t dim = 1u << n;
     uint32_t flip = 0;
+    // A trajectory inside one wave owns its LDS region alone: its exchanges
+    // need no workgroup barrier, only the wave's own (in-order) LDS accesses.
+    const bool shared_tile = WIDE && wpt > 1;
 
     for (uint64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
         const uint64_t traj = g * tpw + grp;
@@ -439,7 +450,10 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
                 const uint32_t lt = swz(c.tl) ^ gx;
 #pragma unroll
                 for (int e = 0; e < 16; ++e) a[e] = xl[lt ^ swz(slot_l(c.rl, e))];
-                __syncthreads();
+                // the barrier that lets the next exchange overwrite this one:
+                // a general channel's reduction in the phase is one already
+                if (!shared_tile) wave_lds_sync();
+                else if (!(uni(H->flags) & kTPhaseReduces)) __syncthreads();
             }
             const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
             for (uint32_t oi = ob; oi < oe; oi += 2) {
@@ -459,7 +473,8 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
                 const uint32_t lt = swz(traj_thread_bits(H, tt)) ^ gx;
 #pragma unroll
                 for (int e = 0; e < 16; ++e) xl[lt ^ swz(slot_l(c.rl, e))] = a[e];
-                __syncthreads();
+                if (shared_tile) __syncthreads();
+                else wave_lds_sync();
             }
         }
 

@@ -236,8 +236,11 @@ struct alignas(16) TPhase {
     uint32_t op_begin, op_end;
     uint32_t reg_q[4];                      // qubit of register bit b
     uint32_t thr_q[kTrajMaxThreadBits];     // qubit of thread bit i (zero-filled past n_eff - 4)
-    uint32_t pad;
+    uint32_t flags;                         // kTPhaseReduces
 };
+// The phase holds a general channel, whose weights are a reduction over the
+// whole state (a workgroup barrier when a trajectory spans several waves).
+constexpr uint32_t kTPhaseReduces = 1u;
 
 int launch_traj(const TPhase *phases, uint32_t n_phases, const TOp *ops, const double2 *pool, int n,
                 int n_eff, uint32_t n_ch, const double *U, uint64_t T, double *z_out, double *norm_out,

@@ -19,7 +19,8 @@ from oracle.trajectories import apply_matrix
 MAGIC = 0x54445156
 TOP_MAT, TOP_DTHR, TOP_MIX, TOP_KRAUS, TOP_DREG, TOP_DMIX = 1, 2, 3, 4, 5, 6
 
-PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4", 9), ("pad", "<u4")])
+PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4", 9), ("flags", "<u4")])
+PHASE_REDUCES = 1
 OP = np.dtype([("kind", "<u4"), ("mask", "<u4"), ("mat", "<u4"), ("real", "<u4"), ("nk", "<u4"),
                ("chan", "<u4"), ("nd", "<u4"), ("dmask", "<u4"), ("dq", "<u4", 2), ("rmask", "<u4"),
                ("gdiag", "<u4")])
@@ -92,6 +93,9 @@ def run(plan: dict, U: np.ndarray):
         psi = np.zeros(1 << ne, dtype=complex)
         psi[0] = 1
         for ph in plan["phases"]:
+            # the flag that lets the kernel drop an exchange barrier
+            kinds = [int(o["kind"]) for o in plan["ops"][int(ph["ob"]):int(ph["oe"])]]
+            assert bool(int(ph["flags"]) & PHASE_REDUCES) == (TOP_KRAUS in kinds)
             for op in plan["ops"][int(ph["ob"]):int(ph["oe"])]:
                 kind = int(op["kind"])
                 if kind == TOP_DTHR:
