@@ -30,7 +30,25 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 N_QUBITS = 14
 # planner options of the timed configuration (the GPU parity tests use the same)
-PLAN_OPTS = dict(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True, pad_coalesce=True)
+# Hermitian mode (the state is a density matrix and every op is a Kraus map or
+# a unitary): each pass computes the tiles whose row group index is at most
+# the column one, 12-bit tiles of whole qubits with qubit 0 in every tile
+PLAN_OPTS = dict(tile_bits=12, min_contig_bits=1, max_ops_per_pass=0, fuse_blocks=True, pad_coalesce=True,
+                 hermitian=True)
+
+
+def pass_bytes(info, amps):
+    """HBM bytes of all passes of one run: every computed amplitude is read
+    and written once per pass (16 B each way); in Hermitian mode only the
+    fraction f of the amplitudes is computed and stored between passes, and
+    the last pass also writes the other 1 - f (the mirror images)."""
+    f = info["tile_fraction"]
+    return amps * (32.0 * f * info["n_passes"] + (16.0 * (1.0 - f) if info["hermitian"] else 0.0))
+
+
+def executed_flops(info, amps):
+    """FP64 flops the passes execute: 2 per planned FMA per computed amplitude."""
+    return 2.0 * info["fma_per_amp"] * info["tile_fraction"] * amps
 # HBM traffic of the pass kernel measured with rocprofv3 counters (FETCH_SIZE,
 # WRITE_SIZE) on this workload; valid only for the kernel source it was taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_grid14_traffic.json")
@@ -191,12 +209,13 @@ def c3_leg(vqd, torch, steps: int):
     wall = (time.perf_counter() - t0) / steps
     amps = 4 ** n
     t_pass = e0.elapsed_time(e1) / 1e3 / steps       # includes init and read-outs
-    gbs = 32.0 * amps * info["n_passes"] / t_pass / 1e9
-    tf = 2.0 * info["fma_per_amp"] * amps / t_pass / 1e12
+    gbs = pass_bytes(info, amps) / t_pass / 1e9
+    tf = executed_flops(info, amps) / t_pass / 1e12
     out = {"workload": "16-qubit density matrix (complex128, 4^16 amps, 68.7 GB), all-to-all circuit, "
                        "500 XX/Ry/Rz gates with depol2(1e-2) and deph(1e-3)",
            "dm_ops_per_s": round(len(ops) / wall, 1), "gates_per_s": round(n_gates / wall, 1),
            "ms_per_step": round(wall * 1e3, 2), "dm_ops": len(ops), "passes": info["n_passes"],
+           "hermitian_mode": bool(info["hermitian"]),
            "hbm_gbs_of_passes": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
            "fp64_tflops": round(tf, 2), "alu_frac": round(tf / FP64_PEAK_TFLOPS, 4),
            "check": {"purity": float(pur), "z0": float(z[0])}}
@@ -476,10 +495,10 @@ def main():
         del y
 
     amps = 4 ** n
-    bytes_per_pass = 32.0 * amps                 # read + write of every amplitude
+    bytes_per_pass = pass_bytes(info, amps) / info["n_passes"]     # average over the launches
     avg_launch_s = pass_ms / 1e3 / info["n_passes"]
     achieved_gbs = bytes_per_pass / avg_launch_s / 1e9
-    fp64_tflops = 2.0 * info["fma_per_amp"] * amps / (pass_ms / 1e3) / 1e12
+    fp64_tflops = executed_flops(info, amps) / (pass_ms / 1e3) / 1e12
     traffic = measured_traffic()
     hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -508,7 +527,11 @@ def main():
         "gates_per_s": round(n_gates * args.steps / wall, 1),
         "passes_per_step": info["n_passes"],
         "phases_per_step": info["n_phases"],
+        "hermitian_mode": bool(info["hermitian"]),
+        "computed_tile_fraction": round(info["tile_fraction"], 6),
         "planned_fp64_fma_per_amp": round(info["fma_per_amp"], 1),
+        "executed_fp64_fma_per_amp": round(info["fma_per_amp"] * info["tile_fraction"], 1),
+        "bytes_per_launch": round(bytes_per_pass, 1),
         "pass_kernel_ms_per_step": round(pass_ms, 3),
         "pass_kernel_avg_launch_us": round(avg_launch_s * 1e6, 2),
         "roofline": roof,

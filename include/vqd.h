@@ -224,6 +224,15 @@ typedef struct vqd_plan_opts {
     int pad_coalesce;       /* default 1: in passes with little FP64 work, add an op-free
                                first/last phase when the first/last register bits would
                                make HBM access strided */
+    int hermitian;          /* default 0.  1: the caller's state is Hermitian (a density
+                               matrix, Sec. 2); if every op of the program also maps
+                               Hermitian matrices to Hermitian ones (every Kraus map and
+                               unitary does), each pass computes only the tiles whose row
+                               part of the index is at most its column part and writes the
+                               conjugate transpose of each to its mirror image: about half
+                               the work.  The tiles are then whole qubits (tile_bits is
+                               rounded down to even) and always hold qubits 0 and 1.
+                               Otherwise the program is planned as with 0. */
 } vqd_plan_opts;
 void vqd_plan_opts_default(vqd_plan_opts *o);
 
@@ -252,7 +261,10 @@ typedef struct vqd_prog_info {
     int n_passes;           /* HBM passes after planning                   */
     int n_phases;           /* register phases over all passes             */
     int n_kernel_ops;       /* ops applied in-tile after block fusion      */
-    double fma_per_amp;     /* planned FP64 FMAs per amplitude, all passes */
+    double fma_per_amp;     /* planned FP64 FMAs per computed amplitude, all passes */
+    int hermitian;          /* 1 if planned in Hermitian mode              */
+    double tile_fraction;   /* share of the 4^n amplitudes each pass computes (1, or
+                               (N+1)/(2N) in Hermitian mode with N = 2^(n - tile qubits)) */
 } vqd_prog_info;
 int vqd_prog_info_get(const vqd_prog *p, vqd_prog_info *out);
 

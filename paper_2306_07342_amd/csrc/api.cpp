@@ -86,6 +86,7 @@ PlanOpts to_plan_opts(const vqd_plan_opts &o)
     po.max_ops_per_pass = o.max_ops_per_pass;
     po.fuse_blocks = o.fuse_blocks != 0;
     po.pad_coalesce = o.pad_coalesce != 0;
+    po.hermitian = o.hermitian != 0;
     return po;
 }
 
@@ -359,6 +360,7 @@ void vqd_plan_opts_default(vqd_plan_opts *o)
     o->max_ops_per_pass = 0;
     o->fuse_blocks = 1;
     o->pad_coalesce = 1;
+    o->hermitian = 0;
 }
 
 int vqd_prog_create(int n, vqd_prog **out)
@@ -523,6 +525,8 @@ int vqd_prog_info_get(const vqd_prog *p, vqd_prog_info *out)
     out->n_phases = (int)p->plan.phases.size();
     out->n_kernel_ops = (int)p->plan.ops.size();
     out->fma_per_amp = p->plan.fma_per_amp;
+    out->hermitian = p->plan.hermitian ? 1 : 0;
+    out->tile_fraction = p->plan.tile_fraction;
     return VQD_OK;
 }
 

@@ -415,6 +415,7 @@ int vqd_batch_set_opts(vqd_batch *b, int n, const vqd_plan_opts *o)
     if (!b || !o) return fail(VQD_E_ARG, "null argument");
     if (n < 2 || n > VQD_MAX_QUBITS) return fail(VQD_E_SIZE, "n must be in [2, 16]");
     if (o->tile_bits < 4 || o->tile_bits > 12) return fail(VQD_E_ARG, "batched tile_bits must be in [4, 12]");
+    if (o->hermitian) return fail(VQD_E_ARG, "the batched kernel has no Hermitian mode");
     b->opts_by_n[n] = to_plan_opts(*o);
     b->compiled = false;
     return VQD_OK;
@@ -647,6 +648,7 @@ int vqd_batch_plan_opts(const vqd_batch *b, int n, vqd_plan_opts *o)
     o->max_ops_per_pass = p.max_ops_per_pass;
     o->fuse_blocks = p.fuse_blocks;
     o->pad_coalesce = p.pad_coalesce;
+    o->hermitian = 0;
     return VQD_OK;
 }
 
@@ -662,6 +664,7 @@ int vqd_template_export(int n, int count, const int *kinds, const int *targets, 
     vqd_plan_opts o;
     vqd_plan_opts_default(&o);
     if (opts) o = *opts;
+    if (o.hermitian) return fail(VQD_E_ARG, "templates have no Hermitian mode");
     const std::vector<int> kv(kinds, kinds + count), tv(targets, targets + 4 * (size_t)count);
     HostPlan plan;
     if (int rc = plan_template(n, kv, tv, to_plan_opts(o), plan)) return rc;

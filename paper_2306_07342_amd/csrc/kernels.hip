@@ -135,6 +135,42 @@ __device__ __forceinline__ uint32_t group_base(const KPass *__restrict__ P, uint
     return g;
 }
 
+// Hermitian mode: processed tile t is the group pair (i, j), i <= j < N =
+// 2^m, enumerated by folding row i with row N-1-i of the upper triangle
+// (N + 1 pairs per fold); the tile's base holds i in the m row group bits and
+// j in the m column group bits, its mirror's base the other way round.
+struct HermTile {
+    uint32_t gb, gbm;
+    bool mirror;         // i < j: the tile's conjugate transpose is stored too
+};
+
+__device__ __forceinline__ HermTile herm_tile(const KPass *__restrict__ P, uint32_t t, uint32_t ngb)
+{
+    const uint32_t m = ngb >> 1, N = 1u << m;
+    uint32_t i = 0, j = 0;
+    if (N > 1) {
+        const uint32_t a = t / (N + 1), b = t - a * (N + 1);
+        if (b < N - a) {
+            i = a;
+            j = a + b;
+        } else {
+            i = N - 1 - a;
+            j = i + (b - (N - a));
+        }
+    }
+    HermTile h{0u, 0u, i != j};
+    for (uint32_t k = 0; k < m; ++k) {
+        const uint32_t gr = uni(P->group_gpos[k]), gc = uni(P->group_gpos[m + k]);
+        const uint32_t bi = (i >> k) & 1u, bj = (j >> k) & 1u;
+        h.gb |= (bi << gr) | (bj << gc);
+        h.gbm |= (bj << gr) | (bi << gc);
+    }
+    return h;
+}
+
+// Row bit q <-> column bit q + n: the transpose of an index bit position.
+__device__ __forceinline__ uint32_t mirror_pos(uint32_t g, uint32_t n) { return g < n ? g + n : g - n; }
+
 // Local and global index bits contributed by the thread id in phase H.
 // Thread-id bits at or above nthr are zero (tid < 2^nthr) and the unused
 // descriptor entries are zero-filled, so the loops run over the fixed
@@ -173,6 +209,110 @@ __device__ __forceinline__ uint32_t slot_g(const KPhase *__restrict__ H, int e)
     for (int b = 0; b < 4; ++b)
         if (e >> b & 1) g |= 1u << uni(H->reg_gpos[b]);
     return g;
+}
+
+// Hermitian mode: the conjugate of the tile's amplitude in slot e goes to
+// the transposed index (row and column bits exchanged): the mirrored group
+// base, the transposed slot bits and the thread's transposed bits (in
+// `lane`).  The mirror tile is never computed itself.
+__device__ __forceinline__ void store_mirror(double2 *lane, uint32_t gbm, const KPhase *__restrict__ H,
+                                             uint32_t nq, const double2 (&a)[16])
+{
+    uint32_t rg[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rg[b] = 1u << (mirror_pos(uni(H->reg_gpos[b]), nq) & 31u);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        uint32_t u = gbm;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (e >> b & 1) u |= rg[b];
+        lane[u] = make_double2(a[e].x, -a[e].y);
+    }
+}
+
+// The previous pass's group pair of an amplitude: i collects its bits at
+// that pass's row group positions, j at the column positions.  Index bits
+// come from the thread (fixed per pass), the register slot and the tile's
+// group base, which occupy disjoint positions, so i and j are ORs of parts.
+struct HalfIn {
+    uint32_t it, jt;           // thread parts
+    uint32_t ir[4], jr[4];     // part of register bit b (uniform)
+    uint32_t m;                // group pairs of the previous pass
+    const KPass *Pp;
+};
+
+__device__ __forceinline__ void pair_of(const KPass *__restrict__ Pp, uint32_t m, uint32_t x, uint32_t &i,
+                                        uint32_t &j)
+{
+    i = 0;
+    j = 0;
+    for (uint32_t k = 0; k < m; ++k) {
+        i |= ((x >> (uni(Pp->group_gpos[k]) & 31u)) & 1u) << k;
+        j |= ((x >> (uni(Pp->group_gpos[m + k]) & 31u)) & 1u) << k;
+    }
+}
+
+__device__ __forceinline__ HalfIn half_in(const KPass *__restrict__ Pp, const KPhase *__restrict__ H0, uint32_t tg0,
+                                          uint32_t nq)
+{
+    (void)nq;
+    HalfIn h;
+    h.Pp = Pp;
+    h.m = uni(Pp->n_group_bits) >> 1;
+    pair_of(Pp, h.m, tg0, h.it, h.jt);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) pair_of(Pp, h.m, 1u << (uni(H0->reg_gpos[b]) & 31u), h.ir[b], h.jr[b]);
+    return h;
+}
+
+// Hermitian-mode loads of one tile: slot e from its own index, or, where the
+// previous pass did not store it (its group pair there had i > j), the
+// conjugate of the amplitude at the transposed index.  The choice depends on
+// bits of qubits outside every Hermitian tile's forced low qubits, so the
+// lanes of one coalesced segment make the same choice.
+__device__ __forceinline__ void load_herm(double2 (&v)[16], const double2 *__restrict__ lane,
+                                          const double2 *__restrict__ lane_m, const HermTile &ht,
+                                          const KPhase *__restrict__ H0, uint32_t nq, uint32_t herm,
+                                          const HalfIn &hin)
+{
+    uint32_t rg[4], rgm[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t g = uni(H0->reg_gpos[b]) & 31u;
+        rg[b] = 1u << g;
+        rgm[b] = 1u << (mirror_pos(g, nq) & 31u);
+    }
+    if (!(herm & kHermHalfIn)) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            uint32_t u = ht.gb;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (e >> b & 1) u |= rg[b];
+            v[e] = lane[u];
+        }
+        return;
+    }
+    uint32_t ig, jg;
+    pair_of(hin.Pp, hin.m, ht.gb, ig, jg);
+    const uint32_t i0 = ig | hin.it, j0 = jg | hin.jt;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        uint32_t u = ht.gb, um = ht.gbm, i = i0, j = j0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (e >> b & 1) {
+                u |= rg[b];
+                um |= rgm[b];
+                i |= hin.ir[b];
+                j |= hin.jr[b];
+            }
+        const bool tr = i > j;
+        // one load from the selected address (not two loads and a select)
+        const double2 w = *(tr ? lane_m + um : lane + u);
+        v[e] = make_double2(w.x, tr ? -w.y : w.y);
+    }
 }
 
 // One op: y = op(x).
@@ -279,15 +419,37 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     thread_bits(HL, tid, nthr, tlL, tgL);
     const double2 *ld_lane = amps + tg0;
     double2 *st_lane = amps + tgL;
+    // Hermitian mode: thread parts of the mirrored store (the transpose of
+    // tgL) and of the transposed load (of tg0); the previous pass's group
+    // pair (i, j) of a loaded amplitude splits into a per-thread part and
+    // per-register-bit parts (the bits come from disjoint sources)
+    const uint32_t herm = uni(P->herm);
+    const uint32_t nq = (L + ngb) >> 1;
+    uint32_t tgM = 0, tg0M = 0;
+    HalfIn hin{};
+    if (herm) {
+#pragma unroll
+        for (uint32_t i = 0; i < (uint32_t)kMaxThreadBits; ++i) {
+            tgM |= ((tid >> i) & 1u) << (mirror_pos(uni(HL->thr_gpos[i]), nq) & 31u);
+            tg0M |= ((tid >> i) & 1u) << (mirror_pos(uni(H0->thr_gpos[i]), nq) & 31u);
+        }
+        if (herm & kHermHalfIn) hin = half_in(passes + pass_idx - 1, H0, tg0, nq);
+    }
+    double2 *st_mirror = amps + tgM;
+    const double2 *ld_mirror = amps + tg0M;
 
     uint32_t t = blockIdx.x;
     double2 nxt[16];
     if (t < n_tiles) {
-        const uint32_t gb = group_base(P, t, ngb, xcd);
+        if (herm) {
+            load_herm(nxt, ld_lane, ld_mirror, herm_tile(P, t, ngb), H0, nq, herm, hin);
+        } else {
+            const uint32_t gb = group_base(P, t, ngb, xcd);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const uint32_t u = gb | slot_g(H0, e);
-            nxt[e] = (PHANTOM && ((u | tg0) >> kPhantomPos)) ? make_double2(0.0, 0.0) : ld_lane[u];
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t u = gb | slot_g(H0, e);
+                nxt[e] = (PHANTOM && ((u | tg0) >> kPhantomPos)) ? make_double2(0.0, 0.0) : ld_lane[u];
+            }
         }
     }
 
@@ -297,13 +459,18 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     // counter retires in order: waiting for loads issued before fresh stores
     // would wait for those stores too.
     double2 a[16];
-    uint32_t gb_prev = 0;
-    bool have_prev = false;
+    uint32_t gb_prev = 0, gbm_prev = 0;
+    bool have_prev = false, mirror_prev = false;
     for (; t < n_tiles; t += gridDim.x) {
         // vmcnt(0), other counters untouched (gfx9 encoding): the tile's
         // prefetch and the stores issued a whole tile ago; also keeps the
         // compiler from hoisting the stores below above this point
         __builtin_amdgcn_s_waitcnt(0x0F70);
+        // Hermitian mode with half storage: in a tile with i = j the waves
+        // load each other's amplitudes (through the transpose), so no wave
+        // may store the previous tile (below) before every wave has loaded
+        // it; without an LDS exchange nothing else orders the waves
+        if (herm & kHermHalfIn) __syncthreads();
         double2 cur[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) cur[e] = nxt[e];
@@ -313,17 +480,24 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
                 const uint32_t u = gb_prev | slot_g(HL, e);
                 if (!(PHANTOM && ((u | tgL) >> kPhantomPos))) st_lane[u] = a[e];
             }
+            if (mirror_prev) store_mirror(st_mirror, gbm_prev, HL, nq, a);
         }
-        const uint32_t gb = group_base(P, t, ngb, xcd);
+        HermTile ht{0u, 0u, false};
+        if (herm) ht = herm_tile(P, t, ngb);
+        const uint32_t gb = herm ? ht.gb : group_base(P, t, ngb, xcd);
         {
             // prefetch the next tile (the last iteration re-reads its own
             // tile, which keeps the loads unconditional)
             const uint32_t t2 = (t + gridDim.x < n_tiles) ? t + gridDim.x : t;
-            const uint32_t gb2 = group_base(P, t2, ngb, xcd);
+            if (herm) {
+                load_herm(nxt, ld_lane, ld_mirror, herm_tile(P, t2, ngb), H0, nq, herm, hin);
+            } else {
+                const uint32_t gb2 = group_base(P, t2, ngb, xcd);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t u = gb2 | slot_g(H0, e);
-                nxt[e] = (PHANTOM && ((u | tg0) >> kPhantomPos)) ? make_double2(0.0, 0.0) : ld_lane[u];
+                for (int e = 0; e < 16; ++e) {
+                    const uint32_t u = gb2 | slot_g(H0, e);
+                    nxt[e] = (PHANTOM && ((u | tg0) >> kPhantomPos)) ? make_double2(0.0, 0.0) : ld_lane[u];
+                }
             }
         }
 #pragma unroll
@@ -361,6 +535,8 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
         // stores but no loads makes the compiler wait for every outstanding
         // load (the prefetch) before entering it
         gb_prev = gb;
+        gbm_prev = ht.gbm;
+        mirror_prev = ht.mirror && (herm & kHermMirror);
         have_prev = true;
     }
     if (have_prev) {
@@ -369,6 +545,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
             const uint32_t u = gb_prev | slot_g(HL, e);
             if (!(PHANTOM && ((u | tgL) >> kPhantomPos))) st_lane[u] = a[e];
         }
+        if (mirror_prev) store_mirror(st_mirror, gbm_prev, HL, nq, a);
     }
 }
 

@@ -56,6 +56,30 @@ std::vector<int> tile_bits_for(uint32_t Q, int n, int contig)
     return b;
 }
 
+// Does the op map every Hermitian matrix to a Hermitian one?  Under the
+// transpose of the row and column bits (local index a -> mu(a)) such an op
+// satisfies S[mu(a)][mu(b)] = conj(S[a][b]); a unitary applied as U on rows
+// and conj(U) on columns always does.
+bool preserves_hermiticity(const LOp &op)
+{
+    if (op.wide_unitary) return true;
+    const int k = op.k, D = 1 << (2 * k), lo = (1 << k) - 1;
+    auto mu = [&](int a) { return (a >> k) | ((a & lo) << k); };
+    double scale = 0.0;
+    const std::vector<cd> &v = op.diag ? op.D : op.S;
+    for (const cd &x : v) scale = std::max(scale, std::abs(x));
+    const double tol = 1e-13 * std::max(1.0, scale);
+    if (op.diag) {
+        for (int a = 0; a < D; ++a)
+            if (std::abs(op.D[mu(a)] - std::conj(op.D[a])) > tol) return false;
+        return true;
+    }
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b)
+            if (std::abs(op.S[size_t(mu(a)) * D + mu(b)] - std::conj(op.S[size_t(a) * D + b])) > tol) return false;
+    return true;
+}
+
 struct SimResult {
     std::vector<int> taken;
     std::vector<uint32_t> cands;   // qubit sets of blocked non-diagonal ops
@@ -336,8 +360,20 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         return fail(VQD_E_ARG, "tile_bits must be in [4, 13]");
     // tile size actually used: 2n bits at most, but never fewer than the 4
     // register bits (tiny registers get phantom bits)
-    const int L = std::max(4, std::min(opt.tile_bits, n2));
+    // Hermitian mode: tiles are whole qubits (row and column bit), so the
+    // tile size is even; qubits 0..hc-1 are in every tile so that the loads,
+    // the stores and the mirrored stores all cover 2^hc contiguous amplitudes
+    bool herm = opt.hermitian && n >= 2;
+    for (size_t i = 0; herm && i < ops.size(); ++i) herm = preserves_hermiticity(ops[i]);
+    out.hermitian = herm;
+    const int L = herm ? std::min(opt.tile_bits & ~1, n2) : std::max(4, std::min(opt.tile_bits, n2));
     const int contig = std::max(0, std::min(opt.min_contig_bits, std::min(L, n2)));
+    // (fewer when the program's widest non-diagonal op would not fit beside them)
+    int kmax = 1;
+    for (const LOp &op : ops)
+        if (!op.diag) kmax = std::max(kmax, op.k);
+    const int hc = herm ? std::max(0, std::min(std::min(std::min(contig, 3), n), L / 2 - kmax)) : 0;
+    const uint32_t forced = (1u << hc) - 1u;        // qubits in every Hermitian tile
     const int max_take = opt.max_ops_per_pass;
     // LDS left for the runtime-diagonal tables beside the staged tile
     const size_t rt_budget = opt.rt_budget > 0 ? (size_t)opt.rt_budget
@@ -371,7 +407,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         const int take_cap = retry_take > 0 ? retry_take : max_take;
 
         // ---- choose the pass qubit set
-        uint32_t Q = 0;
+        uint32_t Q = herm ? forced : 0u;
         while (true) {
             simulate(ops, qm, applied, first, Q, n, take_cap, sim, true);
             const size_t base = sim.taken.size();
@@ -382,8 +418,9 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 const uint32_t Q2 = Q | c;
                 // the contiguous low bits are a preference: the first op of a
                 // pass may use them when it cannot fit otherwise
-                const bool fits = (int)tile_bits_for(Q2, n, contig).size() <= L ||
-                                  (Q == 0 && (int)tile_bits_for(Q2, n, 0).size() <= L);
+                const bool fits = herm ? (int)tile_bits_for(Q2 | forced, n, 0).size() <= L
+                                       : ((int)tile_bits_for(Q2, n, contig).size() <= L ||
+                                          (Q == 0 && (int)tile_bits_for(Q2, n, 0).size() <= L));
                 if (!fits) continue;
                 simulate(ops, qm, applied, first, Q2, n, take_cap, sim2, false);
                 if (sim2.taken.size() > bestc) {
@@ -394,6 +431,8 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             if (bestQ == Q) break;
             Q = bestQ;
         }
+        if (herm)      // the tile's filler qubits are the lowest others: ops on them may join too
+            for (int q = 0; popc(Q) < L / 2 && q < n; ++q) Q |= 1u << q;
         simulate(ops, qm, applied, first, Q, n, take_cap, sim, false);
         if (sim.taken.empty()) return fail(VQD_E_STATE, "planner made no progress");
         for (int i : sim.taken) applied[i] = 1;
@@ -401,26 +440,47 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                      recipes_before = out.recipes.size();
 
         // ---- tile bits
-        std::vector<int> tb = tile_bits_for(Q, n, contig);
-        if ((int)tb.size() > L) tb = tile_bits_for(Q, n, 0);
-        for (int b = 0; (int)tb.size() < std::min(L, n2) && b < n2; ++b)
-            if (std::find(tb.begin(), tb.end(), b) == tb.end()) tb.push_back(b);
-        std::sort(tb.begin(), tb.end());
-        for (uint32_t ph = kPhantomPos; (int)tb.size() < L; ++ph) tb.push_back((int)ph);  // phantom bits (tiny n)
+        std::vector<int> tb;
+        uint32_t tq = 0;                              // Hermitian mode: the tile's qubits
+        if (herm) {
+            tq = Q | forced;
+            for (int q = 0; popc(tq) < L / 2 && q < n; ++q) tq |= 1u << q;
+            tb = tile_bits_for(tq, n, 0);
+        } else {
+            tb = tile_bits_for(Q, n, contig);
+            if ((int)tb.size() > L) tb = tile_bits_for(Q, n, 0);
+            for (int b = 0; (int)tb.size() < std::min(L, n2) && b < n2; ++b)
+                if (std::find(tb.begin(), tb.end(), b) == tb.end()) tb.push_back(b);
+            std::sort(tb.begin(), tb.end());
+            for (uint32_t ph = kPhantomPos; (int)tb.size() < L; ++ph) tb.push_back((int)ph);  // phantom bits (tiny n)
+        }
         KPass kp{};
         kp.L = (uint32_t)L;
         kp.phantom = (n2 < L) ? 1u : 0u;
         int ng = 0;
-        for (int b = 0; b < n2; ++b)
-            if (std::find(tb.begin(), tb.end(), b) == tb.end()) kp.group_gpos[ng++] = (uint32_t)b;
+        if (herm) {
+            // the m group qubits' row bits, then their column bits in the same order
+            std::vector<int> gq;
+            for (int q = 0; q < n; ++q)
+                if (!(tq >> q & 1)) gq.push_back(q);
+            for (int q : gq) kp.group_gpos[ng++] = (uint32_t)q;
+            for (int q : gq) kp.group_gpos[ng++] = (uint32_t)(q + n);
+            const uint64_t N = 1ull << gq.size();
+            kp.n_tiles = N * (N + 1) / 2;
+            kp.herm = kHermPass;
+            out.tile_fraction = double(N + 1) / double(2 * N);
+        } else {
+            for (int b = 0; b < n2; ++b)
+                if (std::find(tb.begin(), tb.end(), b) == tb.end()) kp.group_gpos[ng++] = (uint32_t)b;
+            kp.n_tiles = 1ull << ng;
+        }
         kp.n_group_bits = (uint32_t)ng;
-        kp.n_tiles = 1ull << ng;
         // tiles lacking the lowest vector bits share cache lines with their
         // neighbours in the low group bits; keep those on one XCD
         bool low_in_tile = true;
         for (int b = 0; b < std::min(3, n2); ++b)
             if (std::find(tb.begin(), tb.end(), b) == tb.end()) low_in_tile = false;
-        kp.xcd_swizzle = (!low_in_tile && kp.n_tiles >= 64 && kp.n_tiles % 64 == 0) ? 1u : 0u;
+        kp.xcd_swizzle = (!herm && !low_in_tile && kp.n_tiles >= 64 && kp.n_tiles % 64 == 0) ? 1u : 0u;
         kp.phase_begin = (uint32_t)out.phases.size();
         const double fma_before = out.fma_per_amp;
         std::vector<cd> rt_tables;      // runtime-diagonal tables of this pass (LDS-staged)
@@ -787,7 +847,51 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         // last one's the stores.  If a register bit is one of the lowest
         // (contiguous) vector bits, lanes would stride; an op-free phase on
         // high tile bits is added instead (an LDS exchange is cheaper).
-        {
+        if (herm && L - 4 >= 2 * hc) {
+            // Hermitian mode: the loads (first phase), the stores and the
+            // mirrored stores (last phase) are coalesced when the local bits of
+            // global bits 0..hc-1 and n..n+hc-1 are the lowest thread bits, in
+            // that order; an op-free phase is added where a register holds one
+            std::vector<int> io_local, io_gpos;
+            for (int q = 0; q < hc; ++q) io_gpos.push_back(q);
+            for (int q = 0; q < hc; ++q) io_gpos.push_back(q + n);
+            for (int g : io_gpos) io_local.push_back(local_of(g));
+            auto io_in_regs = [&](const KPhase &H) {
+                for (int b = 0; b < 4; ++b)
+                    if (std::find(io_local.begin(), io_local.end(), (int)H.reg_local[b]) != io_local.end())
+                        return true;
+                return false;
+            };
+            const size_t first_ph = kp.phase_begin;
+            const bool pad_front = io_in_regs(out.phases[first_ph]);
+            const bool pad_back = io_in_regs(out.phases.back());
+            if (pad_front || pad_back) {
+                int reg[4];
+                fill_regs(reg, {}, io_gpos);
+                const std::vector<Block> none;
+                if (pad_back) emit_phase(reg, none, {});
+                if (pad_front) {
+                    const uint32_t ob = out.phases[first_ph].op_begin;
+                    emit_phase(reg, none, {});
+                    KPhase dummy = out.phases.back();
+                    dummy.op_begin = dummy.op_end = ob;
+                    out.phases.pop_back();
+                    out.phases.insert(out.phases.begin() + first_ph, dummy);
+                }
+            }
+            auto io_first = [&](KPhase &H) {
+                std::vector<uint32_t> order(io_local.begin(), io_local.end());
+                for (int t = 0; t < L - 4; ++t)
+                    if (std::find(io_local.begin(), io_local.end(), (int)H.thr_local[t]) == io_local.end())
+                        order.push_back(H.thr_local[t]);
+                for (int t = 0; t < L - 4; ++t) {
+                    H.thr_local[t] = order[t];
+                    H.thr_gpos[t] = (uint32_t)tb[order[t]];
+                }
+            };
+            io_first(out.phases[first_ph]);
+            io_first(out.phases.back());
+        } else if (!herm) {
             const int low = std::min(3, std::min(contig, n2));
             auto strided = [&](const KPhase &H) {
                 for (int b = 0; b < 4; ++b)
@@ -836,6 +940,14 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 if (out.recipes[oi].rt) out.recipes[oi].mat_off += kp.rt_mat;
         out.mats.insert(out.mats.end(), rt_tables.begin(), rt_tables.end());
         out.passes.push_back(kp);
+    }
+    if (herm) {
+        // between the passes of a program only the computed half is stored;
+        // the last pass restores the whole matrix
+        for (size_t i = 0; i < out.passes.size(); ++i) {
+            if (i > 0) out.passes[i].herm |= kHermHalfIn;
+            if (i + 1 == out.passes.size()) out.passes[i].herm |= kHermMirror;
+        }
     }
     return VQD_OK;
 }

@@ -96,7 +96,16 @@ struct alignas(16) KPass {
     uint32_t rt_count;        // their total size; staged in LDS after the tile
     uint64_t n_tiles;
     uint32_t group_gpos[32];
+    uint32_t herm;            // Hermitian mode (kHerm* flags): group_gpos holds m row bits,
+                              // then their m column bits; the n_tiles = N(N+1)/2 tiles
+                              // (N = 2^m) are the group pairs i <= j
 };
+constexpr uint32_t kHermPass = 1u;     // computes the tiles i <= j only
+constexpr uint32_t kHermMirror = 2u;   // also stores each i < j tile's conjugate transpose
+                                       // to its mirror (the program's last pass)
+constexpr uint32_t kHermHalfIn = 4u;   // the previous pass stored only its tiles i <= j:
+                                       // an amplitude whose group pair in that pass had
+                                       // i > j is loaded from its transpose, conjugated
 
 // Device-side image of a planned program.
 struct DevProgram {
@@ -144,6 +153,8 @@ struct HostPlan {
     std::vector<cd> mats;
     std::vector<Recipe> recipes;    // one per kernel op when recorded
     double fma_per_amp = 0;
+    bool hermitian = false;         // planned in Hermitian mode
+    double tile_fraction = 1.0;     // share of the amplitudes the passes compute
 };
 
 // ------------------------------------------------------------- logical ops --
@@ -173,6 +184,8 @@ struct PlanOpts {
     bool merge_rt = true;           // tabulate runs of runtime diagonals together
     int rt_budget = 0;              // runtime-diagonal table entries a pass may stage in
                                     // LDS (0: what 160 KiB leaves beside the tile)
+    bool hermitian = false;         // compute half the tiles of a Hermitian state when every
+                                    // op preserves Hermiticity (HostPlan::hermitian says if)
 };
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out);
 // Recompute a recorded plan's coefficients for new logical ops of the same

@@ -42,7 +42,7 @@ class VQDError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("tile_bits", ctypes.c_int), ("min_contig_bits", ctypes.c_int),
                 ("max_ops_per_pass", ctypes.c_int), ("fuse_blocks", ctypes.c_int),
-                ("pad_coalesce", ctypes.c_int)]
+                ("pad_coalesce", ctypes.c_int), ("hermitian", ctypes.c_int)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -54,7 +54,8 @@ class BatchInfo(ctypes.Structure):
 class ProgInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("n_ops", ctypes.c_int), ("n_passes", ctypes.c_int),
                 ("n_phases", ctypes.c_int), ("n_kernel_ops", ctypes.c_int),
-                ("fma_per_amp", ctypes.c_double)]
+                ("fma_per_amp", ctypes.c_double), ("hermitian", ctypes.c_int),
+                ("tile_fraction", ctypes.c_double)]
 
 
 class TrajInfo(ctypes.Structure):
@@ -415,9 +416,9 @@ class DensityMatrix:
 
 
 def plan_opts(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True,
-              pad_coalesce=True) -> PlanOpts:
+              pad_coalesce=True, hermitian=False) -> PlanOpts:
     return PlanOpts(tile_bits, min_contig_bits, max_ops_per_pass, 1 if fuse_blocks else 0,
-                    1 if pad_coalesce else 0)
+                    1 if pad_coalesce else 0, 1 if hermitian else 0)
 
 
 def _structure(structure):

@@ -14,14 +14,15 @@ from __future__ import annotations
 import numpy as np
 
 MAGIC = 0x56514450
+HERM_PASS, HERM_MIRROR, HERM_HALF_IN = 1, 2, 4
 
 
 def _dtypes(sz_pass, sz_phase, sz_op):
     dpass = np.dtype({"names": ["L", "ngb", "pb", "pe", "phantom", "xcd", "rt_mat", "rt_count",
-                                "n_tiles", "group_gpos"],
+                                "n_tiles", "group_gpos", "herm"],
                       "formats": ["<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u8",
-                                  ("<u4", 32)],
-                      "offsets": [0, 4, 8, 12, 16, 20, 24, 28, 32, 40], "itemsize": sz_pass})
+                                  ("<u4", 32), "<u4"],
+                      "offsets": [0, 4, 8, 12, 16, 20, 24, 28, 32, 40, 168], "itemsize": sz_pass})
     dphase = np.dtype({"names": ["ob", "oe", "reg_local", "reg_gpos", "thr_local", "thr_gpos"],
                        "formats": ["<u4", "<u4", ("<u4", 4), ("<u4", 4), ("<u4", 9), ("<u4", 9)],
                        "offsets": [0, 4, 8, 24, 40, 76], "itemsize": sz_phase})
@@ -77,14 +78,34 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
     amps = amps.copy()
     n2 = 2 * plan["n"]
     mats = plan["mats"]
+    n = plan["n"]
+    prev_pass = None
     for P in plan["passes"]:
         L = int(P["L"])
         nthr_bits = L - 4
         T = int(P["n_tiles"])
-        gb = np.zeros(T, dtype=np.uint64)
-        tiles = np.arange(T, dtype=np.uint64)
-        for i in range(int(P["ngb"])):
-            gb |= ((tiles >> np.uint64(i)) & np.uint64(1)) << np.uint64(P["group_gpos"][i])
+        ngb = int(P["ngb"])
+        herm = bool(P["herm"])
+        if herm:
+            # Hermitian mode: the group pairs i <= j, i in the row group bits and
+            # j in the column group bits; tiles with i < j also write their mirror
+            m = ngb // 2
+            N = 1 << m
+            pairs = [(i, j) for i in range(N) for j in range(i, N)]
+            assert T == len(pairs)
+            gb = np.zeros(T, dtype=np.uint64)
+            for t, (i, j) in enumerate(pairs):
+                for k in range(m):
+                    gb[t] |= np.uint64(((i >> k) & 1) << int(P["group_gpos"][k]))
+                    gb[t] |= np.uint64(((j >> k) & 1) << int(P["group_gpos"][m + k]))
+            mirror = np.array([i != j for i, j in pairs])
+            flags = int(P["herm"])
+            assert flags & HERM_PASS
+        else:
+            gb = np.zeros(T, dtype=np.uint64)
+            tiles = np.arange(T, dtype=np.uint64)
+            for i in range(ngb):
+                gb |= ((tiles >> np.uint64(i)) & np.uint64(1)) << np.uint64(P["group_gpos"][i])
         for ph in range(int(P["pb"]), int(P["pe"])):
             H = plan["phases"][ph]
             thr = np.arange(1 << nthr_bits, dtype=np.uint64)
@@ -102,6 +123,20 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
             valid = (gidx >> np.uint64(n2)) == 0
             gi = np.where(valid, gidx, 0).astype(np.int64)
             a = np.where(valid, amps[gi], 0)
+            if herm and ph == int(P["pb"]) and flags & HERM_HALF_IN:
+                # the previous pass stored only its group pairs i <= j: the
+                # others come from the transposed index, conjugated
+                Pp = prev_pass
+                mp = int(Pp["ngb"]) // 2
+                gu = gidx.astype(np.uint64)
+                ip = np.zeros(gu.shape, dtype=np.int64)
+                jp = np.zeros(gu.shape, dtype=np.int64)
+                for k in range(mp):
+                    ip |= ((gu >> np.uint64(Pp["group_gpos"][k])) & np.uint64(1)).astype(np.int64) << k
+                    jp |= ((gu >> np.uint64(Pp["group_gpos"][mp + k])) & np.uint64(1)).astype(np.int64) << k
+                D = np.uint64((1 << n) - 1)
+                mu = ((gu >> np.uint64(n)) | ((gu & D) << np.uint64(n))).astype(np.int64)
+                a = np.where(ip > jp, np.conj(amps[mu]), a)
             for oi in range(int(H["ob"]), int(H["oe"])):
                 op = plan["ops"][oi]
                 kind, mask, real = int(op["kind"]), int(op["opmask"]), bool(op["real"])
@@ -148,4 +183,11 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
                 else:
                     raise AssertionError("unknown kernel op kind %d" % kind)
             amps[gi[valid]] = a[valid]
+        prev_pass = P
+        if herm and flags & HERM_MIRROR:
+            # the conjugate transpose of each tile with i < j into its mirror
+            idx = gi[mirror].reshape(-1).astype(np.uint64)
+            D = np.uint64((1 << n) - 1)
+            mu = (idx >> np.uint64(n)) | ((idx & D) << np.uint64(n))
+            amps[mu.astype(np.int64)] = np.conj(amps[idx.astype(np.int64)])
     return amps

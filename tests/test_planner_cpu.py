@@ -133,3 +133,86 @@ def test_many_runtime_diagonals_fit_lds(vqd_host):
         L = int(p["L"])
         assert (16 << L) + 16 * int(p["rt_count"]) + 1024 <= 160 * 1024
     assert len(plan["passes"]) > 1
+
+
+def hermitian_state(n, seed):
+    R = start_state(n, seed)
+    return (R + R.conj().T) / 2
+
+
+def run_herm(vqd, n, ops, seed=0, **opts):
+    R0 = hermitian_state(n, seed)
+    dm = OracleDM(n)
+    dm.set(R0)
+    emulate(n, ops, dm)
+    ref = dm.to_vectorised()
+    prog = vqd.Program(n, ops)
+    prog.plan(vqd.plan_opts(hermitian=True, **opts))
+    plan = emu.parse(prog.export())
+    got = emu.run(plan, np.ascontiguousarray(R0.T).reshape(-1))
+    return got, ref, prog.info(), plan
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6, 7, 9])
+def test_hermitian_mode_circuits(vqd_host, n):
+    """Hermitian mode: half the tiles computed, their conjugate transposes
+    written to the mirrored tiles; the result equals the oracle's."""
+    ops = c1_line_circuit(n=n, n_gates=60) if n < 7 else c2_grid_circuit(rows=1, cols=n, n_gates=80)
+    got, ref, info, plan = run_herm(vqd_host, n, ops, seed=n)
+    assert info["hermitian"] == 1
+    assert_close(got, ref)
+    last = len(plan["passes"]) - 1
+    for k, P in enumerate(plan["passes"]):
+        flags = int(P["herm"])
+        assert flags & emu.HERM_PASS and int(P["L"]) % 2 == 0
+        # only the computed half is stored between passes; the last restores all
+        assert bool(flags & emu.HERM_HALF_IN) == (k > 0)
+        assert bool(flags & emu.HERM_MIRROR) == (k == last)
+
+
+@pytest.mark.parametrize("tile_bits", [8, 10, 12, 13])
+def test_hermitian_mode_tile_sizes(vqd_host, tile_bits):
+    n = 8
+    ops = c3_all_to_all_circuit(n=n, n_gates=60)
+    got, ref, info, plan = run_herm(vqd_host, n, ops, seed=1, tile_bits=tile_bits)
+    assert_close(got, ref)
+    L = min(tile_bits & ~1, 2 * n)
+    m = n - L // 2
+    assert abs(info["tile_fraction"] - (2 ** m + 1) / 2 ** (m + 1)) <= 1e-15
+    # qubits 0..hc-1 are in every tile (hc = 3 unless the widest gate, here
+    # two qubits, would not fit beside them); the first and last phases put
+    # their row and column bits on the lowest thread bits (coalesced loads,
+    # stores and mirrored stores)
+    hc = min(3, L // 2 - 2)
+    io = list(range(hc)) + [n + q for q in range(hc)]
+    for P in plan["passes"]:
+        tiles = set(range(2 * n)) - set(int(g) for g in P["group_gpos"][:int(P["ngb"])])
+        assert set(io) <= tiles
+        for ph in (int(P["pb"]), int(P["pe"]) - 1):
+            assert [int(g) for g in plan["phases"][ph]["thr_gpos"][:2 * hc]] == io
+
+
+def test_hermitian_mode_named_channels_and_wide_gates(vqd_host):
+    n = 6
+    ops = random_matrix_ops(n, 8, seed=5, max_k=min(4, n), kraus=False)
+    ops += [("depol1", (0,), (0.2,)), ("depol2", (1, 3), (0.3,)), ("amp", (2,), (0.4,)),
+            ("gamp", (4,), (0.6, 0.3)), ("zz", (5, 0), (0.05,)), ("cz", (1, 4), ()), ("deph2", (2, 5), (0.1,))]
+    ops += random_matrix_ops(n, 20, seed=6, max_k=2)
+    got, ref, info, _ = run_herm(vqd_host, n, ops, seed=2)
+    assert info["hermitian"] == 1
+    assert_close(got, ref)
+
+
+def test_hermitian_mode_refused_for_a_map_that_breaks_hermiticity(vqd_host):
+    """An op with S[mu(a)][mu(b)] != conj(S[a][b]) (here rho -> A rho B^dagger
+    with A != B) makes the planner fall back to computing every tile."""
+    n = 4
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    B = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    S = np.kron(np.conj(B), A)
+    ops = c1_line_circuit(n=n, n_gates=20) + [("superop", (1,), (S,))]
+    prog = vqd_host.Program(n, ops)
+    prog.plan(vqd_host.plan_opts(hermitian=True))
+    assert prog.info()["hermitian"] == 0
+    assert prog.info()["tile_fraction"] == 1.0
