@@ -77,7 +77,8 @@ def test_diagonal_tiles_of_passes_without_exchange(gpu_lib):
     without an LDS exchange only the kernel's barrier keeps a wave from
     storing the tile before the others have loaded it.  The 13-qubit grid
     circuit with three forced qubits has such passes; its result must equal
-    the plan without Hermitian mode and be exactly Hermitian."""
+    the plan without Hermitian mode and be Hermitian to rounding (a stale
+    load leaves errors of the size of one pass's change, about 1e-10)."""
     n = 13
     D = 1 << n
     ops = c2_grid_circuit(rows=1, cols=n, n_gates=2000)
@@ -91,4 +92,4 @@ def test_diagonal_tiles_of_passes_without_exchange(gpu_lib):
     got = dm.to_numpy()
     assert np.abs(got - want).max() <= 1e-12
     G = got.reshape(D, D)
-    assert np.abs(G - G.conj().T).max() == 0.0
+    assert np.abs(G - G.conj().T).max() <= 1e-15
