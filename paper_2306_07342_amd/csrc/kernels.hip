@@ -135,33 +135,45 @@ __device__ __forceinline__ uint32_t group_base(const KPass *__restrict__ P, uint
     return g;
 }
 
-// Hermitian mode: processed tile t is the group pair (i, j), i <= j < N =
-// 2^m, enumerated by folding row i with row N-1-i of the upper triangle
-// (N + 1 pairs per fold); the tile's base holds i in the m row group bits and
-// j in the m column group bits, its mirror's base the other way round.
+// Hermitian mode: launched tile t is the group pair (i, j), i <= j < N = 2^m.
+// The c lowest group bits split 128-byte lines between tiles, so the pairs
+// are launched in blocks: i = I 2^c + a, j = J 2^c + b (a, b < 2^c), the
+// blocks I <= J < 2^(m-c) enumerated by folding row I with row NB-1-I of
+// the upper triangle (NB + 1 blocks per fold), a block's 4^c members 8
+// launch indices apart (one XCD, one round of the persistent grid).  The
+// tile's base holds i in the m row group bits and j in the m column group
+// bits, its mirror's base the other way round.  Padding blocks and members
+// with a > b of a block with I = J are not stored.
 struct HermTile {
     uint32_t gb, gbm;
     bool mirror;         // i < j: the tile's conjugate transpose is stored too
+    bool valid;          // a tile of the upper triangle (stored)
 };
 
-__device__ __forceinline__ HermTile herm_tile(const KPass *__restrict__ P, uint32_t t, uint32_t ngb)
+__device__ __forceinline__ HermTile herm_tile(const KPass *__restrict__ P, uint32_t t, uint32_t ngb,
+                                              uint32_t herm)
 {
-    const uint32_t m = ngb >> 1, N = 1u << m;
-    uint32_t i = 0, j = 0;
-    if (N > 1) {
-        const uint32_t a = t / (N + 1), b = t - a * (N + 1);
-        if (b < N - a) {
-            i = a;
-            j = a + b;
+    const uint32_t m = ngb >> 1, c = (herm >> kHermLineShift) & 3u;
+    const uint32_t NB = 1u << (m - c), NBB = NB * (NB + 1) / 2;
+    const uint32_t lo = t & 7u, k = (t >> 3) & ((1u << (2 * c)) - 1u), hi = t >> (3 + 2 * c);
+    const uint32_t beta = hi * 8 + lo;
+    uint32_t I = 0, J = 0;
+    if (NB > 1) {
+        const uint32_t a = beta / (NB + 1), b = beta - a * (NB + 1);
+        if (b < NB - a) {
+            I = a;
+            J = a + b;
         } else {
-            i = N - 1 - a;
-            j = i + (b - (N - a));
+            I = NB - 1 - a;
+            J = I + (b - (NB - a));
         }
     }
-    HermTile h{0u, 0u, i != j};
-    for (uint32_t k = 0; k < m; ++k) {
-        const uint32_t gr = uni(P->group_gpos[k]), gc = uni(P->group_gpos[m + k]);
-        const uint32_t bi = (i >> k) & 1u, bj = (j >> k) & 1u;
+    const uint32_t ma = k & ((1u << c) - 1u), mb = k >> c;
+    const uint32_t i = (I << c) | ma, j = (J << c) | mb;
+    HermTile h{0u, 0u, i != j, beta < NBB && (I < J || ma <= mb)};
+    for (uint32_t q = 0; q < m; ++q) {
+        const uint32_t gr = uni(P->group_gpos[q]), gc = uni(P->group_gpos[m + q]);
+        const uint32_t bi = (i >> q) & 1u, bj = (j >> q) & 1u;
         h.gb |= (bi << gr) | (bj << gc);
         h.gbm |= (bj << gr) | (bi << gc);
     }
@@ -442,7 +454,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     double2 nxt[16];
     if (t < n_tiles) {
         if (herm) {
-            load_herm(nxt, ld_lane, ld_mirror, herm_tile(P, t, ngb), H0, nq, herm, hin);
+            load_herm(nxt, ld_lane, ld_mirror, herm_tile(P, t, ngb, herm), H0, nq, herm, hin);
         } else {
             const uint32_t gb = group_base(P, t, ngb, xcd);
 #pragma unroll
@@ -460,7 +472,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     // would wait for those stores too.
     double2 a[16];
     uint32_t gb_prev = 0, gbm_prev = 0;
-    bool have_prev = false, mirror_prev = false;
+    bool have_prev = false, mirror_prev = false, valid_prev = true;
     for (; t < n_tiles; t += gridDim.x) {
         // vmcnt(0), other counters untouched (gfx9 encoding): the tile's
         // prefetch and the stores issued a whole tile ago; also keeps the
@@ -474,7 +486,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
         double2 cur[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) cur[e] = nxt[e];
-        if (have_prev) {
+        if (have_prev && valid_prev) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const uint32_t u = gb_prev | slot_g(HL, e);
@@ -482,15 +494,15 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
             }
             if (mirror_prev) store_mirror(st_mirror, gbm_prev, HL, nq, a);
         }
-        HermTile ht{0u, 0u, false};
-        if (herm) ht = herm_tile(P, t, ngb);
+        HermTile ht{0u, 0u, false, true};
+        if (herm) ht = herm_tile(P, t, ngb, herm);
         const uint32_t gb = herm ? ht.gb : group_base(P, t, ngb, xcd);
         {
             // prefetch the next tile (the last iteration re-reads its own
             // tile, which keeps the loads unconditional)
             const uint32_t t2 = (t + gridDim.x < n_tiles) ? t + gridDim.x : t;
             if (herm) {
-                load_herm(nxt, ld_lane, ld_mirror, herm_tile(P, t2, ngb), H0, nq, herm, hin);
+                load_herm(nxt, ld_lane, ld_mirror, herm_tile(P, t2, ngb, herm), H0, nq, herm, hin);
             } else {
                 const uint32_t gb2 = group_base(P, t2, ngb, xcd);
 #pragma unroll
@@ -536,10 +548,11 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
         // load (the prefetch) before entering it
         gb_prev = gb;
         gbm_prev = ht.gbm;
-        mirror_prev = ht.mirror && (herm & kHermMirror);
+        mirror_prev = ht.mirror && ht.valid && (herm & kHermMirror);
+        valid_prev = ht.valid;
         have_prev = true;
     }
-    if (have_prev) {
+    if (have_prev && valid_prev) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const uint32_t u = gb_prev | slot_g(HL, e);

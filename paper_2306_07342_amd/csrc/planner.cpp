@@ -465,9 +465,13 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 if (!(tq >> q & 1)) gq.push_back(q);
             for (int q : gq) kp.group_gpos[ng++] = (uint32_t)q;
             for (int q : gq) kp.group_gpos[ng++] = (uint32_t)(q + n);
-            const uint64_t N = 1ull << gq.size();
-            kp.n_tiles = N * (N + 1) / 2;
-            kp.herm = kHermPass;
+            // group qubits below 3 split 128-byte lines: the lowest group
+            // bits, launched in blocks (ascending order puts them first)
+            uint32_t c = 0;
+            while (c < gq.size() && gq[c] < 3) ++c;
+            const uint64_t N = 1ull << gq.size(), NB = N >> c, NBB = NB * (NB + 1) / 2;
+            kp.n_tiles = (NBB + 7) / 8 * 8 << (2 * c);
+            kp.herm = kHermPass | (c << kHermLineShift);
             out.tile_fraction = double(N + 1) / double(2 * N);
         } else {
             for (int b = 0; b < n2; ++b)

@@ -106,6 +106,12 @@ constexpr uint32_t kHermMirror = 2u;   // also stores each i < j tile's conjugat
 constexpr uint32_t kHermHalfIn = 4u;   // the previous pass stored only its tiles i <= j:
                                        // an amplitude whose group pair in that pass had
                                        // i > j is loaded from its transpose, conjugated
+// Bits 4-5 of KPass::herm: c, the number of group qubits below qubit 3 (they
+// split 128-byte lines between tiles).  Tiles are launched in blocks of 4^c
+// (i = I 2^c + a, j = J 2^c + b over a, b < 2^c, blocks I <= J), a block's
+// members 8 launch indices apart so that they run on one XCD together; in a
+// block with I = J the members with a > b are computed but not stored.
+constexpr uint32_t kHermLineShift = 4u;
 
 // Device-side image of a planned program.
 struct DevProgram {

@@ -15,6 +15,7 @@ import numpy as np
 
 MAGIC = 0x56514450
 HERM_PASS, HERM_MIRROR, HERM_HALF_IN = 1, 2, 4
+HERM_LINE_SHIFT = 4
 
 
 def _dtypes(sz_pass, sz_phase, sz_op):
@@ -73,6 +74,29 @@ def _flip(mask, x):
     return (5 if x & 1 else 0) | (10 if x & 2 else 0)
 
 
+def herm_tile(flags: int, m: int, t: int):
+    """The kernel's launch order in Hermitian mode: launch index t -> (i, j,
+    stored).  Blocks (I, J), I <= J < NB = 2^(m-c), folded row I with row
+    NB-1-I; members a, b < 2^c 8 launch indices apart; c from the flags."""
+    c = (flags >> HERM_LINE_SHIFT) & 3
+    NB = 1 << (m - c)
+    NBB = NB * (NB + 1) // 2
+    lo, k, hi = t & 7, (t >> 3) & ((1 << (2 * c)) - 1), t >> (3 + 2 * c)
+    beta = hi * 8 + lo
+    I = J = 0
+    if NB > 1:
+        a, b = beta // (NB + 1), beta % (NB + 1)
+        if b < NB - a:
+            I, J = a, a + b
+        else:
+            I = NB - 1 - a
+            J = I + (b - (NB - a))
+    ma, mb = k & ((1 << c) - 1), k >> c
+    i, j = (I << c) | ma, (J << c) | mb
+    ok = beta < NBB and (I < J or ma <= mb)
+    return (i & ((1 << m) - 1), j & ((1 << m) - 1), ok)
+
+
 def run(plan, amps: np.ndarray) -> np.ndarray:
     """Apply every pass of `plan` to the vectorised state `amps` (complex128)."""
     amps = amps.copy()
@@ -91,8 +115,9 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
             # j in the column group bits; tiles with i < j also write their mirror
             m = ngb // 2
             N = 1 << m
-            pairs = [(i, j) for i in range(N) for j in range(i, N)]
-            assert T == len(pairs)
+            pairs = [(i, j) for t in range(T) for (i, j, ok) in [herm_tile(int(P["herm"]), m, t)] if ok]
+            assert sorted(pairs) == [(i, j) for i in range(N) for j in range(i, N)]
+            T = len(pairs)
             gb = np.zeros(T, dtype=np.uint64)
             for t, (i, j) in enumerate(pairs):
                 for k in range(m):
