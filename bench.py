@@ -37,11 +37,6 @@ PLAN_OPTS = dict(tile_bits=12, min_contig_bits=1, max_ops_per_pass=0, fuse_block
                  hermitian=True)
 
 
-# the 16-qubit all-to-all circuit: 64-byte segments (qubits 0 and 1 in every
-# tile) are faster there than the 14-qubit plan's 32-byte ones
-C3_PLAN_OPTS = dict(PLAN_OPTS, min_contig_bits=2)
-
-
 def pass_bytes(info, amps):
     """HBM bytes of all passes of one run: every computed amplitude is read
     and written once per pass (16 B each way); in Hermitian mode only the
@@ -192,7 +187,7 @@ def c3_leg(vqd, torch, steps: int):
     n = 16
     ops = c3_all_to_all_circuit(n=n, n_gates=500)
     n_gates = sum(1 for k, _, _ in ops if k in ("xx", "ry", "rz"))
-    prog = vqd.Program(n, ops).compile(vqd.plan_opts(**C3_PLAN_OPTS))
+    prog = vqd.Program(n, ops).compile(vqd.plan_opts(**PLAN_OPTS))
     info = prog.info()
     dm = vqd.DensityMatrix(n)
     stream = torch.cuda.current_stream()
