@@ -74,6 +74,11 @@ PlanOpts default_opts(int n)
     o.pad_coalesce = false;
     // k_batch stages a full 2^12 tile and keeps 1 KiB of its own beside it
     o.rt_budget = (160 * 1024 - 1024 - (16 << kBatchTile)) / 16;
+    // every named op preserves Hermiticity and each instance starts from
+    // |0..0><0..0|: half the tiles per pass (the planner falls back for a
+    // program with an op that does not preserve it)
+    o.hermitian = true;
+    o.min_contig_bits = 1;
     return o;
 }
 
@@ -415,7 +420,6 @@ int vqd_batch_set_opts(vqd_batch *b, int n, const vqd_plan_opts *o)
     if (!b || !o) return fail(VQD_E_ARG, "null argument");
     if (n < 2 || n > VQD_MAX_QUBITS) return fail(VQD_E_SIZE, "n must be in [2, 16]");
     if (o->tile_bits < 4 || o->tile_bits > 12) return fail(VQD_E_ARG, "batched tile_bits must be in [4, 12]");
-    if (o->hermitian) return fail(VQD_E_ARG, "the batched kernel has no Hermitian mode");
     b->opts_by_n[n] = to_plan_opts(*o);
     b->compiled = false;
     return VQD_OK;
@@ -560,7 +564,8 @@ int vqd_batch_autotune(vqd_batch *b, void *arena, size_t arena_bytes, double *ou
     int rc = VQD_OK;
     for (auto &kv : by_n) {
         const int n = kv.first;
-        const std::string key = arch + ":n" + std::to_string(n);
+        const bool herm = default_opts(n).hermitian;
+        const std::string key = arch + (herm ? ":herm:n" : ":n") + std::to_string(n);
         auto hit = cache.find(key);
         if (hit != cache.end()) {
             PlanOpts o = default_opts(n);
@@ -574,9 +579,12 @@ int vqd_batch_autotune(vqd_batch *b, void *arena, size_t arena_bytes, double *ou
         // a sample of template instances only where no ordinary ones are
         const bool use_tmpl = sel.empty();
         std::vector<PlanOpts> cands;
-        for (int tb : {12, 11, 10, 9}) {
+        // Hermitian mode: tiles of whole qubits (even sizes), 1-3 forced qubits
+        const std::vector<int> tbs = herm ? std::vector<int>{12, 10, 8} : std::vector<int>{12, 11, 10, 9};
+        const std::vector<int> cs = herm ? std::vector<int>{1, 2, 3} : std::vector<int>{0, 2, 3};
+        for (int tb : tbs) {
             const int t = std::min(tb, 2 * n);
-            for (int c : {0, 2, 3}) {
+            for (int c : cs) {
                 PlanOpts o = default_opts(n);
                 o.tile_bits = t;
                 o.min_contig_bits = std::min(c, t);
@@ -648,7 +656,7 @@ int vqd_batch_plan_opts(const vqd_batch *b, int n, vqd_plan_opts *o)
     o->max_ops_per_pass = p.max_ops_per_pass;
     o->fuse_blocks = p.fuse_blocks;
     o->pad_coalesce = p.pad_coalesce;
-    o->hermitian = 0;
+    o->hermitian = p.hermitian ? 1 : 0;
     return VQD_OK;
 }
 
@@ -664,7 +672,6 @@ int vqd_template_export(int n, int count, const int *kinds, const int *targets, 
     vqd_plan_opts o;
     vqd_plan_opts_default(&o);
     if (opts) o = *opts;
-    if (o.hermitian) return fail(VQD_E_ARG, "templates have no Hermitian mode");
     const std::vector<int> kv(kinds, kinds + count), tv(targets, targets + 4 * (size_t)count);
     HostPlan plan;
     if (int rc = plan_template(n, kv, tv, to_plan_opts(o), plan)) return rc;

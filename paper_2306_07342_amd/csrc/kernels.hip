@@ -780,59 +780,78 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
     const KPhase *H0 = phases + pb, *HL = phases + pe - 1;
     const uint32_t ngb = uni(P->n_group_bits);
     const uint32_t n_tiles = (uint32_t)P->n_tiles;
+    const uint32_t L = uni(P->L);
     uint32_t tl0, tlL;
     uint32_t tg0, tgL;
-    thread_bits(H0, active ? tid : 0u, nthr, tl0, tg0);
-    thread_bits(HL, active ? tid : 0u, nthr, tlL, tgL);
+    const uint32_t ttid = active ? tid : 0u;
+    thread_bits(H0, ttid, nthr, tl0, tg0);
+    thread_bits(HL, ttid, nthr, tlL, tgL);
     const double2 *ld_lane = amps + tg0;
     double2 *st_lane = amps + tgL;
     const uint32_t wave_base = uni(tid & ~63u);
-    double2 A[16], B[16];
-    {
-        const uint32_t gb = group_base(P, 0, ngb, false);
+    // Hermitian mode, as in k_pass: tile pairs i <= j, the previous pass's
+    // stored half read directly or through the transpose, mirror images in
+    // the instance's last pass
+    const uint32_t herm = uni(P->herm);
+    const uint32_t nq = (L + ngb) >> 1;
+    uint32_t tgM = 0, tg0M = 0;
+    HalfIn hin{};
+    if (herm) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) A[e] = ld_lane[gb | slot_g(H0, e)];
+        for (uint32_t i = 0; i < (uint32_t)kMaxThreadBits; ++i) {
+            tgM |= ((ttid >> i) & 1u) << (mirror_pos(uni(HL->thr_gpos[i]), nq) & 31u);
+            tg0M |= ((ttid >> i) & 1u) << (mirror_pos(uni(H0->thr_gpos[i]), nq) & 31u);
+        }
+        if (herm & kHermHalfIn) hin = half_in(P - 1, H0, tg0, nq);
     }
+    double2 *st_mirror = amps + tgM;
+    const double2 *ld_mirror = amps + tg0M;
+    auto tile_at = [&](uint32_t t) {
+        if (herm) return herm_tile(P, t, ngb, herm);
+        HermTile h{group_base(P, t, ngb, false), 0u, false, true};
+        return h;
+    };
+    auto load = [&](double2 (&v)[16], const HermTile &h) {
+        if (herm) {
+            load_herm(v, ld_lane, ld_mirror, h, H0, nq, herm, hin);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = ld_lane[h.gb | slot_g(H0, e)];
+        }
+    };
+    auto store = [&](const double2 (&v)[16], const HermTile &h) {
+        if (!active || !h.valid) return;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) st_lane[h.gb | slot_g(HL, e)] = v[e];
+        if (h.mirror && (herm & kHermMirror)) store_mirror(st_mirror, h.gbm, HL, nq, v);
+    };
+    // a tile with i = j is read through the transpose by other waves than
+    // the ones that store it: every wave's loads come before any store
+    const bool half_in_sync = (herm & kHermHalfIn) != 0;
+    double2 A[16], B[16];
+    load(A, tile_at(0));
     for (uint32_t t = 0; t < n_tiles; t += 2) {
         // tile t in A; the previous tile's results are in B
         __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0) only (gfx9 encoding)
-        const uint32_t gb = group_base(P, t, ngb, false);
-        if (active && t > 0) {
-            const uint32_t gbp = group_base(P, t - 1, ngb, false);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) st_lane[gbp | slot_g(HL, e)] = B[e];
-        }
-        {
-            const uint32_t gb2 = group_base(P, (t + 1 < n_tiles) ? t + 1 : t, ngb, false);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) B[e] = ld_lane[gb2 | slot_g(H0, e)];
-        }
-        batch_phases(A, phases, ops, mats, lds, lds_rt, pb, pe, gb, tl0, tlL, wave_base, nthr, active);
+        if (half_in_sync) __syncthreads();
+        const HermTile h0 = tile_at(t);
+        if (t > 0) store(B, tile_at(t - 1));
+        load(B, tile_at((t + 1 < n_tiles) ? t + 1 : t));
+        batch_phases(A, phases, ops, mats, lds, lds_rt, pb, pe, h0.gb, tl0, tlL, wave_base, nthr, active);
         if (t + 1 >= n_tiles) break;
         // tile t + 1 in B; tile t's results in A
         __builtin_amdgcn_s_waitcnt(0x0F70);
-        const uint32_t gb1 = group_base(P, t + 1, ngb, false);
-        if (active) {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) st_lane[gb | slot_g(HL, e)] = A[e];
-        }
-        {
-            const uint32_t gb2 = group_base(P, (t + 2 < n_tiles) ? t + 2 : t + 1, ngb, false);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) A[e] = ld_lane[gb2 | slot_g(H0, e)];
-        }
-        batch_phases(B, phases, ops, mats, lds, lds_rt, pb, pe, gb1, tl0, tlL, wave_base, nthr, active);
+        if (half_in_sync) __syncthreads();
+        const HermTile h1 = tile_at(t + 1);
+        store(A, h0);
+        load(A, tile_at((t + 2 < n_tiles) ? t + 2 : t + 1));
+        batch_phases(B, phases, ops, mats, lds, lds_rt, pb, pe, h1.gb, tl0, tlL, wave_base, nthr, active);
     }
     // the last tile's results: in A when n_tiles is odd, else in B
-    if (active && n_tiles > 0) {
-        const uint32_t gbl = group_base(P, n_tiles - 1, ngb, false);
-        if (n_tiles & 1u) {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) st_lane[gbl | slot_g(HL, e)] = A[e];
-        } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) st_lane[gbl | slot_g(HL, e)] = B[e];
-        }
+    if (n_tiles > 0) {
+        const HermTile hl = tile_at(n_tiles - 1);
+        if (n_tiles & 1u) store(A, hl);
+        else store(B, hl);
     }
 }
 

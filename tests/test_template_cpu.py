@@ -149,3 +149,25 @@ def test_template_rejects_bad_input(vqd_host):
     P[0, 0] = np.nan
     with pytest.raises(vqd_host.VQDError):
         vqd_host.template_export(3, [("rx", (0,))], P)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_hermitian_template_instances_match_oracle(vqd_host, seed):
+    """Templates in Hermitian mode (the batched kernel's default plan): the
+    structure planned once, each instance's coefficients filled in, half the
+    tiles computed and the rest restored as conjugate transposes."""
+    n = 6
+    structure = random_structure(n, 50, seed=200 + seed)
+    for inst in range(2):
+        P = random_params(structure, seed=2000 * seed + inst)
+        got = run_template(vqd_host, n, structure, P,
+                           vqd_host.plan_opts(tile_bits=8, min_contig_bits=1, hermitian=True))
+        ref = emulate(n, as_ops(structure, P)).to_vectorised()
+        assert np.abs(got - ref).max() <= TOL
+
+
+def test_batch_default_plan_is_hermitian(vqd_host):
+    b = vqd_host.Batch()
+    b.add(9, [("h", (0,), ())])
+    o = b.plan_opts(9)
+    assert o["hermitian"] == 1 and o["min_contig_bits"] == 1
