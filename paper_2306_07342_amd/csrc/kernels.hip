@@ -139,8 +139,9 @@ __device__ __forceinline__ uint32_t group_base(const KPass *__restrict__ P, uint
 // The c lowest group bits split 128-byte lines between tiles, so the pairs
 // are launched in blocks: i = I 2^c + a, j = J 2^c + b (a, b < 2^c), the
 // blocks I <= J < 2^(m-c) enumerated by folding row I with row NB-1-I of
-// the upper triangle (NB + 1 blocks per fold), a block's 4^c members 8
-// launch indices apart (one XCD, one round of the persistent grid).  The
+// the upper triangle (NB + 1 blocks per fold), a block's 4^c members s =
+// min(8, blocks) launch indices apart (one XCD, one round of the persistent
+// grid; no padding when a pass has fewer than 8 blocks).  The
 // tile's base holds i in the m row group bits and j in the m column group
 // bits, its mirror's base the other way round.  Padding blocks and members
 // with a > b of a block with I = J are not stored.
@@ -153,10 +154,11 @@ struct HermTile {
 __device__ __forceinline__ HermTile herm_tile(const KPass *__restrict__ P, uint32_t t, uint32_t ngb,
                                               uint32_t herm)
 {
-    const uint32_t m = ngb >> 1, c = (herm >> kHermLineShift) & 3u;
+    const uint32_t m = ngb >> 1, c = (herm >> kHermLineShift) & 3u, st = (herm >> kHermStrideShift) & 15u;
     const uint32_t NB = 1u << (m - c), NBB = NB * (NB + 1) / 2;
-    const uint32_t lo = t & 7u, k = (t >> 3) & ((1u << (2 * c)) - 1u), hi = t >> (3 + 2 * c);
-    const uint32_t beta = hi * 8 + lo;
+    const uint32_t q0 = t / st, lo = t - q0 * st;
+    const uint32_t k = q0 & ((1u << (2 * c)) - 1u), hi = q0 >> (2 * c);
+    const uint32_t beta = hi * st + lo;
     uint32_t I = 0, J = 0;
     if (NB > 1) {
         const uint32_t a = beta / (NB + 1), b = beta - a * (NB + 1);

@@ -470,8 +470,9 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             uint32_t c = 0;
             while (c < gq.size() && gq[c] < 3) ++c;
             const uint64_t N = 1ull << gq.size(), NB = N >> c, NBB = NB * (NB + 1) / 2;
-            kp.n_tiles = (NBB + 7) / 8 * 8 << (2 * c);
-            kp.herm = kHermPass | (c << kHermLineShift);
+            const uint32_t stride = (uint32_t)std::min<uint64_t>(8, NBB);
+            kp.n_tiles = (NBB + stride - 1) / stride * stride << (2 * c);
+            kp.herm = kHermPass | (c << kHermLineShift) | (stride << kHermStrideShift);
             out.tile_fraction = double(N + 1) / double(2 * N);
         } else {
             for (int b = 0; b < n2; ++b)

@@ -112,6 +112,9 @@ constexpr uint32_t kHermHalfIn = 4u;   // the previous pass stored only its tile
 // members 8 launch indices apart so that they run on one XCD together; in a
 // block with I = J the members with a > b are computed but not stored.
 constexpr uint32_t kHermLineShift = 4u;
+// Bits 8-11: the block stride s = min(8, number of blocks), the launch-index
+// distance between a block's members (no padding when there are few blocks).
+constexpr uint32_t kHermStrideShift = 8u;
 
 // Device-side image of a planned program.
 struct DevProgram {

@@ -16,6 +16,7 @@ import numpy as np
 MAGIC = 0x56514450
 HERM_PASS, HERM_MIRROR, HERM_HALF_IN = 1, 2, 4
 HERM_LINE_SHIFT = 4
+HERM_STRIDE_SHIFT = 8
 
 
 def _dtypes(sz_pass, sz_phase, sz_op):
@@ -77,12 +78,15 @@ def _flip(mask, x):
 def herm_tile(flags: int, m: int, t: int):
     """The kernel's launch order in Hermitian mode: launch index t -> (i, j,
     stored).  Blocks (I, J), I <= J < NB = 2^(m-c), folded row I with row
-    NB-1-I; members a, b < 2^c 8 launch indices apart; c from the flags."""
+    NB-1-I; members a, b < 2^c s = min(8, blocks) launch indices apart; c and
+    s from the flags."""
     c = (flags >> HERM_LINE_SHIFT) & 3
+    st = (flags >> HERM_STRIDE_SHIFT) & 15
     NB = 1 << (m - c)
     NBB = NB * (NB + 1) // 2
-    lo, k, hi = t & 7, (t >> 3) & ((1 << (2 * c)) - 1), t >> (3 + 2 * c)
-    beta = hi * 8 + lo
+    q0, lo = t // st, t % st
+    k, hi = q0 & ((1 << (2 * c)) - 1), q0 >> (2 * c)
+    beta = hi * st + lo
     I = J = 0
     if NB > 1:
         a, b = beta // (NB + 1), beta % (NB + 1)
