@@ -231,8 +231,14 @@ typedef struct vqd_plan_opts {
                                part of the index is at most its column part and writes the
                                conjugate transpose of each to its mirror image: about half
                                the work.  The tiles are then whole qubits (tile_bits is
-                               rounded down to even) and always hold qubits 0 and 1.
-                               Otherwise the program is planned as with 0. */
+                               rounded down to even) and always hold qubits
+                               0..min(min_contig_bits, 3)-1 (fewer if the widest gate
+                               would not fit), whose row and column bits give the
+                               loads and stores their contiguous runs.  Between the
+                               passes of a run only the computed half is current; the
+                               last pass restores the whole matrix.  Otherwise the
+                               program is planned as with 0.  Batches default to 1
+                               (every instance starts from |0..0><0..0|). */
 } vqd_plan_opts;
 void vqd_plan_opts_default(vqd_plan_opts *o);
 
@@ -300,7 +306,10 @@ int vqd_batch_destroy(vqd_batch *b);
 /* Append a copy of program p's ops as a new instance (its index in *index). */
 int vqd_batch_add(vqd_batch *b, const vqd_prog *p, int *index);
 
-/* Plan options for every instance with n qubits (tile_bits in [4, 12]). */
+/* Plan options for every instance with n qubits (tile_bits in [4, 12]).
+ * The defaults are tile_bits min(12, 2n), min_contig_bits 1, hermitian 1;
+ * vqd_batch_plan_opts reports the options in use (set, autotuned or
+ * default). */
 int vqd_batch_set_opts(vqd_batch *b, int n, const vqd_plan_opts *opts);
 int vqd_batch_plan_opts(const vqd_batch *b, int n, vqd_plan_opts *opts);
 
