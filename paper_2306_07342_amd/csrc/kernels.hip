@@ -156,7 +156,7 @@ __device__ __forceinline__ HermTile herm_tile(const KPass *__restrict__ P, uint3
 {
     const uint32_t m = ngb >> 1, c = (herm >> kHermLineShift) & 3u, st = (herm >> kHermStrideShift) & 15u;
     const uint32_t NB = 1u << (m - c), NBB = NB * (NB + 1) / 2;
-    const uint32_t q0 = t / st, lo = t - q0 * st;
+    const uint32_t q0 = (st == 8u) ? t >> 3 : t / st, lo = t - q0 * st;
     const uint32_t k = q0 & ((1u << (2 * c)) - 1u), hi = q0 >> (2 * c);
     const uint32_t beta = hi * st + lo;
     uint32_t I = 0, J = 0;
@@ -454,9 +454,11 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
 
     uint32_t t = blockIdx.x;
     double2 nxt[16];
+    HermTile ht_nxt{0u, 0u, false, true};     // Hermitian mode: the prefetched tile
     if (t < n_tiles) {
         if (herm) {
-            load_herm(nxt, ld_lane, ld_mirror, herm_tile(P, t, ngb, herm), H0, nq, herm, hin);
+            ht_nxt = herm_tile(P, t, ngb, herm);
+            load_herm(nxt, ld_lane, ld_mirror, ht_nxt, H0, nq, herm, hin);
         } else {
             const uint32_t gb = group_base(P, t, ngb, xcd);
 #pragma unroll
@@ -496,15 +498,15 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
             }
             if (mirror_prev) store_mirror(st_mirror, gbm_prev, HL, nq, a);
         }
-        HermTile ht{0u, 0u, false, true};
-        if (herm) ht = herm_tile(P, t, ngb, herm);
+        const HermTile ht = ht_nxt;              // the tile prefetched last iteration
         const uint32_t gb = herm ? ht.gb : group_base(P, t, ngb, xcd);
         {
             // prefetch the next tile (the last iteration re-reads its own
             // tile, which keeps the loads unconditional)
             const uint32_t t2 = (t + gridDim.x < n_tiles) ? t + gridDim.x : t;
             if (herm) {
-                load_herm(nxt, ld_lane, ld_mirror, herm_tile(P, t2, ngb, herm), H0, nq, herm, hin);
+                if (t2 != t) ht_nxt = herm_tile(P, t2, ngb, herm);
+                load_herm(nxt, ld_lane, ld_mirror, ht_nxt, H0, nq, herm, hin);
             } else {
                 const uint32_t gb2 = group_base(P, t2, ngb, xcd);
 #pragma unroll
