@@ -415,7 +415,8 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
  * parameters each, as for named_many); with all three NULL only *out_count
  * is set.  Unspecified gate kinds take no time and add no noise.  Host only.
  *
- * vqd_device_set_angle_scaling: for a parameterised gate kind, multiply its
+ * vqd_device_set_angle_scaling: for a parameterised gate kind (and its
+ * per-target specifications), multiply its
  * active noise probabilities (scale_noise) and/or its duration
  * (scale_duration) by |theta| / pi, theta the gate's first parameter (App.
  * C); a scaled probability above 1 makes insert_noise fail with VQD_E_ARG.
@@ -440,6 +441,13 @@ typedef struct vqd_device vqd_device;
 int vqd_device_create(int n, vqd_device **out);      /* 1 <= n <= 64 */
 int vqd_device_destroy(vqd_device *d);
 int vqd_device_set_gate(vqd_device *d, int kind, double duration, double p_depol, double p_deph);
+/* The specification of one gate kind on one set of targets (nq = the kind's
+ * qubit count; the order of the targets does not matter), overriding the
+ * kind's own for gates on exactly these qubits: per-qubit rotation
+ * fidelities and per-pair two-qubit gates (App. C).  The kind's angle
+ * scaling applies to it as well. */
+int vqd_device_set_gate_on(vqd_device *d, int kind, int nq, const int *targets, double duration, double p_depol,
+                           double p_deph);
 int vqd_device_set_angle_scaling(vqd_device *d, int kind, int scale_noise, int scale_duration);
 int vqd_device_set_passive(vqd_device *d, const double *T1, const double *T2);   /* n each */
 int vqd_device_set_thermal(vqd_device *d, const double *p0);                     /* n */

@@ -23,7 +23,11 @@ Readings (the paper describes the behaviour, not a procedure):
   qubit, the batch minus the gate for a qubit whose gate is shorter).
 * Operations with no effect are left out: zero probabilities, zero idle
   time, a disabled T1 or T2 (<= 0), zero crosstalk phase.
-* Gate kinds without a specification take no time and add no noise.
+* Gate kinds without a specification take no time and add no noise.  A
+  specification for a gate kind on a particular set of qubits (App. C: per-
+  qubit rotation fidelities, per-pair two-qubit gates) replaces the kind's
+  for gates on exactly those qubits, in any order; the kind's angle scaling
+  applies to it.
 * T1 decay is amp_t1, or gamp_t1(p0, dt, T1) when the qubit's thermal ground
   population p0 is below 1 (relaxation towards the state it is initialised
   in, eq. thermalstate), or depol_t1 when that form is chosen; T2 decay is
@@ -48,6 +52,7 @@ class Device:
     def __init__(self, n: int):
         self.n = n
         self.gates: Dict[str, Tuple[float, float, float]] = {}   # kind -> (duration, p_depol, p_deph)
+        self.gates_on: Dict[Tuple[str, Tuple[int, ...]], Tuple[float, float, float]] = {}
         self.scaling: Dict[str, Tuple[bool, bool]] = {}          # kind -> (noise, duration)
         self.T1 = [0.0] * n
         self.T2 = [0.0] * n
@@ -58,6 +63,9 @@ class Device:
         self.static_zz: List[Tuple[int, int, float]] = []
         self.t_meas = 0.0
         self.eps = [0.0] * n
+
+    def set_gate_on(self, kind: str, qubits, duration: float, p_depol: float = 0.0, p_deph: float = 0.0):
+        self.gates_on[(kind, tuple(sorted(qubits)))] = (duration, p_depol, p_deph)
 
     def set_angle_scaling(self, kind: str, noise: bool = True, duration: bool = False):
         self.scaling[kind] = (noise, duration)
@@ -119,8 +127,8 @@ def insert_noise(dev: Device, gates: Sequence) -> List[tuple]:
     for batch in schedule(dev.n, gates):
         spec = []
         for i in batch:
-            kind, _, params = gates[i]
-            d, pd, pq = dev.gates.get(kind, (0.0, 0.0, 0.0))
+            kind, qs, params = gates[i]
+            d, pd, pq = dev.gates_on.get((kind, tuple(sorted(qs))), dev.gates.get(kind, (0.0, 0.0, 0.0)))
             scale_noise, scale_dur = dev.scaling.get(kind, (False, False))
             f = abs(params[0]) / math.pi if (scale_noise or scale_dur) else 1.0
             if scale_noise:

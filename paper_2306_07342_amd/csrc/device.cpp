@@ -13,6 +13,7 @@
 // for the measurement time and depolarising noise on either side of the
 // projection) comes from its own call.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -37,6 +38,8 @@ struct Op {
 struct vqd_device {
     int n = 0;
     GateSpec gate[VQD_K_COUNT];
+    // per-target specifications: (kind, sorted targets) -> spec
+    std::vector<std::pair<std::array<int, 5>, GateSpec>> gate_on;
     std::vector<double> T1, T2;
     std::vector<double> p0;                    // thermal ground populations
     int t1_kind = VQD_K_AMP_T1, t2_kind = VQD_K_DEPH_T2;
@@ -90,6 +93,25 @@ int write_ops(const OpList &out, int cap, int *out_count, int *out_kinds, int *o
 }
 
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+std::array<int, 5> target_key(int kind, int nq, const int *t)
+{
+    std::array<int, 5> k{kind, -1, -1, -1, -1};
+    for (int j = 0; j < nq; ++j) k[1 + j] = t[j];
+    std::sort(k.begin() + 1, k.begin() + 1 + nq);
+    return k;
+}
+
+// The gate's specification: the one for its exact target set, else its kind's.
+const GateSpec &spec_for(const vqd_device *d, int kind, int nq, const int *t)
+{
+    if (!d->gate_on.empty()) {
+        const std::array<int, 5> k = target_key(kind, nq, t);
+        for (const auto &e : d->gate_on)
+            if (e.first == k) return e.second;
+    }
+    return d->gate[kind];
+}
 
 }  // namespace
 
@@ -162,6 +184,30 @@ int vqd_device_set_crosstalk(vqd_device *d, int n_edges, const int *edges, doubl
     return VQD_OK;
 }
 
+int vqd_device_set_gate_on(vqd_device *d, int kind, int nq, const int *targets, double duration, double p_depol,
+                           double p_deph)
+{
+    clear_error();
+    if (!d || !targets) return fail(VQD_E_ARG, "null argument");
+    int k_nq = 0;
+    if (kind_arity(kind, &k_nq, nullptr) != 0 || kind_is_channel(kind))
+        return fail(VQD_E_ARG, "not a gate kind: " + std::to_string(kind));
+    if (nq != k_nq) return fail(VQD_E_ARG, "target count does not match the gate kind");
+    if (int rc = check_targets(d->n, nq, targets)) return rc;
+    if (!(duration >= 0.0) || !std::isfinite(duration)) return fail(VQD_E_ARG, "duration must be finite and >= 0");
+    if (!(p_depol >= 0.0 && p_depol <= 1.0) || !(p_deph >= 0.0 && p_deph <= 1.0))
+        return fail(VQD_E_ARG, "noise probabilities outside [0, 1]");
+    const std::array<int, 5> key = target_key(kind, nq, targets);
+    GateSpec g{duration, p_depol, p_deph, d->gate[kind].scale_noise, d->gate[kind].scale_duration};
+    for (auto &e : d->gate_on)
+        if (e.first == key) {
+            e.second = g;
+            return VQD_OK;
+        }
+    d->gate_on.emplace_back(key, g);
+    return VQD_OK;
+}
+
 int vqd_device_set_angle_scaling(vqd_device *d, int kind, int scale_noise, int scale_duration)
 {
     clear_error();
@@ -171,6 +217,11 @@ int vqd_device_set_angle_scaling(vqd_device *d, int kind, int scale_noise, int s
         return fail(VQD_E_ARG, "not a parameterised gate kind: " + std::to_string(kind));
     d->gate[kind].scale_noise = scale_noise != 0;
     d->gate[kind].scale_duration = scale_duration != 0;
+    for (auto &e : d->gate_on)
+        if (e.first[0] == kind) {
+            e.second.scale_noise = scale_noise != 0;
+            e.second.scale_duration = scale_duration != 0;
+        }
     return VQD_OK;
 }
 
@@ -290,10 +341,10 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
         std::fill(active.begin(), active.end(), 0);
         pairs.clear();
         for (int i : batch) {
-            const GateSpec &g = d->gate[kinds[i]];
             int nq = 0;
             kind_arity(kinds[i], &nq, nullptr);
             const int *t = targets + 4 * (size_t)i;
+            const GateSpec &g = spec_for(d, kinds[i], nq, t);
             const double *par = params + 4 * (size_t)i;
             const double s = std::fabs(par[0]) / 3.14159265358979323846;
             const double gd = g.scale_duration ? g.duration * s : g.duration;

@@ -166,6 +166,8 @@ def load(path: str = LIB_PATH):
         "vqd_device_set_crosstalk": ([vp, ctypes.c_int, _ip, ctypes.c_double], ctypes.c_int),
         "vqd_device_preset": ([ctypes.c_int, ctypes.POINTER(vp), _dp], ctypes.c_int),
         "vqd_device_preset_qubits": ([ctypes.c_int, _ip], ctypes.c_int),
+        "vqd_device_set_gate_on": ([vp, ctypes.c_int, ctypes.c_int, _ip, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double], ctypes.c_int),
         "vqd_device_set_angle_scaling": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "vqd_device_set_thermal": ([vp, _dp], ctypes.c_int),
         "vqd_device_set_passive_forms": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
@@ -591,6 +593,10 @@ class Device:
     def set_crosstalk(self, edges, alpha: float):
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         check(lib().vqd_device_set_crosstalk(self.handle, e.shape[0], _i(e), alpha))
+
+    def set_gate_on(self, kind: str, qubits, duration: float, p_depol: float = 0.0, p_deph: float = 0.0):
+        q = np.ascontiguousarray(qubits, dtype=np.int32)
+        check(lib().vqd_device_set_gate_on(self.handle, KINDS[kind], q.size, _i(q), duration, p_depol, p_deph))
 
     def set_angle_scaling(self, kind: str, noise: bool = True, duration: bool = False):
         check(lib().vqd_device_set_angle_scaling(self.handle, KINDS[kind], int(noise), int(duration)))

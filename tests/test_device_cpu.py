@@ -22,6 +22,8 @@ def lib_device(vqd, ref: dv.Device):
         d.set_gate(k, t, p, q)
     d.set_passive(ref.T1, ref.T2)
     d.set_crosstalk(ref.edges, ref.alpha)
+    for (k, qs), (t, p, q) in ref.gates_on.items():
+        d.set_gate_on(k, qs, t, p, q)
     for k, (noise, dur) in ref.scaling.items():
         d.set_angle_scaling(k, noise, dur)
     d.set_thermal(ref.p0)
@@ -79,6 +81,13 @@ def test_random_devices_with_every_rule(vqd_host, seed):
                      float(rng.choice([0.0, 2e-3])))
     for k in ("rx", "ry"):
         ref.set_angle_scaling(k, bool(rng.integers(2)), bool(rng.integers(2)))
+    for q in range(n):                            # per-qubit rotation specs
+        if rng.random() < 0.5:
+            ref.set_gate_on("rx", (q,), float(rng.choice([0.03, 0.07])), float(rng.uniform(0, 2e-3)))
+    for a in range(n - 1):                        # per-pair CZ specs
+        if rng.random() < 0.5:
+            ref.set_gate_on("cz", (a + 1, a), float(rng.choice([0.2, 0.4])), float(rng.uniform(0, 1e-2)),
+                            float(rng.uniform(0, 1e-2)))
     ref.set_passive(list(rng.uniform(20, 200, n) * (rng.random(n) < 0.8)),
                     list(rng.uniform(10, 100, n) * (rng.random(n) < 0.8)))
     ref.set_thermal(list(np.where(rng.random(n) < 0.5, 1.0, rng.uniform(0.9, 1.0, n))))
@@ -118,6 +127,12 @@ def test_errors(vqd_host):
     assert d.insert_noise([]) == []
     with pytest.raises(v.VQDError):
         d.set_angle_scaling("h")                     # no angle
+    with pytest.raises(v.VQDError):
+        d.set_gate_on("cz", (0,), 0.1)              # two targets needed
+    with pytest.raises(v.VQDError):
+        d.set_gate_on("cz", (0, 0), 0.1)
+    with pytest.raises(v.VQDError):
+        d.set_gate_on("depol1", (0,), 0.1)
     with pytest.raises(v.VQDError):
         d.set_thermal([1.0, 1.2, 0.5])
     with pytest.raises(v.VQDError):

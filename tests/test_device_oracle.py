@@ -174,3 +174,27 @@ def test_zz_strength_closed_forms():
     assert abs(zz_strength(J, fc - ft, ac, at) - zz_strength(J, ft - fc, at, ac)) <= 1e-15
     D, a = -400.0, 297.0
     assert abs(zz_strength(J, D, a, a) - 2 * a * J * J / (D * D - a * a)) <= 1e-15
+
+
+def test_per_target_specifications():
+    """A pair's own CZ specification and a qubit's own rotation noise replace
+    the kind's; angle scaling applies to both."""
+    d = dv.Device(3)
+    d.set_gate("cz", 0.2, p_depol=0.01)
+    d.set_gate_on("cz", (2, 1), 0.3, p_depol=0.02, p_deph=0.03)
+    d.set_gate("rx", 0.1, p_depol=0.004)
+    d.set_gate_on("rx", (2,), 0.1, p_depol=0.008)
+    d.set_angle_scaling("rx", noise=True)
+    gates = [("cz", (1, 2), ()), ("rx", (0,), (np.pi / 2,)), ("rx", (2,), (np.pi,)), ("cz", (0, 1), ())]
+    got = dv.insert_noise(d, gates)
+    expect = [
+        # batch 0: CZ(1, 2) with the pair's spec (0.3 us), Rx(pi/2) on 0 (0.05 us)
+        ("cz", (1, 2), ()), ("depol2", (1, 2), (0.02,)), ("deph2", (1, 2), (0.03,)),
+        ("rx", (0,), (np.pi / 2,)), ("depol1", (0,), (0.002,)),
+        # batch 1: Rx(pi) on 2 with qubit 2's own noise, CZ(0, 1) with the kind's
+        ("rx", (2,), (np.pi,)), ("depol1", (2,), (0.008,)),
+        ("cz", (0, 1), ()), ("depol2", (0, 1), (0.01,)),
+    ]
+    assert len(got) == len(expect), got
+    for g, e in zip(got, expect):
+        assert g[0] == e[0] and g[1] == e[1] and np.allclose(g[2], e[2], rtol=0, atol=1e-15), (g, e)
