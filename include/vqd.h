@@ -160,6 +160,11 @@ enum vqd_kind {
     VQD_K_DEPOL_T1,     /* dt, T1: depol1(3/4 (1 - exp(-dt/T1)))  (eq. depolt1) */
     VQD_K_GAMP_T1,      /* p, dt, T1: gamp(p, 1 - exp(-dt/T1)), T1 relaxation
                            towards p|0><0| + (1-p)|1><1|      (eq. gdamp)     */
+    VQD_K_RABI,         /* Omega, phi, Delta, t: the driven two-level unitary
+                           U(phi, Delta, t) of Rabi frequency Omega (eq. u)   */
+    VQD_K_OFFRES,       /* Omega, Delta, t: the drive a bystander qubit detuned
+                           by Delta receives while a neighbour is driven at
+                           Rabi frequency Omega for t (eq. off_resonant)      */
     VQD_K_COUNT
 };
 

@@ -71,9 +71,40 @@ def gate_matrix(kind, params):
     if kind == "zz":
         # ZZ crosstalk exp(-i alpha Z_p Z_q), eq. (weak_dephasing_zz) of Sec. 3.4
         return expm(-1j * params[0] * on2(Z, Z))
+    if kind == "rabi":
+        return rabi_u(*params)
+    if kind == "offres":
+        return off_resonant(*params)
     if kind == "matrix":
         return np.asarray(params[0], dtype=np.complex128)
     raise KeyError(kind)
+
+
+def rabi_u(omega, phi, delta, t):
+    """eq. (u): U(phi, Delta, t) of a two-level system driven at Rabi
+    frequency omega with phase phi and detuning Delta for a time t, with
+    the generalised frequency W = sqrt(omega^2 + Delta^2).  Reading: at
+    W = 0 (no drive, no detuning) the matrix is its limit, the identity."""
+    W = math.sqrt(omega * omega + delta * delta)
+    if W == 0.0:
+        return I2.copy()
+    c, s = math.cos(W * t / 2), math.sin(W * t / 2)
+    return np.array([[c - 1j * delta / W * s, -1j * omega / W * s * np.exp(1j * phi)],
+                     [-1j * omega / W * s * np.exp(-1j * phi), c + 1j * delta / W * s]])
+
+
+def off_resonant(omega, delta, t):
+    """eq. (off_resonant): the unitary a passive qubit detuned by delta from
+    a qubit driven at Rabi frequency omega for a time t undergoes, written in
+    the driven qubit's frame, with W = sqrt(omega^2 + delta^2).  Reading: at
+    W = 0 the identity, its limit."""
+    W = math.sqrt(omega * omega + delta * delta)
+    if W == 0.0:
+        return I2.copy()
+    c, s = math.cos(W * t / 2), math.sin(W * t / 2)
+    ep, em = np.exp(1j * W * t / 2), np.exp(-1j * W * t / 2)
+    return np.array([[(c - 1j * delta / W * s) * ep, -1j * omega / W * s * ep],
+                     [-1j * omega / W * s * em, (c + 1j * delta / W * s) * em]])
 
 
 # ------------------------------------------------------------- channels --

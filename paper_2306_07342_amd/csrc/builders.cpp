@@ -158,9 +158,34 @@ int channel_kraus(int kind, const double *p, int &k, std::vector<std::vector<cd>
     }
 }
 
+// Driven two-level system (eq. u): with W = sqrt(Omega^2 + Delta^2) and
+// a = W t / 2 the matrix is
+//   [cos a - i Delta/W sin a,         -i Omega/W sin a e^{+i phi}]
+//   [-i Omega/W sin a e^{-i phi},     cos a + i Delta/W sin a    ].
+// frame = true multiplies row 0 by e^{+i a} and row 1 by e^{-i a}: the
+// bystander seen from the driven qubit's frame (eq. off_resonant, phi = 0).
+// W = 0 (no drive, no detuning) is the identity.
+int rabi(double omega, double phi, double delta, double t, bool frame, std::vector<cd> &U)
+{
+    const double w = std::hypot(omega, delta);
+    const double a = 0.5 * w * t;
+    const double c = std::cos(a), s = std::sin(a);
+    const double sw = (w > 0.0) ? s / w : 0.5 * t;     // sin(a)/W, its limit at W = 0
+    const cd off = -I * (omega * sw);
+    U = {cd(c, -delta * sw), off * std::exp(I * phi), off * std::exp(-I * phi), cd(c, delta * sw)};
+    if (frame) {
+        const cd e0 = std::exp(I * a), e1 = std::conj(e0);
+        U[0] *= e0;      // row 0 (row-major)
+        U[1] *= e0;
+        U[2] *= e1;      // row 1
+        U[3] *= e1;
+    }
+    return VQD_OK;
+}
+
 bool is_channel(int kind)
 {
-    return kind >= VQD_K_DEPOL1 && kind < VQD_K_COUNT;
+    return kind >= VQD_K_DEPOL1 && kind <= VQD_K_GAMP_T1;
 }
 
 }  // namespace
@@ -174,6 +199,8 @@ void canonical_params(int kind, double *p)
     case VQD_K_GAMP_T1: p[0] = 0.83; p[1] = 0.3; p[2] = 17.0; break;
     case VQD_K_AMP_T1: case VQD_K_DEPH_T2: case VQD_K_DEPH_T2S: case VQD_K_DEPOL_T1:
         p[0] = 0.3; p[1] = 17.0; break;
+    case VQD_K_RABI: p[0] = 5.0; p[1] = 0.4; p[2] = 1.3; p[3] = 0.21; break;
+    case VQD_K_OFFRES: p[0] = 5.0; p[1] = 2.7; p[2] = 0.21; break;
     case VQD_K_RX: case VQD_K_RY: case VQD_K_RZ: case VQD_K_CPHASE: case VQD_K_XX: case VQD_K_ZZ:
         p[0] = 0.7371; break;
     default: p[0] = 0.0123; break;        // channel probabilities
@@ -183,9 +210,9 @@ void canonical_params(int kind, double *p)
 int kind_arity(int kind, int *nq, int *np)
 {
     static const int Q[VQD_K_COUNT] = {0, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2,
-                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1, 1};
+                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 1};
     static const int P[VQD_K_COUNT] = {0, 1, 1, 1, 0, 0, 0, 0, 4, 0, 1, 1, 1,
-                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2, 3};
+                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2, 3, 4, 3};
     if (kind <= 0 || kind >= VQD_K_COUNT) return -1;
     if (nq) *nq = Q[kind];
     if (np) *np = P[kind];
@@ -254,6 +281,10 @@ int kind_matrix(int kind, const double *p, std::vector<cd> &U, int &k)
         }
         break;
     }
+    case VQD_K_RABI:
+        return rabi(p[0], p[1], p[2], p[3], false, U);
+    case VQD_K_OFFRES:
+        return rabi(p[0], 0.0, p[1], p[2], true, U);
     default:
         return fail(VQD_E_ARG, "not a gate kind");
     }

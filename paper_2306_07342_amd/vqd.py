@@ -23,7 +23,7 @@ KINDS = {
     "cz": 9, "cphase": 10, "xx": 11, "zz": 12,
     "depol1": 13, "depol2": 14, "deph1": 15, "deph2": 16, "amp": 17, "gamp": 18,
     "bitflip1": 19, "bitflip2": 20, "amp_t1": 21, "deph_t2": 22, "deph_t2s": 23, "depol_t1": 24,
-    "gamp_t1": 25,
+    "gamp_t1": 25, "rabi": 26, "offres": 27,
 }
 BLOCK_UNITARY = 0
 BLOCK_SUPEROP = 1

@@ -311,14 +311,6 @@ def test_silicon_parity_decay_map():
 
 # ------------------------------------------------------- gate identities --
 
-def raman_u(phi, delta, omega, t):
-    """eq. (u) of Sec. 6 (neutral atoms)."""
-    w = math.sqrt(omega ** 2 + delta ** 2)
-    c, s = math.cos(w * t / 2), math.sin(w * t / 2)
-    return np.array([[c - 1j * delta / w * s, -1j * omega / w * s * np.exp(1j * phi)],
-                     [-1j * omega / w * s * np.exp(-1j * phi), c + 1j * delta / w * s]])
-
-
 def same_up_to_phase(A, B):
     k = np.argmax(np.abs(B))
     ph = A.flat[k] / B.flat[k]
@@ -327,14 +319,54 @@ def same_up_to_phase(A, B):
 
 @pytest.mark.parametrize("theta", [0.3, 1.7, 4.0])
 def test_rx_is_raman_u_at_zero_detuning(theta):
+    """Sec. 6 after eq. (u): U(0, 0, theta / Omega) is Rx(theta), here the
+    matrix exponential exp(-i theta X / 2)."""
+    from scipy.linalg import expm
     omega = 2.3
-    assert np.allclose(ch.gate_matrix("rx", (theta,)), raman_u(0, 0, omega, theta / omega), atol=1e-14)
+    assert np.abs(ch.gate_matrix("rabi", (omega, 0.0, 0.0, theta / omega))
+                  - expm(-0.5j * theta * ch.X)).max() < 1e-14
 
 
 def test_hadamard_from_raman_u():
+    """Sec. 6 after eq. (u): U(0, Omega, pi / W) is a Hadamard gate (up to a
+    global phase)."""
     omega = 1.1
     w = math.sqrt(2) * omega
-    assert same_up_to_phase(raman_u(0, omega, omega, math.pi / w), ch.gate_matrix("h", ()))
+    assert same_up_to_phase(ch.gate_matrix("rabi", (omega, 0.0, omega, math.pi / w)), (ch.X + ch.Z) / math.sqrt(2))
+
+
+@pytest.mark.parametrize("omega,phi,delta,t", [(2.3, 0.0, 0.0, 0.4), (1.7, 0.9, -0.6, 1.3),
+                                               (0.4, -2.2, 3.1, 2.9), (5.0, 0.4, 1.3, 0.21)])
+def test_raman_u_is_the_driven_two_level_propagator(omega, phi, delta, t):
+    """eq. (u) is the propagator of the drive Hamiltonian
+    (Omega cos(phi) X - Omega sin(phi) Y + Delta Z) / 2 for a time t, here by
+    scipy's matrix exponential; a sign of phi or Delta, a transposed
+    off-diagonal or a dropped factor 1/W each fail it."""
+    from scipy.linalg import expm
+    H = 0.5 * (omega * math.cos(phi) * ch.X - omega * math.sin(phi) * ch.Y + delta * ch.Z)
+    assert np.abs(ch.gate_matrix("rabi", (omega, phi, delta, t)) - expm(-1j * t * H)).max() < 1e-13
+    assert np.abs(ch.gate_matrix("rabi", (0.0, phi, 0.0, t)) - np.eye(2)).max() == 0.0
+
+
+@pytest.mark.parametrize("omega,delta,t", [(1.0, 2.0, 0.7), (5.0, 2.7, 0.21), (0.3, 40.0, 1.9)])
+def test_off_resonant_is_the_bystander_in_the_drive_frame(omega, delta, t):
+    """eq. (off_resonant): the detuned propagator of the same Hamiltonian
+    with phi = 0, followed by the frame rotation exp(i W t Z / 2) of the
+    driven qubit (W = sqrt(Omega^2 + Delta^2)); unitary."""
+    from scipy.linalg import expm
+    w = math.sqrt(omega ** 2 + delta ** 2)
+    H = 0.5 * (omega * ch.X + delta * ch.Z)
+    ref = expm(0.5j * w * t * ch.Z) @ expm(-1j * t * H)
+    U = ch.gate_matrix("offres", (omega, delta, t))
+    assert np.abs(U - ref).max() < 1e-13
+    assert np.abs(U.conj().T @ U - np.eye(2)).max() < 1e-14
+
+
+def test_off_resonant_without_drive_is_identity():
+    """An undriven bystander (Omega = 0, Delta > 0) receives no operation: the
+    detuning phase and the frame rotation cancel."""
+    for delta, t in ((0.5, 3.0), (7.0, 0.11)):
+        assert np.abs(ch.gate_matrix("offres", (0.0, delta, t)) - np.eye(2)).max() < 1e-15
 
 
 def test_rydberg_cz_phi_zero_is_cz():
@@ -355,22 +387,19 @@ def test_exchange_at_pi_is_swap():
 
 
 def test_off_resonant_tends_to_identity():
-    """eq. (off_resonant) approaches the identity (up to phases on the diagonal
-    that cancel in rho) as the detuning grows."""
+    """Sec. 3.3: eq. (off_resonant) approaches the identity as the detuning
+    grows, here within Omega / Delta, and a state's populations stay put."""
     omega, t = 1.0, 3.0
     dm = OracleDM(1)
     dm.apply_matrix((0,), ch.gate_matrix("h", ()))
     ref = dm.R.copy()
-    for delta, tol in ((1e2, 1e-2), (1e4, 1e-4)):
-        w = math.sqrt(omega ** 2 + delta ** 2)
-        c, s = math.cos(w * t / 2), math.sin(w * t / 2)
-        U = np.array([[(c - 1j * delta / w * s) * np.exp(1j * w * t / 2), -1j * omega / w * s * np.exp(1j * w * t / 2)],
-                      [-1j * omega / w * s * np.exp(-1j * w * t / 2), (c + 1j * delta / w * s) * np.exp(-1j * w * t / 2)]])
+    for delta in (1e2, 1e4):
+        U = ch.gate_matrix("offres", (omega, delta, t))
+        assert np.abs(U - np.eye(2)).max() <= omega / delta
         d2 = OracleDM(1)
         d2.set(ref)
         d2.apply_matrix((0,), U)
-        # populations are unchanged up to O(omega/delta)
-        assert abs(d2.R[0, 0] - ref[0, 0]) < tol
+        assert abs(d2.R[0, 0] - ref[0, 0]) < omega / delta
 
 
 def test_xx_at_half_pi_is_maximally_entangling():
