@@ -433,6 +433,16 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
  * (VQD_K_DEPH_T2, the default, or VQD_K_DEPH_T2S, eq. depht2s).
  * vqd_device_set_static_zz: couplings beta[e] (radians of ZZ phase, as in
  * exp(-i a Z(x)Z), per unit time) on the pairs edges[2e], edges[2e+1].
+ * vqd_device_set_off_resonant: off-resonant driving (Sec. 3.3; the silicon
+ * device of Sec. 7).  rabi[q] >= 0 and freq[q] are qubit q's Rabi frequency
+ * and its own frequency, both angular (radians per unit time); rabi = NULL
+ * turns the model off.  A one-qubit gate of duration t > 0 on a qubit q with
+ * rabi[q] > 0 drives q, and every qubit j that no gate of the batch targets
+ * receives VQD_K_OFFRES(rabi[q], freq[j] - freq[q], t) (eq. off_resonant).
+ * These ops follow the batch's gates and their active noise, by driving
+ * gate in input order and then ascending j, and precede crosstalk and
+ * passive decay.  VQD_E_ARG for a negative or non-finite rabi[q] or a
+ * non-finite freq[q].
  *
  * vqd_device_set_readout / vqd_device_readout_noise: the read-out model of
  * Sec. 8, T1 decay for the measurement time t_meas, then depolarising
@@ -459,6 +469,7 @@ int vqd_device_set_thermal(vqd_device *d, const double *p0);                    
 int vqd_device_set_passive_forms(vqd_device *d, int t1_kind, int t2_kind);
 int vqd_device_set_crosstalk(vqd_device *d, int n_edges, const int *edges, double alpha);
 int vqd_device_set_static_zz(vqd_device *d, int n_edges, const int *edges, const double *beta);
+int vqd_device_set_off_resonant(vqd_device *d, const double *rabi, const double *freq);  /* n each */
 int vqd_device_set_readout(vqd_device *d, double t_meas, const double *eps);     /* eps: n */
 int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int stage, int cap,
                              int *out_count, int *out_kinds, int *out_targets, double *out_params);

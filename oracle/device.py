@@ -38,6 +38,15 @@ Readings (the paper describes the behaviour, not a procedure):
   pair (the paper: a driven coupler gate removes it).
 * Angle scaling (App. C) multiplies a gate's active noise probabilities,
   and if asked its duration, by |theta|/pi for its first parameter theta.
+* Off-resonant driving (Sec. 3.3, used by the silicon device of Sec. 7):
+  with per-qubit Rabi frequencies Omega_q and qubit frequencies w_q (both
+  angular, per unit time), a one-qubit gate of duration t > 0 on a qubit q
+  with Omega_q > 0 drives q, and every qubit j that is passive in the batch
+  (not a target of any of its gates) receives eq. off_resonant with
+  (Omega_q, w_j - w_q, t).  These ops follow the batch's gates and active
+  noise, grouped by driving gate in input order and, within one, by
+  ascending j; they precede crosstalk and passive decay.  Several drives in
+  one batch act one after another.
 * Read-out (Sec. 8): T1 decay for the measurement time, then
   depolarising noise eps, before the projection; depolarising noise eps
   after it.  Qubits not measured idle for the measurement time (T1, T2).
@@ -63,6 +72,8 @@ class Device:
         self.static_zz: List[Tuple[int, int, float]] = []
         self.t_meas = 0.0
         self.eps = [0.0] * n
+        self.rabi: List[float] = []      # off-resonant driving: Omega_q and w_q
+        self.freq: List[float] = []
 
     def set_gate_on(self, kind: str, qubits, duration: float, p_depol: float = 0.0, p_deph: float = 0.0):
         self.gates_on[(kind, tuple(sorted(qubits)))] = (duration, p_depol, p_deph)
@@ -81,6 +92,9 @@ class Device:
 
     def set_readout(self, t_meas: float, eps: Sequence[float]):
         self.t_meas, self.eps = t_meas, list(eps)
+
+    def set_off_resonant(self, rabi: Sequence[float], freq: Sequence[float]):
+        self.rabi, self.freq = list(rabi), list(freq)
 
     def set_gate(self, kind: str, duration: float, p_depol: float = 0.0, p_deph: float = 0.0):
         self.gates[kind] = (duration, p_depol, p_deph)
@@ -153,6 +167,15 @@ def insert_noise(dev: Device, gates: Sequence) -> List[tuple]:
                 out.append(("deph1" if k == 1 else "deph2", tuple(qs), (pq,)))
             for q in qs:
                 busy[q] = d
+        if dev.rabi:
+            for i, (d, _, _) in zip(batch, spec):
+                qs = gates[i][1]
+                if len(qs) != 1 or d <= 0 or dev.rabi[qs[0]] <= 0:
+                    continue
+                q = qs[0]
+                for j in range(dev.n):
+                    if j not in busy:
+                        out.append(("offres", (j,), (dev.rabi[q], dev.freq[j] - dev.freq[q], d)))
         if pairs and dev.alpha != 0:
             for a, b in dev.edges:
                 if a not in busy and b not in busy:

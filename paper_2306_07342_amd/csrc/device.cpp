@@ -49,6 +49,7 @@ struct vqd_device {
     std::vector<double> zz_beta;
     double t_meas = 0.0;
     std::vector<double> eps;                   // read-out infidelities
+    std::vector<double> rabi, freq;            // off-resonant driving (empty: off)
 };
 
 namespace {
@@ -266,6 +267,25 @@ int vqd_device_set_static_zz(vqd_device *d, int n_edges, const int *edges, const
     return VQD_OK;
 }
 
+int vqd_device_set_off_resonant(vqd_device *d, const double *rabi, const double *freq)
+{
+    clear_error();
+    if (!d) return fail(VQD_E_ARG, "null device");
+    if (!rabi) {
+        d->rabi.clear();
+        d->freq.clear();
+        return VQD_OK;
+    }
+    if (!freq) return fail(VQD_E_ARG, "null qubit frequencies");
+    for (int q = 0; q < d->n; ++q) {
+        if (!finite_nonneg(rabi[q])) return fail(VQD_E_ARG, "Rabi frequency negative or not finite");
+        if (!std::isfinite(freq[q])) return fail(VQD_E_ARG, "qubit frequency not finite");
+    }
+    d->rabi.assign(rabi, rabi + d->n);
+    d->freq.assign(freq, freq + d->n);
+    return VQD_OK;
+}
+
 int vqd_device_set_readout(vqd_device *d, double t_meas, const double *eps)
 {
     clear_error();
@@ -334,12 +354,14 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
     std::vector<double> busy(n);
     std::vector<char> active(n);
     std::vector<std::pair<int, int>> pairs;      // two-qubit gates of the batch
+    std::vector<std::pair<int, double>> drives;  // driven one-qubit gates: (qubit, duration)
     for (const auto &batch : batches) {
         double dur = 0.0;
         bool two = false;
         std::fill(busy.begin(), busy.end(), 0.0);
         std::fill(active.begin(), active.end(), 0);
         pairs.clear();
+        drives.clear();
         for (int i : batch) {
             int nq = 0;
             kind_arity(kinds[i], &nq, nullptr);
@@ -363,11 +385,17 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
             if (pq > 0.0) emit(out, nq == 1 ? VQD_K_DEPH1 : VQD_K_DEPH2, t[0], nq > 1 ? t[1] : 0, pq);
             two = two || nq == 2;
             if (nq == 2) pairs.emplace_back(std::min(t[0], t[1]), std::max(t[0], t[1]));
+            if (nq == 1 && gd > 0.0 && !d->rabi.empty() && d->rabi[t[0]] > 0.0) drives.emplace_back(t[0], gd);
             for (int j = 0; j < nq; ++j) {
                 busy[t[j]] = gd;
                 active[t[j]] = 1;
             }
         }
+        // off-resonant driving of the batch's passive qubits (eq. off_resonant)
+        for (const auto &dv : drives)
+            for (int j = 0; j < n; ++j)
+                if (!active[j])
+                    emit(out, VQD_K_OFFRES, j, 0, d->rabi[dv.first], d->freq[j] - d->freq[dv.first], dv.second);
         if (two && d->alpha != 0.0)
             for (const auto &e : d->edges)
                 if (!active[e.first] && !active[e.second]) emit(out, VQD_K_ZZ, e.first, e.second, d->alpha);

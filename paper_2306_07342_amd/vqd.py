@@ -173,6 +173,7 @@ def load(path: str = LIB_PATH):
         "vqd_device_set_passive_forms": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "vqd_device_set_static_zz": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
         "vqd_device_set_readout": ([vp, ctypes.c_double, _dp], ctypes.c_int),
+        "vqd_device_set_off_resonant": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_device_readout_noise": ([vp, ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip, _dp],
                                      ctypes.c_int),
         "vqd_device_insert_noise": ([vp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int, _ip, _ip, _ip, _dp],
@@ -620,6 +621,16 @@ class Device:
         if b.shape[0] != e.shape[0]:
             raise ValueError("one coupling per edge")
         check(lib().vqd_device_set_static_zz(self.handle, e.shape[0], _i(e), _d(b) if b.size else None))
+
+    def set_off_resonant(self, rabi=None, freq=None):
+        """Off-resonant driving: per-qubit angular Rabi and qubit frequencies;
+        rabi None turns it off."""
+        if rabi is None:
+            check(lib().vqd_device_set_off_resonant(self.handle, None, None))
+            return
+        r = self._per_qubit(rabi, "rabi")
+        f = self._per_qubit(freq, "freq")
+        check(lib().vqd_device_set_off_resonant(self.handle, _d(r), _d(f)))
 
     def set_readout(self, t_meas: float, eps):
         a = self._per_qubit(eps, "eps")

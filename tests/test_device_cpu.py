@@ -30,6 +30,8 @@ def lib_device(vqd, ref: dv.Device):
     d.set_passive_forms(ref.t1_form, ref.t2_form)
     d.set_static_zz([(a, b) for a, b, _ in ref.static_zz], [x for _, _, x in ref.static_zz])
     d.set_readout(ref.t_meas, ref.eps)
+    if ref.rabi:
+        d.set_off_resonant(ref.rabi, ref.freq)
     return d
 
 
@@ -95,12 +97,30 @@ def test_random_devices_with_every_rule(vqd_host, seed):
     ref.set_crosstalk([(i, i + 1) for i in range(n - 1)], 0.01)
     ref.set_static_zz([(i, i + 1) for i in range(n - 1)] + [(0, n - 1)], list(rng.uniform(-0.05, 0.05, n)))
     ref.set_readout(float(rng.uniform(1, 5)), list(rng.uniform(0, 0.05, n) * (rng.random(n) < 0.7)))
+    ref.set_off_resonant(list(rng.uniform(1, 10, n) * (rng.random(n) < 0.7)), list(rng.uniform(-50, 50, n)))
     gates = random_gates(n, 80, seed)
     lib = lib_device(vqd_host, ref)
     same_stream(lib.insert_noise(gates), dv.insert_noise(ref, gates))
     for qs in ([0], [3, 1], list(range(n)), []):
         for stage in (0, 1):
             same_stream(lib.readout_noise(qs, stage), dv.readout_noise(ref, qs, stage))
+
+
+def test_off_resonant_hand_stream(vqd_host):
+    ref = dv.Device(3)
+    ref.set_gate("rx", 0.1)
+    ref.set_gate("ry", 0.3)
+    ref.set_off_resonant([2.0, 0.0, 5.0], [10.0, 13.0, 17.0])
+    gates = [("rx", (0,), (0.5,)), ("rz", (1,), (0.2,)), ("cz", (1, 2), ()), ("ry", (2,), (1.0,)),
+             ("rx", (1,), (0.3,))]
+    lib = lib_device(vqd_host, ref)
+    same_stream(lib.insert_noise(gates), dv.insert_noise(ref, gates))
+    lib.set_off_resonant(None)                      # off again: no offres ops
+    assert all(k != "offres" for k, _, _ in lib.insert_noise(gates))
+    with pytest.raises(vqd_host.VQDError):
+        lib.set_off_resonant([1.0, -1.0, 0.0], [0.0, 0.0, 0.0])
+    with pytest.raises(vqd_host.VQDError):
+        lib.set_off_resonant([1.0, 1.0, 0.0], [0.0, float("nan"), 0.0])
 
 
 def test_zz_strength(vqd_host):

@@ -198,3 +198,42 @@ def test_per_target_specifications():
     assert len(got) == len(expect), got
     for g, e in zip(got, expect):
         assert g[0] == e[0] and g[1] == e[1] and np.allclose(g[2], e[2], rtol=0, atol=1e-15), (g, e)
+
+
+def test_off_resonant_hand_stream():
+    """Sec. 3.3 by hand: a driven one-qubit gate gives every passive qubit of
+    its batch eq. off_resonant with the driver's Rabi frequency, the
+    bystander's frequency difference and the gate's duration; targets of
+    other gates in the batch, undriven qubits and gates of no duration
+    drive nothing."""
+    d = dv.Device(3)
+    d.set_gate("rx", 0.1)
+    d.set_gate("ry", 0.3)
+    d.set_off_resonant([2.0, 0.0, 5.0], [10.0, 13.0, 17.0])
+    gates = [("rx", (0,), (0.5,)), ("rz", (1,), (0.2,)),    # batch 1: 2 is passive
+             ("cz", (1, 2), ()),                             # batch 2: no drive
+             ("ry", (2,), (1.0,)),                           # batch 3: 0 is passive
+             ("rx", (1,), (0.3,))]                           # batch 3: Rabi 0 on qubit 1
+    want = [("rx", (0,), (0.5,)), ("rz", (1,), (0.2,)), ("offres", (2,), (2.0, 7.0, 0.1)),
+            ("cz", (1, 2), ()),
+            ("ry", (2,), (1.0,)), ("rx", (1,), (0.3,)), ("offres", (0,), (5.0, -7.0, 0.3))]
+    got = dv.insert_noise(d, gates)
+    assert [(k, tuple(q), tuple(p)) for k, q, p in got] == want
+
+
+@pytest.mark.parametrize("delta", [0.0, 1.5, -4.0, 40.0])
+def test_off_resonant_bystander_follows_rabi_formula(delta):
+    """A resonant pi pulse on qubit 0 (duration pi / Omega) excites a passive
+    qubit detuned by Delta with Rabi's probability
+    (Omega/W)^2 sin^2(W t / 2), W = sqrt(Omega^2 + Delta^2)."""
+    omega = 3.0
+    t = np.pi / omega
+    d = dv.Device(2)
+    d.set_gate("rx", t)
+    d.set_off_resonant([omega, 0.0], [1.0, 1.0 + delta])
+    dm = emulate(2, dv.insert_noise(d, [("rx", (0,), (np.pi,))]))
+    w = np.hypot(omega, delta)
+    p1 = dm.R[2, 2].real + dm.R[3, 3].real             # qubit 1 excited
+    assert abs(p1 - (omega / w) ** 2 * np.sin(w * t / 2) ** 2) <= 1e-14
+    p0 = dm.R[1, 1].real + dm.R[3, 3].real             # qubit 0: the pi pulse itself
+    assert abs(p0 - 1.0) <= 1e-14

@@ -61,3 +61,38 @@ def test_superconducting_preset_with_readout(gpu_lib):
     gpu_lib.Program(n, post).compile().run(dm)
     emulate(n, dv.readout_noise(ref, list(range(n)), 1), want)
     assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
+
+
+def test_off_resonant_driving_on_the_density_matrix(gpu_lib):
+    """Off-resonant driving (Sec. 3.3) with silicon-like qubit and Rabi
+    frequencies (Sec. 7 table; angular, per microsecond): x and y rotations
+    of angle-scaled duration drive the passive qubits, on the GPU against the
+    oracle, in the default and the Hermitian plan."""
+    n = 6
+    two_pi = 2 * np.pi
+    freq = [two_pi * f for f in (15.62e3, 15.88e3, 16.3e3, 16.1e3, 15.9e3, 15.69e3)]
+    ref = dv.Device(n)
+    for k in ("rx", "ry"):
+        ref.set_gate(k, 0.1, 0.0, 1e-4)
+        ref.set_angle_scaling(k, True, True)
+    ref.set_gate("cz", 0.2, 0.0, 2e-3)
+    ref.set_passive([1e4] * n, [14.0, 21.1, 40.1, 37.2, 44.7, 26.7])
+    # frequency differences divided by 100 (Omega / Delta of order 1 instead
+    # of ~0.02), so that the detuned drives move the bystanders visibly
+    ref.set_off_resonant([two_pi * 5.0] * n, [f / 100.0 for f in freq])
+    rng = np.random.default_rng(11)
+    ideal = []
+    for _ in range(60):
+        if rng.random() < 0.25:
+            a = int(rng.integers(n - 1))
+            ideal.append(("cz", (a, a + 1), ()))
+        else:
+            ideal.append((str(rng.choice(["rx", "ry"])), (int(rng.integers(n)),), (float(rng.uniform(-np.pi, np.pi)),)))
+    noisy = lib_device(gpu_lib, ref).insert_noise(ideal)
+    assert sum(1 for k, _, _ in noisy if k == "offres") > 50
+    print("off-resonant stream: %d ops" % len(noisy), flush=True)
+    want = emulate(n, dv.insert_noise(ref, ideal))
+    for opts in (None, gpu_lib.plan_opts(hermitian=True, tile_bits=8, min_contig_bits=1)):
+        dm = gpu_lib.DensityMatrix(n)
+        gpu_lib.Program(n, noisy).compile(opts).run(dm)
+        assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
