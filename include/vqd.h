@@ -165,6 +165,8 @@ enum vqd_kind {
     VQD_K_OFFRES,       /* Omega, Delta, t: the drive a bystander qubit detuned
                            by Delta receives while a neighbour is driven at
                            Rabi frequency Omega for t (eq. off_resonant)      */
+    VQD_K_CRZ,          /* alpha: |0><0| (x) I + |1><1| (x) Rz(alpha), control
+                           targets[0] (eq. weak_dephasing)                    */
     VQD_K_COUNT
 };
 
@@ -443,6 +445,17 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
  * gate in input order and then ascending j, and precede crosstalk and
  * passive decay.  VQD_E_ARG for a negative or non-finite rabi[q] or a
  * non-finite freq[q].
+ * vqd_device_set_serial: serial != 0 runs every gate in a batch of its own,
+ * in input order (Sec. 7), instead of the as-soon-as-possible batches.
+ * vqd_device_set_exchange_crosstalk: residual exchange on the edges
+ * (edges[2e], edges[2e+1]), as the conditional Z rotation of eq.
+ * weak_dephasing (VQD_K_CRZ, control edges[2e]) on edges whose two qubits
+ * no gate of the batch targets (Sec. 7).  While a two-qubit gate on edge i
+ * runs, edge j != i receives crz(on[i * n_edges + j] * theta / pi), theta
+ * the gate's first parameter (pi for a kind without parameters); a batch
+ * with no two-qubit gate gives edge j crz(off[j]).  Zero values emit
+ * nothing; these ops follow the off-resonant ones.  n_edges = 0 turns the
+ * model off.  VQD_E_ARG for a bad or repeated edge or a non-finite value.
  *
  * vqd_device_set_readout / vqd_device_readout_noise: the read-out model of
  * Sec. 8, T1 decay for the measurement time t_meas, then depolarising
@@ -470,6 +483,9 @@ int vqd_device_set_passive_forms(vqd_device *d, int t1_kind, int t2_kind);
 int vqd_device_set_crosstalk(vqd_device *d, int n_edges, const int *edges, double alpha);
 int vqd_device_set_static_zz(vqd_device *d, int n_edges, const int *edges, const double *beta);
 int vqd_device_set_off_resonant(vqd_device *d, const double *rabi, const double *freq);  /* n each */
+int vqd_device_set_serial(vqd_device *d, int serial);
+int vqd_device_set_exchange_crosstalk(vqd_device *d, int n_edges, const int *edges, const double *on,
+                                      const double *off);    /* on: n_edges^2 (row: active edge), off: n_edges */
 int vqd_device_set_readout(vqd_device *d, double t_meas, const double *eps);     /* eps: n */
 int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int stage, int cap,
                              int *out_count, int *out_kinds, int *out_targets, double *out_params);
@@ -494,10 +510,21 @@ int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int
  * 0.1 : 0.9, 5 us; T1 amplitude damping and Gaussian T2* dephasing
  * (3e9 us, 1e6 us).  p0 receives the initialisation fidelity 0.9999.
  *
+ * VQD_PRESET_SILICON (Sec. 7, table conf:silicon), 6 qubits in a line,
+ * serial: Rx, Ry (and H, X, Y as pi rotations) with per-qubit pure
+ * dephasing from the tabulated fidelities (x = 0), 0.1 us per pi, Rx and Ry
+ * scaled by |theta| / pi, driving the other qubits off resonance (Rabi
+ * frequency 2 pi 5 MHz, qubit frequencies 2 pi x the table's); CZ and CPhase
+ * (scaled by |theta| / pi) on the pairs (q, q+1) with two-qubit dephasing
+ * from the per-pair fidelities and 1 / (2 x the pair's gate frequency);
+ * exchange crosstalk with the tabulated on-matrix and off-values on those
+ * pairs; depolarising T1 decay (1e4 us) and per-qubit T2 dephasing.  p0
+ * receives 1.  The parity read-out is not part of it.
+ *
  * vqd_device_preset creates *out (destroy with vqd_device_destroy); p0 is
  * NULL or holds vqd_device_preset_qubits(preset) doubles.  VQD_E_ARG for an
  * unknown preset. */
-enum vqd_preset { VQD_PRESET_SUPERCONDUCTING = 1, VQD_PRESET_TRAPPED_ION = 2 };
+enum vqd_preset { VQD_PRESET_SUPERCONDUCTING = 1, VQD_PRESET_TRAPPED_ION = 2, VQD_PRESET_SILICON = 3 };
 int vqd_device_preset(int preset, vqd_device **out, double *p0);
 int vqd_device_preset_qubits(int preset, int *n);
 int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, const int *targets,

@@ -71,6 +71,11 @@ def gate_matrix(kind, params):
     if kind == "zz":
         # ZZ crosstalk exp(-i alpha Z_p Z_q), eq. (weak_dephasing_zz) of Sec. 3.4
         return expm(-1j * params[0] * on2(Z, Z))
+    if kind == "crz":
+        # eq. (weak_dephasing): the target (qubits[1]) turns by Rz(alpha) where
+        # the control (qubits[0], the low index bit) is 1
+        a = params[0]
+        return np.diag([1, np.exp(-0.5j * a), 1, np.exp(0.5j * a)]).astype(np.complex128)
     if kind == "rabi":
         return rabi_u(*params)
     if kind == "offres":

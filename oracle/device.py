@@ -47,6 +47,15 @@ Readings (the paper describes the behaviour, not a procedure):
   noise, grouped by driving gate in input order and, within one, by
   ascending j; they precede crosstalk and passive decay.  Several drives in
   one batch act one after another.
+* Serial devices (Sec. 7): every gate forms a batch of its own, in input
+  order.
+* Exchange crosstalk (Sec. 7) on listed edges (c, t): the conditional Z
+  rotation of eq. weak_dephasing, control c, on edges whose two qubits are
+  passive in the batch.  A two-qubit gate of angle theta (its first
+  parameter, pi for a gate without one) on listed edge i gives every other
+  edge j crz(on[i][j] theta / pi), by gate in input order and then by edge;
+  a batch without two-qubit gates gives edge j crz(off[j]).  Zero angles are
+  left out.  These ops follow the off-resonant ones.
 * Read-out (Sec. 8): T1 decay for the measurement time, then
   depolarising noise eps, before the projection; depolarising noise eps
   after it.  Qubits not measured idle for the measurement time (T1, T2).
@@ -74,6 +83,10 @@ class Device:
         self.eps = [0.0] * n
         self.rabi: List[float] = []      # off-resonant driving: Omega_q and w_q
         self.freq: List[float] = []
+        self.serial = False
+        self.xe_edges: List[Tuple[int, int]] = []   # exchange crosstalk
+        self.xe_on: List[List[float]] = []
+        self.xe_off: List[float] = []
 
     def set_gate_on(self, kind: str, qubits, duration: float, p_depol: float = 0.0, p_deph: float = 0.0):
         self.gates_on[(kind, tuple(sorted(qubits)))] = (duration, p_depol, p_deph)
@@ -92,6 +105,14 @@ class Device:
 
     def set_readout(self, t_meas: float, eps: Sequence[float]):
         self.t_meas, self.eps = t_meas, list(eps)
+
+    def set_serial(self, serial: bool = True):
+        self.serial = bool(serial)
+
+    def set_exchange_crosstalk(self, edges, on, off):
+        self.xe_edges = [tuple(int(x) for x in e) for e in edges]
+        self.xe_on = [list(r) for r in on]
+        self.xe_off = list(off)
 
     def set_off_resonant(self, rabi: Sequence[float], freq: Sequence[float]):
         self.rabi, self.freq = list(rabi), list(freq)
@@ -138,7 +159,8 @@ def _t2(dev: Device, q: int, dt: float) -> List[tuple]:
 
 def insert_noise(dev: Device, gates: Sequence) -> List[tuple]:
     out: List[tuple] = []
-    for batch in schedule(dev.n, gates):
+    batches = [[i] for i in range(len(gates))] if dev.serial else schedule(dev.n, gates)
+    for batch in batches:
         spec = []
         for i in batch:
             kind, qs, params = gates[i]
@@ -176,6 +198,22 @@ def insert_noise(dev: Device, gates: Sequence) -> List[tuple]:
                 for j in range(dev.n):
                     if j not in busy:
                         out.append(("offres", (j,), (dev.rabi[q], dev.freq[j] - dev.freq[q], d)))
+        def passive_edge(e):
+            return e[0] not in busy and e[1] not in busy
+        for i in batch:
+            kind, qs, params = gates[i]
+            if len(qs) != 2 or frozenset(qs) not in [frozenset(e) for e in dev.xe_edges]:
+                continue
+            a = [frozenset(e) for e in dev.xe_edges].index(frozenset(qs))
+            theta = params[0] if params else math.pi
+            for j, e in enumerate(dev.xe_edges):
+                alpha = dev.xe_on[a][j] * theta / math.pi
+                if j != a and alpha != 0 and passive_edge(e):
+                    out.append(("crz", e, (alpha,)))
+        if not pairs:
+            for j, e in enumerate(dev.xe_edges):
+                if dev.xe_off[j] != 0 and passive_edge(e):
+                    out.append(("crz", e, (dev.xe_off[j],)))
         if pairs and dev.alpha != 0:
             for a, b in dev.edges:
                 if a not in busy and b not in busy:

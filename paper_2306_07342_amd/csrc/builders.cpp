@@ -202,6 +202,7 @@ void canonical_params(int kind, double *p)
     case VQD_K_RABI: p[0] = 5.0; p[1] = 0.4; p[2] = 1.3; p[3] = 0.21; break;
     case VQD_K_OFFRES: p[0] = 5.0; p[1] = 2.7; p[2] = 0.21; break;
     case VQD_K_RX: case VQD_K_RY: case VQD_K_RZ: case VQD_K_CPHASE: case VQD_K_XX: case VQD_K_ZZ:
+    case VQD_K_CRZ:
         p[0] = 0.7371; break;
     default: p[0] = 0.0123; break;        // channel probabilities
     }
@@ -210,9 +211,9 @@ void canonical_params(int kind, double *p)
 int kind_arity(int kind, int *nq, int *np)
 {
     static const int Q[VQD_K_COUNT] = {0, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2,
-                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 1};
+                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 1, 2};
     static const int P[VQD_K_COUNT] = {0, 1, 1, 1, 0, 0, 0, 0, 4, 0, 1, 1, 1,
-                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2, 3, 4, 3};
+                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2, 3, 4, 3, 1};
     if (kind <= 0 || kind >= VQD_K_COUNT) return -1;
     if (nq) *nq = Q[kind];
     if (np) *np = P[kind];
@@ -281,6 +282,10 @@ int kind_matrix(int kind, const double *p, std::vector<cd> &U, int &k)
         }
         break;
     }
+    case VQD_K_CRZ:
+        // index b(control) + 2 b(target): the target's Rz acts where the control is 1
+        U[0] = 1; U[5] = std::exp(-I * (p[0] / 2)); U[10] = 1; U[15] = std::exp(I * (p[0] / 2));
+        break;
     case VQD_K_RABI:
         return rabi(p[0], p[1], p[2], p[3], false, U);
     case VQD_K_OFFRES:

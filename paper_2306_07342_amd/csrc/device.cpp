@@ -50,6 +50,9 @@ struct vqd_device {
     double t_meas = 0.0;
     std::vector<double> eps;                   // read-out infidelities
     std::vector<double> rabi, freq;            // off-resonant driving (empty: off)
+    bool serial = false;                       // one gate per batch
+    std::vector<std::pair<int, int>> xe_edges; // exchange crosstalk: edges,
+    std::vector<double> xe_on, xe_off;         // on[i * m + j], off[j]
 };
 
 namespace {
@@ -286,6 +289,41 @@ int vqd_device_set_off_resonant(vqd_device *d, const double *rabi, const double 
     return VQD_OK;
 }
 
+int vqd_device_set_serial(vqd_device *d, int serial)
+{
+    clear_error();
+    if (!d) return fail(VQD_E_ARG, "null device");
+    d->serial = serial != 0;
+    return VQD_OK;
+}
+
+int vqd_device_set_exchange_crosstalk(vqd_device *d, int n_edges, const int *edges, const double *on,
+                                      const double *off)
+{
+    clear_error();
+    if (!d) return fail(VQD_E_ARG, "null device");
+    if (n_edges < 0 || (n_edges > 0 && (!edges || !on || !off))) return fail(VQD_E_ARG, "bad edge arrays");
+    std::vector<std::pair<int, int>> e;
+    for (int i = 0; i < n_edges; ++i) {
+        if (int rc = check_targets(d->n, 2, edges + 2 * (size_t)i)) return rc;
+        const std::pair<int, int> k(std::min(edges[2 * i], edges[2 * i + 1]),
+                                    std::max(edges[2 * i], edges[2 * i + 1]));
+        for (const auto &x : e)
+            if (std::min(x.first, x.second) == k.first && std::max(x.first, x.second) == k.second)
+                return fail(VQD_E_ARG, "repeated edge");
+        e.emplace_back(edges[2 * i], edges[2 * i + 1]);
+    }
+    const size_t m = (size_t)n_edges;
+    for (size_t i = 0; i < m * m; ++i)
+        if (!std::isfinite(on[i])) return fail(VQD_E_ARG, "exchange crosstalk not finite");
+    for (size_t i = 0; i < m; ++i)
+        if (!std::isfinite(off[i])) return fail(VQD_E_ARG, "exchange crosstalk not finite");
+    d->xe_edges = std::move(e);
+    d->xe_on.assign(on, on + m * m);
+    d->xe_off.assign(off, off + m);
+    return VQD_OK;
+}
+
 int vqd_device_set_readout(vqd_device *d, double t_meas, const double *eps)
 {
     clear_error();
@@ -341,7 +379,7 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
         if (kind_arity(kinds[i], &nq, &np) != 0 || kind_is_channel(kinds[i]))
             return fail(VQD_E_ARG, "gate " + std::to_string(i) + ": not a gate kind");
         if (int rc = check_targets(n, nq, targets + 4 * (size_t)i)) return rc;
-        int b = 0;
+        int b = d->serial ? i : 0;
         for (int j = 0; j < nq; ++j) b = std::max(b, last[targets[4 * (size_t)i + j]] + 1);
         for (int j = 0; j < nq; ++j) last[targets[4 * (size_t)i + j]] = b;
         batch_of[i] = b;
@@ -355,6 +393,8 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
     std::vector<char> active(n);
     std::vector<std::pair<int, int>> pairs;      // two-qubit gates of the batch
     std::vector<std::pair<int, double>> drives;  // driven one-qubit gates: (qubit, duration)
+    std::vector<std::pair<int, double>> xon;     // two-qubit gates on crosstalk edges: (edge, theta)
+    const int m = (int)d->xe_edges.size();
     for (const auto &batch : batches) {
         double dur = 0.0;
         bool two = false;
@@ -362,6 +402,7 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
         std::fill(active.begin(), active.end(), 0);
         pairs.clear();
         drives.clear();
+        xon.clear();
         for (int i : batch) {
             int nq = 0;
             kind_arity(kinds[i], &nq, nullptr);
@@ -384,7 +425,17 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
             if (pd > 0.0) emit(out, nq == 1 ? VQD_K_DEPOL1 : VQD_K_DEPOL2, t[0], nq > 1 ? t[1] : 0, pd);
             if (pq > 0.0) emit(out, nq == 1 ? VQD_K_DEPH1 : VQD_K_DEPH2, t[0], nq > 1 ? t[1] : 0, pq);
             two = two || nq == 2;
-            if (nq == 2) pairs.emplace_back(std::min(t[0], t[1]), std::max(t[0], t[1]));
+            if (nq == 2) {
+                pairs.emplace_back(std::min(t[0], t[1]), std::max(t[0], t[1]));
+                int np = 0;
+                kind_arity(kinds[i], nullptr, &np);
+                for (int e = 0; e < m; ++e) {
+                    const auto &x = d->xe_edges[e];
+                    if (std::min(x.first, x.second) == pairs.back().first &&
+                        std::max(x.first, x.second) == pairs.back().second)
+                        xon.emplace_back(e, np > 0 ? par[0] : 3.14159265358979323846);
+                }
+            }
             if (nq == 1 && gd > 0.0 && !d->rabi.empty() && d->rabi[t[0]] > 0.0) drives.emplace_back(t[0], gd);
             for (int j = 0; j < nq; ++j) {
                 busy[t[j]] = gd;
@@ -396,6 +447,20 @@ int vqd_device_insert_noise(const vqd_device *d, int count, const int *kinds, co
             for (int j = 0; j < n; ++j)
                 if (!active[j])
                     emit(out, VQD_K_OFFRES, j, 0, d->rabi[dv.first], d->freq[j] - d->freq[dv.first], dv.second);
+        // residual exchange on passive edges (eq. weak_dephasing)
+        auto passive_edge = [&](int e) {
+            return !active[d->xe_edges[e].first] && !active[d->xe_edges[e].second];
+        };
+        for (const auto &g : xon)
+            for (int e = 0; e < m; ++e) {
+                const double a = d->xe_on[(size_t)g.first * m + e] * g.second / 3.14159265358979323846;
+                if (e != g.first && a != 0.0 && passive_edge(e))
+                    emit(out, VQD_K_CRZ, d->xe_edges[e].first, d->xe_edges[e].second, a);
+            }
+        if (!two)
+            for (int e = 0; e < m; ++e)
+                if (d->xe_off[e] != 0.0 && passive_edge(e))
+                    emit(out, VQD_K_CRZ, d->xe_edges[e].first, d->xe_edges[e].second, d->xe_off[e]);
         if (two && d->alpha != 0.0)
             for (const auto &e : d->edges)
                 if (!active[e.first] && !active[e.second]) emit(out, VQD_K_ZZ, e.first, e.second, d->alpha);

@@ -23,6 +23,19 @@
 // the reported fidelity split 0.1 : 0.9 into depolarising and dephasing
 // noise, duration 1 / (2 x its gate frequency).  Ion transport, remote
 // entanglement and the ions' bit-flip read-out are not part of the preset.
+//
+// Silicon (Sec. 7, table conf:silicon): six spin qubits in a line, gates run
+// one at a time.  x and y rotations: pure dephasing from the per-qubit
+// fidelity (error ratio 0:1), 1 / (2 x Rabi frequency) per pi, noise and
+// duration scaled by |theta| / pi; they drive the other qubits off
+// resonance (eq. off_resonant) with the 5 MHz Rabi frequency and the qubit
+// frequencies of the table.  CZ (and CPhase, scaled by |theta| / pi) on the
+// five neighbouring pairs: two-qubit dephasing from the per-pair fidelity,
+// 1 / (2 x the pair's gate frequency).  Residual exchange on passive
+// neighbouring pairs as conditional Z rotations (eq. weak_dephasing): the
+// ExchangeRotOn matrix while a CZ or CPhase runs, ExchangeRotOff otherwise.
+// Passive noise: depolarising T1 decay (eq. depolt1) and T2 dephasing.  The
+// parity read-out of the edge pairs is not part of the preset.
 #include <cmath>
 #include <string>
 
@@ -120,6 +133,65 @@ int trapped_ion(vqd_device **out, double *p0)
     return VQD_OK;
 }
 
+int silicon(vqd_device **out, double *p0)
+{
+    constexpr int n = 6, np = n - 1;
+    const double T1 = 1e4;
+    const double T2[n] = {14, 21.1, 40.1, 37.2, 44.7, 26.7};
+    const double qfreq[n] = {15.62e3, 15.88e3, 16.3e3, 16.1e3, 15.9e3, 15.69e3};
+    const double rabi = 5.0;
+    const double fid_xy[n] = {0.9977, 0.9987, 0.9996, 0.9988, 0.9991, 0.9989};
+    const double freq_cz[np] = {12.1, 11.1, 6.6, 9.8, 5.4};
+    const double fid_cz[np] = {0.937, 0.934, 0.929, 0.997, 0.979};
+    const double rot_on[np * np] = {0, 0.023, 0.018, 0.03, 0.04,
+                                    0.05, 0, 0.03, 0.03, 0.04,
+                                    0.05, 0.03, 0, 0.07, 0.042,
+                                    0.038, 0.03, 0.031, 0, 0.25,
+                                    0.033, 0.03, 0.02, 0.03, 0};
+    const double rot_off[np] = {0.039, 0.015, 0.03, 0.02, 0.028};
+
+    vqd_device *d = nullptr;
+    if (int rc = vqd_device_create(n, &d)) return rc;
+    double t1[n], w_rabi[n], w_q[n];
+    int edges[2 * np];
+    for (int q = 0; q < n; ++q) {
+        t1[q] = T1;
+        w_rabi[q] = kTwoPi * rabi;
+        w_q[q] = kTwoPi * qfreq[q];
+    }
+    const double t_pi = 1.0 / (2.0 * rabi);
+    int rc = VQD_OK;
+    for (int q = 0; q < n && !rc; ++q) {
+        double pd = 0, pq = 0;
+        rc = vqd_fidelity_to_errors(1, fid_xy[q], 0.0, &pd, &pq);
+        for (int k : {VQD_K_RX, VQD_K_RY, VQD_K_H, VQD_K_X, VQD_K_Y})
+            if (!rc) rc = vqd_device_set_gate_on(d, k, 1, &q, t_pi, pd, pq);
+    }
+    for (int k : {VQD_K_RX, VQD_K_RY, VQD_K_CPHASE})
+        if (!rc) rc = vqd_device_set_angle_scaling(d, k, 1, 1);
+    for (int e = 0; e < np && !rc; ++e) {
+        edges[2 * e] = e;
+        edges[2 * e + 1] = e + 1;
+        double pd = 0, pq = 0;
+        rc = vqd_fidelity_to_errors(2, fid_cz[e], 0.0, &pd, &pq);
+        for (int k : {VQD_K_CZ, VQD_K_CPHASE})
+            if (!rc) rc = vqd_device_set_gate_on(d, k, 2, edges + 2 * e, 1.0 / (2.0 * freq_cz[e]), pd, pq);
+    }
+    if (!rc) rc = vqd_device_set_passive(d, t1, T2);
+    if (!rc) rc = vqd_device_set_passive_forms(d, VQD_K_DEPOL_T1, VQD_K_DEPH_T2);
+    if (!rc) rc = vqd_device_set_off_resonant(d, w_rabi, w_q);
+    if (!rc) rc = vqd_device_set_exchange_crosstalk(d, np, edges, rot_on, rot_off);
+    if (!rc) rc = vqd_device_set_serial(d, 1);
+    if (rc) {
+        vqd_device_destroy(d);
+        return rc;
+    }
+    if (p0)
+        for (int q = 0; q < n; ++q) p0[q] = 1.0;
+    *out = d;
+    return VQD_OK;
+}
+
 }  // namespace
 
 using namespace vqd;
@@ -135,6 +207,7 @@ int vqd_device_preset(int preset, vqd_device **out, double *p0)
     switch (preset) {
     case VQD_PRESET_SUPERCONDUCTING: rc = superconducting(out, p0); break;
     case VQD_PRESET_TRAPPED_ION: rc = trapped_ion(out, p0); break;
+    case VQD_PRESET_SILICON: rc = silicon(out, p0); break;
     default: return fail(VQD_E_ARG, "unknown preset " + std::to_string(preset));
     }
     return rc;
@@ -147,6 +220,7 @@ int vqd_device_preset_qubits(int preset, int *n)
     switch (preset) {
     case VQD_PRESET_SUPERCONDUCTING: *n = 6; return VQD_OK;
     case VQD_PRESET_TRAPPED_ION: *n = 8; return VQD_OK;
+    case VQD_PRESET_SILICON: *n = 6; return VQD_OK;
     default: return fail(VQD_E_ARG, "unknown preset " + std::to_string(preset));
     }
 }

@@ -23,7 +23,7 @@ KINDS = {
     "cz": 9, "cphase": 10, "xx": 11, "zz": 12,
     "depol1": 13, "depol2": 14, "deph1": 15, "deph2": 16, "amp": 17, "gamp": 18,
     "bitflip1": 19, "bitflip2": 20, "amp_t1": 21, "deph_t2": 22, "deph_t2s": 23, "depol_t1": 24,
-    "gamp_t1": 25, "rabi": 26, "offres": 27,
+    "gamp_t1": 25, "rabi": 26, "offres": 27, "crz": 28,
 }
 BLOCK_UNITARY = 0
 BLOCK_SUPEROP = 1
@@ -174,6 +174,8 @@ def load(path: str = LIB_PATH):
         "vqd_device_set_static_zz": ([vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
         "vqd_device_set_readout": ([vp, ctypes.c_double, _dp], ctypes.c_int),
         "vqd_device_set_off_resonant": ([vp, _dp, _dp], ctypes.c_int),
+        "vqd_device_set_serial": ([vp, ctypes.c_int], ctypes.c_int),
+        "vqd_device_set_exchange_crosstalk": ([vp, ctypes.c_int, _ip, _dp, _dp], ctypes.c_int),
         "vqd_device_readout_noise": ([vp, ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip, _dp],
                                      ctypes.c_int),
         "vqd_device_insert_noise": ([vp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int, _ip, _ip, _ip, _dp],
@@ -542,7 +544,7 @@ class Program:
 KIND_NAMES = {v: k for k, v in KINDS.items()}
 
 
-PRESETS = {"superconducting": 1, "trapped_ion": 2}
+PRESETS = {"superconducting": 1, "trapped_ion": 2, "silicon": 3}
 
 
 class Device:
@@ -631,6 +633,21 @@ class Device:
         r = self._per_qubit(rabi, "rabi")
         f = self._per_qubit(freq, "freq")
         check(lib().vqd_device_set_off_resonant(self.handle, _d(r), _d(f)))
+
+    def set_serial(self, serial: bool = True):
+        check(lib().vqd_device_set_serial(self.handle, int(bool(serial))))
+
+    def set_exchange_crosstalk(self, edges, on, off):
+        """Residual exchange on `edges`: `on` (one row per active edge) while
+        a two-qubit gate runs, `off` otherwise."""
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        m = e.shape[0]
+        a = np.ascontiguousarray(on, dtype=np.float64).reshape(-1)
+        b = np.ascontiguousarray(off, dtype=np.float64).reshape(-1)
+        if a.size != m * m or b.size != m:
+            raise ValueError("on needs n_edges^2 values and off n_edges")
+        check(lib().vqd_device_set_exchange_crosstalk(self.handle, m, _i(e) if m else None,
+                                                      _d(a) if m else None, _d(b) if m else None))
 
     def set_readout(self, t_meas: float, eps):
         a = self._per_qubit(eps, "eps")

@@ -96,7 +96,8 @@ def test_channel_superops_match_oracle_kraus(vqd_host, kind, params):
     ("rx", (0.7,)), ("ry", (1.9,)), ("rz", (2.5,)), ("h", ()), ("x", ()), ("y", ()), ("z", ()),
     ("su2", (0.3, -1.1, 0.4, 2.0)), ("cz", ()), ("cphase", (0.6,)), ("xx", (1.1,)), ("zz", (0.01,)),
     ("rabi", (1.7, 0.9, -0.6, 1.3)), ("rabi", (0.0, 0.3, 0.0, 2.0)), ("rabi", (5.0, -2.2, 3.1, 0.21)),
-    ("offres", (1.0, 2.0, 0.7)), ("offres", (0.0, 7.0, 0.11)), ("offres", (0.3, 40.0, 1.9))])
+    ("offres", (1.0, 2.0, 0.7)), ("offres", (0.0, 7.0, 0.11)), ("offres", (0.3, 40.0, 1.9)),
+    ("crz", (0.45,)), ("crz", (-2.8,))])
 def test_gate_matrices_match_oracle(vqd_host, kind, params):
     U = vqd_host.kind_matrix(kind, params)
     assert np.abs(U - och.gate_matrix(kind, params)).max() < 1e-14

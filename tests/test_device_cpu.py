@@ -32,6 +32,9 @@ def lib_device(vqd, ref: dv.Device):
     d.set_readout(ref.t_meas, ref.eps)
     if ref.rabi:
         d.set_off_resonant(ref.rabi, ref.freq)
+    d.set_serial(ref.serial)
+    if ref.xe_edges:
+        d.set_exchange_crosstalk(ref.xe_edges, ref.xe_on, ref.xe_off)
     return d
 
 
@@ -98,6 +101,10 @@ def test_random_devices_with_every_rule(vqd_host, seed):
     ref.set_static_zz([(i, i + 1) for i in range(n - 1)] + [(0, n - 1)], list(rng.uniform(-0.05, 0.05, n)))
     ref.set_readout(float(rng.uniform(1, 5)), list(rng.uniform(0, 0.05, n) * (rng.random(n) < 0.7)))
     ref.set_off_resonant(list(rng.uniform(1, 10, n) * (rng.random(n) < 0.7)), list(rng.uniform(-50, 50, n)))
+    xe = [(i + 1, i) if rng.random() < 0.5 else (i, i + 1) for i in range(n - 1)] + [(0, 2)]
+    ref.set_exchange_crosstalk(xe, rng.uniform(0, 0.1, (len(xe), len(xe))) * (rng.random((len(xe), len(xe))) < 0.7),
+                               rng.uniform(0, 0.05, len(xe)) * (rng.random(len(xe)) < 0.7))
+    ref.set_serial(seed % 2 == 0)
     gates = random_gates(n, 80, seed)
     lib = lib_device(vqd_host, ref)
     same_stream(lib.insert_noise(gates), dv.insert_noise(ref, gates))
@@ -121,6 +128,13 @@ def test_off_resonant_hand_stream(vqd_host):
         lib.set_off_resonant([1.0, -1.0, 0.0], [0.0, 0.0, 0.0])
     with pytest.raises(vqd_host.VQDError):
         lib.set_off_resonant([1.0, 1.0, 0.0], [0.0, float("nan"), 0.0])
+    with pytest.raises(vqd_host.VQDError):
+        lib.set_exchange_crosstalk([(0, 1), (1, 0)], np.zeros((2, 2)), [0.0, 0.0])     # repeated edge
+    with pytest.raises(vqd_host.VQDError):
+        lib.set_exchange_crosstalk([(0, 3)], [[0.0]], [0.0])                         # no qubit 3
+    with pytest.raises(vqd_host.VQDError):
+        lib.set_exchange_crosstalk([(0, 1)], [[float("inf")]], [0.0])
+    lib.set_exchange_crosstalk([], [], [])                                           # off
 
 
 def test_zz_strength(vqd_host):

@@ -237,3 +237,52 @@ def test_off_resonant_bystander_follows_rabi_formula(delta):
     assert abs(p1 - (omega / w) ** 2 * np.sin(w * t / 2) ** 2) <= 1e-14
     p0 = dm.R[1, 1].real + dm.R[3, 3].real             # qubit 0: the pi pulse itself
     assert abs(p0 - 1.0) <= 1e-14
+
+
+@pytest.mark.parametrize("alpha", [0.3, -1.7, 2.9])
+def test_crz_is_a_target_rotation_and_a_zz_phase(alpha):
+    """eq. (weak_dephasing) against two independent forms: the projector sum
+    |0><0| (x) I + |1><1| (x) exp(-i alpha Z / 2) built with scipy's expm,
+    and the product Rz_t(alpha / 2) exp(+i alpha/4 Z(x)Z) of the two
+    crosstalk forms of Sec. 3.4."""
+    from scipy.linalg import expm
+    from oracle import channels as ch
+    P0, P1 = np.diag([1.0, 0.0]), np.diag([0.0, 1.0])
+    want = np.kron(np.eye(2), P0) + np.kron(expm(-0.5j * alpha * ch.Z), P1)   # control = low bit
+    U = ch.gate_matrix("crz", (alpha,))
+    assert np.abs(U - want).max() < 1e-15
+    rz_t = np.kron(ch.gate_matrix("rz", (alpha / 2,)), np.eye(2))
+    assert np.abs(U - rz_t @ ch.gate_matrix("zz", (-alpha / 4,))).max() < 1e-15
+
+
+def test_serial_device_runs_one_gate_per_batch():
+    """Two gates on different qubits share a batch as soon as possible, and
+    run one after another on a serial device: the idle qubit then waits for
+    each of them."""
+    d = dv.Device(2)
+    d.set_gate("x", 0.5)
+    d.set_passive([0.0, 0.0], [10.0, 10.0])
+    gates = [("x", (0,), ()), ("x", (1,), ())]
+    assert [k for k, _, _ in dv.insert_noise(d, gates)] == ["x", "x"]
+    d.set_serial(True)
+    want = [("x", (0,), ()), ("deph_t2", (1,), (0.5, 10.0)), ("x", (1,), ()), ("deph_t2", (0,), (0.5, 10.0))]
+    assert [(k, tuple(q), tuple(p)) for k, q, p in dv.insert_noise(d, gates)] == want
+
+
+def test_exchange_crosstalk_hand_stream():
+    """Sec. 7 by hand on a line of four qubits, edges (0,1), (1,2), (2,3):
+    a CPhase(theta) on edge 0 turns the passive edge 2 by on[0][2] theta/pi
+    (edge 1 touches an active qubit); a batch of one-qubit gates gives every
+    passive edge its off value; zero entries emit nothing."""
+    d = dv.Device(4)
+    d.set_serial(True)
+    on = [[0.0, 0.1, 0.2], [0.3, 0.0, 0.0], [0.5, 0.6, 0.0]]
+    d.set_exchange_crosstalk([(0, 1), (1, 2), (3, 2)], on, [0.01, 0.0, 0.03])
+    gates = [("cphase", (1, 0), (np.pi / 2,)), ("rx", (0,), (0.4,)), ("cz", (2, 3), ())]
+    want = [("cphase", (1, 0), (np.pi / 2,)), ("crz", (3, 2), (0.1,)),
+            ("rx", (0,), (0.4,)), ("crz", (3, 2), (0.03,)),
+            ("cz", (2, 3), ()), ("crz", (0, 1), (0.5,))]
+    got = [(k, tuple(q), tuple(p)) for k, q, p in dv.insert_noise(d, gates)]
+    assert len(got) == len(want)
+    for g, w in zip(got, want):
+        assert g[:2] == w[:2] and np.allclose(g[2], w[2], rtol=0, atol=1e-15), (g, w)

@@ -96,3 +96,20 @@ def test_off_resonant_driving_on_the_density_matrix(gpu_lib):
         dm = gpu_lib.DensityMatrix(n)
         gpu_lib.Program(n, noisy).compile(opts).run(dm)
         assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
+
+
+def test_silicon_preset_on_the_density_matrix(gpu_lib):
+    """The silicon preset (serial gates, off-resonant driving, exchange
+    crosstalk, per-qubit and per-pair dephasing) on the GPU against the
+    oracle's device built from the printed table."""
+    from tests.test_presets import oracle_silicon, si_gates
+    n = 6
+    lib, _ = gpu_lib.Device.preset("silicon")
+    ref, _ = oracle_silicon()
+    ideal = si_gates(n, 80, 21)
+    noisy = lib.insert_noise(ideal)
+    print("silicon stream: %d ops" % len(noisy), flush=True)
+    dm = gpu_lib.DensityMatrix(n)
+    gpu_lib.Program(n, noisy).compile().run(dm)
+    want = emulate(n, dv.insert_noise(ref, ideal))
+    assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10

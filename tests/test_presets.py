@@ -58,6 +58,47 @@ def oracle_trapped_ion():
     return d, [t["FidInit"]] * n
 
 
+def oracle_silicon():
+    t = TABLES["silicon"]
+    n = t["QubitNum"]
+    d = dv.Device(n)
+    x1 = t["EFSingleXY"][0] / sum(t["EFSingleXY"])
+    x2 = t["EFCZ"][0] / sum(t["EFCZ"])
+    for q in range(n):
+        p, s = severity(t["FidSingleXY"][q], 1, x1)
+        for k in ("rx", "ry", "h", "x", "y"):
+            d.set_gate_on(k, (q,), 1 / (2 * t["RabiFreq"][q]), p, s)
+    for k in ("rx", "ry", "cphase"):
+        d.set_angle_scaling(k, noise=True, duration=True)
+    edges = [(q, q + 1) for q in range(n - 1)]
+    for e, (a, b) in enumerate(edges):
+        p, s = severity(t["FidCZ"][e], 2, x2)
+        for k in ("cz", "cphase"):
+            d.set_gate_on(k, (a, b), 1 / (2 * t["FreqCZ"][e]), p, s)
+    d.set_passive([t["T1"]] * n, t["T2"])
+    d.set_passive_forms("depol_t1", "deph_t2")
+    d.set_off_resonant([2 * math.pi * f for f in t["RabiFreq"]], [2 * math.pi * f for f in t["QubitFreq"]])
+    d.set_exchange_crosstalk(edges, t["ExchangeRotOn"], t["ExchangeRotOff"])
+    d.set_serial(True)
+    return d, [1.0] * n
+
+
+def si_gates(n, count, seed):
+    """x and y rotations, Hadamards, CZ and CPhase on the line of spins."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        k = int(rng.integers(0, 5))
+        if k < 2:
+            out.append((("rx", "ry")[k], (int(rng.integers(n)),), (float(rng.uniform(-3, 3)),)))
+        elif k == 2:
+            out.append(("h", (int(rng.integers(n)),), ()))
+        else:
+            a = int(rng.integers(n - 1))
+            out.append(("cz", (a, a + 1), ()) if k == 3 else ("cphase", (a + 1, a), (float(rng.uniform(-3, 3)),)))
+    return out
+
+
 def close_stream(a, b, tol):
     assert len(a) == len(b)
     for x, y in zip(a, b):
@@ -106,6 +147,18 @@ def test_trapped_ion_preset(vqd_host):
     close_stream(lib.insert_noise(gates), dv.insert_noise(ref, gates), 1e-9)
 
 
+def test_silicon_preset(vqd_host):
+    lib, p0 = vqd_host.Device.preset("silicon")
+    ref, rp0 = oracle_silicon()
+    assert lib.n == ref.n == 6
+    assert np.abs(p0 - rp0).max() == 0
+    gates = si_gates(6, 60, 13)
+    got = lib.insert_noise(gates)
+    close_stream(got, dv.insert_noise(ref, gates), 1e-9)
+    kinds = {k for k, _, _ in got}
+    assert {"offres", "crz", "deph1", "deph2", "depol_t1", "deph_t2"} <= kinds and "depol1" not in kinds
+
+
 def test_superconducting_coupling_values():
     """Spot values of the Sec. 8 formula on the tabulated pair (Q0, Q1):
     J = 4, Delta = -400, alpha = 296.7 and 298.6 MHz."""
@@ -116,7 +169,7 @@ def test_superconducting_coupling_values():
 
 def test_unknown_preset(vqd_host):
     with pytest.raises(KeyError):
-        vqd_host.Device.preset("silicon")
+        vqd_host.Device.preset("nv_centre")
     import ctypes
     h = ctypes.c_void_p()
     assert vqd_host.lib().vqd_device_preset(99, ctypes.byref(h), None) != 0

@@ -33,7 +33,7 @@ GATE_KINDS = {
     "h": (), "x": (), "y": (), "z": (),
     "su2": ("g0", "g1", "g2", "g3"),      # 4 raw Gaussian draws (a quaternion)
     "cz": (), "cphase": ("theta",), "xx": ("theta",), "zz": ("alpha",),
-    "rabi": ("Omega", "phi", "Delta", "t"), "offres": ("Omega", "Delta", "t"),
+    "rabi": ("Omega", "phi", "Delta", "t"), "offres": ("Omega", "Delta", "t"), "crz": ("alpha",),
     "matrix": ("M",),                       # explicit 2^k x 2^k matrix (tests)
 }
 # Channel kinds and their parameter lists.
