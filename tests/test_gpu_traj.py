@@ -131,3 +131,27 @@ def test_repeatable_and_edge_cases(gpu_lib):
     psi, _ = tj.run(n, gates, [])
     assert np.abs(z - tj.expec_z(psi)).max() <= TOL
     torch.cuda.synchronize()
+
+
+def test_silicon_device_stream_as_trajectories(gpu_lib):
+    """The silicon preset's noisy stream (off-resonant drives, exchange
+    crosstalk, dephasing, T1/T2 decay) as trajectories: sampled
+    trajectories against the oracle, and the mean of 20000 within 5
+    standard errors of the density-matrix oracle's <Z_q>."""
+    from tests.test_presets import si_gates
+    n = 6
+    lib, _ = gpu_lib.Device.preset("silicon")
+    ops = lib.insert_noise(si_gates(n, 40, 31))
+    say("silicon trajectories: %d ops" % len(ops))
+    prog = gpu_lib.Trajectories(n, ops).compile()
+    T = 20000
+    U = uniforms(T, tj.n_channels(ops), seed=91)
+    out = prog.run(cuda(U))
+    Z = out["z"]
+    for t in (0, 4321, T - 1):
+        psi, _ = tj.run(n, ops, U[t])
+        assert np.abs(Z[t].cpu().numpy() - tj.expec_z(psi)).max() <= TOL, t
+    mean, sem = gpu_lib.Trajectories.stats(Z)
+    mean, sem = mean.cpu().numpy(), sem.cpu().numpy()
+    exact = emulate(n, ops).expec_z()
+    assert np.all(np.abs(mean - exact) <= 5 * sem + 1e-12), (mean, exact, sem)
