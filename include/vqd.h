@@ -167,6 +167,10 @@ enum vqd_kind {
                            Rabi frequency Omega for t (eq. off_resonant)      */
     VQD_K_CRZ,          /* alpha: |0><0| (x) I + |1><1| (x) Rz(alpha), control
                            targets[0] (eq. weak_dephasing)                    */
+    VQD_K_PARITY_DECAY, /* no parameters: the decay |0 1> -> |1 0> (ket |a b>,
+                           a on targets[0]) that accompanies the silicon parity
+                           read-out, Kraus set {|00><00|, |11><11|, |10><10|,
+                           |10><01|} (Sec. 7, eq. projmeas)                   */
     VQD_K_COUNT
 };
 
@@ -457,6 +461,15 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
  * nothing; these ops follow the off-resonant ones.  n_edges = 0 turns the
  * model off.  VQD_E_ARG for a bad or repeated edge or a non-finite value.
  *
+ * vqd_device_set_parity_readout / vqd_device_parity_readout_noise: the
+ * silicon parity read-out of a pair (Sec. 7, eq. projmeas): the two-qubit
+ * bit flip bitflip2(b) (eq. bf2) on either side of the parity projection
+ * (eq. m), which is accompanied by VQD_K_PARITY_DECAY, while every other
+ * qubit idles for t_meas.  parity_readout_noise emits stage 0 (before the
+ * projection): bitflip2(b) on (q0, q1), T1 and T2 decay for t_meas on every
+ * other qubit in ascending order, then PARITY_DECAY on (q0, q1); stage 1
+ * (after it): bitflip2(b).  Zero b or t_meas emit nothing.  VQD_E_ARG for
+ * b outside [0, 0.75], a negative or non-finite t_meas, or bad qubits.
  * vqd_device_set_readout / vqd_device_readout_noise: the read-out model of
  * Sec. 8, T1 decay for the measurement time t_meas, then depolarising
  * noise eps[q], then the projective measurement, then depolarising noise
@@ -487,6 +500,9 @@ int vqd_device_set_serial(vqd_device *d, int serial);
 int vqd_device_set_exchange_crosstalk(vqd_device *d, int n_edges, const int *edges, const double *on,
                                       const double *off);    /* on: n_edges^2 (row: active edge), off: n_edges */
 int vqd_device_set_readout(vqd_device *d, double t_meas, const double *eps);     /* eps: n */
+int vqd_device_set_parity_readout(vqd_device *d, double t_meas, double b);
+int vqd_device_parity_readout_noise(const vqd_device *d, int q0, int q1, int stage, int cap, int *out_count,
+                                    int *out_kinds, int *out_targets, double *out_params);
 int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int stage, int cap,
                              int *out_count, int *out_kinds, int *out_targets, double *out_params);
 
@@ -518,8 +534,8 @@ int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int
  * (scaled by |theta| / pi) on the pairs (q, q+1) with two-qubit dephasing
  * from the per-pair fidelities and 1 / (2 x the pair's gate frequency);
  * exchange crosstalk with the tabulated on-matrix and off-values on those
- * pairs; depolarising T1 decay (1e4 us) and per-qubit T2 dephasing.  p0
- * receives 1.  The parity read-out is not part of it.
+ * pairs; depolarising T1 decay (1e4 us) and per-qubit T2 dephasing; the
+ * parity read-out with b = 1 - 0.99 and 10 us.  p0 receives 1.
  *
  * vqd_device_preset creates *out (destroy with vqd_device_destroy); p0 is
  * NULL or holds vqd_device_preset_qubits(preset) doubles.  VQD_E_ARG for an

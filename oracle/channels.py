@@ -119,6 +119,18 @@ def depol1(p):
     return [math.sqrt(1 - p) * I2] + [math.sqrt(p / 3) * s for s in (X, Y, Z)]
 
 
+def parity_decay():
+    """Sec. 7 (eq. projmeas): the decay of |0_i 1_j> to |1_i 0_j> that comes
+    with the silicon parity read-out, as the Kraus set {|00><00|, |11><11|,
+    |10><10|, |10><01|}; ket |a b> has a on qubits[0], the low index bit."""
+    def ket(a, b):
+        v = np.zeros(4, dtype=np.complex128)
+        v[a + 2 * b] = 1
+        return v
+    return [np.outer(ket(0, 0), ket(0, 0)), np.outer(ket(1, 1), ket(1, 1)),
+            np.outer(ket(1, 0), ket(1, 0)), np.outer(ket(1, 0), ket(0, 1))]
+
+
 def depol2(p):
     """eq. (depol2): (1-p) rho + p/15 sum over the 15 non-identity two-qubit
     Pauli products.  The operators follow the order in which the equation
@@ -199,7 +211,7 @@ CHANNELS = {
     "depol1": depol1, "depol2": depol2, "deph1": deph1, "deph2": deph2,
     "amp": amp, "gamp": gamp, "bitflip1": bitflip1, "bitflip2": bitflip2,
     "amp_t1": amp_t1, "deph_t2": deph_t2, "deph_t2s": deph_t2s, "depol_t1": depol_t1,
-    "gamp_t1": gamp_t1,
+    "gamp_t1": gamp_t1, "parity_decay": parity_decay,
 }
 
 

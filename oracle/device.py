@@ -56,6 +56,10 @@ Readings (the paper describes the behaviour, not a procedure):
   edge j crz(on[i][j] theta / pi), by gate in input order and then by edge;
   a batch without two-qubit gates gives edge j crz(off[j]).  Zero angles are
   left out.  These ops follow the off-resonant ones.
+* Parity read-out (Sec. 7, eq. projmeas) of a pair: bitflip2(b) (eq. bf2),
+  T1 and T2 decay for the read-out time on every other qubit (ascending),
+  then the decay map parity_decay on the pair, before the parity projection
+  (eq. m); bitflip2(b) after it.
 * Read-out (Sec. 8): T1 decay for the measurement time, then
   depolarising noise eps, before the projection; depolarising noise eps
   after it.  Qubits not measured idle for the measurement time (T1, T2).
@@ -84,6 +88,7 @@ class Device:
         self.rabi: List[float] = []      # off-resonant driving: Omega_q and w_q
         self.freq: List[float] = []
         self.serial = False
+        self.par_t, self.par_b = 0.0, 0.0           # parity read-out
         self.xe_edges: List[Tuple[int, int]] = []   # exchange crosstalk
         self.xe_on: List[List[float]] = []
         self.xe_off: List[float] = []
@@ -105,6 +110,9 @@ class Device:
 
     def set_readout(self, t_meas: float, eps: Sequence[float]):
         self.t_meas, self.eps = t_meas, list(eps)
+
+    def set_parity_readout(self, t_meas: float, b: float):
+        self.par_t, self.par_b = t_meas, b
 
     def set_serial(self, serial: bool = True):
         self.serial = bool(serial)
@@ -244,4 +252,19 @@ def readout_noise(dev: Device, qubits: Sequence[int], stage: int) -> List[tuple]
         for q in range(dev.n):
             if q not in qubits:
                 out += _t1(dev, q, dev.t_meas) + _t2(dev, q, dev.t_meas)
+    return out
+
+
+def parity_readout_noise(dev: Device, q0: int, q1: int, stage: int) -> List[tuple]:
+    """Noise of the parity read-out of (q0, q1): stage 0 before the parity
+    projection (ending with the read-out's decay map), stage 1 after it."""
+    out: List[tuple] = []
+    if dev.par_b > 0:
+        out.append(("bitflip2", (q0, q1), (dev.par_b,)))
+    if stage == 0:
+        if dev.par_t > 0:
+            for q in range(dev.n):
+                if q not in (q0, q1):
+                    out += _t1(dev, q, dev.par_t) + _t2(dev, q, dev.par_t)
+        out.append(("parity_decay", (q0, q1), ()))
     return out

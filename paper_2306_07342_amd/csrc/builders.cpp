@@ -144,6 +144,16 @@ int channel_kraus(int kind, const double *p, int &k, std::vector<std::vector<cd>
         Ks.push_back(scaled(m2v(pauli(1)), std::sqrt(p[0])));
         return VQD_OK;
     }
+    case VQD_K_PARITY_DECAY: {
+        // index a + 2 b of the ket |a b>; row-major 4x4 operators
+        k = 2;
+        for (int e : {0, 15, 5, 6}) {        // |00><00|, |11><11|, |10><10|, |10><01|
+            std::vector<cd> K(16, cd(0));
+            K[e] = 1;
+            Ks.push_back(K);
+        }
+        return VQD_OK;
+    }
     case VQD_K_BITFLIP2: {
         if (!need_prob(p[0], 1.0)) return fail(VQD_E_ARG, "bitflip2: b outside [0, 1]");
         k = 2;
@@ -185,7 +195,7 @@ int rabi(double omega, double phi, double delta, double t, bool frame, std::vect
 
 bool is_channel(int kind)
 {
-    return kind >= VQD_K_DEPOL1 && kind <= VQD_K_GAMP_T1;
+    return (kind >= VQD_K_DEPOL1 && kind <= VQD_K_GAMP_T1) || kind == VQD_K_PARITY_DECAY;
 }
 
 }  // namespace
@@ -211,9 +221,9 @@ void canonical_params(int kind, double *p)
 int kind_arity(int kind, int *nq, int *np)
 {
     static const int Q[VQD_K_COUNT] = {0, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2,
-                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 1, 2};
+                                       1, 2, 1, 2, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 1, 2, 2};
     static const int P[VQD_K_COUNT] = {0, 1, 1, 1, 0, 0, 0, 0, 4, 0, 1, 1, 1,
-                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2, 3, 4, 3, 1};
+                                       1, 1, 1, 1, 1, 2, 1, 1, 2, 2, 2, 2, 3, 4, 3, 1, 0};
     if (kind <= 0 || kind >= VQD_K_COUNT) return -1;
     if (nq) *nq = Q[kind];
     if (np) *np = P[kind];

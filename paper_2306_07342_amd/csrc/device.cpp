@@ -50,6 +50,7 @@ struct vqd_device {
     double t_meas = 0.0;
     std::vector<double> eps;                   // read-out infidelities
     std::vector<double> rabi, freq;            // off-resonant driving (empty: off)
+    double par_t = 0.0, par_b = 0.0;           // parity read-out
     bool serial = false;                       // one gate per batch
     std::vector<std::pair<int, int>> xe_edges; // exchange crosstalk: edges,
     std::vector<double> xe_on, xe_off;         // on[i * m + j], off[j]
@@ -287,6 +288,39 @@ int vqd_device_set_off_resonant(vqd_device *d, const double *rabi, const double 
     d->rabi.assign(rabi, rabi + d->n);
     d->freq.assign(freq, freq + d->n);
     return VQD_OK;
+}
+
+int vqd_device_set_parity_readout(vqd_device *d, double t_meas, double b)
+{
+    clear_error();
+    if (!d) return fail(VQD_E_ARG, "null device");
+    if (!finite_nonneg(t_meas)) return fail(VQD_E_ARG, "read-out time negative or not finite");
+    if (!(b >= 0.0 && b <= 0.75)) return fail(VQD_E_ARG, "bit-flip probability outside [0, 0.75]");
+    d->par_t = t_meas;
+    d->par_b = b;
+    return VQD_OK;
+}
+
+int vqd_device_parity_readout_noise(const vqd_device *d, int q0, int q1, int stage, int cap, int *out_count,
+                                    int *out_kinds, int *out_targets, double *out_params)
+{
+    clear_error();
+    if (!d || !out_count) return fail(VQD_E_ARG, "null argument");
+    const int t[2] = {q0, q1};
+    if (int rc = check_targets(d->n, 2, t)) return rc;
+    if (stage != 0 && stage != 1) return fail(VQD_E_ARG, "stage must be 0 or 1");
+    OpList out;
+    if (d->par_b > 0.0) emit(out, VQD_K_BITFLIP2, q0, q1, d->par_b);
+    if (stage == 0) {
+        if (d->par_t > 0.0)
+            for (int q = 0; q < d->n; ++q)
+                if (q != q0 && q != q1) {
+                    t1_decay(d, out, q, d->par_t);
+                    t2_decay(d, out, q, d->par_t);
+                }
+        emit(out, VQD_K_PARITY_DECAY, q0, q1, 0.0);
+    }
+    return write_ops(out, cap, out_count, out_kinds, out_targets, out_params);
 }
 
 int vqd_device_set_serial(vqd_device *d, int serial)

@@ -34,8 +34,9 @@
 // 1 / (2 x the pair's gate frequency).  Residual exchange on passive
 // neighbouring pairs as conditional Z rotations (eq. weak_dephasing): the
 // ExchangeRotOn matrix while a CZ or CPhase runs, ExchangeRotOff otherwise.
-// Passive noise: depolarising T1 decay (eq. depolt1) and T2 dephasing.  The
-// parity read-out of the edge pairs is not part of the preset.
+// Passive noise: depolarising T1 decay (eq. depolt1) and T2 dephasing.
+// Parity read-out: bit flips with b = 1 - the read-out fidelity around the
+// decaying parity projection, 10 us during which the other qubits idle.
 #include <cmath>
 #include <string>
 
@@ -149,6 +150,7 @@ int silicon(vqd_device **out, double *p0)
                                     0.038, 0.03, 0.031, 0, 0.25,
                                     0.033, 0.03, 0.02, 0.03, 0};
     const double rot_off[np] = {0.039, 0.015, 0.03, 0.02, 0.028};
+    const double fid_read = 0.99, t_read = 10.0;
 
     vqd_device *d = nullptr;
     if (int rc = vqd_device_create(n, &d)) return rc;
@@ -182,6 +184,7 @@ int silicon(vqd_device **out, double *p0)
     if (!rc) rc = vqd_device_set_off_resonant(d, w_rabi, w_q);
     if (!rc) rc = vqd_device_set_exchange_crosstalk(d, np, edges, rot_on, rot_off);
     if (!rc) rc = vqd_device_set_serial(d, 1);
+    if (!rc) rc = vqd_device_set_parity_readout(d, t_read, 1.0 - fid_read);
     if (rc) {
         vqd_device_destroy(d);
         return rc;

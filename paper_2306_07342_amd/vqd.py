@@ -23,7 +23,7 @@ KINDS = {
     "cz": 9, "cphase": 10, "xx": 11, "zz": 12,
     "depol1": 13, "depol2": 14, "deph1": 15, "deph2": 16, "amp": 17, "gamp": 18,
     "bitflip1": 19, "bitflip2": 20, "amp_t1": 21, "deph_t2": 22, "deph_t2s": 23, "depol_t1": 24,
-    "gamp_t1": 25, "rabi": 26, "offres": 27, "crz": 28,
+    "gamp_t1": 25, "rabi": 26, "offres": 27, "crz": 28, "parity_decay": 29,
 }
 BLOCK_UNITARY = 0
 BLOCK_SUPEROP = 1
@@ -175,6 +175,9 @@ def load(path: str = LIB_PATH):
         "vqd_device_set_readout": ([vp, ctypes.c_double, _dp], ctypes.c_int),
         "vqd_device_set_off_resonant": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_device_set_serial": ([vp, ctypes.c_int], ctypes.c_int),
+        "vqd_device_set_parity_readout": ([vp, ctypes.c_double, ctypes.c_double], ctypes.c_int),
+        "vqd_device_parity_readout_noise": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip,
+                                             _ip, _dp], ctypes.c_int),
         "vqd_device_set_exchange_crosstalk": ([vp, ctypes.c_int, _ip, _dp, _dp], ctypes.c_int),
         "vqd_device_readout_noise": ([vp, ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip, _dp],
                                      ctypes.c_int),
@@ -682,6 +685,15 @@ class Device:
             p[i, :len(par)] = par
         return self._decode(lambda cap, cnt, a, b, c: lib().vqd_device_insert_noise(
             self.handle, m, _i(k), _i(t), _d(p), cap, cnt, a, b, c))
+
+    def set_parity_readout(self, t_meas: float, b: float):
+        check(lib().vqd_device_set_parity_readout(self.handle, t_meas, b))
+
+    def parity_readout_noise(self, q0: int, q1: int, stage: int) -> list:
+        """Noise ops of the parity read-out of (q0, q1): stage 0 before the
+        parity projection (ending with the decay map), stage 1 after it."""
+        return self._decode(lambda cap, cnt, a, b, c: lib().vqd_device_parity_readout_noise(
+            self.handle, q0, q1, stage, cap, cnt, a, b, c))
 
     def readout_noise(self, qubits, stage: int) -> list:
         """Read-out noise ops of the measured ``qubits``: stage 0 before the

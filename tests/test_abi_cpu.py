@@ -76,7 +76,7 @@ def test_argument_errors(vqd_host):
 @pytest.mark.parametrize("kind,params", [
     ("depol1", (0.1,)), ("depol2", (0.2,)), ("deph1", (0.3,)), ("deph2", (0.4,)),
     ("amp", (0.25,)), ("gamp", (0.7, 0.2)), ("bitflip1", (0.1,)), ("bitflip2", (0.3,)),
-    ("amp_t1", (0.5, 30.0)), ("deph_t2", (0.5, 20.0))])
+    ("amp_t1", (0.5, 30.0)), ("deph_t2", (0.5, 20.0)), ("parity_decay", ())])
 def test_channel_superops_match_oracle_kraus(vqd_host, kind, params):
     S = vqd_host.kind_superop(kind, params)
     Ks = och.CHANNELS[kind](*params)

@@ -33,6 +33,7 @@ def lib_device(vqd, ref: dv.Device):
     if ref.rabi:
         d.set_off_resonant(ref.rabi, ref.freq)
     d.set_serial(ref.serial)
+    d.set_parity_readout(ref.par_t, ref.par_b)
     if ref.xe_edges:
         d.set_exchange_crosstalk(ref.xe_edges, ref.xe_on, ref.xe_off)
     return d
@@ -105,12 +106,16 @@ def test_random_devices_with_every_rule(vqd_host, seed):
     ref.set_exchange_crosstalk(xe, rng.uniform(0, 0.1, (len(xe), len(xe))) * (rng.random((len(xe), len(xe))) < 0.7),
                                rng.uniform(0, 0.05, len(xe)) * (rng.random(len(xe)) < 0.7))
     ref.set_serial(seed % 2 == 0)
+    ref.set_parity_readout(float(rng.uniform(0, 12)), float(rng.uniform(0, 0.1)))
     gates = random_gates(n, 80, seed)
     lib = lib_device(vqd_host, ref)
     same_stream(lib.insert_noise(gates), dv.insert_noise(ref, gates))
     for qs in ([0], [3, 1], list(range(n)), []):
         for stage in (0, 1):
             same_stream(lib.readout_noise(qs, stage), dv.readout_noise(ref, qs, stage))
+    for q0, q1 in ((0, 1), (5, 2)):
+        for stage in (0, 1):
+            same_stream(lib.parity_readout_noise(q0, q1, stage), dv.parity_readout_noise(ref, q0, q1, stage))
 
 
 def test_off_resonant_hand_stream(vqd_host):
@@ -135,6 +140,14 @@ def test_off_resonant_hand_stream(vqd_host):
     with pytest.raises(vqd_host.VQDError):
         lib.set_exchange_crosstalk([(0, 1)], [[float("inf")]], [0.0])
     lib.set_exchange_crosstalk([], [], [])                                           # off
+    with pytest.raises(vqd_host.VQDError):
+        lib.set_parity_readout(10.0, 0.8)                                            # b > 0.75
+    with pytest.raises(vqd_host.VQDError):
+        lib.set_parity_readout(-1.0, 0.1)
+    with pytest.raises(vqd_host.VQDError):
+        lib.parity_readout_noise(0, 0, 0)
+    with pytest.raises(vqd_host.VQDError):
+        lib.parity_readout_noise(0, 1, 2)
 
 
 def test_zz_strength(vqd_host):

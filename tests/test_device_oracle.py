@@ -286,3 +286,18 @@ def test_exchange_crosstalk_hand_stream():
     assert len(got) == len(want)
     for g, w in zip(got, want):
         assert g[:2] == w[:2] and np.allclose(g[2], w[2], rtol=0, atol=1e-15), (g, w)
+
+
+def test_parity_readout_hand_stream():
+    """Sec. 7 by hand: bit flips on the measured pair, the other qubits'
+    passive decay for the read-out time, the decay map before the parity
+    projection; bit flips again after it."""
+    d = dv.Device(3)
+    d.set_passive([0.0, 0.0, 50.0], [0.0, 0.0, 20.0])
+    d.set_passive_forms("depol_t1", "deph_t2")
+    d.set_parity_readout(10.0, 0.01)
+    got0 = [(k, tuple(q), tuple(p)) for k, q, p in dv.parity_readout_noise(d, 1, 0, 0)]
+    assert got0 == [("bitflip2", (1, 0), (0.01,)), ("depol_t1", (2,), (10.0, 50.0)),
+                    ("deph_t2", (2,), (10.0, 20.0)), ("parity_decay", (1, 0), ())]
+    got1 = [(k, tuple(q), tuple(p)) for k, q, p in dv.parity_readout_noise(d, 1, 0, 1)]
+    assert got1 == [("bitflip2", (1, 0), (0.01,))]

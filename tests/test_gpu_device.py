@@ -113,3 +113,14 @@ def test_silicon_preset_on_the_density_matrix(gpu_lib):
     gpu_lib.Program(n, noisy).compile().run(dm)
     want = emulate(n, dv.insert_noise(ref, ideal))
     assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
+    # parity read-out of the two edge pairs (eq. projmeas, eq. m)
+    from oracle import measure as om
+    for (q0, q1), u in (((0, 1), 0.3), ((4, 5), 0.8)):
+        gpu_lib.Program(n, lib.parity_readout_noise(q0, q1, 0)).compile().run(dm)
+        emulate(n, dv.parity_readout_noise(ref, q0, q1, 0), want)
+        m, w = dm.measure_parity(q0, q1, u)
+        mr, wr = om.measure_parity(want, q0, q1, u)
+        assert m == mr and abs(w - wr[mr]) <= 1e-10
+        gpu_lib.Program(n, lib.parity_readout_noise(q0, q1, 1)).compile().run(dm)
+        emulate(n, dv.parity_readout_noise(ref, q0, q1, 1), want)
+        assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10

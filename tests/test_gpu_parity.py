@@ -219,8 +219,8 @@ def test_every_named_kind_in_a_program(gpu_lib):
               "amp": (0.4,), "gamp": (0.6, 0.3), "bitflip1": (0.2,), "bitflip2": (0.3,), "amp_t1": (0.5, 2.0),
               "deph_t2": (0.5, 1.0), "deph_t2s": (0.7, 1.5), "depol_t1": (0.6, 2.5),
               "gamp_t1": (0.9, 0.6, 2.0), "rabi": (1.7, 0.9, -0.6, 1.3), "offres": (1.0, 2.0, 0.7),
-              "crz": (0.8,)}
-    two = {"cz", "cphase", "xx", "zz", "crz", "depol2", "deph2", "bitflip2"}
+              "crz": (0.8,), "parity_decay": ()}
+    two = {"cz", "cphase", "xx", "zz", "crz", "parity_decay", "depol2", "deph2", "bitflip2"}
     ops = []
     for i, kind in enumerate(sorted(KINDS, key=KINDS.get)):
         q = i % n

@@ -294,19 +294,16 @@ def test_cptp_sets_and_cptn_leakage():
 
 
 def test_silicon_parity_decay_map():
-    """Sec. 7: K = {|00><00|, |11><11|, |10><10|, |10><01|} sums to the identity and
-    sends |0_i 1_j> to |1_i 0_j> (ket |a b> on (i, j) means a on i)."""
-    def ket(a, b):       # a on qubits[0] (LSB), b on qubits[1]
-        v = np.zeros(4)
-        v[a + 2 * b] = 1
-        return v
-    Ks = [np.outer(ket(0, 0), ket(0, 0)), np.outer(ket(1, 1), ket(1, 1)),
-          np.outer(ket(1, 0), ket(1, 0)), np.outer(ket(1, 0), ket(0, 1))]
-    assert np.allclose(sum(K.T @ K for K in Ks), np.eye(4))
-    dm = OracleDM(3)
-    dm.init_basis(0b100)         # qubit i=1 is 0, qubit j=2 is 1
-    dm.apply_kraus((1, 2), Ks)
-    assert abs(dm.R[0b010, 0b010] - 1) < 1e-15
+    """Sec. 7: the parity read-out's decay map is trace preserving, sends
+    |0_i 1_j> to |1_i 0_j> (ket |a b> on (i, j) means a on i), and leaves
+    |00>, |11> and |10> unchanged, so it keeps each parity."""
+    Ks = ch.parity_decay()
+    assert np.abs(sum(K.conj().T @ K for K in Ks) - np.eye(4)).max() == 0
+    for start, end in ((0b100, 0b010), (0b000, 0b000), (0b110, 0b110), (0b010, 0b010)):
+        dm = OracleDM(3)
+        dm.init_basis(start)         # bit 1 is qubit i, bit 2 qubit j
+        dm.apply_kraus((1, 2), Ks)
+        assert abs(dm.R[end, end] - 1) < 1e-15, (start, end)
 
 
 # ------------------------------------------------------- gate identities --

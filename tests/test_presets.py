@@ -80,6 +80,7 @@ def oracle_silicon():
     d.set_off_resonant([2 * math.pi * f for f in t["RabiFreq"]], [2 * math.pi * f for f in t["QubitFreq"]])
     d.set_exchange_crosstalk(edges, t["ExchangeRotOn"], t["ExchangeRotOff"])
     d.set_serial(True)
+    d.set_parity_readout(t["DurRead"], 1 - t["FidRead"])
     return d, [1.0] * n
 
 
@@ -157,6 +158,9 @@ def test_silicon_preset(vqd_host):
     close_stream(got, dv.insert_noise(ref, gates), 1e-9)
     kinds = {k for k, _, _ in got}
     assert {"offres", "crz", "deph1", "deph2", "depol_t1", "deph_t2"} <= kinds and "depol1" not in kinds
+    for q0, q1 in ((0, 1), (4, 5)):
+        for stage in (0, 1):
+            close_stream(lib.parity_readout_noise(q0, q1, stage), dv.parity_readout_noise(ref, q0, q1, stage), 1e-15)
 
 
 def test_superconducting_coupling_values():

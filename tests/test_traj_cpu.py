@@ -56,7 +56,7 @@ def test_named_gates_and_channels(vqd_host):
            ("bitflip1", (4,), (0.2,)), ("bitflip2", (2, 1), (0.3,)), ("amp_t1", (0,), (0.5, 2.0)),
            ("deph_t2", (3,), (0.5, 1.0)), ("gamp_t1", (2,), (0.9, 0.5, 2.0)), ("depol_t1", (4,), (0.3, 2.0)),
            ("deph_t2s", (1,), (0.4, 1.5)), ("rabi", (3,), (1.7, 0.9, -0.6, 1.3)),
-           ("offres", (0,), (1.0, 2.0, 0.7)), ("crz", (1, 4), (0.8,))]
+           ("offres", (0,), (1.0, 2.0, 0.7)), ("crz", (1, 4), (0.8,)), ("parity_decay", (2, 0), ())]
     _, plan = check_plan(vqd_host, n, ops * 3, T=24)
     kinds = set(int(k) for k in plan["ops"]["kind"])
     assert kinds == {emu.TOP_MAT, emu.TOP_DTHR, emu.TOP_DREG, emu.TOP_DMIX, emu.TOP_MIX, emu.TOP_KRAUS}

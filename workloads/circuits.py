@@ -41,7 +41,7 @@ CHANNEL_KINDS = {
     "depol1": ("p",), "depol2": ("p",), "deph1": ("p",), "deph2": ("p",),
     "amp": ("p",), "bitflip1": ("b",), "bitflip2": ("b",),
     "amp_t1": ("dt", "T1"), "deph_t2": ("dt", "T2"), "deph_t2s": ("dt", "T2s"), "depol_t1": ("dt", "T1"),
-    "gamp": ("p", "gamma"), "gamp_t1": ("p", "dt", "T1"),
+    "gamp": ("p", "gamma"), "gamp_t1": ("p", "dt", "T1"), "parity_decay": (),
     "kraus": ("Ks",),                       # explicit Kraus list (tests)
 }
 
