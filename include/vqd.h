@@ -470,6 +470,11 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
  * other qubit in ascending order, then PARITY_DECAY on (q0, q1); stage 1
  * (after it): bitflip2(b).  Zero b or t_meas emit nothing.  VQD_E_ARG for
  * b outside [0, 0.75], a negative or non-finite t_meas, or bad qubits.
+ * vqd_device_set_readout_form: VQD_K_DEPOL1 (the default, the model below)
+ * or VQD_K_BITFLIP1, the trapped-ion read-out of Sec. 4: a symmetric bit
+ * flip bitflip1(eps[q]) (eq. bf) on each listed qubit before the
+ * projection, nothing after it, and T1 and T2 decay for t_meas on the
+ * unlisted qubits.  VQD_E_ARG for another kind.
  * vqd_device_set_readout / vqd_device_readout_noise: the read-out model of
  * Sec. 8, T1 decay for the measurement time t_meas, then depolarising
  * noise eps[q], then the projective measurement, then depolarising noise
@@ -501,6 +506,7 @@ int vqd_device_set_exchange_crosstalk(vqd_device *d, int n_edges, const int *edg
                                       const double *off);    /* on: n_edges^2 (row: active edge), off: n_edges */
 int vqd_device_set_readout(vqd_device *d, double t_meas, const double *eps);     /* eps: n */
 int vqd_device_set_parity_readout(vqd_device *d, double t_meas, double b);
+int vqd_device_set_readout_form(vqd_device *d, int kind);
 int vqd_device_parity_readout_noise(const vqd_device *d, int q0, int q1, int stage, int cap, int *out_count,
                                     int *out_kinds, int *out_targets, double *out_params);
 int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int stage, int cap,
@@ -524,7 +530,9 @@ int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int
  * 0.99999 (vqd_fidelity_to_errors, x = 1), 0.05 us per pi, noise and time
  * scaled by |theta| / pi; H, X, Y as pi rotations; CZ of fidelity 0.999 split
  * 0.1 : 0.9, 5 us; T1 amplitude damping and Gaussian T2* dephasing
- * (3e9 us, 1e6 us).  p0 receives the initialisation fidelity 0.9999.
+ * (3e9 us, 1e6 us); read-out: bit flips of probability 0.001 (the
+ * VQD_K_BITFLIP1 form), 50 us.  p0 receives the initialisation fidelity
+ * 0.9999.
  *
  * VQD_PRESET_SILICON (Sec. 7, table conf:silicon), 6 qubits in a line,
  * serial: Rx, Ry (and H, X, Y as pi rotations) with per-qubit pure

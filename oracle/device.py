@@ -60,6 +60,9 @@ Readings (the paper describes the behaviour, not a procedure):
   T1 and T2 decay for the read-out time on every other qubit (ascending),
   then the decay map parity_decay on the pair, before the parity projection
   (eq. m); bitflip2(b) after it.
+* Read-out form "bitflip1" (the trapped ions, Sec. 4): a symmetric bit flip
+  eps (eq. bf) on each measured qubit before the projection, nothing after
+  it; qubits not measured idle for the measurement time (T1, T2).
 * Read-out (Sec. 8): T1 decay for the measurement time, then
   depolarising noise eps, before the projection; depolarising noise eps
   after it.  Qubits not measured idle for the measurement time (T1, T2).
@@ -89,6 +92,7 @@ class Device:
         self.freq: List[float] = []
         self.serial = False
         self.par_t, self.par_b = 0.0, 0.0           # parity read-out
+        self.readout_form = "depol1"
         self.xe_edges: List[Tuple[int, int]] = []   # exchange crosstalk
         self.xe_on: List[List[float]] = []
         self.xe_off: List[float] = []
@@ -113,6 +117,9 @@ class Device:
 
     def set_parity_readout(self, t_meas: float, b: float):
         self.par_t, self.par_b = t_meas, b
+
+    def set_readout_form(self, kind: str = "depol1"):
+        self.readout_form = kind
 
     def set_serial(self, serial: bool = True):
         self.serial = bool(serial)
@@ -244,6 +251,10 @@ def readout_noise(dev: Device, qubits: Sequence[int], stage: int) -> List[tuple]
         raise ValueError("duplicate qubit")
     out: List[tuple] = []
     for q in qubits:
+        if dev.readout_form == "bitflip1":
+            if stage == 0 and dev.eps[q] > 0:
+                out.append(("bitflip1", (q,), (dev.eps[q],)))
+            continue
         if stage == 0:
             out += _t1(dev, q, dev.t_meas)
         if dev.eps[q] > 0:

@@ -49,6 +49,7 @@ struct vqd_device {
     std::vector<double> zz_beta;
     double t_meas = 0.0;
     std::vector<double> eps;                   // read-out infidelities
+    int readout_kind = VQD_K_DEPOL1;           // or VQD_K_BITFLIP1 (Sec. 4)
     std::vector<double> rabi, freq;            // off-resonant driving (empty: off)
     double par_t = 0.0, par_b = 0.0;           // parity read-out
     bool serial = false;                       // one gate per batch
@@ -323,6 +324,16 @@ int vqd_device_parity_readout_noise(const vqd_device *d, int q0, int q1, int sta
     return write_ops(out, cap, out_count, out_kinds, out_targets, out_params);
 }
 
+int vqd_device_set_readout_form(vqd_device *d, int kind)
+{
+    clear_error();
+    if (!d) return fail(VQD_E_ARG, "null device");
+    if (kind != VQD_K_DEPOL1 && kind != VQD_K_BITFLIP1)
+        return fail(VQD_E_ARG, "read-out form must be VQD_K_DEPOL1 or VQD_K_BITFLIP1");
+    d->readout_kind = kind;
+    return VQD_OK;
+}
+
 int vqd_device_set_serial(vqd_device *d, int serial)
 {
     clear_error();
@@ -384,8 +395,13 @@ int vqd_device_readout_noise(const vqd_device *d, int nq, const int *qubits, int
         measured[qubits[i]] = 1;
     }
     OpList out;
+    const bool flips = d->readout_kind == VQD_K_BITFLIP1;
     for (int i = 0; i < nq; ++i) {
         const int q = qubits[i];
+        if (flips) {
+            if (stage == 0 && d->eps[q] > 0.0) emit(out, VQD_K_BITFLIP1, q, 0, d->eps[q]);
+            continue;
+        }
         if (stage == 0) t1_decay(d, out, q, d->t_meas);
         if (d->eps[q] > 0.0) emit(out, VQD_K_DEPOL1, q, 0, d->eps[q]);
     }

@@ -21,8 +21,10 @@
 // noise from the reported fidelity (App. B), scaled with the duration by
 // |theta| / pi (App. C); a pi rotation takes 1 / (2 x Rabi frequency).  CZ:
 // the reported fidelity split 0.1 : 0.9 into depolarising and dephasing
-// noise, duration 1 / (2 x its gate frequency).  Ion transport, remote
-// entanglement and the ions' bit-flip read-out are not part of the preset.
+// noise, duration 1 / (2 x its gate frequency).  Read-out: a symmetric bit
+// flip of the tabulated probability before the projection (eq. bf), 50 us
+// during which the other ions idle.  Ion transport and remote entanglement
+// are not part of the preset.
 //
 // Silicon (Sec. 7, table conf:silicon): six spin qubits in a line, gates run
 // one at a time.  x and y rotations: pure dephasing from the per-qubit
@@ -103,6 +105,7 @@ int trapped_ion(vqd_device **out, double *p0)
     const double T1 = 3e9, T2s = 10e5, fid_init = 0.9999;
     const double fid_xy = 0.99999, x_xy = 1.0, rabi = 10.0;
     const double fid_cz = 0.999, x_cz = 0.1, freq_cz = 0.1;
+    const double t_read = 50.0, bf_read = 0.001;
 
     vqd_device *d = nullptr;
     if (int rc = vqd_device_create(n, &d)) return rc;
@@ -124,6 +127,10 @@ int trapped_ion(vqd_device **out, double *p0)
     if (!rc) rc = vqd_device_set_gate(d, VQD_K_CZ, t_cz, pd2, pq2);
     if (!rc) rc = vqd_device_set_passive(d, t1, t2);
     if (!rc) rc = vqd_device_set_passive_forms(d, VQD_K_AMP_T1, VQD_K_DEPH_T2S);
+    double eps[n];
+    for (int q = 0; q < n; ++q) eps[q] = bf_read;
+    if (!rc) rc = vqd_device_set_readout(d, t_read, eps);
+    if (!rc) rc = vqd_device_set_readout_form(d, VQD_K_BITFLIP1);
     if (rc) {
         vqd_device_destroy(d);
         return rc;

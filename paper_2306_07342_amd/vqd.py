@@ -175,6 +175,7 @@ def load(path: str = LIB_PATH):
         "vqd_device_set_readout": ([vp, ctypes.c_double, _dp], ctypes.c_int),
         "vqd_device_set_off_resonant": ([vp, _dp, _dp], ctypes.c_int),
         "vqd_device_set_serial": ([vp, ctypes.c_int], ctypes.c_int),
+        "vqd_device_set_readout_form": ([vp, ctypes.c_int], ctypes.c_int),
         "vqd_device_set_parity_readout": ([vp, ctypes.c_double, ctypes.c_double], ctypes.c_int),
         "vqd_device_parity_readout_noise": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip,
                                              _ip, _dp], ctypes.c_int),
@@ -636,6 +637,9 @@ class Device:
         r = self._per_qubit(rabi, "rabi")
         f = self._per_qubit(freq, "freq")
         check(lib().vqd_device_set_off_resonant(self.handle, _d(r), _d(f)))
+
+    def set_readout_form(self, kind: str = "depol1"):
+        check(lib().vqd_device_set_readout_form(self.handle, KINDS[kind]))
 
     def set_serial(self, serial: bool = True):
         check(lib().vqd_device_set_serial(self.handle, int(bool(serial))))

@@ -34,6 +34,7 @@ def lib_device(vqd, ref: dv.Device):
         d.set_off_resonant(ref.rabi, ref.freq)
     d.set_serial(ref.serial)
     d.set_parity_readout(ref.par_t, ref.par_b)
+    d.set_readout_form(ref.readout_form)
     if ref.xe_edges:
         d.set_exchange_crosstalk(ref.xe_edges, ref.xe_on, ref.xe_off)
     return d
@@ -107,6 +108,7 @@ def test_random_devices_with_every_rule(vqd_host, seed):
                                rng.uniform(0, 0.05, len(xe)) * (rng.random(len(xe)) < 0.7))
     ref.set_serial(seed % 2 == 0)
     ref.set_parity_readout(float(rng.uniform(0, 12)), float(rng.uniform(0, 0.1)))
+    ref.set_readout_form(["depol1", "bitflip1"][seed % 2])
     gates = random_gates(n, 80, seed)
     lib = lib_device(vqd_host, ref)
     same_stream(lib.insert_noise(gates), dv.insert_noise(ref, gates))
@@ -140,6 +142,8 @@ def test_off_resonant_hand_stream(vqd_host):
     with pytest.raises(vqd_host.VQDError):
         lib.set_exchange_crosstalk([(0, 1)], [[float("inf")]], [0.0])
     lib.set_exchange_crosstalk([], [], [])                                           # off
+    with pytest.raises(vqd_host.VQDError):
+        lib.set_readout_form("amp")
     with pytest.raises(vqd_host.VQDError):
         lib.set_parity_readout(10.0, 0.8)                                            # b > 0.75
     with pytest.raises(vqd_host.VQDError):

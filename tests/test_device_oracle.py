@@ -301,3 +301,20 @@ def test_parity_readout_hand_stream():
                     ("deph_t2", (2,), (10.0, 20.0)), ("parity_decay", (1, 0), ())]
     got1 = [(k, tuple(q), tuple(p)) for k, q, p in dv.parity_readout_noise(d, 1, 0, 1)]
     assert got1 == [("bitflip2", (1, 0), (0.01,))]
+
+
+def test_bit_flip_readout_form():
+    """Sec. 4: the ions' read-out error is a symmetric bit flip before the
+    projection.  The stream holds it for the measured ion and idle decay for
+    the others; a prepared |1> then reads 0 with probability b exactly."""
+    from oracle import measure as om
+    d = dv.Device(2)
+    d.set_passive([0.0, 40.0], [0.0, 30.0])
+    d.set_readout(50.0, [0.001, 0.002])
+    d.set_readout_form("bitflip1")
+    got = [(k, tuple(q), tuple(p)) for k, q, p in dv.readout_noise(d, [0], 0)]
+    assert got == [("bitflip1", (0,), (0.001,)), ("amp_t1", (1,), (50.0, 40.0)), ("deph_t2", (1,), (50.0, 30.0))]
+    assert dv.readout_noise(d, [0], 1) == []
+    dm = emulate(2, [("x", (0,), ())] + dv.readout_noise(d, [0], 0))
+    _, w = om.measure_z(dm, 0, 0.5)
+    assert abs(w[0] - 0.001) <= 1e-16 and abs(w[1] - 0.999) <= 1e-15

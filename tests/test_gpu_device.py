@@ -124,3 +124,31 @@ def test_silicon_preset_on_the_density_matrix(gpu_lib):
         gpu_lib.Program(n, lib.parity_readout_noise(q0, q1, 1)).compile().run(dm)
         emulate(n, dv.parity_readout_noise(ref, q0, q1, 1), want)
         assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
+
+
+def test_trapped_ion_preset_with_readout(gpu_lib):
+    """The trapped-ion preset end to end on the GPU: initialisation errors,
+    the noisy circuit, the bit-flip read-out of two ions and their
+    projective measurements, against the oracle."""
+    from oracle import measure as om
+    from oracle.core import OracleDM
+    from tests.test_device_oracle import random_gates
+    from tests.test_presets import oracle_trapped_ion
+    n = 8
+    dev, p0 = gpu_lib.Device.preset("trapped_ion")
+    ref, rp0 = oracle_trapped_ion()
+    gates = random_gates(n, 60, 23)
+    noisy = dev.insert_noise(gates) + dev.readout_noise([2, 6], 0)
+    print("trapped-ion preset: %d ops" % len(noisy), flush=True)
+    dm = gpu_lib.DensityMatrix(n)
+    dm.init_product_diag(p0)
+    gpu_lib.Program(n, noisy).compile().run(dm)
+    want = OracleDM(n)
+    want.init_product_diag(rp0)
+    emulate(n, dv.insert_noise(ref, gates) + dv.readout_noise(ref, [2, 6], 0), want)
+    assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
+    for q, u in ((2, 0.4), (6, 0.9)):
+        m, w = dm.measure_z(q, u)
+        mr, wr = om.measure_z(want, q, u)
+        assert m == mr and abs(w - wr[mr]) <= 1e-10
+    assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10

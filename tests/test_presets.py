@@ -55,6 +55,8 @@ def oracle_trapped_ion():
     d.set_gate("cz", 1 / (2 * t["FreqCZ"]), p2, q2)
     d.set_passive([t["T1"]] * n, [t["T2s"]] * n)
     d.set_passive_forms("amp_t1", "deph_t2s")
+    d.set_readout(t["DurRead"], [t["BFProb"]] * n)
+    d.set_readout_form("bitflip1")
     return d, [t["FidInit"]] * n
 
 
@@ -146,6 +148,10 @@ def test_trapped_ion_preset(vqd_host):
     gates = random_gates(8, 60, 12)
     # closed-form root (library) against bisection (oracle)
     close_stream(lib.insert_noise(gates), dv.insert_noise(ref, gates), 1e-9)
+    for qs in ([0], [7, 2]):
+        for stage in (0, 1):
+            same_stream(lib.readout_noise(qs, stage), dv.readout_noise(ref, qs, stage))
+    assert [k for k, _, _ in lib.readout_noise([3], 0)][0] == "bitflip1" and lib.readout_noise([3], 1) == []
 
 
 def test_silicon_preset(vqd_host):
