@@ -109,9 +109,13 @@ def test_silicon_preset_on_the_density_matrix(gpu_lib):
     ideal = si_gates(n, 80, 21)
     noisy = lib.insert_noise(ideal)
     print("silicon stream: %d ops" % len(noisy), flush=True)
+    want = emulate(n, dv.insert_noise(ref, ideal))
+    # the Hermitian plan first (every op here preserves Hermiticity)
+    herm = gpu_lib.DensityMatrix(n)
+    gpu_lib.Program(n, noisy).compile(gpu_lib.plan_opts(hermitian=True, tile_bits=8, min_contig_bits=1)).run(herm)
+    assert np.abs(herm.to_numpy() - want.to_vectorised()).max() <= 1e-10
     dm = gpu_lib.DensityMatrix(n)
     gpu_lib.Program(n, noisy).compile().run(dm)
-    want = emulate(n, dv.insert_noise(ref, ideal))
     assert np.abs(dm.to_numpy() - want.to_vectorised()).max() <= 1e-10
     # parity read-out of the two edge pairs (eq. projmeas, eq. m)
     from oracle import measure as om
