@@ -207,3 +207,27 @@ def test_template_only_batch_graph_and_autotune(gpu_lib):
     for j in (0, 77, 255):
         ref = emulate(10, c5_ansatz_circuit(dev[j], ang[j]))
         assert np.abs(b.expec_z(idx[j]) - ref.expec_z()).max() <= TOL, j
+
+
+def test_device_preset_streams_in_one_batch(gpu_lib):
+    """Noisy streams of the three device presets (silicon: off-resonant
+    drives, exchange crosstalk, serial; trapped ions; superconducting), twelve
+    instances in one persistent launch, each against the oracle."""
+    from tests.test_device_oracle import random_gates
+    from tests.test_presets import sc_gates, si_gates
+    insts = []
+    for i in range(12):
+        name = ("silicon", "trapped_ion", "superconducting")[i % 3]
+        dev, _ = gpu_lib.Device.preset(name)
+        n = dev.n
+        gates = (si_gates(n, 30, 400 + i) if name == "silicon" else
+                 random_gates(n, 30, 400 + i) if name == "trapped_ion" else sc_gates(n, 30, 400 + i))
+        insts.append((n, dev.insert_noise(gates)))
+    say("preset batch: %d instances, %d ops" % (len(insts), sum(len(o) for _, o in insts)))
+    refs = [emulate(n, ops) for n, ops in insts]
+    b = gpu_lib.Batch()
+    for n, ops in insts:
+        b.add(n, ops)
+    b.compile()
+    b.run()
+    check_batch(gpu_lib, b, insts, refs)
