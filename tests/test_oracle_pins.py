@@ -426,3 +426,110 @@ def test_unital_channels_do_not_raise_purity():
         cur = dm.purity()
         assert cur <= last + 1e-15
         last = cur
+
+
+# ------------------------------------------- builders with their own pins --
+
+@pytest.mark.parametrize("seed", range(6))
+def test_su2_draw_is_special_unitary(seed):
+    """The Haar SU(2) draw of the grid circuit's one-qubit layers: a
+    normalised Gaussian quaternion gives a unitary of determinant 1, and
+    scaling the four draws does not change the gate."""
+    g = np.random.default_rng(seed).standard_normal(4)
+    U = ch.su2_from_gaussians(g)
+    assert np.abs(U.conj().T @ U - np.eye(2)).max() < 1e-15
+    assert abs(np.linalg.det(U) - 1) < 1e-15
+    assert np.abs(ch.su2_from_gaussians(3.7 * g) - U).max() < 1e-15
+
+
+def test_su2_draw_unit_quaternions():
+    """The four unit quaternions give I, -iX, -iY, -iZ, written out entry by
+    entry."""
+    i = 1j
+    want = {
+        (1, 0, 0, 0): [[1, 0], [0, 1]],
+        (0, 1, 0, 0): [[0, -i], [-i, 0]],
+        (0, 0, 1, 0): [[0, -1], [1, 0]],
+        (0, 0, 0, 1): [[-i, 0], [0, i]],
+    }
+    for a, M in want.items():
+        assert np.abs(ch.su2_from_gaussians(a) - np.array(M)).max() < 1e-15
+
+
+@pytest.mark.parametrize("theta,axis", [(0.3, (1, 0, 0)), (2.1, (0, 1, 0)), (4.0, (0, 0, 1)),
+                                        (1.234, (0.48, -0.6, 0.64))])
+def test_su2_draw_is_a_rotation(theta, axis):
+    """A quaternion (cos(theta/2), sin(theta/2) n) is the rotation
+    exp(-i theta n.sigma / 2); the exponential is taken by scipy, so a wrong
+    sign or a swapped Pauli in the quaternion form fails here."""
+    from scipy.linalg import expm
+    n = np.asarray(axis, dtype=float)
+    n /= np.linalg.norm(n)
+    a = np.concatenate([[math.cos(theta / 2)], math.sin(theta / 2) * n])
+    G = n[0] * ch.X + n[1] * ch.Y + n[2] * ch.Z
+    assert np.abs(ch.su2_from_gaussians(a) - expm(-0.5j * theta * G)).max() < 1e-14
+
+
+def test_cphase_at_pi_is_cz():
+    """Sec. 7 (silicon native operations): CZ is CPh(theta) at theta = pi."""
+    assert np.abs(ch.gate_matrix("cphase", (math.pi,)) - np.diag([1, 1, 1, -1])).max() < 1e-15
+
+
+@pytest.mark.parametrize("phi", [0.4, 1.9, -2.5])
+def test_cphase_moves_only_the_one_one_phase(phi):
+    """CPh(phi) on |++>: the state is (|00>+|01>+|10>+e^{i phi}|11>)/2, so
+    rho_{00,11} = e^{-i phi}/4 and every coherence that does not involve
+    |11> stays 1/4."""
+    h = ch.gate_matrix("h", ())
+    dm = emulate(2, [("h", (0,), ()), ("h", (1,), ()), ("cphase", (0, 1), (phi,))])
+    R = dm.R
+    assert abs(R[0, 3] - np.exp(-1j * phi) / 4) < 1e-15
+    assert abs(R[3, 0] - np.exp(1j * phi) / 4) < 1e-15
+    for r in range(3):
+        for c in range(3):
+            assert abs(R[r, c] - 0.25) < 1e-15
+    assert np.abs(h @ h - np.eye(2)).max() < 1e-15
+
+
+@pytest.mark.parametrize("b", [0.05, 0.3, 0.75])
+def test_bitflip2_populations_from_zero(b):
+    """eq. (bf2) on |00>: populations 1-b on 00 and b/3 on each of 10, 01,
+    11.  X_i and X_iX_j both flip Z_i, so <Z_i> = <Z_j> = 1 - 4b/3, and
+    <Z_i Z_j> = 1 - b - b/3 = 1 - 4b/3 as well."""
+    dm = emulate(2, [("bitflip2", (0, 1), (b,))])
+    p = dm.probs()
+    assert np.abs(p - np.array([1 - b, b / 3, b / 3, b / 3])).max() < 1e-15
+    assert abs(dm.expec_zz([(0, 1)])[0] - (1 - 4 * b / 3)) < 1e-15
+    assert np.abs(dm.expec_z() - (1 - 4 * b / 3)).max() < 1e-15
+
+
+@pytest.mark.parametrize("b", [0.1, 0.5])
+def test_bitflip2_keeps_plus_plus(b):
+    """eq. (bf2) holds only X errors, and |++> is an eigenstate of X_i, X_j
+    and X_iX_j: the state is unchanged.  A Y or Z in place of an X would move
+    it."""
+    ops = [("h", (0,), ()), ("h", (1,), ())]
+    ref = emulate(2, ops).R
+    got = emulate(2, ops + [("bitflip2", (0, 1), (b,))]).R
+    assert np.abs(got - ref).max() < 1e-15
+    # a coherent state off the X axis does move: |+i> on qubit 0
+    ops_y = [("h", (0,), ()), ("rz", (0,), (math.pi / 2,))]
+    a = emulate(2, ops_y).R
+    m = emulate(2, ops_y + [("bitflip2", (0, 1), (b,))]).R
+    # X_i and X_iX_j (weight 2b/3) flip <Y_0>: it scales by 1 - 4b/3
+    y0 = lambda R: 2 * R[1, 0].imag
+    assert abs(y0(a) - 1) < 1e-15
+    assert abs(y0(m) - (1 - 4 * b / 3)) < 1e-15
+
+
+@pytest.mark.parametrize("theta", [0.2, 1.0, math.pi / 2, 2.8])
+def test_xx_sign_of_the_exponent(theta):
+    """XX(theta) = exp(-i theta/2 X(x)X) (reading of the Moelmer-Soerensen
+    gate) takes |00> to cos(theta/2)|00> - i sin(theta/2)|11>, so
+    rho_{00,11} = i sin(theta)/2: its imaginary part is positive on
+    (0, pi).  The opposite sign of the exponent flips it."""
+    R = emulate(2, [("xx", (0, 1), (theta,))]).R
+    assert abs(R[0, 3] - 0.5j * math.sin(theta)) < 1e-15
+    assert R[0, 3].imag > 0
+    assert abs(R[0, 0] - math.cos(theta / 2) ** 2) < 1e-15
+    assert abs(R[3, 3] - math.sin(theta / 2) ** 2) < 1e-15
