@@ -40,6 +40,23 @@ static inline uint64_t deposit(uint64_t base, int k, const int *t, unsigned sub)
     return r;
 }
 
+/* For each row a of the d x d matrices M[0..nm-1], the columns b whose entry
+ * M[a][b] is not an exact zero: cols[(j*d + a)*d + 0 .. cnt[j*d + a] - 1].
+ * A product with an exact zero entry adds an exact zero to a sum, so the sums
+ * below leave those terms out and are unchanged (at most the sign of a zero
+ * result differs).  Pauli-product Kraus operators and diagonal gates have one
+ * nonzero per row, which is where this saves time. */
+static void nonzero_cols(const cplx *M, int nm, unsigned d, unsigned char *cols, unsigned char *cnt)
+{
+    for (int j = 0; j < nm; ++j)
+        for (unsigned a = 0; a < d; ++a) {
+            unsigned c = 0;
+            for (unsigned b = 0; b < d; ++b)
+                if (M[((size_t)j * d + a) * d + b] != 0) cols[((size_t)j * d + a) * d + c++] = (unsigned char)b;
+            cnt[(size_t)j * d + a] = (unsigned char)c;
+        }
+}
+
 /* True if none of the target bits is set in x. */
 static inline int targets_clear(uint64_t x, int k, const int *t)
 {
@@ -83,6 +100,9 @@ void orc_apply_matrix(double *Rd, int n, int k, const int *t, const double *Md)
     const cplx *M = (const cplx *)Md;
     const int64_t D = (int64_t)1 << n;
     const unsigned d = 1u << k;
+    unsigned char *nzc = malloc((size_t)d * d), *nzn = malloc(d);
+    if (!nzc || !nzn) { free(nzc); free(nzn); return; }
+    nonzero_cols(M, 1, d, nzc, nzn);
 
     /* left multiplication: rho <- M rho; each group of d rows that differ
      * only in the target bits is combined column by column */
@@ -96,7 +116,10 @@ void orc_apply_matrix(double *Rd, int n, int k, const int *t, const double *Md)
             for (unsigned a = 0; a < d; ++a) v[a] = R[rows[a] * D + c];
             for (unsigned a = 0; a < d; ++a) {
                 cplx s = 0;
-                for (unsigned b = 0; b < d; ++b) s += M[a * d + b] * v[b];
+                for (unsigned i = 0; i < nzn[a]; ++i) {
+                    unsigned b = nzc[a * d + i];
+                    s += M[a * d + b] * v[b];
+                }
                 w[a] = s;
             }
             for (unsigned a = 0; a < d; ++a) R[rows[a] * D + c] = w[a];
@@ -113,13 +136,18 @@ void orc_apply_matrix(double *Rd, int n, int k, const int *t, const double *Md)
                 v[b] = R[r * D + deposit(c0, k, t, b)];
             for (unsigned a = 0; a < d; ++a) {
                 cplx s = 0;
-                for (unsigned b = 0; b < d; ++b) s += v[b] * conj(M[a * d + b]);
+                for (unsigned i = 0; i < nzn[a]; ++i) {
+                    unsigned b = nzc[a * d + i];
+                    s += v[b] * conj(M[a * d + b]);
+                }
                 w[a] = s;
             }
             for (unsigned a = 0; a < d; ++a)
                 R[r * D + deposit(c0, k, t, a)] = w[a];
         }
     }
+    free(nzc);
+    free(nzn);
 }
 
 /* rho <- sum_j K_j rho K_j^dagger.  K holds nk matrices of size 2^k x 2^k,
@@ -131,6 +159,9 @@ void orc_apply_kraus(double *Rd, int n, int k, const int *t, int nk, const doubl
     const cplx *K = (const cplx *)Kd;
     const int64_t D = (int64_t)1 << n;
     const unsigned d = 1u << k;
+    unsigned char *nzc = malloc((size_t)nk * d * d), *nzn = malloc((size_t)nk * d);
+    if (!nzc || !nzn) { free(nzc); free(nzn); return; }
+    nonzero_cols(K, nk, d, nzc, nzn);
 
 #pragma omp parallel for schedule(static)
     for (int64_t r0 = 0; r0 < D; ++r0) {
@@ -144,18 +175,25 @@ void orc_apply_kraus(double *Rd, int n, int k, const int *t, int nk, const doubl
             for (unsigned i = 0; i < d * d; ++i) out[i] = 0;
             for (int j = 0; j < nk; ++j) {
                 const cplx *Kj = K + (size_t)j * d * d;
+                const unsigned char *cj = nzc + (size_t)j * d * d, *nj = nzn + (size_t)j * d;
                 /* KB = K_j B */
                 for (unsigned a = 0; a < d; ++a)
                     for (unsigned b = 0; b < d; ++b) {
                         cplx s = 0;
-                        for (unsigned m = 0; m < d; ++m) s += Kj[a * d + m] * B[m * d + b];
+                        for (unsigned i = 0; i < nj[a]; ++i) {
+                            unsigned m = cj[a * d + i];
+                            s += Kj[a * d + m] * B[m * d + b];
+                        }
                         KB[a * d + b] = s;
                     }
                 /* out += KB K_j^dagger */
                 for (unsigned a = 0; a < d; ++a)
                     for (unsigned b = 0; b < d; ++b) {
                         cplx s = 0;
-                        for (unsigned m = 0; m < d; ++m) s += KB[a * d + m] * conj(Kj[b * d + m]);
+                        for (unsigned i = 0; i < nj[b]; ++i) {
+                            unsigned m = cj[b * d + i];
+                            s += KB[a * d + m] * conj(Kj[b * d + m]);
+                        }
                         out[a * d + b] += s;
                     }
             }
@@ -164,6 +202,8 @@ void orc_apply_kraus(double *Rd, int n, int k, const int *t, int nk, const doubl
                     R[deposit(r0, k, t, a) * D + deposit(c0, k, t, b)] = out[a * d + b];
         }
     }
+    free(nzc);
+    free(nzn);
 }
 
 /* ---- compensated summation (Neumaier) -------------------------------- */
