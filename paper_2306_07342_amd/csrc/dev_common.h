@@ -27,12 +27,8 @@ __host__ __device__ constexpr int popc4(int m)
     return (m & 1) + (m >> 1 & 1) + (m >> 2 & 1) + (m >> 3 & 1);
 }
 
-// LDS index swizzle: xor the low 3 bits of the local index with a hash of
-// the higher bits so that strided register phases spread over the banks.
-__device__ __forceinline__ uint32_t swz(uint32_t l)
-{
-    return l ^ (((l >> 3) ^ (l >> 6) ^ (l >> 9)) & 7u);
-}
+// LDS index swizzle (see lds_swizzle).
+__device__ __forceinline__ uint32_t swz(uint32_t l) { return lds_swizzle(l); }
 
 __device__ __forceinline__ uint32_t uni(uint32_t x)
 {

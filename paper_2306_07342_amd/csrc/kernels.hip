@@ -182,8 +182,6 @@ __device__ __forceinline__ HermTile herm_tile(const KPass *__restrict__ P, uint3
     return h;
 }
 
-// Row bit q <-> column bit q + n: the transpose of an index bit position.
-__device__ __forceinline__ uint32_t mirror_pos(uint32_t g, uint32_t n) { return g < n ? g + n : g - n; }
 
 // Local and global index bits contributed by the thread id in phase H.
 // Thread-id bits at or above nthr are zero (tid < 2^nthr) and the unused
@@ -216,33 +214,18 @@ __device__ __forceinline__ uint32_t thread_local_bits(const KPhase *__restrict__
     return tl;
 }
 
-__device__ __forceinline__ uint32_t slot_g(const KPhase *__restrict__ H, int e)
-{
-    uint32_t g = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-        if (e >> b & 1) g |= 1u << uni(H->reg_gpos[b]);
-    return g;
-}
+// Global index part of register slot e (precomputed by the planner).
+__device__ __forceinline__ uint32_t slot_g(const KPhase *__restrict__ H, int e) { return uni(H->g_slot[e]); }
 
 // Hermitian mode: the conjugate of the tile's amplitude in slot e goes to
 // the transposed index (row and column bits exchanged): the mirrored group
 // base, the transposed slot bits and the thread's transposed bits (in
 // `lane`).  The mirror tile is never computed itself.
 __device__ __forceinline__ void store_mirror(double2 *lane, uint32_t gbm, const KPhase *__restrict__ H,
-                                             uint32_t nq, const double2 (&a)[16])
+                                             const double2 (&a)[16])
 {
-    uint32_t rg[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rg[b] = 1u << (mirror_pos(uni(H->reg_gpos[b]), nq) & 31u);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        uint32_t u = gbm;
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-            if (e >> b & 1) u |= rg[b];
-        lane[u] = make_double2(a[e].x, -a[e].y);
-    }
+    for (int e = 0; e < 16; ++e) lane[gbm | uni(H->gm_slot[e])] = make_double2(a[e].x, -a[e].y);
 }
 
 // The previous pass's group pair of an amplitude: i collects its bits at
@@ -251,9 +234,8 @@ __device__ __forceinline__ void store_mirror(double2 *lane, uint32_t gbm, const 
 // group base, which occupy disjoint positions, so i and j are ORs of parts.
 struct HalfIn {
     uint32_t it, jt;           // thread parts
-    uint32_t ir[4], jr[4];     // part of register bit b (uniform)
     uint32_t m;                // group pairs of the previous pass
-    const KPass *Pp;
+    const KPass *Pp;           // the previous pass
 };
 
 __device__ __forceinline__ void pair_of(const KPass *__restrict__ Pp, uint32_t m, uint32_t x, uint32_t &i,
@@ -267,16 +249,12 @@ __device__ __forceinline__ void pair_of(const KPass *__restrict__ Pp, uint32_t m
     }
 }
 
-__device__ __forceinline__ HalfIn half_in(const KPass *__restrict__ Pp, const KPhase *__restrict__ H0, uint32_t tg0,
-                                          uint32_t nq)
+__device__ __forceinline__ HalfIn half_in(const KPass *__restrict__ P, uint32_t tg0)
 {
-    (void)nq;
     HalfIn h;
-    h.Pp = Pp;
-    h.m = uni(Pp->n_group_bits) >> 1;
-    pair_of(Pp, h.m, tg0, h.it, h.jt);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) pair_of(Pp, h.m, 1u << (uni(H0->reg_gpos[b]) & 31u), h.ir[b], h.jr[b]);
+    h.Pp = P - 1;
+    h.m = uni(h.Pp->n_group_bits) >> 1;
+    pair_of(h.Pp, h.m, tg0, h.it, h.jt);
     return h;
 }
 
@@ -287,25 +265,12 @@ __device__ __forceinline__ HalfIn half_in(const KPass *__restrict__ Pp, const KP
 // lanes of one coalesced segment make the same choice.
 __device__ __forceinline__ void load_herm(double2 (&v)[16], const double2 *__restrict__ lane,
                                           const double2 *__restrict__ lane_m, const HermTile &ht,
-                                          const KPhase *__restrict__ H0, uint32_t nq, uint32_t herm,
-                                          const HalfIn &hin)
+                                          const KPass *__restrict__ P, const KPhase *__restrict__ H0,
+                                          uint32_t herm, const HalfIn &hin)
 {
-    uint32_t rg[4], rgm[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const uint32_t g = uni(H0->reg_gpos[b]) & 31u;
-        rg[b] = 1u << g;
-        rgm[b] = 1u << (mirror_pos(g, nq) & 31u);
-    }
     if (!(herm & kHermHalfIn)) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            uint32_t u = ht.gb;
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (e >> b & 1) u |= rg[b];
-            v[e] = lane[u];
-        }
+        for (int e = 0; e < 16; ++e) v[e] = lane[ht.gb | uni(H0->g_slot[e])];
         return;
     }
     uint32_t ig, jg;
@@ -313,15 +278,8 @@ __device__ __forceinline__ void load_herm(double2 (&v)[16], const double2 *__res
     const uint32_t i0 = ig | hin.it, j0 = jg | hin.jt;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        uint32_t u = ht.gb, um = ht.gbm, i = i0, j = j0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-            if (e >> b & 1) {
-                u |= rg[b];
-                um |= rgm[b];
-                i |= hin.ir[b];
-                j |= hin.jr[b];
-            }
+        const uint32_t u = ht.gb | uni(H0->g_slot[e]), um = ht.gbm | uni(H0->gm_slot[e]);
+        const uint32_t i = i0 | uni(P->hi_slot[e]), j = j0 | uni(P->hj_slot[e]);
         const bool tr = i > j;
         // one load from the selected address (not two loads and a select)
         const double2 w = *(tr ? lane_m + um : lane + u);
@@ -416,6 +374,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     const uint32_t wave_base = uni(tid & ~63u);
     const uint32_t pb = uni(P->phase_begin), pe = uni(P->phase_end);
     const KPhase *H0 = phases + pb, *HL = phases + pe - 1;
+    const bool multi_phase = pe - pb > 1;
 
     // stage the pass's runtime-diagonal factor tables in LDS after the tile
     const uint32_t rt_count = uni(P->rt_count);
@@ -447,7 +406,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
             tgM |= ((tid >> i) & 1u) << (mirror_pos(uni(HL->thr_gpos[i]), nq) & 31u);
             tg0M |= ((tid >> i) & 1u) << (mirror_pos(uni(H0->thr_gpos[i]), nq) & 31u);
         }
-        if (herm & kHermHalfIn) hin = half_in(passes + pass_idx - 1, H0, tg0, nq);
+        if (herm & kHermHalfIn) hin = half_in(P, tg0);
     }
     double2 *st_mirror = amps + tgM;
     const double2 *ld_mirror = amps + tg0M;
@@ -458,7 +417,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     if (t < n_tiles) {
         if (herm) {
             ht_nxt = herm_tile(P, t, ngb, herm);
-            load_herm(nxt, ld_lane, ld_mirror, ht_nxt, H0, nq, herm, hin);
+            load_herm(nxt, ld_lane, ld_mirror, ht_nxt, P, H0, herm, hin);
         } else {
             const uint32_t gb = group_base(P, t, ngb, xcd);
 #pragma unroll
@@ -482,11 +441,16 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
         // prefetch and the stores issued a whole tile ago; also keeps the
         // compiler from hoisting the stores below above this point
         __builtin_amdgcn_s_waitcnt(0x0F70);
-        // Hermitian mode with half storage: in a tile with i = j the waves
-        // load each other's amplitudes (through the transpose), so no wave
-        // may store the previous tile (below) before every wave has loaded
-        // it; without an LDS exchange nothing else orders the waves
-        if (herm & kHermHalfIn) __syncthreads();
+        // One barrier per tile serves two orderings:
+        // * within a phase each thread writes back to the LDS slots it read,
+        //   so phases need a barrier only between the writes and the next
+        //   reads; but the first writes of this tile land in slots that other
+        //   threads read in the previous tile's last phase;
+        // * Hermitian mode with half storage: in a tile with i = j the waves
+        //   load each other's amplitudes (through the transpose), so no wave
+        //   may store the previous tile (below) before every wave has loaded
+        //   it.
+        if ((herm & kHermHalfIn) || multi_phase) __syncthreads();
         double2 cur[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) cur[e] = nxt[e];
@@ -496,7 +460,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
                 const uint32_t u = gb_prev | slot_g(HL, e);
                 if (!(PHANTOM && ((u | tgL) >> kPhantomPos))) st_lane[u] = a[e];
             }
-            if (mirror_prev) store_mirror(st_mirror, gbm_prev, HL, nq, a);
+            if (mirror_prev) store_mirror(st_mirror, gbm_prev, HL, a);
         }
         const HermTile ht = ht_nxt;              // the tile prefetched last iteration
         const uint32_t gb = herm ? ht.gb : group_base(P, t, ngb, xcd);
@@ -506,7 +470,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
             const uint32_t t2 = (t + gridDim.x < n_tiles) ? t + gridDim.x : t;
             if (herm) {
                 if (t2 != t) ht_nxt = herm_tile(P, t2, ngb, herm);
-                load_herm(nxt, ld_lane, ld_mirror, ht_nxt, H0, nq, herm, hin);
+                load_herm(nxt, ld_lane, ld_mirror, ht_nxt, P, H0, herm, hin);
             } else {
                 const uint32_t gb2 = group_base(P, t2, ngb, xcd);
 #pragma unroll
@@ -535,15 +499,14 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
                     a[e] = *reinterpret_cast<const double2 *>(
-                        reinterpret_cast<const char *>(lds) + (lds_thr ^ (swz(slot_l(c.rl, e)) << 4)));
-                __syncthreads();
+                        reinterpret_cast<const char *>(lds) + (lds_thr ^ uni(H->lds_slot[e])));
             }
             apply_ops(a, H, ops, mats, lds_rt, c);
             if (ph + 1 < pe) {
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
                     *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
-                                                 (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
+                                                 (lds_thr ^ uni(H->lds_slot[e]))) = a[e];
                 __syncthreads();
             }
         }
@@ -562,7 +525,7 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
             const uint32_t u = gb_prev | slot_g(HL, e);
             if (!(PHANTOM && ((u | tgL) >> kPhantomPos))) st_lane[u] = a[e];
         }
-        if (mirror_prev) store_mirror(st_mirror, gbm_prev, HL, nq, a);
+        if (mirror_prev) store_mirror(st_mirror, gbm_prev, HL, a);
     }
 }
 
@@ -745,14 +708,14 @@ __device__ __forceinline__ void batch_phases(double2 (&a)[16], const KPhase *__r
         c.tl = (ph == pb) ? tl0 : (ph == pe - 1) ? tlL
              : thread_local_bits(H, active ? lane_tid(wave_base) : 0u, nthr);
         const uint32_t lds_thr = swz(c.tl) << 4;
-        if (ph != pb) {
-            if (active) {
+        // a thread writes back to the slots it read, so only the writes
+        // need a barrier before the next phase's reads (the first writes of
+        // a tile are ordered after the previous tile's reads by batch_pass)
+        if (ph != pb && active) {
 #pragma unroll
-                for (int e = 0; e < 16; ++e)
-                    a[e] = *reinterpret_cast<const double2 *>(
-                        reinterpret_cast<const char *>(lds) + (lds_thr ^ (swz(slot_l(c.rl, e)) << 4)));
-            }
-            __syncthreads();
+            for (int e = 0; e < 16; ++e)
+                a[e] = *reinterpret_cast<const double2 *>(
+                    reinterpret_cast<const char *>(lds) + (lds_thr ^ uni(H->lds_slot[e])));
         }
         if (active) apply_ops(a, H, ops, mats, lds_rt, c);
         if (ph + 1 < pe) {
@@ -760,7 +723,7 @@ __device__ __forceinline__ void batch_phases(double2 (&a)[16], const KPhase *__r
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
                     *reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
-                                                 (lds_thr ^ (swz(slot_l(c.rl, e)) << 4))) = a[e];
+                                                 (lds_thr ^ uni(H->lds_slot[e]))) = a[e];
             }
             __syncthreads();
         }
@@ -806,7 +769,7 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
             tgM |= ((ttid >> i) & 1u) << (mirror_pos(uni(HL->thr_gpos[i]), nq) & 31u);
             tg0M |= ((ttid >> i) & 1u) << (mirror_pos(uni(H0->thr_gpos[i]), nq) & 31u);
         }
-        if (herm & kHermHalfIn) hin = half_in(P - 1, H0, tg0, nq);
+        if (herm & kHermHalfIn) hin = half_in(P, tg0);
     }
     double2 *st_mirror = amps + tgM;
     const double2 *ld_mirror = amps + tg0M;
@@ -817,7 +780,7 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
     };
     auto load = [&](double2 (&v)[16], const HermTile &h) {
         if (herm) {
-            load_herm(v, ld_lane, ld_mirror, h, H0, nq, herm, hin);
+            load_herm(v, ld_lane, ld_mirror, h, P, H0, herm, hin);
         } else {
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = ld_lane[h.gb | slot_g(H0, e)];
@@ -827,11 +790,13 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
         if (!active || !h.valid) return;
 #pragma unroll
         for (int e = 0; e < 16; ++e) st_lane[h.gb | slot_g(HL, e)] = v[e];
-        if (h.mirror && (herm & kHermMirror)) store_mirror(st_mirror, h.gbm, HL, nq, v);
+        if (h.mirror && (herm & kHermMirror)) store_mirror(st_mirror, h.gbm, HL, v);
     };
-    // a tile with i = j is read through the transpose by other waves than
-    // the ones that store it: every wave's loads come before any store
-    const bool half_in_sync = (herm & kHermHalfIn) != 0;
+    // one barrier per tile: a tile with i = j is read through the transpose
+    // by other waves than the ones that store it, so every wave's loads come
+    // before any store; and the tile's first LDS writes come after the
+    // previous tile's last LDS reads
+    const bool half_in_sync = (herm & kHermHalfIn) != 0 || pe - pb > 1;
     double2 A[16], B[16];
     load(A, tile_at(0));
     for (uint32_t t = 0; t < n_tiles; t += 2) {

@@ -954,7 +954,47 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             if (i + 1 == out.passes.size()) out.passes[i].herm |= kHermMirror;
         }
     }
+    finish_slot_tables(n, out);
     return VQD_OK;
+}
+
+void finish_slot_tables(int n, HostPlan &plan)
+{
+    for (KPhase &H : plan.phases) {
+        for (int e = 0; e < kSlots; ++e) {
+            uint32_t l = 0, g = 0, gm = 0;
+            for (int b = 0; b < kRegBits; ++b)
+                if (e >> b & 1) {
+                    l |= 1u << (H.reg_local[b] & 31u);
+                    g |= 1u << (H.reg_gpos[b] & 31u);
+                    gm |= 1u << (mirror_pos(H.reg_gpos[b], (uint32_t)n) & 31u);
+                }
+            H.lds_slot[e] = lds_swizzle(l) << 4;
+            H.g_slot[e] = g;
+            H.gm_slot[e] = gm;
+        }
+    }
+    for (size_t p = 0; p < plan.passes.size(); ++p) {
+        KPass &P = plan.passes[p];
+        std::fill(P.hi_slot, P.hi_slot + kSlots, 0u);
+        std::fill(P.hj_slot, P.hj_slot + kSlots, 0u);
+        if (!(P.herm & kHermHalfIn) || p == 0) continue;
+        // the bits of slot e's index, taken at the previous pass's row
+        // (i) and column (j) group positions
+        const KPass &Q = plan.passes[p - 1];
+        const KPhase &H0 = plan.phases[P.phase_begin];
+        const uint32_t m = Q.n_group_bits >> 1;
+        for (int e = 0; e < kSlots; ++e) {
+            const uint32_t x = H0.g_slot[e];
+            uint32_t i = 0, j = 0;
+            for (uint32_t k = 0; k < m; ++k) {
+                i |= ((x >> (Q.group_gpos[k] & 31u)) & 1u) << k;
+                j |= ((x >> (Q.group_gpos[m + k] & 31u)) & 1u) << k;
+            }
+            P.hi_slot[e] = i;
+            P.hj_slot[e] = j;
+        }
+    }
 }
 
 namespace {

@@ -78,12 +78,29 @@ struct alignas(16) KOp {
     uint32_t pad[2];
 };
 
+// LDS index swizzle of the pass kernels: xor the low 3 bits of a local index
+// with a hash of its higher bits, so that strided register phases spread over
+// the banks.  Xor-linear: the swizzle of (thread bits | slot bits) is the xor
+// of the two parts' swizzles.
+__host__ __device__ inline uint32_t lds_swizzle(uint32_t l)
+{
+    return l ^ (((l >> 3) ^ (l >> 6) ^ (l >> 9)) & 7u);
+}
+
+// Row bit q <-> column bit q + n: the transpose of an index bit position.
+__host__ __device__ inline uint32_t mirror_pos(uint32_t g, uint32_t n) { return g < n ? g + n : g - n; }
+
 struct alignas(16) KPhase {
     uint32_t op_begin, op_end;
     uint32_t reg_local[4];
     uint32_t reg_gpos[4];
     uint32_t thr_local[kMaxThreadBits];
     uint32_t thr_gpos[kMaxThreadBits];
+    // Per register slot e (filled by finish_slot_tables from the fields
+    // above, so the kernels read them instead of recomputing them):
+    uint32_t lds_slot[kSlots];   // byte offset part in LDS: swizzle(local bits of e) * 16
+    uint32_t g_slot[kSlots];     // global index part: OR of 1 << reg_gpos[b] over the bits b of e
+    uint32_t gm_slot[kSlots];    // the same with every position mirrored (row <-> column bit)
 };
 
 struct alignas(16) KPass {
@@ -99,6 +116,12 @@ struct alignas(16) KPass {
     uint32_t herm;            // Hermitian mode (kHerm* flags): group_gpos holds m row bits,
                               // then their m column bits; the n_tiles = N(N+1)/2 tiles
                               // (N = 2^m) are the group pairs i <= j
+    // kHermHalfIn: the previous pass's group pair (i, j) of the amplitude in
+    // register slot e of this pass's first phase takes the bits hi_slot[e]
+    // into i and hj_slot[e] into j (the thread and tile parts are added by
+    // the kernel); filled by finish_slot_tables
+    uint32_t hi_slot[kSlots];
+    uint32_t hj_slot[kSlots];
 };
 constexpr uint32_t kHermPass = 1u;     // computes the tiles i <= j only
 constexpr uint32_t kHermMirror = 2u;   // also stores each i < j tile's conjugate transpose
@@ -197,6 +220,9 @@ struct PlanOpts {
                                     // op preserves Hermiticity (HostPlan::hermitian says if)
 };
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out);
+// Fill the per-slot tables of every phase and pass of a plan (KPhase::lds_slot,
+// g_slot, gm_slot; KPass::hi_slot, hj_slot) from their bit assignments.
+void finish_slot_tables(int n, HostPlan &plan);
 // Recompute a recorded plan's coefficients for new logical ops of the same
 // structure (same kinds and targets).  mats gets the plan's layout.
 int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std::vector<cd> &mats);
