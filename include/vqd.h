@@ -32,7 +32,10 @@
  * reduction partials), freed by the matching destroy call.
  *
  * Streams.  Apply and init calls are asynchronous on the handle's HIP stream.
- * vqd_calc_* calls synchronise that stream and write host outputs.
+ * vqd_calc_* calls synchronise that stream and write host outputs; their
+ * vqd_calc_*_dev forms are asynchronous, write device outputs and allocate
+ * nothing, so that init, a program and its read-outs can be captured in one
+ * HIP graph.
  *
  * Errors.  Every call returns 0 (VQD_OK) or a negative code; the message of
  * the last failure on the calling thread is returned by vqd_last_error().  No
@@ -192,7 +195,7 @@ int vqd_kind_superop(int kind, const double *params, double *out);
  * share, eps the smaller root in [0, 1]; VQD_E_ARG if there is none.
  * vqd_angle_scaled_error: eps |theta| / pi (App. C, rotation-angle scaling).
  * vqd_zz_crosstalk_strength: the static ZZ coupling of two transmons (Sec.
- * 7), beta = J^2 (1/(delta_ct - alpha_t) - 1/(delta_ct + alpha_c)) from the
+ * 8), beta = J^2 (1/(delta_ct - alpha_t) - 1/(delta_ct + alpha_c)) from the
  * coupling strength J, the frequency difference delta_ct = f_c - f_t and
  * the anharmonicities alpha_c, alpha_t, all in one frequency unit; the
  * result is in that unit.  VQD_E_ARG for a non-finite input or a zero
@@ -400,6 +403,28 @@ int vqd_calc_expec_zz(const vqd_dm *dm, const int *pairs, int npairs, double *ou
 /* Tr(P rho) for the Pauli string P = (x)_q sigma_{codes[q]}, codes[q] in
  * {0=I, 1=X, 2=Y, 3=Z} (Sec. 2: expectation values of Pauli strings). */
 int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, double *im);
+
+/* Device-output read-outs (Sec. 2: expectation values and density-matrix
+ * elements read from the state).  The same quantities, reduced in the same
+ * fixed order as the calls above (so the values are bit-identical to
+ * theirs), written to caller-owned DEVICE memory: out of vqd_calc_trace_dev
+ * holds 2 doubles (re, im), of _purity_dev 1, of _probs_dev 2^n, of
+ * _expec_z_dev n, of _expec_zz_dev npairs, of _expec_pauli_dev 2 (re, im).
+ * vqd_calc_expec_zz_dev reads its pairs from DEVICE memory (2*npairs ints);
+ * the Pauli codes stay a host array (read during the call).
+ * Asynchronous on the handle's stream: the outputs are valid once that
+ * stream has reached the call.  No allocation, no synchronisation and no
+ * host copy: the partial sums go to a scratch buffer that vqd_dm_wrap
+ * allocates once per handle, so these calls may be captured into a HIP graph
+ * together with init and program calls.  Calls on one handle share that
+ * scratch and are ordered by its stream.  Errors: VQD_E_ARG (null pointer,
+ * bad pair count, Pauli code > 3); nothing is enqueued on an error. */
+int vqd_calc_trace_dev(const vqd_dm *dm, double *out);
+int vqd_calc_purity_dev(const vqd_dm *dm, double *out);
+int vqd_calc_probs_dev(const vqd_dm *dm, double *out);
+int vqd_calc_expec_z_dev(const vqd_dm *dm, double *out);
+int vqd_calc_expec_zz_dev(const vqd_dm *dm, const int *pairs, int npairs, double *out);
+int vqd_calc_expec_pauli_dev(const vqd_dm *dm, const uint8_t *codes, double *out);
 
 /* ------------------------------------------------------------- surrogate */
 

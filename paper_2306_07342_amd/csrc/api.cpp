@@ -148,6 +148,16 @@ int vqd_dm_wrap(void *dev_amps, int n, size_t bytes, void *hip_stream, vqd_dm **
     dm->bytes = bytes;
     dm->stream = static_cast<hipStream_t>(hip_stream);
     (void)hipGetDevice(&dm->device);
+    // the device-output read-outs never allocate (they may be captured in a
+    // graph): their scratch is sized for this n here, once (on a host with
+    // no GPU there is nothing to allocate, and those calls report that)
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+        if (int rc = ensure_scratch(dm->gred, readout_scratch_doubles(n), 0)) {
+            delete dm;
+            return rc;
+        }
+    }
     *out = dm;
     return VQD_OK;
 }
@@ -159,6 +169,7 @@ int vqd_dm_destroy(vqd_dm *dm)
     (void)hipStreamSynchronize(dm->stream);
     free_dev_program(dm->imm);
     free_scratch(dm->red);
+    free_scratch(dm->gred);
     delete dm;
     return VQD_OK;
 }
@@ -600,6 +611,66 @@ int vqd_calc_expec_pauli(const vqd_dm *dm, const uint8_t *codes, double *re, dou
     }
     auto *m = const_cast<vqd_dm *>(dm);
     return reduce_pauli(m->amps, m->n, xm, zm, ny, m->red, m->stream, re, im);
+}
+
+// ------------------------------------------------- device-output read-outs --
+
+int vqd_calc_trace_dev(const vqd_dm *dm, double *out)
+{
+    clear_error();
+    if (int rc = check_dm(dm)) return rc;
+    if (!out) return fail(VQD_E_ARG, "null output");
+    return reduce_diag_dev(dm->amps, dm->n, dm->gred, dm->stream, out, nullptr, nullptr);
+}
+
+int vqd_calc_purity_dev(const vqd_dm *dm, double *out)
+{
+    clear_error();
+    if (int rc = check_dm(dm)) return rc;
+    if (!out) return fail(VQD_E_ARG, "null output");
+    return reduce_purity_dev(dm->amps, dm->n, dm->gred, dm->stream, out);
+}
+
+int vqd_calc_probs_dev(const vqd_dm *dm, double *out)
+{
+    clear_error();
+    if (int rc = check_dm(dm)) return rc;
+    if (!out) return fail(VQD_E_ARG, "null output");
+    return reduce_diag_dev(dm->amps, dm->n, dm->gred, dm->stream, nullptr, nullptr, out);
+}
+
+int vqd_calc_expec_z_dev(const vqd_dm *dm, double *out)
+{
+    clear_error();
+    if (int rc = check_dm(dm)) return rc;
+    if (!out) return fail(VQD_E_ARG, "null output");
+    return reduce_diag_dev(dm->amps, dm->n, dm->gred, dm->stream, nullptr, out, nullptr);
+}
+
+int vqd_calc_expec_zz_dev(const vqd_dm *dm, const int *pairs, int npairs, double *out)
+{
+    clear_error();
+    if (int rc = check_dm(dm)) return rc;
+    if (npairs < 0 || (npairs > 0 && (!pairs || !out))) return fail(VQD_E_ARG, "bad pair arguments");
+    if (npairs == 0) return VQD_OK;
+    return reduce_zz_dev(dm->amps, dm->n, pairs, npairs, dm->gred, dm->stream, out);
+}
+
+int vqd_calc_expec_pauli_dev(const vqd_dm *dm, const uint8_t *codes, double *out)
+{
+    clear_error();
+    if (int rc = check_dm(dm)) return rc;
+    if (!codes || !out) return fail(VQD_E_ARG, "null argument");
+    uint64_t xm = 0, zm = 0;
+    int ny = 0;
+    for (int q = 0; q < dm->n; ++q) {
+        const int c = codes[q];
+        if (c > 3) return fail(VQD_E_ARG, "Pauli code must be 0..3");
+        if (c == 1 || c == 2) xm |= 1ull << q;
+        if (c == 2 || c == 3) zm |= 1ull << q;
+        ny += (c == 2);
+    }
+    return reduce_pauli_dev(dm->amps, dm->n, xm, zm, ny, dm->gred, dm->stream, out);
 }
 
 }  // extern "C"

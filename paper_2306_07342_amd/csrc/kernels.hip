@@ -623,6 +623,50 @@ k_finish(const double *__restrict__ partials, int nb, int nv, double *__restrict
     }
 }
 
+// Fixed-order sums of the diagonal partials (layout [block][2 + n]) written
+// to separate outputs: trace (re, im) to tr, <Z_i> to z (either may be null).
+__global__ void __launch_bounds__(kThreads)
+k_finish_diag(const double *__restrict__ partials, int nb, int n, double *__restrict__ tr,
+              double *__restrict__ z)
+{
+    __shared__ double smem[4];
+    const int nv = 2 + n;
+    for (int k = 0; k < nv; ++k) {
+        if ((k < 2 && !tr) || (k >= 2 && !z)) continue;
+        double v[1] = {0.0};
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += partials[(size_t)b * nv + k];
+        block_sum<1>(v, smem);
+        if (threadIdx.x == 0) {
+            if (k < 2) tr[k] = v[0];
+            else z[k - 2] = v[0];
+        }
+        __syncthreads();
+    }
+}
+
+// Fixed-order sum of the Pauli partials (layout [block][2]) times i^ny.
+__global__ void __launch_bounds__(kThreads)
+k_finish_pauli(const double *__restrict__ partials, int nb, int ny, double *__restrict__ out)
+{
+    __shared__ double smem[8];
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        v[0] += partials[(size_t)b * 2];
+        v[1] += partials[(size_t)b * 2 + 1];
+    }
+    block_sum<2>(v, smem);
+    if (threadIdx.x == 0) {
+        double a = v[0], c = v[1];
+        for (int k = 0; k < (ny & 3); ++k) {
+            const double t = a;
+            a = -c;
+            c = t;
+        }
+        out[0] = a;
+        out[1] = c;
+    }
+}
+
 // Diagonal read-out: trace (re, im), <Z_i> and optionally the probabilities.
 // partials layout: [block][2 + n].
 __global__ void __launch_bounds__(kThreads)
@@ -1086,6 +1130,83 @@ int reduce_pauli(const double2 *amps, int n, uint64_t xmask, uint64_t zmask, int
     }
     *re = a;
     *im = b;
+    return VQD_OK;
+}
+
+// ------------------------------------------------- device-output read-outs --
+// The same kernels as the synchronous read-outs, writing into caller device
+// memory; the partials go to a scratch that is allocated once per handle
+// (never inside these calls), so that the calls can be captured in a graph.
+size_t readout_scratch_doubles(int n)
+{
+    const uint64_t D = 1ull << n;
+    const size_t diag = (size_t)256 * (2 + n) + D;      // partials, then the probabilities (<ZZ>)
+    return std::max<size_t>(diag, kRedBlocks) + 8;
+}
+
+static int check_readout_scratch(const ReduceScratch &s, int n)
+{
+    if (!s.dev || s.cap < readout_scratch_doubles(n))
+        return fail(VQD_E_NOMEM, "no device read-out scratch (the handle was wrapped without a GPU)");
+    return VQD_OK;
+}
+
+int reduce_purity_dev(const double2 *amps, int n, const ReduceScratch &s, hipStream_t st, double *out)
+{
+    if (int rc = check_readout_scratch(s, n)) return rc;
+    const uint64_t count = 1ull << (2 * n);
+    uint64_t blocks = (count + kThreads - 1) / kThreads;
+    if (blocks > kRedBlocks) blocks = kRedBlocks;
+    hipLaunchKernelGGL(k_purity, dim3((uint32_t)blocks), dim3(kThreads), 0, st, amps, count, s.dev);
+    VQD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, s.dev, (int)blocks, 1, out);
+    VQD_HIP(hipGetLastError());
+    return VQD_OK;
+}
+
+int reduce_diag_dev(const double2 *amps, int n, const ReduceScratch &s, hipStream_t st, double *tr, double *z,
+                    double *probs)
+{
+    if (int rc = check_readout_scratch(s, n)) return rc;
+    const uint64_t D = 1ull << n;
+    uint64_t blocks = (D + kThreads - 1) / kThreads;
+    if (blocks > 256) blocks = 256;
+    hipLaunchKernelGGL(k_diag, dim3((uint32_t)blocks), dim3(kThreads), 0, st, amps, n, probs, s.dev);
+    VQD_HIP(hipGetLastError());
+    if (tr || z) {
+        hipLaunchKernelGGL(k_finish_diag, dim3(1), dim3(kThreads), 0, st, s.dev, (int)blocks, n, tr, z);
+        VQD_HIP(hipGetLastError());
+    }
+    return VQD_OK;
+}
+
+int reduce_zz_dev(const double2 *amps, int n, const int *pairs, int npairs, const ReduceScratch &s,
+                  hipStream_t st, double *out)
+{
+    if (int rc = check_readout_scratch(s, n)) return rc;
+    const uint64_t D = 1ull << n;
+    uint64_t blocks = (D + kThreads - 1) / kThreads;
+    if (blocks > 256) blocks = 256;
+    double *probs = s.dev + (size_t)256 * (2 + n);
+    hipLaunchKernelGGL(k_diag, dim3((uint32_t)blocks), dim3(kThreads), 0, st, amps, n, probs, s.dev);
+    VQD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_zz, dim3(npairs), dim3(kThreads), 0, st, probs, n, reinterpret_cast<const int2 *>(pairs),
+                       out);
+    VQD_HIP(hipGetLastError());
+    return VQD_OK;
+}
+
+int reduce_pauli_dev(const double2 *amps, int n, uint64_t xmask, uint64_t zmask, int ny, const ReduceScratch &s,
+                     hipStream_t st, double *out)
+{
+    if (int rc = check_readout_scratch(s, n)) return rc;
+    const uint64_t D = 1ull << n;
+    uint64_t blocks = (D + kThreads - 1) / kThreads;
+    if (blocks > 256) blocks = 256;
+    hipLaunchKernelGGL(k_pauli, dim3((uint32_t)blocks), dim3(kThreads), 0, st, amps, n, xmask, zmask, s.dev);
+    VQD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_pauli, dim3(1), dim3(kThreads), 0, st, s.dev, (int)blocks, ny, out);
+    VQD_HIP(hipGetLastError());
     return VQD_OK;
 }
 

@@ -343,6 +343,16 @@ int reduce_zz(const double2 *amps, int n, const int *pairs, int npairs, ReduceSc
               hipStream_t st, double *out);
 int reduce_pauli(const double2 *amps, int n, uint64_t xmask, uint64_t zmask, int ny,
                  ReduceScratch &s, hipStream_t st, double *re, double *im);
+// Device-output forms: no allocation, no synchronisation, no host copy.  `s`
+// holds readout_scratch_doubles(n) doubles of device memory.
+size_t readout_scratch_doubles(int n);
+int reduce_purity_dev(const double2 *amps, int n, const ReduceScratch &s, hipStream_t st, double *out);
+int reduce_diag_dev(const double2 *amps, int n, const ReduceScratch &s, hipStream_t st, double *tr, double *z,
+                    double *probs);
+int reduce_zz_dev(const double2 *amps, int n, const int *pairs, int npairs, const ReduceScratch &s,
+                  hipStream_t st, double *out);
+int reduce_pauli_dev(const double2 *amps, int n, uint64_t xmask, uint64_t zmask, int ny, const ReduceScratch &s,
+                     hipStream_t st, double *out);
 
 // ------------------------------------------------------------- builders --
 int kind_arity(int kind, int *nq, int *np);
@@ -367,7 +377,8 @@ struct vqd_dm {
     hipStream_t stream = nullptr;
     int device = 0;
     vqd::DevProgram imm;            // descriptors of immediate (single-op) calls
-    vqd::ReduceScratch red;
+    vqd::ReduceScratch red;         // synchronous read-outs (grows on demand)
+    vqd::ReduceScratch gred;        // device-output read-outs: fixed size, allocated by the wrap
 };
 
 struct vqd_prog {

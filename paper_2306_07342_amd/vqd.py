@@ -190,6 +190,12 @@ def load(path: str = LIB_PATH):
         "vqd_calc_expec_z": ([vp, _dp], ctypes.c_int),
         "vqd_calc_expec_zz": ([vp, _ip, ctypes.c_int, _dp], ctypes.c_int),
         "vqd_calc_expec_pauli": ([vp, ctypes.POINTER(ctypes.c_uint8), _dp, _dp], ctypes.c_int),
+        "vqd_calc_trace_dev": ([vp, vp], ctypes.c_int),
+        "vqd_calc_purity_dev": ([vp, vp], ctypes.c_int),
+        "vqd_calc_probs_dev": ([vp, vp], ctypes.c_int),
+        "vqd_calc_expec_z_dev": ([vp, vp], ctypes.c_int),
+        "vqd_calc_expec_zz_dev": ([vp, vp, ctypes.c_int, vp], ctypes.c_int),
+        "vqd_calc_expec_pauli_dev": ([vp, ctypes.POINTER(ctypes.c_uint8), vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -422,6 +428,46 @@ class DensityMatrix:
         check(lib().vqd_calc_expec_pauli(self.handle, c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                          ctypes.byref(re), ctypes.byref(im)))
         return complex(re.value, im.value)
+
+    # -- device-output read-outs (asynchronous, no allocation; capturable) --
+    @staticmethod
+    def _dev_out(t, count: int, dtype_name: str = "float64"):
+        import torch
+        want = getattr(torch, dtype_name)
+        if not (t.is_cuda and t.dtype == want and t.is_contiguous() and t.numel() >= count):
+            raise ValueError("output must be a contiguous CUDA %s tensor of at least %d elements"
+                             % (dtype_name, count))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def trace_dev(self, out):
+        """vqd_calc_trace_dev: (re, im) into out[0:2]."""
+        check(lib().vqd_calc_trace_dev(self.handle, self._dev_out(out, 2)))
+        return out
+
+    def purity_dev(self, out):
+        check(lib().vqd_calc_purity_dev(self.handle, self._dev_out(out, 1)))
+        return out
+
+    def probs_dev(self, out):
+        check(lib().vqd_calc_probs_dev(self.handle, self._dev_out(out, 1 << self.n)))
+        return out
+
+    def expec_z_dev(self, out):
+        check(lib().vqd_calc_expec_z_dev(self.handle, self._dev_out(out, self.n)))
+        return out
+
+    def expec_zz_dev(self, pairs, out):
+        """pairs: CUDA int32 tensor (npairs, 2)."""
+        npairs = pairs.numel() // 2
+        check(lib().vqd_calc_expec_zz_dev(self.handle, self._dev_out(pairs, 2 * npairs, "int32"), npairs,
+                                          self._dev_out(out, npairs)))
+        return out
+
+    def expec_pauli_dev(self, codes, out):
+        c = np.ascontiguousarray(codes, dtype=np.uint8)
+        check(lib().vqd_calc_expec_pauli_dev(self.handle, c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                             self._dev_out(out, 2)))
+        return out
 
 
 def plan_opts(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True,
