@@ -426,6 +426,20 @@ int vqd_calc_expec_z_dev(const vqd_dm *dm, double *out);
 int vqd_calc_expec_zz_dev(const vqd_dm *dm, const int *pairs, int npairs, double *out);
 int vqd_calc_expec_pauli_dev(const vqd_dm *dm, const uint8_t *codes, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc), which
+ * therefore cannot wrap a handle: <Z_i> of the state in dev_amps (4^n
+ * complex128, layout as for vqd_dm_wrap, n in [1, VQD_MAX_QUBITS]) written
+ * to the DEVICE array out[n] on hip_stream, asynchronously, with the same
+ * kernels and summation order as vqd_calc_expec_z_dev (bit-identical
+ * values).  Allocates nothing: the partial sums go to a static device
+ * scratch of 256 * (2 + VQD_MAX_QUBITS) doubles (36 KiB) that every GPU the
+ * library runs on holds until the process ends.  All calls on one GPU share
+ * that scratch: calls that overlap in time on one GPU (different streams or
+ * threads without ordering) race and may return wrong values.  Errors:
+ * VQD_E_ARG (null pointer), VQD_E_SIZE (n out of range), VQD_E_HIP. */
+int vqd_calc_expec_z_noalloc(const void *dev_amps, int n, void *hip_stream, double *out);
+
 /* ------------------------------------------------------------- surrogate */
 
 /* Virtual-device noise insertion (Sec. 2: a device specification maps an

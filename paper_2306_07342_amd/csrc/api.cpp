@@ -673,4 +673,13 @@ int vqd_calc_expec_pauli_dev(const vqd_dm *dm, const uint8_t *codes, double *out
     return reduce_pauli_dev(dm->amps, dm->n, xm, zm, ny, dm->gred, dm->stream, out);
 }
 
+int vqd_calc_expec_z_noalloc(const void *dev_amps, int n, void *hip_stream, double *out)
+{
+    clear_error();
+    if (!dev_amps || !out) return fail(VQD_E_ARG, "null argument");
+    if (n < 1 || n > VQD_MAX_QUBITS)
+        return fail(VQD_E_SIZE, "n must be in [1, " + std::to_string(VQD_MAX_QUBITS) + "]");
+    return expec_z_noalloc(static_cast<const double2 *>(dev_amps), n, static_cast<hipStream_t>(hip_stream), out);
+}
+
 }  // extern "C"

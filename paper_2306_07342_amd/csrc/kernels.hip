@@ -8,6 +8,8 @@
 //                 stage, so results are deterministic).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "vqd_internal.h"
 #include "dev_common.h"
 
@@ -1206,6 +1208,54 @@ int reduce_pauli_dev(const double2 *amps, int n, uint64_t xmask, uint64_t zmask,
     hipLaunchKernelGGL(k_pauli, dim3((uint32_t)blocks), dim3(kThreads), 0, st, amps, n, xmask, zmask, s.dev);
     VQD_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_finish_pauli, dim3(1), dim3(kThreads), 0, st, s.dev, (int)blocks, ny, out);
+    VQD_HIP(hipGetLastError());
+    return VQD_OK;
+}
+
+// ----------------------------------------------- read-out without allocation --
+// The partials of vqd_calc_expec_z_noalloc: one file-scope device array,
+// sized for the largest state (256 blocks of 2 + VQD_MAX_QUBITS sums).  Each
+// GPU the library runs on holds its own copy until the process ends.  In host
+// code its name is not a device address; hipGetSymbolAddress gives each
+// device's copy, kept in noalloc_scratch_ptr[device].
+constexpr size_t kNoAllocScratch = (size_t)256 * (2 + VQD_MAX_QUBITS);
+static __device__ __align__(256) double scratch[kNoAllocScratch];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mutex;
+static double *g_noalloc_ptr[kMaxDevices];
+
+static int noalloc_scratch_ptr(double **out)
+{
+    int dev = 0;
+    VQD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(VQD_E_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[dev]) {
+        // once per device, with that device current
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e,
+                                                   "hipGetSymbolAddress(scratch)");
+        g_noalloc_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return VQD_OK;
+}
+
+int expec_z_noalloc(const double2 *amps, int n, hipStream_t st, double *out)
+{
+    double *sc = nullptr;
+    if (int rc = noalloc_scratch_ptr(&sc)) return rc;
+    const uint64_t D = 1ull << n;
+    uint64_t blocks = (D + kThreads - 1) / kThreads;
+    if (blocks > 256) blocks = 256;
+    if (blocks * (2 + (uint64_t)n) > kNoAllocScratch) return fail(VQD_E_SIZE, "state too large for the static scratch");
+    // every block writes its own partials before k_finish_diag reads them,
+    // so nothing left from an earlier call needs clearing
+    hipLaunchKernelGGL(k_diag, dim3((uint32_t)blocks), dim3(kThreads), 0, st, amps, n, nullptr, sc);
+    VQD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_diag, dim3(1), dim3(kThreads), 0, st, sc, (int)blocks, n, nullptr, out);
     VQD_HIP(hipGetLastError());
     return VQD_OK;
 }

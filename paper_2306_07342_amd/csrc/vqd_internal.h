@@ -353,6 +353,9 @@ int reduce_zz_dev(const double2 *amps, int n, const int *pairs, int npairs, cons
                   hipStream_t st, double *out);
 int reduce_pauli_dev(const double2 *amps, int n, uint64_t xmask, uint64_t zmask, int ny, const ReduceScratch &s,
                      hipStream_t st, double *out);
+// <Z_i> into device memory with the library's static device scratch: no
+// handle, no allocation.
+int expec_z_noalloc(const double2 *amps, int n, hipStream_t st, double *out);
 
 // ------------------------------------------------------------- builders --
 int kind_arity(int kind, int *nq, int *np);

@@ -196,6 +196,7 @@ def load(path: str = LIB_PATH):
         "vqd_calc_expec_z_dev": ([vp, vp], ctypes.c_int),
         "vqd_calc_expec_zz_dev": ([vp, vp, ctypes.c_int, vp], ctypes.c_int),
         "vqd_calc_expec_pauli_dev": ([vp, ctypes.POINTER(ctypes.c_uint8), vp], ctypes.c_int),
+        "vqd_calc_expec_z_noalloc": ([vp, ctypes.c_int, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -468,6 +469,18 @@ class DensityMatrix:
         check(lib().vqd_calc_expec_pauli_dev(self.handle, c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                              self._dev_out(out, 2)))
         return out
+
+
+def calc_expec_z_noalloc(amps, n: int, out, stream=None):
+    """vqd_calc_expec_z_noalloc: <Z_i> of the state in the CUDA float64 tensor
+    `amps` (2 * 4^n values) into the CUDA float64 tensor `out` (n values),
+    without a handle and without any allocation by the library."""
+    for t, count in ((amps, 2 * 4 ** n), (out, n)):
+        if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float64" and t.numel() >= count):
+            raise ValueError("amps and out must be contiguous CUDA float64 tensors of 2*4^n and n values")
+    check(lib().vqd_calc_expec_z_noalloc(ctypes.c_void_p(amps.data_ptr()), n, _stream_ptr(stream),
+                                         ctypes.c_void_p(out.data_ptr())))
+    return out
 
 
 def plan_opts(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True,
