@@ -481,6 +481,14 @@ int plan(vqd_traj *t)
         for (int q = 4; q < ne; ++q) ph.thr_q[q - 4] = (uint32_t)q;
         t->phases.push_back(ph);
     }
+    // per-slot LDS index parts (the swizzle is xor-linear in the index bits)
+    for (TPhase &ph : t->phases)
+        for (int e = 0; e < kSlots; ++e) {
+            uint32_t l = 0;
+            for (int b = 0; b < 4; ++b)
+                if (e >> b & 1) l |= 1u << (ph.reg_q[b] & 31u);
+            ph.lds_slot[e] = lds_swizzle(l);
+        }
     // the kernels may read up to 16 operators of 16 entries past an op's data
     t->pool.resize(t->pool.size() + 256, cd(0));
     return VQD_OK;

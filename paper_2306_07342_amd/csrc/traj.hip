@@ -449,7 +449,7 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
             } else {
                 const uint32_t lt = swz(c.tl) ^ gx;
 #pragma unroll
-                for (int e = 0; e < 16; ++e) a[e] = xl[lt ^ swz(slot_l(c.rl, e))];
+                for (int e = 0; e < 16; ++e) a[e] = xl[lt ^ uni(H->lds_slot[e])];
                 // the barrier that lets the next exchange overwrite this one:
                 // a general channel's reduction in the phase is one already
                 if (!shared_tile) wave_lds_sync();
@@ -472,7 +472,7 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
             if (ph + 1 < n_phases) {
                 const uint32_t lt = swz(traj_thread_bits(H, tt)) ^ gx;
 #pragma unroll
-                for (int e = 0; e < 16; ++e) xl[lt ^ swz(slot_l(c.rl, e))] = a[e];
+                for (int e = 0; e < 16; ++e) xl[lt ^ uni(H->lds_slot[e])] = a[e];
                 if (shared_tile) __syncthreads();
                 else wave_lds_sync();
             }

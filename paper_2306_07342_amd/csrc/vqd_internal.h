@@ -285,6 +285,7 @@ struct alignas(16) TPhase {
     uint32_t reg_q[4];                      // qubit of register bit b
     uint32_t thr_q[kTrajMaxThreadBits];     // qubit of thread bit i (zero-filled past n_eff - 4)
     uint32_t flags;                         // kTPhaseReduces
+    uint32_t lds_slot[kSlots];              // swizzled LDS index part of register slot e
 };
 // The phase holds a general channel, whose weights are a reduction over the
 // whole state (a workgroup barrier when a trajectory spans several waves).

@@ -30,9 +30,12 @@ def parse(blob: bytes) -> dict:
     h = np.frombuffer(blob, dtype="<u4", count=10)
     assert h[0] == MAGIC and h[1] == 1
     n, ne, nch, nph, nop, npool, szp, szo = (int(x) for x in h[2:10])
-    assert szp == PHASE.itemsize and szo == OP.itemsize
+    assert szp >= PHASE.itemsize and szo == OP.itemsize
     off = 40
-    phases = np.frombuffer(blob, dtype=PHASE, count=nph, offset=off)
+    # the phase records may carry fields past the ones read here (kernel tables)
+    dph = np.dtype({"names": list(PHASE.names), "formats": [PHASE.fields[k][0] for k in PHASE.names],
+                    "offsets": [PHASE.fields[k][1] for k in PHASE.names], "itemsize": szp})
+    phases = np.frombuffer(blob, dtype=dph, count=nph, offset=off)
     off += nph * szp
     ops = np.frombuffer(blob, dtype=OP, count=nop, offset=off)
     off += nop * szo
