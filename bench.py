@@ -360,9 +360,12 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
     """The learned surrogate of the 10-qubit, 4-layer ansatz (8 device
     parameters + 16 angles -> 10 <Z_i>): training data from the batched
     emulator, training by the library's kernels, then evals/s with fallback
-    (spread > 5e-3) against the emulator alone on a held-out set, judged by
-    the emulator at |dZ| < 1e-2.  A device-parameter sweep at fixed angles is
-    reported beside it."""
+    against the emulator alone on a held-out set, judged by the emulator at
+    |dZ| < 1e-2.  The fallback threshold is the product default, calibrated
+    by the emulator on a validation set; the configured fixed threshold
+    (spread >= 5e-3 falls back) is reported beside it with the accuracy of
+    what it accepts.  A device-parameter sweep at fixed angles is reported
+    beside the uniform-angle workload."""
     import numpy as np
     from paper_2306_07342_amd.surrogate import SurrogateModel, TemplateEmulator, measure_gain
     from workloads import SEED_BASE, c5_draw_samples, c5_params, c5_structure
@@ -395,15 +398,18 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
         t_train = time.perf_counter() - t0
         log("surrogate: %d epochs in %.1f s, loss %s" % (ep, t_train, model.history[-1]))
         Pt, xt = data(n_te, seeds[1], fixed)
-        res = measure_gain(model, emu, Pt, xt, threshold=5e-3, tol=1e-2)
         # the emulator as judge: calibrate the spread threshold on a held-out
         # validation set so that accepted answers stay within |dZ| < 1e-2
+        # (the product default); then measure on the test set with it
         Pv, xv = data(max(1024, n_te // 4), seeds[2], fixed)
-        thr = model.calibrate(xv, emu.run(Pv), tol=1e-2)
-        cal = measure_gain(model, emu, Pt, xt, threshold=thr, tol=1e-2)
-        res["calibrated"] = {k: cal[k] for k in ("threshold", "surrogate_evals_per_s", "surrogate_good_evals_per_s",
-                                                  "gain_at_tol", "fallback_fraction", "accepted_within_tol_fraction",
-                                                  "max_abs_dz_accepted")}
+        model.calibrate(xv, emu.run(Pv), tol=1e-2)
+        res = measure_gain(model, emu, Pt, xt, tol=1e-2)
+        res["threshold_source"] = "calibrated on %d validation samples by the emulator" % Pv.shape[0]
+        fx = measure_gain(model, emu, Pt, xt, threshold=5e-3, tol=1e-2)
+        res["at_configured_5e-3"] = {k: fx[k] for k in ("surrogate_evals_per_s", "surrogate_good_evals_per_s",
+                                                         "gain_at_tol", "fallback_fraction",
+                                                         "accepted_within_tol_fraction", "max_abs_dz_accepted",
+                                                         "median_abs_dz_accepted")}
         res.update({"train_samples": n_tr, "data_gen_s": round(t_data, 2),
                     "data_gen_evals_per_s": round(n_tr / t_data, 1), "epochs": ep, "batch": 512,
                     "train_s": round(t_train, 2), "final_train_mse": [float(v) for v in model.history[-1]]})
@@ -411,7 +417,8 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
 
     out = {"metric": "surrogate vs emulator evals/s at |dZ|<1e-2 (10-qubit 4-layer ansatz)",
            "config": "8 device parameters + 16 angles drawn uniformly, 4 x MLP 24-256-256-256-10 GELU, "
-                     "bf16 operands / FP32 accumulate, fallback when spread > 5e-3"}
+                     "bf16 operands / FP32 accumulate; fallback above an emulator-calibrated spread "
+                     "threshold (the configured 5e-3 reported beside it)"}
     out["template_tiles"] = {"tile_bits": emu.opts.tile_bits, "min_contig_bits": emu.opts.min_contig_bits,
                              "source": "autotuned (%s)" % ("cached" if tuned else "fresh")}
     out["uniform_angles"] = run(n_train, n_test, epochs, (SEED_BASE + 4, SEED_BASE + 6, SEED_BASE + 11))

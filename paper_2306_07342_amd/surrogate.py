@@ -99,6 +99,9 @@ class SurrogateModel:
     def __init__(self, init_params: np.ndarray, max_batch: int = 4096):
         self.net = vqd.Surrogate(members=init_params.shape[0], max_batch=max_batch, params=init_params)
         self.history = []
+        # spread threshold under which a prediction is accepted; set only by
+        # calibrate() against the emulator.  None: every sample falls back.
+        self.threshold: Optional[float] = None
 
     def fit(self, x, y, epochs: int, batch: int = 1024, lr: float = 2e-3, lr_min: float = 1e-5,
             seed: int = 0, log: Optional[Callable[[str], None]] = None):
@@ -131,42 +134,56 @@ class SurrogateModel:
         return self.net.predict(x)
 
     def calibrate(self, x, exact, tol: float = 1e-2, quantile: float = 1.0) -> float:
-        """The largest spread threshold under which the accepted samples of a
-        held-out set (inputs x, exact values from the emulator, the judge)
-        stay within max_i |dZ_i| < tol; with quantile < 1 that fraction of
-        them must.  Returns 0 when even the lowest-spread sample misses."""
-        import torch
+        """Set and return the spread threshold: a prediction is accepted when
+        its spread is strictly below it.  Chosen on a held-out set (inputs x,
+        exact values from the emulator, the judge) as the largest threshold
+        under which the accepted samples stay within max_i |dZ_i| < tol; with
+        quantile < 1, that fraction of them must.  Samples whose spread ties
+        a rejected one are rejected with it.  0 (accept nothing) when even
+        the lowest-spread sample misses."""
         mean, spread = self.net.predict(x)
         err = (mean.double() - exact).abs().max(dim=1).values.cpu().numpy()
-        sp = spread.cpu().numpy()
+        sp = spread.double().cpu().numpy()
         order = np.argsort(sp, kind="stable")
         bad = err[order] >= tol
-        # accepted set {spread <= thr} grows along `order`; keep the longest
+        # accepted set {spread < thr} grows along `order`; keep the longest
         # prefix whose miss fraction stays within 1 - quantile
         misses = np.cumsum(bad)
         ok = misses <= (1.0 - quantile) * np.arange(1, len(order) + 1)
         if not ok[0]:
-            return 0.0
-        last = int(np.nonzero(~ok)[0][0]) - 1 if (~ok).any() else len(order) - 1
-        thr = float(sp[order[last]])
-        # thresholds are compared with "spread > thr" for fallback
+            thr = 0.0
+        elif ok.all():
+            # every held-out sample is good: accept up to the largest spread seen
+            thr = float(np.nextafter(sp[order[-1]], np.inf))
+        else:
+            # the first sample outside the prefix sets the bound (strict <)
+            thr = float(sp[order[int(np.nonzero(~ok)[0][0])]])
+        self.threshold = thr
         return thr
 
-    def predict_with_fallback(self, x, fallback: Callable[[np.ndarray], "object"], threshold: float = 5e-3):
-        """Ensemble mean where the spread is at most ``threshold``; elsewhere
-        ``fallback(indices)`` (exact values, device [k, 10]) is used.  Returns
-        (values [B, 10] float32 device tensor, fell_back bool device tensor)."""
+    def predict_with_fallback(self, x, fallback: Callable[[np.ndarray], "object"],
+                              threshold: Optional[float] = None):
+        """Ensemble mean where the spread is strictly below the threshold;
+        elsewhere ``fallback(indices)`` (exact values, device [k, 10]).  The
+        threshold defaults to the one set by calibrate(); without one every
+        sample falls back, so no answer is accepted that the emulator has not
+        vouched for.  Returns (values [B, 10] float32 device tensor,
+        fell_back bool device tensor)."""
         import torch
         mean, spread = self.net.predict(x)
-        fell = spread > threshold
+        thr = self.threshold if threshold is None else threshold
+        if thr is None:
+            fell = torch.ones_like(spread, dtype=torch.bool)
+        else:
+            fell = spread >= thr
         idx = torch.nonzero(fell).flatten()
         if idx.numel():
             mean[idx] = fallback(idx.cpu().numpy()).to(mean.dtype)
         return mean, fell
 
 
-def measure_gain(model: SurrogateModel, emulator: TemplateEmulator, params: np.ndarray, x, threshold: float = 5e-3,
-                 tol: float = 1e-2) -> dict:
+def measure_gain(model: SurrogateModel, emulator: TemplateEmulator, params: np.ndarray, x,
+                 threshold: Optional[float] = None, tol: float = 1e-2) -> dict:
     """Throughput of the surrogate with fallback against the emulator alone
     on the same samples, the emulator also judging the surrogate's error.
 
@@ -184,9 +201,10 @@ def measure_gain(model: SurrogateModel, emulator: TemplateEmulator, params: np.n
         return r, time.perf_counter() - t0
 
     B = params.shape[0]
+    thr = model.threshold if threshold is None else threshold
     exact, t_emu = timed(lambda: emulator.run(params))
     (vals, fell), t_sur = timed(lambda: model.predict_with_fallback(
-        x, lambda idx: emulator.run(params[idx]), threshold))
+        x, lambda idx: emulator.run(params[idx]), thr))
     err = (vals.double() - exact).abs().max(dim=1).values
     fell_np = fell.cpu().numpy()
     err_np = err.cpu().numpy()
@@ -194,7 +212,7 @@ def measure_gain(model: SurrogateModel, emulator: TemplateEmulator, params: np.n
     good = int((err_np < tol).sum())
     return {
         "samples": B,
-        "threshold": threshold,
+        "threshold": thr,
         "emulator_evals_per_s": round(B / t_emu, 1),
         "surrogate_evals_per_s": round(B / t_sur, 1),
         "surrogate_good_evals_per_s": round(good / t_sur, 1),
