@@ -319,12 +319,43 @@ int plan_template(int n, const std::vector<int> &kinds, const std::vector<int> &
 int template_mats(int n, const std::vector<int> &kinds, const std::vector<int> &targets, const HostPlan &plan,
                   const double *params, std::vector<LOp> &lops, std::vector<cd> &mats)
 {
+    // A circuit repeats few (kind, parameters) pairs many times (one angle on
+    // every qubit of a layer, one noise channel after every gate): each
+    // distinct pair's superoperator is built once per instance, and the ops
+    // are filled in place so that the per-thread scratch is reused.
+    struct Built {
+        int kind, k;
+        double p[4];
+        std::vector<cd> S;
+    };
+    thread_local std::vector<Built> memo;
+    size_t n_memo = 0;
     lops.resize(kinds.size());
-    std::vector<cd> S;
     for (size_t j = 0; j < kinds.size(); ++j) {
-        int k = 0;
-        if (int rc = kind_superop(kinds[j], params + 4 * j, S, k)) return rc;
-        lops[j] = make_superop_op(k, &targets[4 * j], S.data());
+        const double *p = params + 4 * j;
+        int nq = 0, np = 0;
+        if (kind_arity(kinds[j], &nq, &np) != 0) return fail(VQD_E_ARG, "unknown kind in template op");
+        size_t hit = n_memo;
+        for (size_t m = 0; m < n_memo; ++m) {
+            const Built &b = memo[m];
+            if (b.kind != kinds[j]) continue;
+            bool same = true;
+            for (int i = 0; i < np; ++i) same = same && std::memcmp(&b.p[i], &p[i], sizeof(double)) == 0;
+            if (same) {
+                hit = m;
+                break;
+            }
+        }
+        if (hit == n_memo) {
+            if (memo.size() <= n_memo) memo.emplace_back();
+            Built &b = memo[n_memo];
+            b.kind = kinds[j];
+            for (int i = 0; i < 4; ++i) b.p[i] = (i < np) ? p[i] : 0.0;
+            if (int rc = kind_superop(kinds[j], p, b.S, b.k)) return rc;
+            ++n_memo;
+        }
+        const Built &b = memo[hit];
+        fill_superop_op(lops[j], b.k, &targets[4 * j], b.S.data());
     }
     return recompute_mats(n, plan, lops, mats);
 }

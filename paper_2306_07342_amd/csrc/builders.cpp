@@ -362,11 +362,12 @@ int kind_superop(int kind, const double *p, std::vector<cd> &S, int &k)
     return VQD_OK;
 }
 
-LOp make_superop_op(int k, const int *targets, const cd *S)
+void fill_superop_op(LOp &op, int k, const int *targets, const cd *S)
 {
-    LOp op;
     op.k = k;
-    for (int j = 0; j < k; ++j) op.q[j] = targets[j];
+    for (int j = 0; j < 4; ++j) op.q[j] = (j < k) ? targets[j] : 0;
+    op.wide_unitary = false;
+    op.U.clear();
     const int D = 1 << (2 * k);
     bool diag = true;
     for (int i = 0; i < D && diag; ++i)
@@ -376,9 +377,17 @@ LOp make_superop_op(int k, const int *targets, const cd *S)
     if (diag) {
         op.D.resize(D);
         for (int i = 0; i < D; ++i) op.D[i] = S[size_t(i) * D + i];
+        op.S.clear();
     } else {
         op.S.assign(S, S + size_t(D) * D);
+        op.D.clear();
     }
+}
+
+LOp make_superop_op(int k, const int *targets, const cd *S)
+{
+    LOp op;
+    fill_superop_op(op, k, targets, S);
     return op;
 }
 

@@ -23,6 +23,8 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <new>
 
 #include "vqd_internal.h"
 
@@ -1049,7 +1051,8 @@ LOp local_product(const std::vector<LOp> &ops, const std::vector<int> &src, size
 
 int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std::vector<cd> &mats)
 {
-    mats.assign(plan.mats.size(), cd(0));
+    mats.resize(plan.mats.size());
+    std::fill(mats.begin(), mats.end(), cd(0));
     if (plan.recipes.size() != plan.ops.size())
         return fail(VQD_E_STATE, "plan has no coefficient recipes");
     for (const Recipe &r : plan.recipes) {
@@ -1059,7 +1062,7 @@ int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std
             for (const RtPart &pt : r.rt_parts)
                 if (!ops[pt.src].diag)
                     return fail(VQD_E_ARG, "op structure differs from the template (diagonal expected)");
-            std::vector<cd> table;
+            thread_local std::vector<cd> table;
             rt_table(r.mode, r.rt_union, r.rt_parts, ops, table);
             if (r.real && !all_real(table))
                 return fail(VQD_E_ARG, "op structure differs from the template (complex diagonal)");
@@ -1085,7 +1088,10 @@ int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std
         if (first)
             for (int e = 0; e < 16; ++e) m[e * 16 + e] = 1.0;
         // the new coefficients must fit the form chosen for the template's
-        std::vector<cd> data;
+        // (per-thread scratch: this runs once per recipe of every instance)
+        thread_local std::vector<cd> data, sub;
+        thread_local std::vector<int> fl;
+        data.clear();
         if (r.kind == KOP_DIAG) {
             data.resize(16);
             for (int i = 0; i < 16; ++i)
@@ -1094,7 +1100,6 @@ int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std
                         return fail(VQD_E_ARG, "op structure differs from the template (not diagonal)");
             for (int e = 0; e < 16; ++e) data[e] = m[e * 16 + e];
         } else {
-            std::vector<cd> sub;
             if (!restrict_to(m, (int)r.mask, sub))
                 return fail(VQD_E_ARG, "op structure differs from the template");
             const int dim = 1 << popc(r.mask);
@@ -1103,7 +1108,7 @@ int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std
                 for (int j = 0; j < dim; ++j)
                     for (int i = 0; i < dim; ++i) data[j * dim + i] = sub[i * dim + j];
             } else {
-                const std::vector<int> fl = local_flips((int)r.mask);
+                fl = local_flips((int)r.mask);
                 for (int i = 0; i < dim; ++i)
                     for (int j = 0; j < dim; ++j)
                         if (!is_zero(sub[i * dim + j]) && std::find(fl.begin(), fl.end(), i ^ j) == fl.end())
@@ -1115,8 +1120,16 @@ int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std
         }
         if (r.real && !all_real(data))
             return fail(VQD_E_ARG, "op structure differs from the template (complex coefficients)");
-        const std::vector<cd> packed = pack(data, r.real);
-        for (size_t i = 0; i < packed.size(); ++i) mats[r.mat_off + i] = packed[i];
+        // pool layout: complex entries as they are, real ones two per entry
+        if (r.real) {
+            for (size_t i = 0; i < data.size(); ++i) {
+                cd &o = mats[r.mat_off + i / 2];
+                if (i & 1) o.imag(data[i].real());
+                else o = cd(data[i].real(), 0.0);
+            }
+        } else {
+            for (size_t i = 0; i < data.size(); ++i) mats[r.mat_off + i] = data[i];
+        }
     }
     return VQD_OK;
 }
@@ -1140,28 +1153,31 @@ int upload_plan(const HostPlan &plan, DevProgram &dev, hipStream_t stream)
             return fail(VQD_E_NOMEM, "descriptor allocation failed");
         dev.bytes = total;
     }
-    std::vector<unsigned char> host(total, 0);
+    // staging copy (not zero-filled: every byte up to `off` is written below)
+    std::unique_ptr<unsigned char[]> host_buf(new (std::nothrow) unsigned char[total]);
+    if (!host_buf) return fail(VQD_E_NOMEM, "descriptor staging allocation failed");
+    unsigned char *const host = host_buf.get();
+    const size_t mats_bytes = plan.mats.size() * sizeof(double2);
+    std::memset(host, 0, b_pass + b_phase + b_ops);             // descriptor sections and their padding
+    std::memset(host + b_pass + b_phase + b_ops + mats_bytes, 0, b_mats - mats_bytes);
     size_t off = 0;
-    std::memcpy(host.data() + off, plan.passes.data(), plan.passes.size() * sizeof(KPass));
+    std::memcpy(host + off, plan.passes.data(), plan.passes.size() * sizeof(KPass));
     dev.passes = reinterpret_cast<KPass *>((char *)dev.buf + off);
     off += b_pass;
-    std::memcpy(host.data() + off, plan.phases.data(), plan.phases.size() * sizeof(KPhase));
+    std::memcpy(host + off, plan.phases.data(), plan.phases.size() * sizeof(KPhase));
     dev.phases = reinterpret_cast<KPhase *>((char *)dev.buf + off);
     off += b_phase;
-    std::memcpy(host.data() + off, plan.ops.data(), plan.ops.size() * sizeof(KOp));
+    std::memcpy(host + off, plan.ops.data(), plan.ops.size() * sizeof(KOp));
     dev.ops = reinterpret_cast<KOp *>((char *)dev.buf + off);
     off += b_ops;
-    for (size_t i = 0; i < plan.mats.size(); ++i) {
-        double2 v;
-        v.x = plan.mats[i].real();
-        v.y = plan.mats[i].imag();
-        std::memcpy(host.data() + off + i * sizeof(double2), &v, sizeof(double2));
-    }
+    // std::complex<double> is laid out as (re, im), as double2
+    static_assert(sizeof(cd) == sizeof(double2), "complex layout");
+    std::memcpy(host + off, plan.mats.data(), mats_bytes);
     dev.mats = reinterpret_cast<double2 *>((char *)dev.buf + off);
     off += b_mats;
     // ordered on the stream after earlier work that read the old descriptors;
     // the synchronisation keeps the staging vector alive until the copy ends
-    VQD_HIP(hipMemcpyAsync(dev.buf, host.data(), off, hipMemcpyHostToDevice, stream));
+    VQD_HIP(hipMemcpyAsync(dev.buf, host, off, hipMemcpyHostToDevice, stream));
     VQD_HIP(hipStreamSynchronize(stream));
     return VQD_OK;
 }

@@ -202,6 +202,8 @@ struct LOp {
 
 // Build a logical op from a superoperator; detects diagonal structure.
 LOp make_superop_op(int k, const int *targets, const cd *S);
+// The same, written into an existing op (its vectors keep their capacity).
+void fill_superop_op(LOp &op, int k, const int *targets, const cd *S);
 LOp make_unitary_op(int k, const int *targets, const cd *U);
 
 // Planner entry point.  Returns VQD_OK or an error code (message set).
