@@ -111,8 +111,11 @@ C5_TUNE_FILE = os.path.join(ROOT, "paper_2306_07342_amd", "tune", "c5_template_t
 
 def batched_leg(vqd, torch, steps):
     """4096 independent 3..10-qubit noisy line circuits (own noise parameters)
-    in one persistent, graph-captured launch, against looping the
-    single-density-matrix path over a random subset of 512 of them."""
+    in one persistent, graph-captured launch; its FP64 and HBM fractions from
+    the work the instances' plans execute; against the single-density-matrix
+    path over a random subset of 512 of them, looped inside one HIP graph
+    (init, program and a device-output read-out per circuit, no host
+    synchronisation in between) and, for context, looped eagerly."""
     import random
     from workloads import c4_batch_instances
     t0 = time.perf_counter()
@@ -130,52 +133,68 @@ def batched_leg(vqd, torch, steps):
     tuned = os.path.exists(BATCH_TUNE_FILE)
     b.autotune(BATCH_TUNE_FILE if tuned else os.path.join("/tmp", "vqd_batch_tiles.json"), max_per_n=32)
     b.compile()
-    log("batched: setup %.1f s, %s" % (time.perf_counter() - t0, b.info()))
+    info = b.info()
+    log("batched: setup %.1f s, %s" % (time.perf_counter() - t0, info))
     stream = torch.cuda.current_stream()
 
-    def timed(fn, reps):
+    def timed(fn, reps, st=None):
+        st = st or stream
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        e0.record(st)
         for _ in range(reps):
             fn()
-        e1.record(stream)
+        e1.record(st)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3 / reps
 
     t_batch = timed(lambda: b.run(use_graph=True), max(1, steps))
-    # the same circuits, one single-state program each, looped
+    tf = 2.0 * info["fp64_fma"] / t_batch / 1e12
+    gbs = info["pass_bytes"] / t_batch / 1e9
+    # the same circuits, one single-state program each: 512 of them
     sel = random.Random(7).sample(range(len(insts)), 512)
-    progs = [(insts[i]["n"], vqd.Program(insts[i]["n"], insts[i]["ops"]).compile()) for i in sel]
-    dms = {}
-    for n, _ in progs:
-        if n not in dms:
-            dms[n] = vqd.DensityMatrix(n)
+    s = torch.cuda.Stream()
+    zs = torch.empty(sum(insts[i]["n"] for i in sel), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(s):
+        progs = [(insts[i]["n"], vqd.Program(insts[i]["n"], insts[i]["ops"]).compile()) for i in sel]
+        dms = {}
+        for n, _ in progs:
+            if n not in dms:
+                dms[n] = vqd.DensityMatrix(n, stream=s)
 
     def loop():
+        off = 0
         for n, p in progs:
             dm = dms[n]
             dm.init_zero()
             p.run(dm)
-            dm.expec_z()
+            dm.expec_z_dev(zs[off:off + n])
+            off += n
 
-    t_loop = timed(loop, 1)
+    with torch.cuda.stream(s):
+        t_loop_eager = timed(loop, 1, s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            loop()
+        t_loop_graph = timed(g.replay, max(1, steps), s)
     sub = make(sel)
     sub.compile()
-    t_sub = timed(lambda: sub.run(use_graph=True), 2)
-    # the subset is a uniform random eighth of the batch: looping the single
-    # path over all 4096 circuits takes about 8x its time
-    loop_full = t_loop * len(insts) / len(sel)
+    t_sub = timed(lambda: sub.run(use_graph=True), max(1, steps))
     return {"metric": "batched noisy circuits per second (4096 density matrices, 3-10 qubits)",
             "circuits_per_s": round(len(insts) / t_batch, 1),
             "dm_ops_per_s": round(n_ops / t_batch, 1),
             "ms_per_batch": round(t_batch * 1e3, 3),
             "dm_ops": n_ops,
-            "looped_single_ms_extrapolated_4096": round(loop_full * 1e3, 3),
-            "speedup_vs_looped_single": round(loop_full / t_batch, 2),
+            "roofline": {"alu": {"achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(tf / FP64_PEAK_TFLOPS, 4)},
+                         "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(gbs / HBM_PEAK_GBS, 4)},
+                         "work": "executed FMAs and algorithmic bytes of the instances' plans, per run"},
             "subset512_batched_ms": round(t_sub * 1e3, 3),
-            "subset512_looped_single_ms": round(t_loop * 1e3, 3),
+            "subset512_single_path_in_one_graph_ms": round(t_loop_graph * 1e3, 3),
+            "subset512_single_path_eager_ms": round(t_loop_eager * 1e3, 3),
+            "speedup_vs_single_path_graph": round(t_loop_graph / t_sub, 2),
             "tiles": "autotuned (%s)" % ("cached" if tuned else "fresh")}
 
 
@@ -390,6 +409,7 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
         y = emu.run(P).float().contiguous()
         torch.cuda.synchronize()
         t_data = time.perf_counter() - t0
+        gpu_data = emu.last_gpu_s
         log("surrogate: %d training samples in %.1f s" % (n_tr, t_data))
         model = SurrogateModel(init_ensemble(), max_batch=1024)
         t0 = time.perf_counter()
@@ -411,7 +431,9 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
                                                          "accepted_within_tol_fraction", "max_abs_dz_accepted",
                                                          "median_abs_dz_accepted")}
         res.update({"train_samples": n_tr, "data_gen_s": round(t_data, 2),
-                    "data_gen_evals_per_s": round(n_tr / t_data, 1), "epochs": ep, "batch": 512,
+                    "data_gen_evals_per_s": round(n_tr / t_data, 1),
+                    "data_gen_batched_kernel_only_evals_per_s": round(n_tr / gpu_data, 1),
+                    "epochs": ep, "batch": 512,
                     "train_s": round(t_train, 2), "final_train_mse": [float(v) for v in model.history[-1]]})
         return res
 

@@ -312,6 +312,15 @@ typedef struct vqd_batch_info {
     size_t arena_bytes;       /* arena size vqd_batch_run needs  */
     size_t n_outputs;         /* sum of the instances' n         */
     unsigned grid_items;      /* queue length                    */
+    double fp64_fma;          /* FP64 FMAs one run executes: each instance's
+                                 planned FMAs per computed amplitude times its
+                                 computed amplitudes, summed               */
+    double pass_bytes;        /* algorithmic HBM bytes of one run: per
+                                 instance the initial state written (16 B per
+                                 amplitude), every computed amplitude read and
+                                 written once per pass (32 B), the last
+                                 pass's mirror images and the diagonal read
+                                 for <Z_i>, summed                          */
 } vqd_batch_info;
 
 int vqd_batch_create(vqd_batch **out);

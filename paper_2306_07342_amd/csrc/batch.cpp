@@ -49,6 +49,8 @@ struct vqd_batch {
     uint64_t arena_amps = 0;
     size_t n_out = 0;
     size_t total_passes = 0;
+    double fp64_fma = 0;      // executed FP64 FMAs of one run (all instances)
+    double pass_bytes = 0;    // algorithmic HBM bytes of one run (all instances)
     bool compiled = false;
     int device = -1;
     hipGraphExec_t gexec = nullptr;
@@ -58,6 +60,8 @@ struct vqd_batch {
     // (the legacy default stream cannot be captured), ordered after and
     // before the caller's stream with events
     hipStream_t g_stream = nullptr;
+    hipStream_t up_stream = nullptr;   // compile's uploads (into fresh buffers; never waits for
+                                       // work on other streams, so it overlaps a running launch)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
@@ -105,6 +109,8 @@ void free_graph_stream(vqd_batch *b)
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     b->g_stream = nullptr;
     b->ev_in = b->ev_out = nullptr;
+    if (b->up_stream) (void)hipStreamDestroy(b->up_stream);
+    b->up_stream = nullptr;
 }
 
 // Plan all instances of `sel` (indices into b->inst) in parallel.
@@ -144,6 +150,17 @@ int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream, 
     uint64_t arena = 0;
     uint32_t outs = 0, max_rt = 0;
     size_t passes = 0;
+    double fma = 0, hbm = 0;
+    // per instance of n qubits and plan p: the passes' FMAs on the computed
+    // amplitudes; bytes: the initial state written, 16 B read and written
+    // per computed amplitude per pass, the mirror images of the last pass,
+    // and the diagonal read for <Z_i>
+    auto account = [&](int n, const HostPlan &p, double count) {
+        const double amps = std::ldexp(1.0, 2 * n), f = p.tile_fraction;
+        fma += count * p.fma_per_amp * f * amps;
+        hbm += count * (16.0 * amps + 32.0 * f * amps * (double)p.passes.size() +
+                          (p.hermitian ? 16.0 * (1.0 - f) * amps : 0.0) + 16.0 * std::ldexp(1.0, n));
+    };
     for (int i : sel) {
         auto &I = b->inst[i];
         const uint32_t pass_base = (uint32_t)all.passes.size();
@@ -183,6 +200,7 @@ int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream, 
         it.out_off = I.out_off;
         items.push_back(it);
         passes += I.plan.passes.size();
+        account(I.n, I.plan, 1.0);
     }
     std::vector<double> cost;
     for (int i : sel) cost.push_back(b->inst[i].cost);
@@ -253,6 +271,7 @@ int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream, 
                 items.push_back(it);
                 cost.push_back((double)(T.plan.passes.size() + 1) * (double)(1ull << (2 * T.n)));
                 passes += T.plan.passes.size();
+                account(T.n, T.plan, 1.0);
             }
         }
     }
@@ -264,6 +283,8 @@ int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream, 
     for (size_t k : order) queue.push_back(items[k]);
 
     drop_graph(b);
+    // a recompiled batch may still be running from its old buffers
+    if (b->dev.buf || b->dev.prog.buf) VQD_HIP(hipDeviceSynchronize());
     free_batch_dev(b->dev);
     if (!all.passes.empty())
         if (int rc = upload_plan(all, b->dev.prog, stream)) return rc;
@@ -279,6 +300,8 @@ int build_device(vqd_batch *b, const std::vector<int> &sel, hipStream_t stream, 
     b->arena_amps = arena;
     b->n_out = outs;
     b->total_passes = passes;
+    b->fp64_fma = fma;
+    b->pass_bytes = hbm;
     return VQD_OK;
 }
 
@@ -471,7 +494,12 @@ int vqd_batch_compile(vqd_batch *b, size_t *arena_bytes, size_t *n_outputs)
         const PlanOpts o = (it != b->opts_by_n.end()) ? it->second : default_opts(T.n);
         if (int rc = plan_template(T.n, T.kinds, T.targets, o, T.plan)) return rc;
     }
-    if (int rc = build_device(b, all, nullptr)) return rc;
+    // the old device buffers are freed first (a device-wide wait), so the
+    // uploads go to fresh memory on a stream of their own: they overlap work
+    // still running on the caller's streams (an earlier launch of another
+    // batch) instead of queueing behind it
+    if (!b->up_stream) VQD_HIP(hipStreamCreateWithFlags(&b->up_stream, hipStreamNonBlocking));
+    if (int rc = build_device(b, all, b->up_stream)) return rc;
     (void)hipGetDevice(&b->device);
     b->compiled = true;
     if (arena_bytes) *arena_bytes = (size_t)b->arena_amps * 16;
@@ -673,6 +701,8 @@ int vqd_batch_info_get(const vqd_batch *b, vqd_batch_info *out)
     out->arena_bytes = (size_t)b->arena_amps * 16;
     out->n_outputs = b->n_out;
     out->grid_items = b->dev.n_items;
+    out->fp64_fma = b->fp64_fma;
+    out->pass_bytes = b->pass_bytes;
     return VQD_OK;
 }
 

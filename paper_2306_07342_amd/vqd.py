@@ -48,7 +48,7 @@ class PlanOpts(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_instances", ctypes.c_int), ("total_passes", ctypes.c_longlong),
                 ("arena_bytes", ctypes.c_size_t), ("n_outputs", ctypes.c_size_t),
-                ("grid_items", ctypes.c_uint)]
+                ("grid_items", ctypes.c_uint), ("fp64_fma", ctypes.c_double), ("pass_bytes", ctypes.c_double)]
 
 
 class ProgInfo(ctypes.Structure):

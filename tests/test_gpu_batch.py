@@ -231,3 +231,32 @@ def test_device_preset_streams_in_one_batch(gpu_lib):
     b.compile()
     b.run()
     check_batch(gpu_lib, b, insts, refs)
+
+
+def test_batch_reports_the_work_of_its_plans(gpu_lib, mixed):
+    """vqd_batch_info's executed FMAs and algorithmic bytes equal the sums,
+    over the instances, of each instance's own plan (planned on the host with
+    the batch's options for its qubit count)."""
+    insts, _ = mixed
+    b = gpu_lib.Batch()
+    for n, ops in insts:
+        b.add(n, ops)
+    b.compile()
+    info = b.info()
+    fma = byts = 0.0
+    for n, ops in insts:
+        o = b.plan_opts(n)
+        p = gpu_lib.Program(n, ops)
+        p.plan(gpu_lib.plan_opts(tile_bits=o["tile_bits"], min_contig_bits=o["min_contig_bits"],
+                                 max_ops_per_pass=o["max_ops_per_pass"], fuse_blocks=bool(o["fuse_blocks"]),
+                                 pad_coalesce=bool(o["pad_coalesce"]), hermitian=bool(o["hermitian"])))
+        pi = p.info()
+        amps, f = 4.0 ** n, pi["tile_fraction"]
+        fma += pi["fma_per_amp"] * f * amps
+        byts += 16 * amps + 32 * f * amps * pi["n_passes"] + (16 * (1 - f) * amps if pi["hermitian"] else 0) \
+            + 16 * 2.0 ** n
+        p.close()
+    say("batch work", info["fp64_fma"], fma, info["pass_bytes"], byts)
+    assert abs(info["fp64_fma"] - fma) <= 1e-12 * fma
+    assert abs(info["pass_bytes"] - byts) <= 1e-12 * byts
+    assert info["total_passes"] > 0
