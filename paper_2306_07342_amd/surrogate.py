@@ -38,6 +38,7 @@ class TemplateEmulator:
         self.opts = opts              # vqd.PlanOpts for the template, or the library default
         self._arena = None
         self._out = None
+        self.last_gpu_s = 0.0         # time of the batched launches alone in the last run()
 
     def run(self, params: np.ndarray):
         """The host work of a chunk (coefficients of every instance) runs while
@@ -47,6 +48,7 @@ class TemplateEmulator:
         count = P.shape[0]
         res = torch.empty((count, self.n), dtype=torch.float64, device=self.device)
         prev = None
+        events = []
         for lo in range(0, count, self.chunk):
             hi = min(count, lo + self.chunk)
             b = vqd.Batch()
@@ -62,13 +64,27 @@ class TemplateEmulator:
             # the previous launch
             if prev is not None:
                 prev.close()
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record()
             b.run()
-            outs = np.fromiter((b.offsets(i)[1] for i in idx), dtype=np.int64, count=hi - lo)
-            sel = torch.as_tensor(outs, device=self.device)[:, None] + torch.arange(self.n, device=self.device)
-            res[lo:hi] = self._out[sel]
+            ev[1].record()
+            events.append(ev)
+            # one template's instances get consecutive output slots, so the
+            # results are one device slice; no host copy here, which would
+            # wait for the launch and keep the next chunk's host work from
+            # overlapping it
+            first, last = b.offsets(idx[0])[1], b.offsets(idx[-1])[1]
+            if last - first == (hi - lo - 1) * self.n:
+                res[lo:hi] = self._out[first:first + (hi - lo) * self.n].view(hi - lo, self.n)
+            else:
+                outs = np.fromiter((b.offsets(i)[1] for i in idx), dtype=np.int64, count=hi - lo)
+                sel = torch.from_numpy(outs).pin_memory().to(self.device, non_blocking=True)
+                res[lo:hi] = self._out[sel[:, None] + torch.arange(self.n, device=self.device)]
             prev = b
         if prev is not None:
             prev.close()
+        torch.cuda.synchronize()
+        self.last_gpu_s = sum(a.elapsed_time(z) for a, z in events) / 1e3
         return res
 
     def autotune(self, params: np.ndarray, cache_path: str, sample: int = 1024):
