@@ -90,6 +90,44 @@ __device__ __forceinline__ void apply_mat(const double2 (&a)[16], double2 (&y)[1
     }
 }
 
+// KOP_PTM on the register bits in MASK (the row and column bit of one
+// qubit): per group of 4 slots, the block B (B[u][v] at local index u + 2v)
+// has Pauli components a_I = B00 + B11, a_Z = B00 - B11, a_X = B01 + B10,
+// a_Y = i (B01 - B10); the map keeps a_I, h = (R / 2) a for the rows X, Y,
+// Z of its real transfer matrix R, and the new block is B00 = a_I / 2 + h_Z,
+// B11 = a_I / 2 - h_Z, B01 = h_X - i h_Y, B10 = h_X + i h_Y.  Group by group;
+// the scheduling barrier between groups keeps the compiler from
+// interleaving them, which would hold every group's temporaries at once.
+template <int MASK>
+__device__ __forceinline__ void apply_ptm(const double2 (&x)[16], double2 (&y)[16], const double2 *__restrict__ M)
+{
+    constexpr int REST = (~MASK) & 15;
+    double c[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[k] = coef<true>(M, k).x;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int s0 = dep4(0, MASK) | dep4(g, REST), s1 = dep4(1, MASK) | dep4(g, REST);
+        const int s2 = dep4(2, MASK) | dep4(g, REST), s3 = dep4(3, MASK) | dep4(g, REST);
+        const double2 aI = make_double2(x[s0].x + x[s3].x, x[s0].y + x[s3].y);
+        const double2 aX = make_double2(x[s2].x + x[s1].x, x[s2].y + x[s1].y);
+        const double2 d = make_double2(x[s2].x - x[s1].x, x[s2].y - x[s1].y);     // a_Y = i d
+        const double2 aZ = make_double2(x[s0].x - x[s3].x, x[s0].y - x[s3].y);
+        double2 h[3];      // X, Y, Z
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double *w = c + 4 * r;   // columns I, X, Y, Z
+            h[r].x = fma(w[3], aZ.x, fma(-w[2], d.y, fma(w[1], aX.x, w[0] * aI.x)));
+            h[r].y = fma(w[3], aZ.y, fma(w[2], d.x, fma(w[1], aX.y, w[0] * aI.y)));
+        }
+        y[s0] = make_double2(fma(0.5, aI.x, h[2].x), fma(0.5, aI.y, h[2].y));
+        y[s3] = make_double2(fma(0.5, aI.x, -h[2].x), fma(0.5, aI.y, -h[2].y));
+        y[s2] = make_double2(h[0].x + h[1].y, h[0].y - h[1].x);
+        y[s1] = make_double2(h[0].x - h[1].y, h[0].y + h[1].x);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 __device__ __forceinline__ double2 cmul(const double2 m, const double2 x)
 {
     return make_double2(fma(m.x, x.x, -m.y * x.y), fma(m.x, x.y, m.y * x.x));

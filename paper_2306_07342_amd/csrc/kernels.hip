@@ -319,6 +319,9 @@ __device__ __forceinline__ void apply_op(const double2 (&x)[16], double2 (&y)[16
     } else if (kind == KOP_DIAG) {
         if (sel & 16) apply_diag<true>(x, y, M);
         else apply_diag<false>(x, y, M);
+    } else if (kind == KOP_PTM) {
+        if (uni(op->opmask) == 5) apply_ptm<5>(x, y, M);
+        else apply_ptm<10>(x, y, M);
     } else {
         const double2 *T = lds_rt + uni(op->mat);
         switch (uni(op->mode) | (sel & 16)) {

@@ -217,6 +217,51 @@ std::vector<cd> pack(const std::vector<cd> &c, bool real)
     return o;
 }
 
+// Pauli transfer form of a map on two register bits (KOP_PTM).  sub is the
+// 4x4 matrix (row-major, output index first) on the local index u + 2v of the
+// block entry B[u][v].  R_PQ = Tr(P S(Q)) / 2 over P, Q in (I, X, Y, Z) is
+// real exactly when S takes Hermitian blocks to Hermitian blocks, and its row
+// I is (1, 0, 0, 0) exactly when S keeps the trace.  In floating point both
+// hold up to the rounding of the planner's products: accepted to within
+// kPtmTol.  rows gets the rows X, Y, Z of R / 2 (row-major, columns I, X, Y,
+// Z); false when either property fails.
+constexpr double kPtmTol = 1e-14;
+
+bool ptm_of(const std::vector<cd> &sub, std::vector<double> &rows)
+{
+    const cd I1(0.0, 1.0);
+    // the Pauli matrices as local vectors p_l = P[u][v], l = u + 2v
+    const cd pv[4][4] = {{1.0, 0.0, 0.0, 1.0}, {0.0, 1.0, 1.0, 0.0}, {0.0, I1, -I1, 0.0}, {1.0, 0.0, 0.0, -1.0}};
+    double R[4][4];
+    for (int q = 0; q < 4; ++q) {
+        cd sq[4];
+        for (int i = 0; i < 4; ++i) {
+            sq[i] = 0.0;
+            for (int j = 0; j < 4; ++j) sq[i] += sub[i * 4 + j] * pv[q][j];
+        }
+        for (int p = 0; p < 4; ++p) {
+            cd t = 0.0;    // Tr(P B) = sum_l conj(p_l) b_l for Hermitian P
+            for (int l = 0; l < 4; ++l) t += std::conj(pv[p][l]) * sq[l];
+            t *= 0.5;
+            if (std::abs(t.imag()) > kPtmTol * std::max(1.0, std::abs(t.real()))) return false;
+            R[p][q] = t.real();
+        }
+    }
+    if (std::abs(R[0][0] - 1.0) > kPtmTol || std::abs(R[0][1]) > kPtmTol || std::abs(R[0][2]) > kPtmTol ||
+        std::abs(R[0][3]) > kPtmTol)
+        return false;
+    rows.clear();
+    for (int p = 1; p < 4; ++p)
+        for (int q = 0; q < 4; ++q) rows.push_back(0.5 * R[p][q]);
+    return true;
+}
+
+// FP64 work of a KOP_PTM per 16 slots in FMA units (an add or a multiply
+// counts half): per group of 4 slots, 8 adds into the Pauli basis, 3 rows of
+// 4 real coefficients times a complex vector (6 multiplies, 18 FMAs), then 4
+// FMAs and 4 adds back.
+constexpr double kPtmCost = 4 * 31.0;
+
 // Cheapest branch-free kernel form of a slot-space matrix.
 Encoded encode(const Mat16 &m)
 {
@@ -261,6 +306,18 @@ Encoded encode(const Mat16 &m)
             best.real = real;
             best.data = pack(cm, real);
             best.cost = dense;
+        }
+        // Pauli transfer form of a one-qubit map
+        if (nb == 2 && kPtmCost < best.cost) {
+            std::vector<double> rows;
+            if (ptm_of(sub, rows)) {
+                std::vector<cd> c(rows.begin(), rows.end());
+                best.kind = KOP_PTM;
+                best.mask = mask;
+                best.real = true;
+                best.data = pack(c, true);
+                best.cost = kPtmCost;
+            }
         }
         // flip pattern: nonzeros only where row and column bits flip together
         const std::vector<int> fl = local_flips(mask);
@@ -1103,7 +1160,12 @@ int recompute_mats(int n, const HostPlan &plan, const std::vector<LOp> &ops, std
             if (!restrict_to(m, (int)r.mask, sub))
                 return fail(VQD_E_ARG, "op structure differs from the template");
             const int dim = 1 << popc(r.mask);
-            if (r.kind == KOP_MAT) {
+            if (r.kind == KOP_PTM) {
+                thread_local std::vector<double> rows;
+                if (!ptm_of(sub, rows))
+                    return fail(VQD_E_ARG, "op structure differs from the template (Pauli transfer form)");
+                data.assign(rows.begin(), rows.end());
+            } else if (r.kind == KOP_MAT) {
                 data.resize(size_t(dim) * dim);
                 for (int j = 0; j < dim; ++j)
                     for (int i = 0; i < dim; ++i) data[j * dim + i] = sub[i * dim + j];

@@ -53,6 +53,13 @@ enum KOpKind : uint32_t {
                       // flip(x) flipping the row and column bit of the same qubits
     KOP_DIAG = 3,     // 16 element-wise factors indexed by the register slot
     KOP_DIAG_RT = 4,  // element-wise factors from an LDS table indexed by global bits
+    KOP_PTM = 5,      // a trace-preserving map on the two register bits `opmask` (the row
+                      // and column bit of one qubit) that takes Hermitian blocks to
+                      // Hermitian blocks, applied through its real Pauli transfer matrix R:
+                      // the 2x2 block B of each slot group (B[u][v] at local index u + 2v)
+                      // goes to its Pauli components a_P = Tr(P B), a' = R a, and back.
+                      // Coefficients: rows X, Y, Z of R / 2 over the columns (I, X, Y, Z),
+                      // 12 reals packed two per entry (row I is (1, 0, 0, 0))
 };
 
 // KOP_DIAG_RT index modes: which register slot bits feed the table index.

@@ -87,6 +87,20 @@ class TemplateEmulator:
         self.last_gpu_s = sum(a.elapsed_time(z) for a, z in events) / 1e3
         return res
 
+    def reserve(self, params: np.ndarray):
+        """Allocate the device buffers (state arena, outputs) of one full
+        chunk of these settings now, so that a later run() only reuses them."""
+        P = np.ascontiguousarray(params[:self.chunk], dtype=np.float64)
+        b = vqd.Batch()
+        tid = b.add_template(self.n, self.structure)
+        b.add_instances(tid, P)
+        if self.opts is not None:
+            b.set_opts(self.n, self.opts)
+        b.arena, b.out = self._arena, self._out
+        b.compile(device=self.device)
+        self._arena, self._out = b.arena, b.out
+        b.close()
+
     def autotune(self, params: np.ndarray, cache_path: str, sample: int = 1024):
         """Pick the template's tile shape with the batched autotuner (timed
         on ``sample`` instances, result cached in ``cache_path``)."""

@@ -5,7 +5,8 @@ descriptor encoding be checked against the oracle without a GPU.
 It reproduces what k_pass does with each descriptor field: the tile/thread/
 register-slot address split, dense (column-major) and flip-pattern matrices
 with real coefficients packed two per entry, diagonal factors indexed by
-register slots or by global bits in each index mode, phantom bits.  The LDS
+register slots or by global bits in each index mode, one-qubit maps in their
+Pauli transfer form, phantom bits.  The LDS
 exchange between phases only moves values between threads of a tile, so it
 is emulated by scattering back to the state and gathering again.
 """
@@ -190,6 +191,22 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
                                 for g in range(16 >> nb):
                                     so = _dep4(i, mask) | _dep4(g, rest)
                                     y[..., so] += W[x * dim + i] * a[..., so ^ _flip(mask, x)]
+                    a = y
+                elif kind == 5:            # Pauli transfer form of a trace-preserving one-qubit map
+                    H5 = _coefs(mats, int(op["mat"]), 12, True).real.reshape(3, 4)
+                    H5 = np.vstack([[0.5, 0.0, 0.0, 0.0], H5])
+                    rest = (~mask) & 15
+                    y = np.zeros_like(a)
+                    for g in range(4):
+                        s0, s1, s2, s3 = (_dep4(l, mask) | _dep4(g, rest) for l in range(4))
+                        # block B[u][v] at local index u + 2v; components Tr(P B)
+                        comp = np.stack([a[..., s0] + a[..., s3], a[..., s1] + a[..., s2],
+                                         1j * (a[..., s2] - a[..., s1]), a[..., s0] - a[..., s3]])
+                        h = np.tensordot(H5, comp, axes=(1, 0))
+                        y[..., s0] = h[0] + h[3]
+                        y[..., s3] = h[0] - h[3]
+                        y[..., s2] = h[1] - 1j * h[2]
+                        y[..., s1] = h[1] + 1j * h[2]
                     a = y
                 elif kind == 3:
                     F = _coefs(mats, int(op["mat"]), 16, real)

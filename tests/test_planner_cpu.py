@@ -216,3 +216,46 @@ def test_hermitian_mode_refused_for_a_map_that_breaks_hermiticity(vqd_host):
     prog.plan(vqd_host.plan_opts(hermitian=True))
     assert prog.info()["hermitian"] == 0
     assert prog.info()["tile_fraction"] == 1.0
+
+
+def _kinds(vqd, n, ops, **opts):
+    prog = vqd.Program(n, ops)
+    prog.plan(vqd.plan_opts(**opts))
+    plan = emu.parse(prog.export())
+    return [int(o["kind"]) for o in plan["ops"]], prog.info()
+
+
+def test_one_qubit_maps_in_pauli_transfer_form(vqd_host):
+    """Trace-preserving one-qubit maps that keep Hermitian blocks Hermitian
+    are applied through their real Pauli transfer matrix (kernel op kind 5).
+    A trace-decreasing M rho M^dagger and a map rho -> A rho B^dagger
+    (A != B, complex transfer matrix) stay dense matrices (kind 1).  Each
+    result matches the oracle (the last one a direct product here)."""
+    n = 3
+    rng = np.random.default_rng(11)
+    su2 = [("su2", (q,), tuple(float(x) for x in rng.standard_normal(4))) for q in range(n)]
+    noisy = su2 + [("amp", (0,), (0.3,)), ("deph1", (1,), (0.2,)), ("depol1", (2,), (0.1,))]
+    kinds, _ = _kinds(vqd_host, n, noisy)
+    assert kinds and all(k == 5 for k in kinds), kinds
+    got, ref, _ = run_both(vqd_host, n, noisy, seed=4)
+    assert_close(got, ref)
+
+    M = (rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))) * 0.5
+    lossy = [("matrix", (1,), (M,))]
+    assert _kinds(vqd_host, n, lossy)[0] == [1]
+    got, ref, _ = run_both(vqd_host, n, lossy, seed=5)
+    assert_close(got, ref)
+
+    A = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    B = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    skew = [("superop", (2,), (np.kron(np.conj(B), A),))]
+    assert _kinds(vqd_host, n, skew)[0] == [1]
+    prog = vqd_host.Program(n, skew)
+    prog.plan(vqd_host.plan_opts())
+    R0 = start_state(n, 6)
+    got = emu.run(emu.parse(prog.export()), np.ascontiguousarray(R0.T).reshape(-1))
+    # qubit q is index bit q: the full operators with A (B) on qubit 2
+    Af = np.kron(A, np.eye(4))
+    Bf = np.kron(B, np.eye(4))
+    ref = (Af @ R0 @ Bf.conj().T).T.reshape(-1)
+    assert_close(got, ref)
