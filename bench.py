@@ -34,7 +34,7 @@ N_QUBITS = 14
 # a unitary): each pass computes the tiles whose row group index is at most
 # the column one, 12-bit tiles of whole qubits with qubit 0 in every tile
 PLAN_OPTS = dict(tile_bits=12, min_contig_bits=1, max_ops_per_pass=0, fuse_blocks=True, pad_coalesce=True,
-                 hermitian=True)
+                 hermitian=True, relayout=True)
 
 
 def pass_bytes(info, amps):

@@ -253,6 +253,18 @@ typedef struct vqd_plan_opts {
                                last pass restores the whole matrix.  Otherwise the
                                program is planned as with 0.  Batches default to 1
                                (every instance starts from |0..0><0..0|). */
+    int relayout;           /* default 0.  1 (Hermitian-mode programs only): between two
+                               passes the state is stored under a relabelling of the
+                               qubits that puts qubits shared by both passes' tiles
+                               at the lowest positions, so that the loads and stores
+                               of both passes move longer contiguous runs.  A pass
+                               that changes the labelling writes into a second
+                               state-sized buffer, which the density-matrix handle
+                               allocates on the first run of such a program and
+                               keeps until it is destroyed (16 * 4^n bytes; not
+                               under stream capture).  The program always ends in
+                               the caller's buffer under the original labelling.
+                               Batches ignore it. */
 } vqd_plan_opts;
 void vqd_plan_opts_default(vqd_plan_opts *o);
 

@@ -70,7 +70,7 @@ int run_single(vqd_dm *dm, const LOp &op)
     rc = upload_plan(plan, dm->imm, dm->stream);
     if (rc) return rc;
     for (size_t i = 0; i < plan.passes.size(); ++i) {
-        rc = launch_pass(dm->amps, dm->imm, plan.passes[i], (uint32_t)i, dm->stream);
+        rc = launch_pass(dm->amps, dm->amps, dm->imm, plan.passes[i], (uint32_t)i, dm->stream);
         if (rc) return rc;
     }
     return VQD_OK;
@@ -87,6 +87,7 @@ PlanOpts to_plan_opts(const vqd_plan_opts &o)
     po.fuse_blocks = o.fuse_blocks != 0;
     po.pad_coalesce = o.pad_coalesce != 0;
     po.hermitian = o.hermitian != 0;
+    po.relayout = o.relayout != 0;
     return po;
 }
 
@@ -170,6 +171,7 @@ int vqd_dm_destroy(vqd_dm *dm)
     free_dev_program(dm->imm);
     free_scratch(dm->red);
     free_scratch(dm->gred);
+    if (dm->alt) (void)hipFree(dm->alt);
     delete dm;
     return VQD_OK;
 }
@@ -372,6 +374,7 @@ void vqd_plan_opts_default(vqd_plan_opts *o)
     o->fuse_blocks = 1;
     o->pad_coalesce = 1;
     o->hermitian = 0;
+    o->relayout = 0;
 }
 
 int vqd_prog_create(int n, vqd_prog **out)
@@ -521,8 +524,23 @@ int vqd_prog_run(vqd_prog *p, vqd_dm *dm)
     if (p->n != dm->n) return fail(VQD_E_ARG, "program and state have different qubit counts");
     if (!p->plan.passes.empty() && p->device != dm->device)
         return fail(VQD_E_ARG, "program compiled for another device");
-    for (size_t i = 0; i < p->plan.passes.size(); ++i)
-        if (int rc = launch_pass(dm->amps, p->dev, p->plan.passes[i], (uint32_t)i, dm->stream)) return rc;
+    if (p->plan.alt_buffer && !dm->alt) {
+        // the second state buffer of a relabelled plan, kept by the handle
+        const size_t need = size_t(16) << (2 * dm->n);
+        if (hipMalloc(&dm->alt, need) != hipSuccess) {
+            dm->alt = nullptr;
+            return fail(VQD_E_NOMEM, "second state buffer allocation failed");
+        }
+    }
+    // a pass that changes the layout stores into the other buffer; the
+    // planner makes their number even, so the state ends where it started
+    double2 *cur = dm->amps;
+    for (size_t i = 0; i < p->plan.passes.size(); ++i) {
+        double2 *out = p->plan.passes[i].swap_out ? (cur == dm->amps ? dm->alt : dm->amps) : cur;
+        if (int rc = launch_pass(cur, out, p->dev, p->plan.passes[i], (uint32_t)i, dm->stream)) return rc;
+        cur = out;
+    }
+    if (cur != dm->amps) return fail(VQD_E_STATE, "relabelled plan ended in the second buffer");
     return VQD_OK;
 }
 

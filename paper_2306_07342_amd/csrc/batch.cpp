@@ -327,6 +327,7 @@ int plan_template(int n, const std::vector<int> &kinds, const std::vector<int> &
 {
     o.record_recipes = true;
     o.keep_identity = true;
+    o.relayout = false;
     std::vector<LOp> canon(kinds.size());
     for (size_t j = 0; j < kinds.size(); ++j) {
         double p[4];
@@ -475,6 +476,7 @@ int vqd_batch_set_opts(vqd_batch *b, int n, const vqd_plan_opts *o)
     if (n < 2 || n > VQD_MAX_QUBITS) return fail(VQD_E_SIZE, "n must be in [2, 16]");
     if (o->tile_bits < 4 || o->tile_bits > 12) return fail(VQD_E_ARG, "batched tile_bits must be in [4, 12]");
     b->opts_by_n[n] = to_plan_opts(*o);
+    b->opts_by_n[n].relayout = false;     // batched instances keep their layout in place
     b->compiled = false;
     return VQD_OK;
 }
@@ -718,6 +720,7 @@ int vqd_batch_plan_opts(const vqd_batch *b, int n, vqd_plan_opts *o)
     o->fuse_blocks = p.fuse_blocks;
     o->pad_coalesce = p.pad_coalesce;
     o->hermitian = p.hermitian ? 1 : 0;
+    o->relayout = 0;
     return VQD_OK;
 }
 
@@ -735,7 +738,9 @@ int vqd_template_export(int n, int count, const int *kinds, const int *targets, 
     if (opts) o = *opts;
     const std::vector<int> kv(kinds, kinds + count), tv(targets, targets + 4 * (size_t)count);
     HostPlan plan;
-    if (int rc = plan_template(n, kv, tv, to_plan_opts(o), plan)) return rc;
+    PlanOpts po = to_plan_opts(o);
+    po.relayout = false;
+    if (int rc = plan_template(n, kv, tv, po, plan)) return rc;
     if (params) {
         for (size_t j = 0; j < 4 * (size_t)count; ++j)
             if (!std::isfinite(params[j])) return fail(VQD_E_ARG, "non-finite parameter");

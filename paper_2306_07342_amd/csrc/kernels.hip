@@ -148,7 +148,8 @@ __device__ __forceinline__ uint32_t group_base(const KPass *__restrict__ P, uint
 // bits, its mirror's base the other way round.  Padding blocks and members
 // with a > b of a block with I = J are not stored.
 struct HermTile {
-    uint32_t gb, gbm;
+    uint32_t gb, gbm;    // load base and its mirror (the layout the pass loads)
+    uint32_t gbs, gbms;  // store base and its mirror (the layout the pass stores)
     bool mirror;         // i < j: the tile's conjugate transpose is stored too
     bool valid;          // a tile of the upper triangle (stored)
 };
@@ -174,12 +175,15 @@ __device__ __forceinline__ HermTile herm_tile(const KPass *__restrict__ P, uint3
     }
     const uint32_t ma = k & ((1u << c) - 1u), mb = k >> c;
     const uint32_t i = (I << c) | ma, j = (J << c) | mb;
-    HermTile h{0u, 0u, i != j, beta < NBB && (I < J || ma <= mb)};
+    HermTile h{0u, 0u, 0u, 0u, i != j, beta < NBB && (I < J || ma <= mb)};
     for (uint32_t q = 0; q < m; ++q) {
         const uint32_t gr = uni(P->group_gpos[q]), gc = uni(P->group_gpos[m + q]);
+        const uint32_t sr = uni(P->out_gpos[q]), sc = uni(P->out_gpos[m + q]);
         const uint32_t bi = (i >> q) & 1u, bj = (j >> q) & 1u;
         h.gb |= (bi << gr) | (bj << gc);
         h.gbm |= (bj << gr) | (bi << gc);
+        h.gbs |= (bi << sr) | (bj << sc);
+        h.gbms |= (bj << sr) | (bi << sc);
     }
     return h;
 }
@@ -231,7 +235,8 @@ __device__ __forceinline__ void store_mirror(double2 *lane, uint32_t gbm, const 
 }
 
 // The previous pass's group pair of an amplitude: i collects its bits at
-// that pass's row group positions, j at the column positions.  Index bits
+// that pass's row group positions, j at the column positions (in the layout
+// that pass stored, which is the one this pass loads).  Index bits
 // come from the thread (fixed per pass), the register slot and the tile's
 // group base, which occupy disjoint positions, so i and j are ORs of parts.
 struct HalfIn {
@@ -246,8 +251,8 @@ __device__ __forceinline__ void pair_of(const KPass *__restrict__ Pp, uint32_t m
     i = 0;
     j = 0;
     for (uint32_t k = 0; k < m; ++k) {
-        i |= ((x >> (uni(Pp->group_gpos[k]) & 31u)) & 1u) << k;
-        j |= ((x >> (uni(Pp->group_gpos[m + k]) & 31u)) & 1u) << k;
+        i |= ((x >> (uni(Pp->out_gpos[k]) & 31u)) & 1u) << k;
+        j |= ((x >> (uni(Pp->out_gpos[m + k]) & 31u)) & 1u) << k;
     }
 }
 
@@ -364,7 +369,7 @@ __device__ __forceinline__ void apply_ops(double2 (&a)[16], const KPhase *__rest
 // register-slot parts are workgroup-uniform (scalar unit).
 template <bool PHANTOM>
 __global__ void __launch_bounds__(1 << (kMaxTileBits - 4))
-k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
+k_pass(const double2 *__restrict__ amps_in, double2 *__restrict__ amps_out, const KPass *__restrict__ passes,
        const KPhase *__restrict__ phases, const KOp *__restrict__ ops,
        const double2 *__restrict__ mats, uint32_t pass_idx)
 {
@@ -395,8 +400,11 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
     uint32_t tg0, tgL;
     thread_bits(H0, tid, nthr, tl0, tg0);
     thread_bits(HL, tid, nthr, tlL, tgL);
-    const double2 *ld_lane = amps + tg0;
-    double2 *st_lane = amps + tgL;
+    // (amps_in and amps_out are one buffer unless the pass changes the
+    // layout; even then no load reads an address stored in the same launch:
+    // tiles are disjoint and a tile loads before it stores)
+    const double2 *ld_lane = amps_in + tg0;
+    double2 *st_lane = amps_out + tgL;
     // Hermitian mode: thread parts of the mirrored store (the transpose of
     // tgL) and of the transposed load (of tg0); the previous pass's group
     // pair (i, j) of a loaded amplitude splits into a per-thread part and
@@ -413,12 +421,12 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
         }
         if (herm & kHermHalfIn) hin = half_in(P, tg0);
     }
-    double2 *st_mirror = amps + tgM;
-    const double2 *ld_mirror = amps + tg0M;
+    double2 *st_mirror = amps_out + tgM;
+    const double2 *ld_mirror = amps_in + tg0M;
 
     uint32_t t = blockIdx.x;
     double2 nxt[16];
-    HermTile ht_nxt{0u, 0u, false, true};     // Hermitian mode: the prefetched tile
+    HermTile ht_nxt{0u, 0u, 0u, 0u, false, true};     // Hermitian mode: the prefetched tile
     if (t < n_tiles) {
         if (herm) {
             ht_nxt = herm_tile(P, t, ngb, herm);
@@ -518,8 +526,8 @@ k_pass(double2 *__restrict__ amps, const KPass *__restrict__ passes,
         // the stores stay outside the phase loop: a loop holding global
         // stores but no loads makes the compiler wait for every outstanding
         // load (the prefetch) before entering it
-        gb_prev = gb;
-        gbm_prev = ht.gbm;
+        gb_prev = herm ? ht.gbs : gb;
+        gbm_prev = ht.gbms;
         mirror_prev = ht.mirror && ht.valid && (herm & kHermMirror);
         valid_prev = ht.valid;
         have_prev = true;
@@ -824,7 +832,8 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
     const double2 *ld_mirror = amps + tg0M;
     auto tile_at = [&](uint32_t t) {
         if (herm) return herm_tile(P, t, ngb, herm);
-        HermTile h{group_base(P, t, ngb, false), 0u, false, true};
+        const uint32_t gb = group_base(P, t, ngb, false);
+        HermTile h{gb, 0u, gb, 0u, false, true};
         return h;
     };
     auto load = [&](double2 (&v)[16], const HermTile &h) {
@@ -838,8 +847,8 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
     auto store = [&](const double2 (&v)[16], const HermTile &h) {
         if (!active || !h.valid) return;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) st_lane[h.gb | slot_g(HL, e)] = v[e];
-        if (h.mirror && (herm & kHermMirror)) store_mirror(st_mirror, h.gbm, HL, v);
+        for (int e = 0; e < 16; ++e) st_lane[h.gbs | slot_g(HL, e)] = v[e];
+        if (h.mirror && (herm & kHermMirror)) store_mirror(st_mirror, h.gbms, HL, v);
     };
     // one barrier per tile: a tile with i = j is read through the transpose
     // by other waves than the ones that store it, so every wave's loads come
@@ -963,8 +972,8 @@ __global__ void k_reset(uint32_t *counter)
 }  // namespace
 
 // ------------------------------------------------------------- launches --
-int launch_pass(double2 *amps, const DevProgram &dev, const KPass &pass, uint32_t pass_idx,
-                hipStream_t stream)
+int launch_pass(double2 *amps_in, double2 *amps_out, const DevProgram &dev, const KPass &pass,
+                uint32_t pass_idx, hipStream_t stream)
 {
     const uint32_t threads = 1u << (pass.L - 4);
     const size_t lds = ((pass.phase_end - pass.phase_begin > 1) ? (size_t(16) << pass.L) : 0) +
@@ -992,10 +1001,10 @@ int launch_pass(double2 *amps, const DevProgram &dev, const KPass &pass, uint32_
     if (grid == 0) grid = 64;
     if (grid > pass.n_tiles) grid = pass.n_tiles;
     if (pass.phantom)
-        hipLaunchKernelGGL(k_pass<true>, dim3((uint32_t)grid), dim3(threads), lds, stream, amps,
+        hipLaunchKernelGGL(k_pass<true>, dim3((uint32_t)grid), dim3(threads), lds, stream, amps_in, amps_out,
                            dev.passes, dev.phases, dev.ops, dev.mats, pass_idx);
     else
-        hipLaunchKernelGGL(k_pass<false>, dim3((uint32_t)grid), dim3(threads), lds, stream, amps,
+        hipLaunchKernelGGL(k_pass<false>, dim3((uint32_t)grid), dim3(threads), lds, stream, amps_in, amps_out,
                            dev.passes, dev.phases, dev.ops, dev.mats, pass_idx);
     VQD_HIP(hipGetLastError());
     return VQD_OK;

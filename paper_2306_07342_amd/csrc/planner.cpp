@@ -411,6 +411,185 @@ void rt_table(uint32_t mode, int ubits, const std::vector<RtPart> &parts, const 
     }
 }
 
+namespace {
+
+// ---- relabelled layouts (PlanOpts::relayout) ------------------------------
+// A layout lam gives each logical qubit q its physical position lam[q]: the
+// row bit of q is stored at position lam[q], its column bit at lam[q] + n.
+// Applied to rows and columns alike, it keeps the transpose of a physical
+// index a swap of its two halves.
+using Layout = std::vector<int>;
+
+uint32_t phys_bit(const Layout &lam, int n, uint32_t b)
+{
+    return (int)b < n ? (uint32_t)lam[b] : (uint32_t)(lam[b - n] + n);
+}
+
+// Lane order of a phase that loads or stores HBM: the thread bits at the
+// physical row positions 0..c-1, then the same qubits' column positions
+// n..n+c-1, then the others in their order; c is the longest run of
+// qubit positions from 0 whose row and column bits are both thread bits.
+void coalesce_lanes(KPhase &H, uint32_t nthr, int n)
+{
+    auto slot_of = [&](uint32_t g) {
+        for (uint32_t t = 0; t < nthr; ++t)
+            if (H.thr_gpos[t] == g) return (int)t;
+        return -1;
+    };
+    uint32_t c = 0;
+    while (c < 4 && (int)c < n && slot_of(c) >= 0 && slot_of(c + (uint32_t)n) >= 0) ++c;
+    std::vector<uint32_t> want;
+    for (uint32_t k = 0; k < c; ++k) want.push_back(k);
+    for (uint32_t k = 0; k < c; ++k) want.push_back(k + (uint32_t)n);
+    std::vector<std::pair<uint32_t, uint32_t>> ent;    // (local, global) in lane order
+    for (uint32_t g : want) {
+        const int t = slot_of(g);
+        ent.emplace_back(H.thr_local[t], H.thr_gpos[t]);
+    }
+    for (uint32_t t = 0; t < nthr; ++t)
+        if (std::find(want.begin(), want.end(), H.thr_gpos[t]) == want.end())
+            ent.emplace_back(H.thr_local[t], H.thr_gpos[t]);
+    for (uint32_t t = 0; t < nthr; ++t) {
+        H.thr_local[t] = ent[t].first;
+        H.thr_gpos[t] = ent[t].second;
+    }
+}
+
+// The passes of a Hermitian plan, built with logical bit positions, get a
+// layout for the state between every two of them: the qubits that are in
+// both passes' tiles and in no register of the storing or the loading phase
+// at the lowest positions (at most 4), the others in their previous order.
+// Their row bits then lead the lanes of both phases, so both move 2^c
+// contiguous amplitudes.  Every position the kernel reads is rewritten for
+// the layout it applies to: the group bits and the first phase for the
+// layout the pass loads, out_gpos and the last phase for the one it stores,
+// runtime-diagonal gathers for the loaded one (the kernel takes their group
+// bits from the load base).  Constraints: the first pass loads and the last
+// stores the identity layout; a single-phase pass keeps its layout (its one
+// phase loads and stores); a pass that changes the layout stores into the
+// other buffer, so the number of changes is made even by giving up the
+// least useful one.
+void relabel_passes(int n, HostPlan &plan)
+{
+    const size_t K = plan.passes.size();
+    if (K < 2) return;
+    const uint32_t full = (1u << n) - 1u;
+    struct PInfo {
+        uint32_t tile = 0, reg_first = 0, reg_last = 0;
+        bool single = false;
+    };
+    std::vector<PInfo> info(K);
+    auto reg_qubits = [&](const KPhase &H) {
+        uint32_t m = 0;
+        for (int b = 0; b < kRegBits; ++b)
+            if (H.reg_gpos[b] < 2u * (uint32_t)n) m |= 1u << (H.reg_gpos[b] % (uint32_t)n);
+        return m;
+    };
+    for (size_t p = 0; p < K; ++p) {
+        const KPass &P = plan.passes[p];
+        const uint32_t m = P.n_group_bits >> 1;
+        uint32_t g = 0;
+        for (uint32_t k = 0; k < m; ++k) g |= 1u << P.group_gpos[k];
+        info[p].tile = full & ~g;
+        info[p].reg_first = reg_qubits(plan.phases[P.phase_begin]);
+        info[p].reg_last = reg_qubits(plan.phases[P.phase_end - 1]);
+        info[p].single = P.phase_end - P.phase_begin == 1;
+    }
+    Layout id(n);
+    for (int q = 0; q < n; ++q) id[q] = q;
+    std::vector<Layout> lam(K + 1, id);
+    std::vector<int> width(K + 1, 0);
+    for (size_t b = 1; b < K; ++b) {
+        const Layout &prev = lam[b - 1];
+        const uint32_t A = info[b - 1].tile & info[b].tile & ~info[b - 1].reg_last & ~info[b].reg_first;
+        auto by_prev = [&](int x, int y) { return prev[x] < prev[y]; };
+        std::vector<int> low, rest;
+        for (int q = 0; q < n; ++q) ((A >> q & 1) ? low : rest).push_back(q);
+        std::stable_sort(low.begin(), low.end(), by_prev);
+        if (low.size() > 4) {
+            rest.insert(rest.end(), low.begin() + 4, low.end());
+            low.resize(4);
+        }
+        std::stable_sort(rest.begin(), rest.end(), by_prev);
+        low.insert(low.end(), rest.begin(), rest.end());
+        for (int pos = 0; pos < n; ++pos) lam[b][low[pos]] = pos;
+        width[b] = (int)std::min<size_t>(4, (size_t)__builtin_popcount(A));
+    }
+    // runs of single-phase passes share one layout; at the program's ends
+    // it is the identity
+    for (size_t p = 0; p < K;) {
+        if (!info[p].single) {
+            ++p;
+            continue;
+        }
+        size_t q = p;
+        while (q + 1 < K && info[q + 1].single) ++q;
+        const Layout keep = (p == 0 || q + 1 == K) ? id : lam[p];
+        for (size_t b = p; b <= q + 1; ++b) lam[b] = keep;
+        p = q + 1;
+    }
+    auto changes = [&]() {
+        size_t c = 0;
+        for (size_t p = 0; p < K; ++p) c += lam[p] != lam[p + 1] ? 1 : 0;
+        return c;
+    };
+    if (changes() % 2) {
+        size_t best = 0;
+        for (size_t b = 1; b < K; ++b) {
+            if (info[b - 1].single || info[b].single || lam[b] == lam[b - 1]) continue;
+            const Layout keep = lam[b];
+            lam[b] = lam[b - 1];
+            const bool even = changes() % 2 == 0;
+            lam[b] = keep;
+            if (even && (best == 0 || width[b] < width[best])) best = b;
+        }
+        if (best) lam[best] = lam[best - 1];
+        else std::fill(lam.begin(), lam.end(), id);
+    }
+    for (size_t p = 0; p < K; ++p) {
+        KPass &P = plan.passes[p];
+        const Layout &li = lam[p], &lo = lam[p + 1];
+        P.swap_out = (li != lo) ? 1u : 0u;
+        plan.alt_buffer = plan.alt_buffer || P.swap_out != 0;
+        const uint32_t m = P.n_group_bits >> 1;
+        std::vector<int> gq;
+        for (uint32_t k = 0; k < m; ++k) gq.push_back((int)P.group_gpos[k]);
+        std::stable_sort(gq.begin(), gq.end(), [&](int x, int y) { return li[x] < li[y]; });
+        for (uint32_t k = 0; k < m; ++k) {
+            P.group_gpos[k] = (uint32_t)li[gq[k]];
+            P.group_gpos[m + k] = (uint32_t)(li[gq[k]] + n);
+            P.out_gpos[k] = (uint32_t)lo[gq[k]];
+            P.out_gpos[m + k] = (uint32_t)(lo[gq[k]] + n);
+        }
+        // launch blocks over the group qubits that split 128-byte lines
+        // (physical positions below 3 in the loaded layout)
+        uint32_t c = 0;
+        while (c < m && li[gq[c]] < 3) ++c;
+        const uint64_t N = 1ull << m, NB = N >> c, NBB = NB * (NB + 1) / 2;
+        const uint32_t stride = (uint32_t)std::min<uint64_t>(8, NBB);
+        P.n_tiles = (NBB + stride - 1) / stride * stride << (2 * c);
+        P.herm = (P.herm & (kHermHalfIn | kHermMirror)) | kHermPass | (c << kHermLineShift) |
+                 (stride << kHermStrideShift);
+        const uint32_t nthr = P.L - 4;
+        for (uint32_t ph = P.phase_begin; ph < P.phase_end; ++ph) {
+            KPhase &H = plan.phases[ph];
+            const bool last = ph + 1 == P.phase_end && P.phase_end - P.phase_begin > 1;
+            const Layout &lh = last ? lo : li;
+            for (int b = 0; b < kRegBits; ++b) H.reg_gpos[b] = phys_bit(lh, n, H.reg_gpos[b]);
+            for (uint32_t t = 0; t < nthr; ++t) H.thr_gpos[t] = phys_bit(lh, n, H.thr_gpos[t]);
+            for (uint32_t oi = H.op_begin; oi < H.op_end; ++oi) {
+                KOp &o = plan.ops[oi];
+                if (o.kind == KOP_DIAG_RT)
+                    for (uint32_t j = 0; j < o.nbits; ++j) o.gpos[j] = phys_bit(li, n, o.gpos[j]);
+            }
+        }
+        coalesce_lanes(plan.phases[P.phase_begin], nthr, n);
+        if (P.phase_end - P.phase_begin > 1) coalesce_lanes(plan.phases[P.phase_end - 1], nthr, n);
+    }
+}
+
+}  // namespace
+
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out)
 {
     out = HostPlan{};
@@ -1003,6 +1182,8 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             for (uint32_t oi = out.phases[kp.phase_begin].op_begin; oi < out.ops.size(); ++oi)
                 if (out.recipes[oi].rt) out.recipes[oi].mat_off += kp.rt_mat;
         out.mats.insert(out.mats.end(), rt_tables.begin(), rt_tables.end());
+        std::copy(kp.group_gpos, kp.group_gpos + 32, kp.out_gpos);   // the layout stays
+        kp.swap_out = 0;
         out.passes.push_back(kp);
     }
     if (herm) {
@@ -1011,6 +1192,14 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         for (size_t i = 0; i < out.passes.size(); ++i) {
             if (i > 0) out.passes[i].herm |= kHermHalfIn;
             if (i + 1 == out.passes.size()) out.passes[i].herm |= kHermMirror;
+        }
+        if (opt.relayout) {
+            relabel_passes(n, out);
+        } else {
+            for (KPass &P : out.passes) {
+                coalesce_lanes(out.phases[P.phase_begin], P.L - 4, n);
+                if (P.phase_end - P.phase_begin > 1) coalesce_lanes(out.phases[P.phase_end - 1], P.L - 4, n);
+            }
         }
     }
     finish_slot_tables(n, out);
@@ -1039,7 +1228,7 @@ void finish_slot_tables(int n, HostPlan &plan)
         std::fill(P.hj_slot, P.hj_slot + kSlots, 0u);
         if (!(P.herm & kHermHalfIn) || p == 0) continue;
         // the bits of slot e's index, taken at the previous pass's row
-        // (i) and column (j) group positions
+        // (i) and column (j) group positions in the layout it stored
         const KPass &Q = plan.passes[p - 1];
         const KPhase &H0 = plan.phases[P.phase_begin];
         const uint32_t m = Q.n_group_bits >> 1;
@@ -1047,8 +1236,8 @@ void finish_slot_tables(int n, HostPlan &plan)
             const uint32_t x = H0.g_slot[e];
             uint32_t i = 0, j = 0;
             for (uint32_t k = 0; k < m; ++k) {
-                i |= ((x >> (Q.group_gpos[k] & 31u)) & 1u) << k;
-                j |= ((x >> (Q.group_gpos[m + k] & 31u)) & 1u) << k;
+                i |= ((x >> (Q.out_gpos[k] & 31u)) & 1u) << k;
+                j |= ((x >> (Q.out_gpos[m + k] & 31u)) & 1u) << k;
             }
             P.hi_slot[e] = i;
             P.hj_slot[e] = j;

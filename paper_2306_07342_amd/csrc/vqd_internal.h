@@ -129,6 +129,14 @@ struct alignas(16) KPass {
     // the kernel); filled by finish_slot_tables
     uint32_t hi_slot[kSlots];
     uint32_t hj_slot[kSlots];
+    // Relabelled plans: the state between two passes is stored under a
+    // permutation of the qubits (the physical row bit of qubit q at position
+    // lambda(q), its column bit at lambda(q) + n).  group_gpos and the first
+    // phase's positions are in the layout this pass loads; out_gpos and the
+    // last phase's positions in the layout it stores (equal to group_gpos
+    // when the layout stays)
+    uint32_t out_gpos[32];
+    uint32_t swap_out;        // stores into the other state buffer (the layout changes)
 };
 constexpr uint32_t kHermPass = 1u;     // computes the tiles i <= j only
 constexpr uint32_t kHermMirror = 2u;   // also stores each i < j tile's conjugate transpose
@@ -192,6 +200,7 @@ struct HostPlan {
     std::vector<cd> mats;
     std::vector<Recipe> recipes;    // one per kernel op when recorded
     double fma_per_amp = 0;
+    bool alt_buffer = false;        // some pass stores into a second state buffer
     bool hermitian = false;         // planned in Hermitian mode
     double tile_fraction = 1.0;     // share of the amplitudes the passes compute
 };
@@ -227,6 +236,8 @@ struct PlanOpts {
                                     // LDS (0: what 160 KiB leaves beside the tile)
     bool hermitian = false;         // compute half the tiles of a Hermitian state when every
                                     // op preserves Hermiticity (HostPlan::hermitian says if)
+    bool relayout = false;          // Hermitian plans: store the state between passes under
+                                    // qubit relabellings that make tile I/O contiguous
 };
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out);
 // Fill the per-slot tables of every phase and pass of a plan (KPhase::lds_slot,
@@ -332,7 +343,9 @@ struct BatchDev {
 };
 
 // ------------------------------------------------------------- launches --
-int launch_pass(double2 *amps, const DevProgram &dev, const KPass &pass, uint32_t pass_idx,
+// One pass: loads from amps_in, stores to amps_out (the same buffer unless
+// the pass changes the layout).
+int launch_pass(double2 *amps_in, double2 *amps_out, const DevProgram &dev, const KPass &pass, uint32_t pass_idx,
                 hipStream_t stream);
 int launch_init(double2 *amps, int n, int mode, uint64_t b, const double *p0, hipStream_t stream);
 int launch_batch(double2 *arena, const BatchDev &bd, double *out, hipStream_t stream);
@@ -385,6 +398,7 @@ void unitary_to_superop(int k, const cd *U, std::vector<cd> &S);
 // ------------------------------------------------------------- handles --
 struct vqd_dm {
     double2 *amps = nullptr;
+    double2 *alt = nullptr;         // second state buffer of relabelled plans (owned; on demand)
     int n = 0;
     size_t bytes = 0;
     hipStream_t stream = nullptr;

@@ -42,7 +42,7 @@ class VQDError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("tile_bits", ctypes.c_int), ("min_contig_bits", ctypes.c_int),
                 ("max_ops_per_pass", ctypes.c_int), ("fuse_blocks", ctypes.c_int),
-                ("pad_coalesce", ctypes.c_int), ("hermitian", ctypes.c_int)]
+                ("pad_coalesce", ctypes.c_int), ("hermitian", ctypes.c_int), ("relayout", ctypes.c_int)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -484,9 +484,9 @@ def calc_expec_z_noalloc(amps, n: int, out, stream=None):
 
 
 def plan_opts(tile_bits=13, min_contig_bits=3, max_ops_per_pass=0, fuse_blocks=True,
-              pad_coalesce=True, hermitian=False) -> PlanOpts:
+              pad_coalesce=True, hermitian=False, relayout=False) -> PlanOpts:
     return PlanOpts(tile_bits, min_contig_bits, max_ops_per_pass, 1 if fuse_blocks else 0,
-                    1 if pad_coalesce else 0, 1 if hermitian else 0)
+                    1 if pad_coalesce else 0, 1 if hermitian else 0, 1 if relayout else 0)
 
 
 def _structure(structure):

@@ -56,6 +56,30 @@ def test_grid_circuit_eleven_qubits(gpu_lib, contig):
     check(gpu_lib, 11, ops, seed=11, tile_bits=12, min_contig_bits=contig)
 
 
+@pytest.mark.parametrize("n,rows,tile_bits,contig", [(6, 2, 8, 1), (9, 1, 10, 1), (10, 2, 12, 1), (12, 2, 12, 1),
+                                                     (12, 3, 12, 0)])
+def test_relabelled_plans(gpu_lib, n, rows, tile_bits, contig):
+    """relayout: between passes the state is stored under qubit relabellings,
+    in two buffers; the result, in the caller's buffer under the original
+    labelling, equals the oracle's.  Run twice on one handle (the second
+    buffer is allocated once and reused)."""
+    ops = c2_grid_circuit(rows=rows, cols=n // rows, n_gates=40 * n)
+    R0 = hermitian_state(n, n + 100)
+    ref = OracleDM(n)
+    ref.set(R0)
+    emulate(n, ops, ref)
+    want = ref.to_vectorised()
+    prog = gpu_lib.Program(n, ops).compile(gpu_lib.plan_opts(hermitian=True, relayout=True, tile_bits=tile_bits,
+                                                             min_contig_bits=contig))
+    say("relabelled n=%d ops=%d passes=%d" % (n, len(ops), prog.info()["n_passes"]))
+    dm = gpu_lib.DensityMatrix(n)
+    for rep in range(2):
+        dm.from_numpy(np.ascontiguousarray(R0.T).reshape(-1))
+        prog.run(dm)
+        got = dm.to_numpy()
+        assert max(np.abs(got.real - want.real).max(), np.abs(got.imag - want.imag).max()) <= TOL, rep
+
+
 @pytest.mark.parametrize("tile_bits", [8, 10])
 def test_all_to_all_small_tiles(gpu_lib, tile_bits):
     check(gpu_lib, 9, c3_all_to_all_circuit(n=9, n_gates=80), seed=3, tile_bits=tile_bits, min_contig_bits=2)

@@ -259,3 +259,72 @@ def test_one_qubit_maps_in_pauli_transfer_form(vqd_host):
     Bf = np.kron(B, np.eye(4))
     ref = (Af @ R0 @ Bf.conj().T).T.reshape(-1)
     assert_close(got, ref)
+
+
+@pytest.mark.parametrize("n,tile_bits,contig", [(4, 4, 0), (6, 8, 1), (7, 8, 1), (8, 10, 1), (9, 12, 1), (9, 8, 0)])
+def test_relabelled_plans_match_the_oracle(vqd_host, n, tile_bits, contig):
+    """relayout: the state between passes is stored under qubit relabellings;
+    passes that change it write the other buffer (the emulator starts that
+    buffer as NaN, so a read of an amplitude no pass stored shows).  The
+    result, in the caller's buffer under the original labelling, equals the
+    oracle's; the number of buffer changes is even."""
+    ops = c2_grid_circuit(rows=1, cols=n, n_gates=120) if n % 2 else c1_line_circuit(n=n, n_gates=90)
+    got, ref, info, plan = run_herm(vqd_host, n, ops, seed=n, tile_bits=tile_bits,
+                                    min_contig_bits=contig, relayout=True)
+    assert info["hermitian"] == 1
+    assert np.isfinite(got).all()
+    assert_close(got, ref)
+    swaps = [int(P["swap_out"]) for P in plan["passes"]]
+    assert sum(swaps) % 2 == 0
+
+
+def test_relabelled_grid_circuit_layouts(vqd_host):
+    """The 2x5 grid circuit in relabelled Hermitian mode against the oracle;
+    every pass's group bits are a row/column pair in both layouts, a pass
+    that keeps its layout stores with the same group positions it loads,
+    and the lanes of every loading and storing phase start with the row
+    bits of the lowest physical qubits that are thread bits there."""
+    n = 10
+    ops = c2_grid_circuit(rows=2, cols=5, n_gates=160)
+    got, ref, info, plan = run_herm(vqd_host, n, ops, seed=3, tile_bits=12, min_contig_bits=1, relayout=True)
+    assert_close(got, ref)
+    passes = plan["passes"]
+    assert len(passes) > 2 and any(int(P["swap_out"]) for P in passes)
+    for P in passes:
+        m = int(P["ngb"]) // 2
+        g, o = [int(x) for x in P["group_gpos"][:2 * m]], [int(x) for x in P["out_gpos"][:2 * m]]
+        assert all(g[m + i] == g[i] + n and o[m + i] == o[i] + n for i in range(m))
+        if not int(P["swap_out"]):
+            assert g == o
+        for ph in (int(P["pb"]), int(P["pe"]) - 1):
+            thr = [int(x) for x in plan["phases"][ph]["thr_gpos"][:int(P["L"]) - 4]]
+            c = 0
+            while c < 4 and c in thr and c + n in thr:
+                c += 1
+            assert thr[:2 * c] == list(range(c)) + [n + q for q in range(c)]
+
+
+def test_relabelling_lengthens_contiguous_runs(vqd_host):
+    """On the 14-qubit grid circuit's plan the relabelled layouts give most
+    pass boundaries 2 or more shared low qubits (64-byte runs or longer),
+    where the identity layout gives most only qubit 0."""
+    n = 14
+    ops = c2_grid_circuit(rows=2, cols=7, n_gates=2000)
+
+    def runs(relayout):
+        prog = vqd_host.Program(n, ops)
+        prog.plan(vqd_host.plan_opts(tile_bits=12, min_contig_bits=1, hermitian=True, relayout=relayout))
+        plan = emu.parse(prog.export())
+        out = []
+        for P in plan["passes"]:
+            for ph in (int(P["pb"]), int(P["pe"]) - 1):
+                thr = [int(x) for x in plan["phases"][ph]["thr_gpos"][:int(P["L"]) - 4]]
+                c = 0
+                while c < 4 and c in thr and c + n in thr:
+                    c += 1
+                out.append(c)
+        return np.array(out), prog.info()
+    base, info0 = runs(False)
+    rel, info1 = runs(True)
+    assert info0["n_passes"] == info1["n_passes"]
+    assert np.mean(rel >= 2) > 0.6 > np.mean(base >= 2)
