@@ -410,14 +410,13 @@ k_pass(const double2 *__restrict__ amps_in, double2 *__restrict__ amps_out, cons
     // pair (i, j) of a loaded amplitude splits into a per-thread part and
     // per-register-bit parts (the bits come from disjoint sources)
     const uint32_t herm = uni(P->herm);
-    const uint32_t nq = (L + ngb) >> 1;
     uint32_t tgM = 0, tg0M = 0;
     HalfIn hin{};
     if (herm) {
 #pragma unroll
         for (uint32_t i = 0; i < (uint32_t)kMaxThreadBits; ++i) {
-            tgM |= ((tid >> i) & 1u) << (mirror_pos(uni(HL->thr_gpos[i]), nq) & 31u);
-            tg0M |= ((tid >> i) & 1u) << (mirror_pos(uni(H0->thr_gpos[i]), nq) & 31u);
+            tgM |= ((tid >> i) & 1u) << (uni(HL->thr_mpos[i]) & 31u);
+            tg0M |= ((tid >> i) & 1u) << (uni(H0->thr_mpos[i]) & 31u);
         }
         if (herm & kHermHalfIn) hin = half_in(P, tg0);
     }
@@ -817,14 +816,13 @@ __device__ __forceinline__ void batch_pass(double2 *__restrict__ amps, const KPa
     // stored half read directly or through the transpose, mirror images in
     // the instance's last pass
     const uint32_t herm = uni(P->herm);
-    const uint32_t nq = (L + ngb) >> 1;
     uint32_t tgM = 0, tg0M = 0;
     HalfIn hin{};
     if (herm) {
 #pragma unroll
         for (uint32_t i = 0; i < (uint32_t)kMaxThreadBits; ++i) {
-            tgM |= ((ttid >> i) & 1u) << (mirror_pos(uni(HL->thr_gpos[i]), nq) & 31u);
-            tg0M |= ((ttid >> i) & 1u) << (mirror_pos(uni(H0->thr_gpos[i]), nq) & 31u);
+            tgM |= ((ttid >> i) & 1u) << (uni(HL->thr_mpos[i]) & 31u);
+            tg0M |= ((ttid >> i) & 1u) << (uni(H0->thr_mpos[i]) & 31u);
         }
         if (herm & kHermHalfIn) hin = half_in(P, tg0);
     }

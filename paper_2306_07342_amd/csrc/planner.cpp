@@ -414,61 +414,106 @@ void rt_table(uint32_t mode, int ubits, const std::vector<RtPart> &parts, const 
 namespace {
 
 // ---- relabelled layouts (PlanOpts::relayout) ------------------------------
-// A layout lam gives each logical qubit q its physical position lam[q]: the
-// row bit of q is stored at position lam[q], its column bit at lam[q] + n.
-// Applied to rows and columns alike, it keeps the transpose of a physical
-// index a swap of its two halves.
+// A layout phi gives each logical index bit b (row bit q = b < n, column bit
+// q = b - n) its physical position phi[b].  The vectorised layout of the
+// caller's buffer is the identity.  Between two passes of a relabelled plan
+// the state is stored interleaved: qubit q in slot s(q) has its row bit at
+// position 2 s(q) and its column bit at 2 s(q) + 1, so a tile whose qubits
+// hold the lowest slots is one contiguous block.  Either way the transpose
+// of a physical index exchanges the two bits of each qubit.
 using Layout = std::vector<int>;
 
-uint32_t phys_bit(const Layout &lam, int n, uint32_t b)
+Layout vectorised(int n)
 {
-    return (int)b < n ? (uint32_t)lam[b] : (uint32_t)(lam[b - n] + n);
+    Layout phi(2 * n);
+    for (int b = 0; b < 2 * n; ++b) phi[b] = b;
+    return phi;
 }
 
-// Lane order of a phase that loads or stores HBM: the thread bits at the
-// physical row positions 0..c-1, then the same qubits' column positions
-// n..n+c-1, then the others in their order; c is the longest run of
-// qubit positions from 0 whose row and column bits are both thread bits.
-void coalesce_lanes(KPhase &H, uint32_t nthr, int n)
+Layout interleaved(int n, const std::vector<int> &order)    // order[s] = qubit in slot s
+{
+    Layout phi(2 * n);
+    for (int s = 0; s < n; ++s) {
+        phi[order[s]] = 2 * s;
+        phi[order[s] + n] = 2 * s + 1;
+    }
+    return phi;
+}
+
+// Position of the transpose partner of physical position p under phi.
+uint32_t mirror_under(const Layout &phi, int n, uint32_t p)
+{
+    for (int b = 0; b < 2 * n; ++b)
+        if ((uint32_t)phi[b] == p) return (uint32_t)phi[b < n ? b + n : b - n];
+    return p;
+}
+
+// Lane order of a phase that loads or stores HBM: the longest run of
+// physical positions 0, 1, 2, ... among its thread bits, then the transpose
+// partners of those (the mirrored stores and transposed loads), then the
+// other thread bits in their order.
+void coalesce_lanes(KPhase &H, uint32_t nthr, const Layout &phi, int n)
 {
     auto slot_of = [&](uint32_t g) {
         for (uint32_t t = 0; t < nthr; ++t)
             if (H.thr_gpos[t] == g) return (int)t;
         return -1;
     };
-    uint32_t c = 0;
-    while (c < 4 && (int)c < n && slot_of(c) >= 0 && slot_of(c + (uint32_t)n) >= 0) ++c;
     std::vector<uint32_t> want;
-    for (uint32_t k = 0; k < c; ++k) want.push_back(k);
-    for (uint32_t k = 0; k < c; ++k) want.push_back(k + (uint32_t)n);
-    std::vector<std::pair<uint32_t, uint32_t>> ent;    // (local, global) in lane order
-    for (uint32_t g : want) {
-        const int t = slot_of(g);
-        ent.emplace_back(H.thr_local[t], H.thr_gpos[t]);
+    for (uint32_t p = 0; slot_of(p) >= 0; ++p) want.push_back(p);
+    const size_t run = want.size();
+    for (size_t k = 0; k < run; ++k) {
+        const uint32_t mp = mirror_under(phi, n, want[k]);
+        if (slot_of(mp) >= 0 && std::find(want.begin(), want.end(), mp) == want.end()) want.push_back(mp);
     }
+    std::vector<uint32_t> order;                    // thread entries in lane order
+    for (uint32_t g : want) order.push_back((uint32_t)slot_of(g));
     for (uint32_t t = 0; t < nthr; ++t)
-        if (std::find(want.begin(), want.end(), H.thr_gpos[t]) == want.end())
-            ent.emplace_back(H.thr_local[t], H.thr_gpos[t]);
+        if (std::find(want.begin(), want.end(), H.thr_gpos[t]) == want.end()) order.push_back(t);
+    const KPhase old = H;       // the mirror table moves with its entries
     for (uint32_t t = 0; t < nthr; ++t) {
-        H.thr_local[t] = ent[t].first;
-        H.thr_gpos[t] = ent[t].second;
+        H.thr_local[t] = old.thr_local[order[t]];
+        H.thr_gpos[t] = old.thr_gpos[order[t]];
+        H.thr_mpos[t] = old.thr_mpos[order[t]];
+    }
+}
+
+// The phase's positions (logical so far) under phi, with their mirror table.
+void place_phase(KPhase &H, uint32_t nthr, const Layout &phi, int n)
+{
+    for (int b = 0; b < kRegBits; ++b) {
+        H.reg_gpos[b] = (uint32_t)phi[H.reg_gpos[b]];
+        H.reg_mpos[b] = mirror_under(phi, n, H.reg_gpos[b]);
+    }
+    for (uint32_t t = 0; t < (uint32_t)kMaxThreadBits; ++t) {
+        if (t < nthr) {
+            H.thr_gpos[t] = (uint32_t)phi[H.thr_gpos[t]];
+            H.thr_mpos[t] = mirror_under(phi, n, H.thr_gpos[t]);
+        } else {
+            H.thr_gpos[t] = H.thr_mpos[t] = 0;
+        }
     }
 }
 
 // The passes of a Hermitian plan, built with logical bit positions, get a
-// layout for the state between every two of them: the qubits that are in
-// both passes' tiles and in no register of the storing or the loading phase
-// at the lowest positions (at most 4), the others in their previous order.
-// Their row bits then lead the lanes of both phases, so both move 2^c
-// contiguous amplitudes.  Every position the kernel reads is rewritten for
-// the layout it applies to: the group bits and the first phase for the
-// layout the pass loads, out_gpos and the last phase for the one it stores,
-// runtime-diagonal gathers for the loaded one (the kernel takes their group
-// bits from the load base).  Constraints: the first pass loads and the last
-// stores the identity layout; a single-phase pass keeps its layout (its one
-// phase loads and stores); a pass that changes the layout stores into the
-// other buffer, so the number of changes is made even by giving up the
-// least useful one.
+// layout for the state between every two of them, and every position the
+// kernel reads is rewritten for the layout it applies to: the group bits and
+// the first phase for the layout the pass loads, out_gpos and the last phase
+// for the one it stores, runtime-diagonal gathers for the loaded one (the
+// kernel takes their group bits from the load base).
+//
+// The layout before pass b is interleaved with pass b's tile qubits in the
+// lowest slots: the qubits pass b-1 also holds in its tile (and in no
+// register of its storing or pass b's loading phase) first, pass b's other
+// thread qubits next, its first phase's register qubits last, then the
+// other qubits in their previous order.  Pass b then loads one contiguous
+// block per tile, and pass b-1 stores runs of 4^c amplitudes, c the shared
+// qubits in front.
+//
+// Constraints: the first pass loads and the last stores the vectorised
+// layout; a single-phase pass keeps its layout (its one phase loads and
+// stores); a pass that changes the layout stores into the other buffer, so
+// the number of changes is made even by giving up the least useful one.
 void relabel_passes(int n, HostPlan &plan)
 {
     const size_t K = plan.passes.size();
@@ -495,28 +540,28 @@ void relabel_passes(int n, HostPlan &plan)
         info[p].reg_last = reg_qubits(plan.phases[P.phase_end - 1]);
         info[p].single = P.phase_end - P.phase_begin == 1;
     }
-    Layout id(n);
-    for (int q = 0; q < n; ++q) id[q] = q;
-    std::vector<Layout> lam(K + 1, id);
+    const Layout vec = vectorised(n);
+    std::vector<Layout> lam(K + 1, vec);
     std::vector<int> width(K + 1, 0);
+    std::vector<int> slot(n);                       // the previous boundary's slots
+    for (int q = 0; q < n; ++q) slot[q] = q;
     for (size_t b = 1; b < K; ++b) {
-        const Layout &prev = lam[b - 1];
-        const uint32_t A = info[b - 1].tile & info[b].tile & ~info[b - 1].reg_last & ~info[b].reg_first;
-        auto by_prev = [&](int x, int y) { return prev[x] < prev[y]; };
-        std::vector<int> low, rest;
-        for (int q = 0; q < n; ++q) ((A >> q & 1) ? low : rest).push_back(q);
-        std::stable_sort(low.begin(), low.end(), by_prev);
-        if (low.size() > 4) {
-            rest.insert(rest.end(), low.begin() + 4, low.end());
-            low.resize(4);
+        const uint32_t T = info[b].tile, R = info[b].reg_first;
+        const uint32_t C = info[b - 1].tile & T & ~info[b - 1].reg_last & ~R;
+        std::vector<int> groups[4];                 // C, T \ C \ R, R, the others
+        for (int q = 0; q < n; ++q)
+            groups[(C >> q & 1) ? 0 : !(T >> q & 1) ? 3 : (R >> q & 1) ? 2 : 1].push_back(q);
+        std::vector<int> order;
+        for (auto &gr : groups) {
+            std::stable_sort(gr.begin(), gr.end(), [&](int x, int y) { return slot[x] < slot[y]; });
+            order.insert(order.end(), gr.begin(), gr.end());
         }
-        std::stable_sort(rest.begin(), rest.end(), by_prev);
-        low.insert(low.end(), rest.begin(), rest.end());
-        for (int pos = 0; pos < n; ++pos) lam[b][low[pos]] = pos;
-        width[b] = (int)std::min<size_t>(4, (size_t)__builtin_popcount(A));
+        for (int s = 0; s < n; ++s) slot[order[s]] = s;
+        lam[b] = interleaved(n, order);
+        width[b] = __builtin_popcount(C);
     }
     // runs of single-phase passes share one layout; at the program's ends
-    // it is the identity
+    // it is the vectorised one
     for (size_t p = 0; p < K;) {
         if (!info[p].single) {
             ++p;
@@ -524,7 +569,7 @@ void relabel_passes(int n, HostPlan &plan)
         }
         size_t q = p;
         while (q + 1 < K && info[q + 1].single) ++q;
-        const Layout keep = (p == 0 || q + 1 == K) ? id : lam[p];
+        const Layout keep = (p == 0 || q + 1 == K) ? vec : lam[p];
         for (size_t b = p; b <= q + 1; ++b) lam[b] = keep;
         p = q + 1;
     }
@@ -544,7 +589,7 @@ void relabel_passes(int n, HostPlan &plan)
             if (even && (best == 0 || width[b] < width[best])) best = b;
         }
         if (best) lam[best] = lam[best - 1];
-        else std::fill(lam.begin(), lam.end(), id);
+        else std::fill(lam.begin(), lam.end(), vec);
     }
     for (size_t p = 0; p < K; ++p) {
         KPass &P = plan.passes[p];
@@ -557,14 +602,14 @@ void relabel_passes(int n, HostPlan &plan)
         std::stable_sort(gq.begin(), gq.end(), [&](int x, int y) { return li[x] < li[y]; });
         for (uint32_t k = 0; k < m; ++k) {
             P.group_gpos[k] = (uint32_t)li[gq[k]];
-            P.group_gpos[m + k] = (uint32_t)(li[gq[k]] + n);
+            P.group_gpos[m + k] = (uint32_t)li[gq[k] + n];
             P.out_gpos[k] = (uint32_t)lo[gq[k]];
-            P.out_gpos[m + k] = (uint32_t)(lo[gq[k]] + n);
+            P.out_gpos[m + k] = (uint32_t)lo[gq[k] + n];
         }
-        // launch blocks over the group qubits that split 128-byte lines
-        // (physical positions below 3 in the loaded layout)
+        // launch blocks over the group qubits with a bit below position 3
+        // in the loaded layout (they split 128-byte lines between tiles)
         uint32_t c = 0;
-        while (c < m && li[gq[c]] < 3) ++c;
+        while (c < m && std::min(li[gq[c]], li[gq[c] + n]) < 3) ++c;
         const uint64_t N = 1ull << m, NB = N >> c, NBB = NB * (NB + 1) / 2;
         const uint32_t stride = (uint32_t)std::min<uint64_t>(8, NBB);
         P.n_tiles = (NBB + stride - 1) / stride * stride << (2 * c);
@@ -575,17 +620,17 @@ void relabel_passes(int n, HostPlan &plan)
             KPhase &H = plan.phases[ph];
             const bool last = ph + 1 == P.phase_end && P.phase_end - P.phase_begin > 1;
             const Layout &lh = last ? lo : li;
-            for (int b = 0; b < kRegBits; ++b) H.reg_gpos[b] = phys_bit(lh, n, H.reg_gpos[b]);
-            for (uint32_t t = 0; t < nthr; ++t) H.thr_gpos[t] = phys_bit(lh, n, H.thr_gpos[t]);
+            place_phase(H, nthr, lh, n);
             for (uint32_t oi = H.op_begin; oi < H.op_end; ++oi) {
                 KOp &o = plan.ops[oi];
                 if (o.kind == KOP_DIAG_RT)
-                    for (uint32_t j = 0; j < o.nbits; ++j) o.gpos[j] = phys_bit(li, n, o.gpos[j]);
+                    for (uint32_t j = 0; j < o.nbits; ++j) o.gpos[j] = (uint32_t)li[o.gpos[j]];
             }
         }
-        coalesce_lanes(plan.phases[P.phase_begin], nthr, n);
-        if (P.phase_end - P.phase_begin > 1) coalesce_lanes(plan.phases[P.phase_end - 1], nthr, n);
+        coalesce_lanes(plan.phases[P.phase_begin], nthr, li, n);
+        if (P.phase_end - P.phase_begin > 1) coalesce_lanes(plan.phases[P.phase_end - 1], nthr, lo, n);
     }
+    plan.relabelled = true;
 }
 
 }  // namespace
@@ -1193,14 +1238,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             if (i > 0) out.passes[i].herm |= kHermHalfIn;
             if (i + 1 == out.passes.size()) out.passes[i].herm |= kHermMirror;
         }
-        if (opt.relayout) {
-            relabel_passes(n, out);
-        } else {
-            for (KPass &P : out.passes) {
-                coalesce_lanes(out.phases[P.phase_begin], P.L - 4, n);
-                if (P.phase_end - P.phase_begin > 1) coalesce_lanes(out.phases[P.phase_end - 1], P.L - 4, n);
-            }
-        }
+        if (opt.relayout) relabel_passes(n, out);
     }
     finish_slot_tables(n, out);
     return VQD_OK;
@@ -1209,13 +1247,18 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
 void finish_slot_tables(int n, HostPlan &plan)
 {
     for (KPhase &H : plan.phases) {
+        if (!plan.relabelled) {
+            // the vectorised layout throughout
+            for (int b = 0; b < kRegBits; ++b) H.reg_mpos[b] = mirror_pos(H.reg_gpos[b], (uint32_t)n) & 31u;
+            for (int t = 0; t < kMaxThreadBits; ++t) H.thr_mpos[t] = mirror_pos(H.thr_gpos[t], (uint32_t)n) & 31u;
+        }
         for (int e = 0; e < kSlots; ++e) {
             uint32_t l = 0, g = 0, gm = 0;
             for (int b = 0; b < kRegBits; ++b)
                 if (e >> b & 1) {
                     l |= 1u << (H.reg_local[b] & 31u);
                     g |= 1u << (H.reg_gpos[b] & 31u);
-                    gm |= 1u << (mirror_pos(H.reg_gpos[b], (uint32_t)n) & 31u);
+                    gm |= 1u << (H.reg_mpos[b] & 31u);
                 }
             H.lds_slot[e] = lds_swizzle(l) << 4;
             H.g_slot[e] = g;

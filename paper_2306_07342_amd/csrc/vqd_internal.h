@@ -94,7 +94,8 @@ __host__ __device__ inline uint32_t lds_swizzle(uint32_t l)
     return l ^ (((l >> 3) ^ (l >> 6) ^ (l >> 9)) & 7u);
 }
 
-// Row bit q <-> column bit q + n: the transpose of an index bit position.
+// Row bit q <-> column bit q + n: the transpose of an index bit position in
+// the vectorised layout.
 __host__ __device__ inline uint32_t mirror_pos(uint32_t g, uint32_t n) { return g < n ? g + n : g - n; }
 
 struct alignas(16) KPhase {
@@ -108,6 +109,12 @@ struct alignas(16) KPhase {
     uint32_t lds_slot[kSlots];   // byte offset part in LDS: swizzle(local bits of e) * 16
     uint32_t g_slot[kSlots];     // global index part: OR of 1 << reg_gpos[b] over the bits b of e
     uint32_t gm_slot[kSlots];    // the same with every position mirrored (row <-> column bit)
+    // Physical position of the transpose partner (the other bit of the same
+    // qubit) of each reg_gpos / thr_gpos entry, in the layout those positions
+    // are in: n away in the vectorised layout, the neighbouring bit in an
+    // interleaved one (unused thread entries 0)
+    uint32_t reg_mpos[4];
+    uint32_t thr_mpos[kMaxThreadBits];
 };
 
 struct alignas(16) KPass {
@@ -201,6 +208,7 @@ struct HostPlan {
     std::vector<Recipe> recipes;    // one per kernel op when recorded
     double fma_per_amp = 0;
     bool alt_buffer = false;        // some pass stores into a second state buffer
+    bool relabelled = false;        // positions set for per-pass layouts (mirror tables included)
     bool hermitian = false;         // planned in Hermitian mode
     double tile_fraction = 1.0;     // share of the amplitudes the passes compute
 };

@@ -26,9 +26,11 @@ def _dtypes(sz_pass, sz_phase, sz_op):
                       "formats": ["<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u8",
                                   ("<u4", 32), "<u4", ("<u4", 32), "<u4"],
                       "offsets": [0, 4, 8, 12, 16, 20, 24, 28, 32, 40, 168, 300, 428], "itemsize": sz_pass})
-    dphase = np.dtype({"names": ["ob", "oe", "reg_local", "reg_gpos", "thr_local", "thr_gpos"],
-                       "formats": ["<u4", "<u4", ("<u4", 4), ("<u4", 4), ("<u4", 9), ("<u4", 9)],
-                       "offsets": [0, 4, 8, 24, 40, 76], "itemsize": sz_phase})
+    dphase = np.dtype({"names": ["ob", "oe", "reg_local", "reg_gpos", "thr_local", "thr_gpos", "reg_mpos",
+                                 "thr_mpos"],
+                       "formats": ["<u4", "<u4", ("<u4", 4), ("<u4", 4), ("<u4", 9), ("<u4", 9), ("<u4", 4),
+                                   ("<u4", 9)],
+                       "offsets": [0, 4, 8, 24, 40, 76, 304, 320], "itemsize": sz_phase})
     dop = np.dtype({"names": ["kind", "opmask", "mat", "real", "mode", "nbits", "gpos", "lpos"],
                     "formats": ["<u4", "<u4", "<u4", "<u4", "<u4", "<u4", ("<u4", 4), ("<u4", 4)],
                     "offsets": [0, 4, 8, 12, 16, 20, 24, 40], "itemsize": sz_op})
@@ -184,13 +186,17 @@ def _apply_op(op, a, mats, P, li, gb, tl):
 
 
 def _phase_parts(H, nthr):
+    """Local and global index parts of each thread and register slot, and the
+    global parts of their transposes (the phase's mirror tables)."""
     thr = np.arange(1 << nthr, dtype=np.uint64)
     tl = _bits(thr, H["thr_local"], nthr)
     tg = _bits(thr, H["thr_gpos"], nthr)
+    tm = _bits(thr, H["thr_mpos"], nthr)
     e = np.arange(16, dtype=np.uint64)
     sl = _bits(e, H["reg_local"], 4)
     sg = _bits(e, H["reg_gpos"], 4)
-    return tl, tg, sl, sg
+    sm = _bits(e, H["reg_mpos"], 4)
+    return tl, tg, sl, sg, tm, sm
 
 
 def run(plan, amps: np.ndarray) -> np.ndarray:
@@ -227,8 +233,11 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
             gq = list(P["group_gpos"][:m]) + list(P["group_gpos"][m:2 * m])
             oq = list(P["out_gpos"][:m]) + list(P["out_gpos"][m:2 * m])
             ij = ii | (jj << np.uint64(m))
+            ji = jj | (ii << np.uint64(m))
             gb = _bits(ij, gq, 2 * m)
             gbs = _bits(ij, oq, 2 * m)
+            gbm = _bits(ji, gq, 2 * m)          # the transposed tile's base, loaded layout
+            gbms = _bits(ji, oq, 2 * m)         # and stored layout
             mirror = ii != jj
             assert flags & HERM_PASS
         else:
@@ -245,7 +254,7 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
             dst_i = cur
         pb, pe = int(P["pb"]), int(P["pe"])
         # load
-        tl0, tg0, sl0, sg0 = _phase_parts(plan["phases"][pb], nthr)
+        tl0, tg0, sl0, sg0, tm0, sm0 = _phase_parts(plan["phases"][pb], nthr)
         gidx = gb[:, None, None] | tg0[None, :, None] | sg0[None, None, :]
         valid = (gidx >> np.uint64(n2)) == 0
         gi = np.where(valid, gidx, 0).astype(np.int64)
@@ -260,21 +269,22 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
             for k in range(mp):
                 ip |= ((gidx >> np.uint64(Pp["out_gpos"][k])) & np.uint64(1)).astype(np.int64) << k
                 jp |= ((gidx >> np.uint64(Pp["out_gpos"][mp + k])) & np.uint64(1)).astype(np.int64) << k
-            a = np.where(ip > jp, np.conj(src[_mirror(gidx, n).astype(np.int64)]), a)
+            midx = gbm[:, None, None] | tm0[None, :, None] | sm0[None, None, :]
+            a = np.where(ip > jp, np.conj(src[midx.astype(np.int64)]), a)
         X = np.zeros((T, 1 << L), dtype=np.complex128)
         li = (tl0[:, None] | sl0[None, :]).astype(np.int64)
         X[:, li] = a
         # phases
         for ph in range(pb, pe):
             H = plan["phases"][ph]
-            tl, _, sl, _ = _phase_parts(H, nthr)
+            tl, _, sl, _, _, _ = _phase_parts(H, nthr)
             li = (tl[:, None] | sl[None, :]).astype(np.int64)
             a = X[:, li]
             for oi in range(int(H["ob"]), int(H["oe"])):
                 a = _apply_op(plan["ops"][oi], a, mats, P, li.astype(np.uint64), gb, tl)
             X[:, li] = a
         # store
-        tlL, tgL, slL, sgL = _phase_parts(plan["phases"][pe - 1], nthr)
+        tlL, tgL, slL, sgL, tmL, smL = _phase_parts(plan["phases"][pe - 1], nthr)
         li = (tlL[:, None] | slL[None, :]).astype(np.int64)
         a = X[:, li]
         sidx = gbs[:, None, None] | tgL[None, :, None] | sgL[None, None, :]
@@ -282,8 +292,9 @@ def run(plan, amps: np.ndarray) -> np.ndarray:
         dst = bufs[dst_i]
         dst[sidx[ok].astype(np.int64)] = a[ok]
         if herm and flags & HERM_MIRROR:
-            sel = mirror[:, None, None] & ok
-            dst[_mirror(sidx[sel], n).astype(np.int64)] = np.conj(a[sel])
+            sel = np.broadcast_to(mirror[:, None, None], sidx.shape) & ok
+            midx = gbms[:, None, None] | tmL[None, :, None] | smL[None, None, :]
+            dst[midx[sel].astype(np.int64)] = np.conj(a[sel])
         cur = dst_i
         prev_pass = P
     assert cur == 0, "the plan ends in the second buffer"

@@ -279,52 +279,74 @@ def test_relabelled_plans_match_the_oracle(vqd_host, n, tile_bits, contig):
 
 
 def test_relabelled_grid_circuit_layouts(vqd_host):
-    """The 2x5 grid circuit in relabelled Hermitian mode against the oracle;
-    every pass's group bits are a row/column pair in both layouts, a pass
-    that keeps its layout stores with the same group positions it loads,
-    and the lanes of every loading and storing phase start with the row
-    bits of the lowest physical qubits that are thread bits there."""
+    """The 2x5 grid circuit in relabelled Hermitian mode against the oracle.
+    Between passes the state is interleaved (a qubit's row and column bits
+    are neighbours); the first pass loads and the last stores the vectorised
+    layout (the bits of a qubit n apart).  Every pass's group bits come in
+    such pairs in both layouts, a pass that keeps its layout stores with the
+    group positions it loads, and the lanes of every loading and storing
+    phase start with the run of physical positions 0, 1, 2, ... among its
+    thread bits."""
     n = 10
     ops = c2_grid_circuit(rows=2, cols=5, n_gates=160)
     got, ref, info, plan = run_herm(vqd_host, n, ops, seed=3, tile_bits=12, min_contig_bits=1, relayout=True)
     assert_close(got, ref)
     passes = plan["passes"]
-    assert len(passes) > 2 and any(int(P["swap_out"]) for P in passes)
-    for P in passes:
+    assert len(passes) > 2 and sum(int(P["swap_out"]) for P in passes) % 2 == 0
+    steps = []        # the layout kind at every boundary: n (vectorised) or 1 (interleaved)
+    for k, P in enumerate(passes):
         m = int(P["ngb"]) // 2
         g, o = [int(x) for x in P["group_gpos"][:2 * m]], [int(x) for x in P["out_gpos"][:2 * m]]
-        assert all(g[m + i] == g[i] + n and o[m + i] == o[i] + n for i in range(m))
+        s_in, s_out = {g[m + i] - g[i] for i in range(m)}, {o[m + i] - o[i] for i in range(m)}
+        assert len(s_in) == 1 and len(s_out) == 1 and s_in | s_out <= {1, n}
+        if k:
+            assert s_in == steps[-1]
+        steps.append(s_out)
+        if k == 0:
+            assert s_in == {n}
         if not int(P["swap_out"]):
             assert g == o
+    assert steps[-1] == {n} and {1} in steps
+    for P in passes:
+        nthr = int(P["L"]) - 4
         for ph in (int(P["pb"]), int(P["pe"]) - 1):
-            thr = [int(x) for x in plan["phases"][ph]["thr_gpos"][:int(P["L"]) - 4]]
-            c = 0
-            while c < 4 and c in thr and c + n in thr:
-                c += 1
-            assert thr[:2 * c] == list(range(c)) + [n + q for q in range(c)]
+            thr = [int(x) for x in plan["phases"][ph]["thr_gpos"][:nthr]]
+            r = 0
+            while r in thr:
+                r += 1
+            assert thr[:r] == list(range(r))
 
 
-def test_relabelling_lengthens_contiguous_runs(vqd_host):
-    """On the 14-qubit grid circuit's plan the relabelled layouts give most
-    pass boundaries 2 or more shared low qubits (64-byte runs or longer),
-    where the identity layout gives most only qubit 0."""
+def lane_runs(plan, which):
+    """Per pass: the run of physical positions 0, 1, 2, ... that lead the
+    lanes of its loading (which = 0) or storing (1) phase."""
+    out = []
+    for P in plan["passes"]:
+        ph = int(P["pb"]) if which == 0 else int(P["pe"]) - 1
+        thr = [int(x) for x in plan["phases"][ph]["thr_gpos"][:int(P["L"]) - 4]]
+        r = 0
+        while r < len(thr) and thr[r] == r:
+            r += 1
+        out.append(r)
+    return np.array(out)
+
+
+def test_relabelling_makes_tiles_contiguous(vqd_host):
+    """On the 14-qubit grid circuit's plan, the interleaved layouts put each
+    tile's qubits lowest: almost every pass loads whole waves of 64
+    consecutive amplitudes (6 or more leading lanes), and half or more store
+    runs of 16 or more; the vectorised layout leads with its forced qubits'
+    row bits only (runs of 2 to 8)."""
     n = 14
     ops = c2_grid_circuit(rows=2, cols=7, n_gates=2000)
-
-    def runs(relayout):
+    plans = {}
+    for rel in (False, True):
         prog = vqd_host.Program(n, ops)
-        prog.plan(vqd_host.plan_opts(tile_bits=12, min_contig_bits=1, hermitian=True, relayout=relayout))
-        plan = emu.parse(prog.export())
-        out = []
-        for P in plan["passes"]:
-            for ph in (int(P["pb"]), int(P["pe"]) - 1):
-                thr = [int(x) for x in plan["phases"][ph]["thr_gpos"][:int(P["L"]) - 4]]
-                c = 0
-                while c < 4 and c in thr and c + n in thr:
-                    c += 1
-                out.append(c)
-        return np.array(out), prog.info()
-    base, info0 = runs(False)
-    rel, info1 = runs(True)
-    assert info0["n_passes"] == info1["n_passes"]
-    assert np.mean(rel >= 2) > 0.6 > np.mean(base >= 2)
+        prog.plan(vqd_host.plan_opts(tile_bits=12, min_contig_bits=1, hermitian=True, relayout=rel))
+        plans[rel] = (emu.parse(prog.export()), prog.info())
+    assert plans[True][1]["n_passes"] == plans[False][1]["n_passes"]
+    load_rel, store_rel = lane_runs(plans[True][0], 0), lane_runs(plans[True][0], 1)
+    load_vec, store_vec = lane_runs(plans[False][0], 0), lane_runs(plans[False][0], 1)
+    assert np.mean(load_rel[1:] >= 6) > 0.95
+    assert np.mean(store_rel[:-1] >= 4) > 0.5
+    assert load_vec[1:].max() <= 3 and store_vec.max() <= 3
