@@ -310,6 +310,7 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                     t->pool.push_back(cd(cum, q[i]));
                 }
                 size_t mode = keep[0];
+                std::vector<size_t> at;              // pool offset of each operator
                 for (size_t j = 0; j < keep.size(); ++j) {
                     const size_t i = keep[j];
                     std::vector<cd> U = Ks[i];
@@ -321,7 +322,17 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                         if (real) k.rmask |= 1u << j;
                     }
                     if (q[i] > q[mode]) mode = i;
+                    at.push_back(t->pool.size());
                     k.mask = put_matrix(t->pool, U, o.qs, R, true);
+                }
+                if (d == 2 && k.nk == 2 && k.rmask == 3u) {
+                    k.inl = 1;
+                    k.cf[0] = t->pool[k.mat].real();
+                    k.cf[1] = t->pool[k.mat + 1].real();
+                    for (int j = 0; j < 2; ++j) {
+                        k.cf[2 + 2 * j] = t->pool[at[j]].real();         // column-major (0, 0)
+                        k.cf[3 + 2 * j] = t->pool[at[j] + 3].real();     // (1, 1)
+                    }
                 }
                 ++t->n_mixed;
                 std::vector<cd> Um = Ks[mode];
@@ -331,9 +342,11 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                 k.kind = TOP_KRAUS;
                 k.nk = (uint32_t)Ks.size();
                 k.gdiag = 1;
+                std::vector<size_t> gat, kat;        // pool offsets of the G_i and K_i
                 for (const auto &G : Gs) {
                     bool real = false;
                     if (!diag_of(G, real)) k.gdiag = 0;
+                    gat.push_back(t->pool.size());
                     put_matrix(t->pool, G, o.qs, R, false);
                 }
                 size_t mode = 0;
@@ -344,7 +357,17 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                         if (real) k.rmask |= 1u << i;
                     }
                     if (q[i] > q[mode]) mode = i;
+                    kat.push_back(t->pool.size());
                     k.mask = put_matrix(t->pool, Ks[i], o.qs, R, true);
+                }
+                if (d == 2 && k.nk == 2 && k.gdiag && (k.rmask & 1u)) {
+                    k.inl = 1;
+                    for (int i = 0; i < 2; ++i) {
+                        k.cf[2 * i] = t->pool[gat[i]].real();             // (0, 0)
+                        k.cf[2 * i + 1] = t->pool[gat[i] + 3].real();     // (1, 1)
+                    }
+                    k.cf[4] = t->pool[kat[0]].real();
+                    k.cf[5] = t->pool[kat[0] + 3].real();
                 }
                 ++t->n_general;
                 // drawn operator, its scaling, and this thread's part of rho_T

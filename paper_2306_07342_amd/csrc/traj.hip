@@ -265,6 +265,62 @@ __device__ __forceinline__ void traj_channel(const double2 (&x)[16], double2 (&y
     }
 }
 
+// A one-qubit channel whose draw needs only the coefficients inlined in its
+// descriptor (TOp::inl), for trajectories of whole waves: the same draw and
+// arithmetic as traj_channel, with the register bit a uniform runtime value,
+// so one body serves every bit.  Returns false, having written nothing, when
+// a general channel draws its non-diagonal operator (a jump, rare): the
+// caller then runs traj_channel, which repeats the same draw.
+template <bool WIDE>
+__device__ __forceinline__ bool traj_channel_inline(const double2 (&x)[16], double2 (&y)[16], const TOp &op,
+                                                    double u, uint32_t log_tt, double *red, uint32_t wave,
+                                                    uint32_t wpt, uint32_t &flip)
+{
+    const uint32_t mask = uni(op.mask);
+    const uint32_t bit = (mask & 1u) ? 0u : (mask & 2u) ? 1u : (mask & 4u) ? 2u : 3u;
+    const bool mixed = uni(op.kind) == TOP_MIX;
+    double f0, f1, s = 1.0;
+    if (mixed) {
+        const bool j = op.cf[0] <= u * op.cf[1];
+        f0 = j ? op.cf[4] : op.cf[2];
+        f1 = j ? op.cf[5] : op.cf[3];
+    } else {
+        double r[2];
+        switch (mask) {
+        case 1: rho_diag_partial<1>(x, r); break;
+        case 2: rho_diag_partial<2>(x, r); break;
+        case 4: rho_diag_partial<4>(x, r); break;
+        default: rho_diag_partial<8>(x, r); break;
+        }
+        group_sum<2, WIDE>(r, log_tt, red, wave, wpt, flip);
+        // gram_weight of a diagonal G: G_00 r_0, then + G_11 r_1 (its
+        // off-diagonal terms add exact zeros)
+        const double w0 = fma(op.cf[1], r[1], op.cf[0] * r[0]);
+        const double w1 = fma(op.cf[3], r[1], op.cf[2] * r[0]);
+        const double thr = u * (w0 + w1);
+        // operator 0 unless the running sum passes u W only at operator 1
+        // (or never, and the last positive weight is operator 1's)
+        const bool jump = !(w0 > thr) && ((w0 + w1 > thr) || w1 > 0.0);
+        if (jump) return false;
+        f0 = op.cf[4];
+        f1 = op.cf[5];
+        s = 1.0 / sqrt(w0);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const double f = ((uint32_t)e >> bit & 1u) ? f1 : f0;
+        y[e] = make_double2(f * x[e].x, f * x[e].y);
+    }
+    if (!mixed) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            y[e].x *= s;
+            y[e].y *= s;
+        }
+    }
+    return true;
+}
+
 // Diagonal gates.  On register qubits only: one uniform factor per slot.
 template <bool REAL>
 __device__ __forceinline__ void traj_dreg(const double2 (&x)[16], double2 (&y)[16], const double2 *__restrict__ M)
@@ -336,6 +392,7 @@ __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16]
         case 4: traj_dmix<4>(x, y, op, M, c); break;
         default: traj_dmix<8>(x, y, op, M, c); break;
         }
+    } else if (WIDE && uni(op->inl) && traj_channel_inline<WIDE>(x, y, *op, u, log_tt, red, wave, wpt, flip)) {
     } else {
         switch (mask) {
 #define VQD_TCH(m) \

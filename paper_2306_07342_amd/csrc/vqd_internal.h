@@ -306,6 +306,18 @@ struct alignas(16) TOp {
     uint32_t dq[2];   // TOP_DTHR / TOP_DMIX: thread qubits, dq[0] the low bit of the factor index
     uint32_t rmask;   // TOP_MIX / TOP_KRAUS: bit i set if operator i is diagonal and real
     uint32_t gdiag;   // TOP_KRAUS: every K_i^dagger K_i is diagonal (only rho_T's diagonal is needed)
+    // One-qubit channels with two operators whose draw needs only a few
+    // numbers carry them here (inl = 1), so the kernel reads them with the
+    // descriptor instead of in dependent loads from the pool (which still
+    // holds the full form):
+    //  * TOP_MIX, both operators diagonal and real: cf = {running sum 0,
+    //    running sum 1, operator 0's two diagonal entries, operator 1's};
+    //  * TOP_KRAUS with diagonal Gram matrices and a diagonal real K_0:
+    //    cf = {G_0's two diagonal entries, G_1's, K_0's}.
+    // Diagonal entries in register order (register bit value 0, then 1).
+    uint32_t inl;
+    uint32_t pad_[3];
+    double cf[6];
 };
 
 struct alignas(16) TPhase {

@@ -23,7 +23,7 @@ PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4"
 PHASE_REDUCES = 1
 OP = np.dtype([("kind", "<u4"), ("mask", "<u4"), ("mat", "<u4"), ("real", "<u4"), ("nk", "<u4"),
                ("chan", "<u4"), ("nd", "<u4"), ("dmask", "<u4"), ("dq", "<u4", 2), ("rmask", "<u4"),
-               ("gdiag", "<u4")])
+               ("gdiag", "<u4"), ("inl", "<u4"), ("pad", "<u4", 3), ("cf", "<f8", 6)])
 
 
 def parse(blob: bytes) -> dict:

@@ -110,3 +110,37 @@ def test_errors(vqd_host):
     assert t.info()["n_ops"] == 0
     with pytest.raises(v.VQDError):                # not planned yet
         t.export()
+
+
+def test_inline_channel_coefficients_match_the_pool(vqd_host):
+    """One-qubit two-operator channels carry the numbers of their draw in the
+    descriptor (the kernel's inline path); they must equal the pool's full
+    form: a mixed-unitary channel's running sums and its operators'
+    diagonals, a damping channel's Gram diagonals and K_0's diagonal."""
+    from workloads import traj_grid_circuit
+    t = vqd_host.Trajectories(12, traj_grid_circuit())
+    t.plan()
+    plan = emu.parse(t.export())
+    pool = plan["pool"]
+    seen = {emu.TOP_MIX: 0, emu.TOP_KRAUS: 0}
+    for op in plan["ops"]:
+        if not int(op["inl"]):
+            continue
+        kind, m, cf = int(op["kind"]), int(op["mat"]), op["cf"]
+        assert bin(int(op["mask"])).count("1") == 1 and int(op["nk"]) == 2
+        seen[kind] += 1
+        if kind == emu.TOP_MIX:
+            assert cf[0] == pool[m].real and cf[1] == pool[m + 1].real
+            for j in range(2):
+                U = pool[m + 2 + 4 * j:m + 6 + 4 * j]
+                assert U[1] == 0 and U[2] == 0 and U[0].imag == 0 and U[3].imag == 0
+                assert (cf[2 + 2 * j], cf[3 + 2 * j]) == (U[0].real, U[3].real)
+        else:
+            assert kind == emu.TOP_KRAUS and int(op["gdiag"])
+            for i in range(2):
+                G = pool[m + 4 * i:m + 4 * i + 4]
+                assert (cf[2 * i], cf[2 * i + 1]) == (G[0].real, G[3].real)
+            K0 = pool[m + 8:m + 12]
+            assert K0[1] == 0 and K0[2] == 0 and (cf[4], cf[5]) == (K0[0].real, K0[3].real)
+    # the grid circuit's dephasing and damping channels all take the inline path
+    assert seen[emu.TOP_MIX] >= 2000 and seen[emu.TOP_KRAUS] >= 2000
