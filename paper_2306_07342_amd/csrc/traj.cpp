@@ -325,6 +325,10 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                     at.push_back(t->pool.size());
                     k.mask = put_matrix(t->pool, U, o.qs, R, true);
                 }
+                bool first_identity = true;         // operator 0 stored exactly as the identity
+                for (int y = 0; y < d; ++y)
+                    for (int x = 0; x < d; ++x)
+                        first_identity = first_identity && t->pool[at[0] + size_t(y) * d + x] == cd(x == y ? 1.0 : 0.0);
                 if (d == 2 && k.nk == 2 && k.rmask == 3u) {
                     k.inl = 1;
                     k.cf[0] = t->pool[k.mat].real();
@@ -333,6 +337,12 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                         k.cf[2 + 2 * j] = t->pool[at[j]].real();         // column-major (0, 0)
                         k.cf[3 + 2 * j] = t->pool[at[j] + 3].real();     // (1, 1)
                     }
+                } else if (k.nk >= 2 && first_identity) {
+                    // the common draw, operator 0 = the identity, needs only
+                    // the first running sum and the total
+                    k.inl = 2;
+                    k.cf[0] = t->pool[k.mat].real();
+                    k.cf[1] = t->pool[k.mat + k.nk - 1].real();
                 }
                 ++t->n_mixed;
                 std::vector<cd> Um = Ks[mode];

@@ -392,7 +392,13 @@ __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16]
         case 4: traj_dmix<4>(x, y, op, M, c); break;
         default: traj_dmix<8>(x, y, op, M, c); break;
         }
-    } else if (WIDE && uni(op->inl) && traj_channel_inline<WIDE>(x, y, *op, u, log_tt, red, wave, wpt, flip)) {
+    } else if (WIDE && uni(op->inl) == 2u && op->cf[0] > u * op->cf[1]) {
+        // operator 0, the identity, is drawn (no running sum is <= u W);
+        // the general path would multiply by factors of exactly 1
+#pragma unroll
+        for (int e = 0; e < 16; ++e) y[e] = x[e];
+    } else if (WIDE && uni(op->inl) == 1u &&
+               traj_channel_inline<WIDE>(x, y, *op, u, log_tt, red, wave, wpt, flip)) {
     } else {
         switch (mask) {
 #define VQD_TCH(m) \

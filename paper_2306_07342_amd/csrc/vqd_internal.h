@@ -85,13 +85,14 @@ struct alignas(16) KOp {
     uint32_t pad[2];
 };
 
-// LDS index swizzle of the pass kernels: xor the low 3 bits of a local index
-// with a hash of its higher bits, so that strided register phases spread over
-// the banks.  Xor-linear: the swizzle of (thread bits | slot bits) is the xor
-// of the two parts' swizzles.
+// LDS index swizzle of the pass kernels: xor the low 4 bits of a local index
+// (16 elements of 16 bytes: one pass of 16 lanes of a 128-bit LDS access
+// over the banks) with its bits 4-7 and 8-11, so that strided register phases
+// spread over the banks.  Xor-linear: the swizzle of (thread bits | slot
+// bits) is the xor of the two parts' swizzles.
 __host__ __device__ inline uint32_t lds_swizzle(uint32_t l)
 {
-    return l ^ (((l >> 3) ^ (l >> 6) ^ (l >> 9)) & 7u);
+    return l ^ (((l >> 4) ^ (l >> 8)) & 15u);
 }
 
 // Row bit q <-> column bit q + n: the transpose of an index bit position in
@@ -315,6 +316,9 @@ struct alignas(16) TOp {
     //  * TOP_KRAUS with diagonal Gram matrices and a diagonal real K_0:
     //    cf = {G_0's two diagonal entries, G_1's, K_0's}.
     // Diagonal entries in register order (register bit value 0, then 1).
+    // inl = 2: another mixed-unitary channel whose operator 0 is stored as
+    // exactly the identity: cf = {running sum 0, the total}, enough to see
+    // that operator 0 is drawn (the common case).
     uint32_t inl;
     uint32_t pad_[3];
     double cf[6];

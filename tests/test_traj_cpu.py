@@ -116,17 +116,28 @@ def test_inline_channel_coefficients_match_the_pool(vqd_host):
     """One-qubit two-operator channels carry the numbers of their draw in the
     descriptor (the kernel's inline path); they must equal the pool's full
     form: a mixed-unitary channel's running sums and its operators'
-    diagonals, a damping channel's Gram diagonals and K_0's diagonal."""
+    diagonals, a damping channel's Gram diagonals and K_0's diagonal.  Other
+    mixed-unitary channels whose operator 0 is the identity carry their
+    first running sum and total."""
     from workloads import traj_grid_circuit
     t = vqd_host.Trajectories(12, traj_grid_circuit())
     t.plan()
     plan = emu.parse(t.export())
     pool = plan["pool"]
-    seen = {emu.TOP_MIX: 0, emu.TOP_KRAUS: 0}
+    seen = {emu.TOP_MIX: 0, emu.TOP_KRAUS: 0, "identity_first": 0}
     for op in plan["ops"]:
         if not int(op["inl"]):
             continue
         kind, m, cf = int(op["kind"]), int(op["mat"]), op["cf"]
+        if int(op["inl"]) == 2:
+            # a mixed-unitary channel whose operator 0 is the identity: the
+            # first running sum and the total
+            nk = int(op["nk"])
+            d = 1 << bin(int(op["mask"])).count("1")
+            assert kind == emu.TOP_MIX and cf[0] == pool[m].real and cf[1] == pool[m + nk - 1].real
+            assert np.array_equal(pool[m + nk:m + nk + d * d], np.eye(d).reshape(-1))
+            seen["identity_first"] += 1
+            continue
         assert bin(int(op["mask"])).count("1") == 1 and int(op["nk"]) == 2
         seen[kind] += 1
         if kind == emu.TOP_MIX:
@@ -142,5 +153,6 @@ def test_inline_channel_coefficients_match_the_pool(vqd_host):
                 assert (cf[2 * i], cf[2 * i + 1]) == (G[0].real, G[3].real)
             K0 = pool[m + 8:m + 12]
             assert K0[1] == 0 and K0[2] == 0 and (cf[4], cf[5]) == (K0[0].real, K0[3].real)
-    # the grid circuit's dephasing and damping channels all take the inline path
-    assert seen[emu.TOP_MIX] >= 2000 and seen[emu.TOP_KRAUS] >= 2000
+    # the grid circuit's dephasing and damping channels all take the inline
+    # path, its two-qubit depolarising channels the identity-first one
+    assert seen[emu.TOP_MIX] >= 2000 and seen[emu.TOP_KRAUS] >= 2000 and seen["identity_first"] >= 500
