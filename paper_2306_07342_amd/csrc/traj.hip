@@ -53,21 +53,57 @@ __device__ __forceinline__ uint32_t traj_thread_bits(const TPhase *__restrict__ 
 }
 
 // Sum of v over the threads of one trajectory, bitwise identical in all of
-// them: a butterfly over the lane bits inside the wave (each pairwise sum is
-// formed from the same two operands on both lanes), then, when a trajectory
-// spans several waves, the per-wave sums added in wave order through LDS.
+// them: inside the wave a butterfly (each pairwise sum is formed from the
+// same two operands on both lanes; DPP steps for whole waves, lane shuffles
+// below), then, when a trajectory spans several waves, the per-wave sums
+// added in wave order through LDS.
 // The cross-wave sums alternate between two LDS buffers (`flip`), so one
 // barrier per reduction suffices: a buffer is written again only after every
 // wave has passed the barrier of the reduction in between, which follows its
 // reads of that buffer.
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_value(double x, int lane)
+{
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave, the same bits in every lane: lanes
+// exchange with a partner in DPP steps (quad swaps, then mirror images
+// within 8 and 16 lanes), each pair forming the same sum of the same two
+// values, until each row of 16 holds its total; the four row totals are
+// then added in a fixed order from scalar reads.
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x += dpp_partner<0xB1>(x);      // quad_perm [1, 0, 3, 2]
+    x += dpp_partner<0x4E>(x);      // quad_perm [2, 3, 0, 1]
+    x += dpp_partner<0x141>(x);     // row_half_mirror
+    x += dpp_partner<0x140>(x);     // row_mirror
+    return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
+}
+
 template <int CNT, bool WIDE>
 __device__ __forceinline__ void group_sum(double (&v)[CNT], uint32_t log_tt, double *red, uint32_t wave,
                                           uint32_t wpt, uint32_t &flip)
 {
-    const uint32_t steps = WIDE ? 6u : log_tt;
-    for (uint32_t s = 0; s < steps; ++s) {
+    if (WIDE) {
 #pragma unroll
-        for (int i = 0; i < CNT; ++i) v[i] += __shfl_xor(v[i], 1 << s);
+        for (int i = 0; i < CNT; ++i) v[i] = wave_sum(v[i]);
+    } else {
+        for (uint32_t s = 0; s < log_tt; ++s) {
+#pragma unroll
+            for (int i = 0; i < CNT; ++i) v[i] += __shfl_xor(v[i], 1 << s);
+        }
     }
     if (WIDE && wpt > 1) {
         double *buf = red + flip * (kTrajMaxWaves * kTrajRed);
