@@ -560,6 +560,7 @@ def main():
         "passes_per_step": info["n_passes"],
         "phases_per_step": info["n_phases"],
         "hermitian_mode": bool(info["hermitian"]),
+        "relabelled_layouts": bool(info["relabelled"]),
         "computed_tile_fraction": round(info["tile_fraction"], 6),
         "planned_fp64_fma_per_amp": round(info["fma_per_amp"], 1),
         "executed_fp64_fma_per_amp": round(info["fma_per_amp"] * info["tile_fraction"], 1),

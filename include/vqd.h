@@ -297,6 +297,9 @@ typedef struct vqd_prog_info {
     int hermitian;          /* 1 if planned in Hermitian mode              */
     double tile_fraction;   /* share of the 4^n amplitudes each pass computes (1, or
                                (N+1)/(2N) in Hermitian mode with N = 2^(n - tile qubits)) */
+    int relabelled;         /* 1 if the passes store the state between them under
+                               qubit relabellings (vqd_plan_opts.relayout)          */
+    int layout_changes;     /* passes that store into the second state buffer (even) */
 } vqd_prog_info;
 int vqd_prog_info_get(const vqd_prog *p, vqd_prog_info *out);
 

@@ -556,6 +556,9 @@ int vqd_prog_info_get(const vqd_prog *p, vqd_prog_info *out)
     out->fma_per_amp = p->plan.fma_per_amp;
     out->hermitian = p->plan.hermitian ? 1 : 0;
     out->tile_fraction = p->plan.tile_fraction;
+    out->relabelled = p->plan.relabelled ? 1 : 0;
+    out->layout_changes = 0;
+    for (const KPass &P : p->plan.passes) out->layout_changes += P.swap_out ? 1 : 0;
     return VQD_OK;
 }
 

@@ -55,7 +55,8 @@ class ProgInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("n_ops", ctypes.c_int), ("n_passes", ctypes.c_int),
                 ("n_phases", ctypes.c_int), ("n_kernel_ops", ctypes.c_int),
                 ("fma_per_amp", ctypes.c_double), ("hermitian", ctypes.c_int),
-                ("tile_fraction", ctypes.c_double)]
+                ("tile_fraction", ctypes.c_double), ("relabelled", ctypes.c_int),
+                ("layout_changes", ctypes.c_int)]
 
 
 class TrajInfo(ctypes.Structure):

@@ -276,6 +276,7 @@ def test_relabelled_plans_match_the_oracle(vqd_host, n, tile_bits, contig):
     assert_close(got, ref)
     swaps = [int(P["swap_out"]) for P in plan["passes"]]
     assert sum(swaps) % 2 == 0
+    assert info["relabelled"] == (len(plan["passes"]) > 1) and info["layout_changes"] == sum(swaps)
 
 
 def test_relabelled_grid_circuit_layouts(vqd_host):
