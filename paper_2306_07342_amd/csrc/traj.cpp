@@ -389,6 +389,41 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
     return VQD_OK;
 }
 
+// Runs of one-qubit channels with inline coefficients (TOp::grp).  A
+// mixed-unitary member must leave every population as it is (diagonal
+// entries of magnitude 1, up to the rounding of the stored unitary's
+// normalisation), so that the damping members' weights can all be formed
+// from the run's input state.
+constexpr double kUnitTol = 1e-15;
+
+void mark_groups(std::vector<TOp> &kops, uint32_t begin, uint32_t end)
+{
+    auto member = [&](const TOp &k) {
+        if (k.inl != 1u) return false;
+        if (k.kind == TOP_KRAUS) return true;
+        if (k.kind != TOP_MIX) return false;
+        for (int j = 2; j < 6; ++j)
+            if (std::abs(std::abs(k.cf[j]) - 1.0) > kUnitTol) return false;
+        return true;
+    };
+    uint32_t i = begin;
+    while (i < end) {
+        if (!member(kops[i])) {
+            ++i;
+            continue;
+        }
+        uint32_t j = i, kraus = 0;
+        while (j < end && j - i < kTrajGroupMax && member(kops[j])) {
+            const bool damp = kops[j].kind == TOP_KRAUS;
+            if (damp && kraus == kTrajGroupKraus) break;
+            kraus += damp ? 1u : 0u;
+            ++j;
+        }
+        if (kraus >= 2) kops[i].grp = j - i;
+        i = j;
+    }
+}
+
 int plan(vqd_traj *t)
 {
     t->phases.clear();
@@ -503,6 +538,7 @@ int plan(vqd_traj *t)
         for (int q : rest) ph.thr_q[ti++] = (uint32_t)q;
         if (int rc = encode_phase(t, R.data(), fused)) return rc;
         ph.op_end = (uint32_t)t->kops.size();
+        mark_groups(t->kops, ph.op_begin, ph.op_end);
         for (uint32_t i = ph.op_begin; i < ph.op_end; ++i)
             if (t->kops[i].kind == TOP_KRAUS) ph.flags |= kTPhaseReduces;
         t->phases.push_back(ph);

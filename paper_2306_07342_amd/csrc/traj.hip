@@ -491,6 +491,144 @@ struct UBlock {
     }
 };
 
+// A run of one-qubit channels with inline coefficients (TOp::grp), drawn
+// with one reduction for trajectories of whole waves.  Damping members are
+// diagonal when no jump is drawn and the mixed-unitary members leave the
+// populations alone, so every damping draw's weights follow from the run's
+// input populations p_e: with q_e^(k) = p_e times the no-jump Gram factors
+// G0 of the damping members before member k, and C_k = sum_e q_e^(k)
+// (C_0 = 1), the state before member k is the input scaled by its no-jump
+// factors over sqrt(C_k), so that member's weights are C_(k+1) / C_k for the
+// no-jump operator and D_k / C_k (D_k: the same sum with G1) for the jump.
+// The draws compare C_(k+1) and C_(k+1) + D_k with u times the total (the
+// common factor 1 / C_k dropped); the result is the input times every
+// member's diagonal factors, over sqrt of the last C.  When some member
+// draws its jump nothing is written and false is returned: the caller then
+// takes the members one by one, which repeats the same draws.
+__device__ __forceinline__ uint32_t member_bit(uint32_t mask)
+{
+    return (mask & 1u) ? 0u : (mask & 2u) ? 1u : (mask & 4u) ? 2u : 3u;
+}
+
+template <bool WIDE>
+__device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+                                           uint32_t k, UBlock &ub, uint32_t &next_ch, uint32_t log_tt,
+                                           double *red, uint32_t wave, uint32_t wpt, uint32_t &flip)
+{
+    constexpr int NK = (int)kTrajGroupKraus;
+    double u[kTrajGroupMax];
+#pragma unroll
+    for (uint32_t i = 0; i < kTrajGroupMax; ++i) {
+        u[i] = 0.0;
+        if (i < k) u[i] = ub.take<WIDE>(next_ch++);
+    }
+    double q[16], r[2 * NK];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) q[e] = fma(x[e].x, x[e].x, x[e].y * x[e].y);
+#pragma unroll
+    for (int j = 0; j < 2 * NK; ++j) r[j] = 0.0;
+    uint32_t kk = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kTrajGroupMax; ++i) {
+        if (i < k && uni(op[i].kind) == TOP_KRAUS) {
+            const uint32_t bit = member_bit(uni(op[i].mask));
+            const double g00 = op[i].cf[0], g01 = op[i].cf[1], g10 = op[i].cf[2], g11 = op[i].cf[3];
+            double cs = 0.0, ds = 0.0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const bool one = ((uint32_t)e >> bit) & 1u;
+                ds = fma(q[e], one ? g11 : g10, ds);
+                q[e] *= one ? g01 : g00;
+                cs += q[e];
+            }
+#pragma unroll
+            for (int j = 0; j < NK; ++j) {
+                r[2 * j] += (kk == (uint32_t)j) ? cs : 0.0;
+                r[2 * j + 1] += (kk == (uint32_t)j) ? ds : 0.0;
+            }
+            ++kk;
+        }
+    }
+    group_sum<2 * NK, WIDE>(r, log_tt, red, wave, wpt, flip);
+    bool jump = false;
+    double last = 1.0, f0b[4] = {1.0, 1.0, 1.0, 1.0}, f1b[4] = {1.0, 1.0, 1.0, 1.0};
+    kk = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kTrajGroupMax; ++i) {
+        if (i < k) {
+            const TOp &m = op[i];
+            const uint32_t bit = member_bit(uni(m.mask));
+            double f0, f1;
+            if (uni(m.kind) == TOP_MIX) {
+                const bool j = m.cf[0] <= u[i] * m.cf[1];
+                f0 = j ? m.cf[4] : m.cf[2];
+                f1 = j ? m.cf[5] : m.cf[3];
+            } else {
+                double cw = r[0], dw = r[1];
+#pragma unroll
+                for (int j = 1; j < NK; ++j) {
+                    cw = (kk == (uint32_t)j) ? r[2 * j] : cw;
+                    dw = (kk == (uint32_t)j) ? r[2 * j + 1] : dw;
+                }
+                const double tot = cw + dw, thr = u[i] * tot;
+                jump = jump || (!(cw > thr) && (tot > thr || dw > 0.0));
+                last = cw;
+                ++kk;
+                f0 = m.cf[4];
+                f1 = m.cf[5];
+            }
+#pragma unroll
+            for (uint32_t b = 0; b < 4; ++b) {
+                f0b[b] *= (bit == b) ? f0 : 1.0;
+                f1b[b] *= (bit == b) ? f1 : 1.0;
+            }
+        }
+    }
+    if (jump) return false;
+    const double s = 1.0 / sqrt(last);
+    double lo[4], hi[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        lo[v] = ((v & 1) ? f1b[0] : f0b[0]) * ((v & 2) ? f1b[1] : f0b[1]) * s;
+        hi[v] = ((v & 1) ? f1b[2] : f0b[2]) * ((v & 2) ? f1b[3] : f0b[3]);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const double f = lo[e & 3] * hi[e >> 2];
+        y[e] = make_double2(f * x[e].x, f * x[e].y);
+    }
+    return true;
+}
+
+// One step of a phase's op list, x -> y: a marked run as one draw when the
+// trajectory is whole waves and no member jumps, else the op at oi alone.
+// Returns the index of the next op.
+template <bool WIDE>
+__device__ __forceinline__ uint32_t traj_step(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ ops,
+                                              uint32_t oi, const double2 *__restrict__ pool, const TCtx &c,
+                                              UBlock &ub, uint32_t &next_ch, uint32_t log_tt, double *red,
+                                              uint32_t wave, uint32_t wpt, uint32_t &flip)
+{
+    const TOp *op = ops + oi;
+    if (WIDE) {
+        const uint32_t k = uni(op->grp);
+        if (k > 1u) {
+            const uint32_t base = ub.base, ch = next_ch;
+            const double cur = ub.cur, nxt = ub.nxt;
+            if (traj_group<WIDE>(x, y, op, k, ub, next_ch, log_tt, red, wave, wpt, flip)) return oi + k;
+            // the members one by one, from the same uniforms
+            ub.base = base;
+            ub.cur = cur;
+            ub.nxt = nxt;
+            next_ch = ch;
+        }
+    }
+    double u = 0.0;
+    if (is_channel(uni(op->kind))) u = ub.take<WIDE>(next_ch++);
+    traj_op<WIDE>(x, y, op, pool, c, u, log_tt, red, wave, wpt, flip);
+    return oi + 1;
+}
+
 // Orders one wave's LDS accesses for the compiler; the hardware executes a
 // wave's LDS instructions in issue order.
 __device__ __forceinline__ void wave_lds_sync()
@@ -554,15 +692,12 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
                 if (!shared_tile) wave_lds_sync();
                 else if (!(uni(H->flags) & kTPhaseReduces)) __syncthreads();
             }
-            const uint32_t ob = uni(H->op_begin), oe = uni(H->op_end);
-            for (uint32_t oi = ob; oi < oe; oi += 2) {
-                double u = 0.0;
-                if (is_channel(uni(ops[oi].kind))) u = ub.take<WIDE>(next_ch++);
-                traj_op<WIDE>(a, b, ops + oi, pool, c, u, log_tt, red, wave, wpt, flip);
-                if (oi + 1 < oe) {
-                    u = 0.0;
-                    if (is_channel(uni(ops[oi + 1].kind))) u = ub.take<WIDE>(next_ch++);
-                    traj_op<WIDE>(b, a, ops + oi + 1, pool, c, u, log_tt, red, wave, wpt, flip);
+            const uint32_t oe = uni(H->op_end);
+            uint32_t oi = uni(H->op_begin);
+            while (oi < oe) {
+                oi = traj_step<WIDE>(a, b, ops, oi, pool, c, ub, next_ch, log_tt, red, wave, wpt, flip);
+                if (oi < oe) {
+                    oi = traj_step<WIDE>(b, a, ops, oi, pool, c, ub, next_ch, log_tt, red, wave, wpt, flip);
                 } else {
 #pragma unroll
                     for (int e = 0; e < 16; ++e) a[e] = b[e];

@@ -320,9 +320,17 @@ struct alignas(16) TOp {
     // exactly the identity: cf = {running sum 0, the total}, enough to see
     // that operator 0 is drawn (the common case).
     uint32_t inl;
-    uint32_t pad_[3];
+    // On the first op of a run of inl = 1 channels in one phase (at most
+    // kTrajGroupMax ops, at most kTrajGroupKraus of them damping, at least
+    // two; the mixed-unitary ones with diagonal entries of magnitude 1 within
+    // 1e-15): the run's length.  Trajectories of whole waves draw the run with
+    // one reduction; 0 elsewhere.
+    uint32_t grp;
+    uint32_t pad_[2];
     double cf[6];
 };
+constexpr uint32_t kTrajGroupMax = 8;
+constexpr uint32_t kTrajGroupKraus = 4;
 
 struct alignas(16) TPhase {
     uint32_t op_begin, op_end;

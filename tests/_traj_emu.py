@@ -23,7 +23,7 @@ PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4"
 PHASE_REDUCES = 1
 OP = np.dtype([("kind", "<u4"), ("mask", "<u4"), ("mat", "<u4"), ("real", "<u4"), ("nk", "<u4"),
                ("chan", "<u4"), ("nd", "<u4"), ("dmask", "<u4"), ("dq", "<u4", 2), ("rmask", "<u4"),
-               ("gdiag", "<u4"), ("inl", "<u4"), ("pad", "<u4", 3), ("cf", "<f8", 6)])
+               ("gdiag", "<u4"), ("inl", "<u4"), ("grp", "<u4"), ("pad", "<u4", 2), ("cf", "<f8", 6)])
 
 
 def parse(blob: bytes) -> dict:
@@ -84,14 +84,55 @@ def _draw(w, u):
     return max(i for i, x in enumerate(w) if x > 0)
 
 
-def run(plan: dict, U: np.ndarray):
+def _group(psi, members, reg, urow):
+    """A marked run of inline one-qubit channels drawn the way trajectories
+    of whole waves draw it: every damping member's weights from the run's
+    input populations (times the no-jump Gram factors of the damping members
+    before it), one product of diagonal factors, one normalisation.  None if
+    some damping member draws its jump (the kernel then takes the members
+    one by one)."""
+    x = np.arange(psi.size)
+    bits = [(x >> int(reg[int(m["mask"]).bit_length() - 1])) & 1 for m in members]
+    q = np.abs(psi) ** 2
+    C, D = [], []
+    for m, b in zip(members, bits):
+        if int(m["kind"]) == TOP_KRAUS:
+            cf = m["cf"]
+            D.append(float(np.sum(q * np.where(b == 1, cf[3], cf[2]))))
+            q = q * np.where(b == 1, cf[1], cf[0])
+            C.append(float(np.sum(q)))
+    f = np.ones(psi.size)
+    last, kk = 1.0, 0
+    for m, b in zip(members, bits):
+        cf, u = m["cf"], float(urow[int(m["chan"])])
+        if int(m["kind"]) == TOP_MIX:
+            j = cf[0] <= u * cf[1]
+            f0, f1 = (cf[4], cf[5]) if j else (cf[2], cf[3])
+        else:
+            c, d = C[kk], D[kk]
+            tot = c + d
+            thr = u * tot
+            if not (c > thr) and (tot > thr or d > 0.0):
+                return None
+            last, kk = c, kk + 1
+            f0, f1 = cf[4], cf[5]
+        f = f * np.where(b == 1, f1, f0)
+    return psi * f / math.sqrt(last)
+
+
+def run(plan: dict, U: np.ndarray, groups: bool = False, stats: dict = None):
     """Per-trajectory <Z_q> (T x n), squared norms (T) and the channel order
-    met (one list of channel indices)."""
+    met (one list of channel indices).  groups: draw the marked runs of
+    inline channels as trajectories of whole waves do (counted in stats:
+    'grouped' runs, 'fallback' runs with a jump)."""
     n, ne, pool = plan["n"], plan["n_eff"], plan["pool"]
     T = U.shape[0]
     Z = np.empty((T, n))
     N = np.empty(T)
     order = []
+    if stats is not None:
+        stats.setdefault("grouped", 0)
+        stats.setdefault("fallback", 0)
     for t in range(T):
         psi = np.zeros(1 << ne, dtype=complex)
         psi[0] = 1
@@ -99,7 +140,24 @@ def run(plan: dict, U: np.ndarray):
             # the flag that lets the kernel drop an exchange barrier
             kinds = [int(o["kind"]) for o in plan["ops"][int(ph["ob"]):int(ph["oe"])]]
             assert bool(int(ph["flags"]) & PHASE_REDUCES) == (TOP_KRAUS in kinds)
-            for op in plan["ops"][int(ph["ob"]):int(ph["oe"])]:
+            skip = 0
+            for idx in range(int(ph["ob"]), int(ph["oe"])):
+                if skip:
+                    skip -= 1
+                    continue
+                op = plan["ops"][idx]
+                k = int(op["grp"])
+                if groups and k > 1:
+                    members = plan["ops"][idx:idx + k]
+                    out = _group(psi, members, ph["reg"], U[t])
+                    if stats is not None:
+                        stats["grouped" if out is not None else "fallback"] += 1
+                    if out is not None:
+                        psi = out
+                        skip = k - 1
+                        if t == 0:
+                            order.extend(int(m["chan"]) for m in members)
+                        continue
                 kind = int(op["kind"])
                 if kind == TOP_DTHR:
                     qs = [int(q) for q in op["dq"][:int(op["nd"])]]

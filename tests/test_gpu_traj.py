@@ -12,7 +12,7 @@ import pytest
 
 from oracle import trajectories as tj
 from oracle.emulator import emulate
-from workloads import c1_line_circuit, random_tp_ops, traj_grid_circuit, uniforms
+from workloads import c1_line_circuit, damped_layer_circuit, random_tp_ops, traj_grid_circuit, uniforms
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -49,6 +49,28 @@ def test_trajectories_match_oracle(gpu_lib, n, T):
     ops = mixed_ops(n, seed=500 + n, count=24 if n < 12 else 10)
     prog = gpu_lib.Trajectories(n, ops).compile()
     U = uniforms(T, tj.n_channels(ops), seed=600 + n)
+    out = prog.run(cuda(U), state=True)
+    Z = out["z"].cpu().numpy()
+    N = out["norm"].cpu().numpy()
+    S = out["state"].cpu().numpy()
+    for t in range(T):
+        psi, _ = tj.run(n, ops, U[t])
+        assert np.abs(Z[t] - tj.expec_z(psi)).max() <= TOL, (t, Z[t], tj.expec_z(psi))
+        assert abs(N[t] - tj.norm2(psi)) <= TOL
+        assert np.abs(S[t] - psi).max() <= TOL
+
+
+@pytest.mark.parametrize("n,T", [(6, 40), (10, 24), (11, 12), (12, 8), (13, 4)])
+def test_damping_runs_match_oracle(gpu_lib, n, T):
+    """Runs of damping and dephasing draws taken with one reduction
+    (trajectories of whole waves: 10 qubits and up, one to eight waves), with
+    damping strong enough that many runs draw a jump and go member by member;
+    below a wave (6 qubits) the runs are taken member by member.  Every
+    trajectory against the oracle."""
+    say("traj damping runs n=%d T=%d" % (n, T))
+    ops = damped_layer_circuit(n, 3, seed=80 + n)
+    prog = gpu_lib.Trajectories(n, ops).compile()
+    U = uniforms(T, tj.n_channels(ops), seed=90 + n)
     out = prog.run(cuda(U), state=True)
     Z = out["z"].cpu().numpy()
     N = out["norm"].cpu().numpy()

@@ -6,8 +6,8 @@ import pytest
 
 from oracle import trajectories as tj
 from tests import _traj_emu as emu
-from workloads import (c1_line_circuit, c2_grid_circuit, c3_all_to_all_circuit, random_tp_ops,
-                       uniforms)
+from workloads import (c1_line_circuit, c2_grid_circuit, c3_all_to_all_circuit, damped_layer_circuit,
+                       random_tp_ops, uniforms)
 
 
 def check_plan(vqd, n, ops, T=8, seed=0, tol=1e-12):
@@ -156,3 +156,58 @@ def test_inline_channel_coefficients_match_the_pool(vqd_host):
     # the grid circuit's dephasing and damping channels all take the inline
     # path, its two-qubit depolarising channels the identity-first one
     assert seen[emu.TOP_MIX] >= 2000 and seen[emu.TOP_KRAUS] >= 2000 and seen["identity_first"] >= 500
+
+
+def test_inline_runs_are_marked(vqd_host):
+    """Runs of one-qubit channels with inline coefficients carry their length
+    on their first op: members inline, in one phase, at most 8 ops and 4
+    damping channels, at least 2 of them, and mixed-unitary members with
+    diagonal entries of magnitude 1 up to rounding (they must not move
+    populations).  In
+    the 12-qubit grid circuit every damping channel is in such a run."""
+    from workloads import traj_grid_circuit
+    for n, ops in ((12, traj_grid_circuit()), (11, damped_layer_circuit(11, 3, seed=5)), (6, damped_layer_circuit(6, 2, seed=6))):
+        t = vqd_host.Trajectories(n, ops)
+        t.plan()
+        plan = emu.parse(t.export())
+        O = plan["ops"]
+        covered = np.zeros(len(O), dtype=bool)
+        for ph in plan["phases"]:
+            ob, oe = int(ph["ob"]), int(ph["oe"])
+            for i in range(ob, oe):
+                k = int(O[i]["grp"])
+                if not k:
+                    continue
+                assert 2 <= k <= 8 and i + k <= oe and not covered[i]
+                kinds = [int(m["kind"]) for m in O[i:i + k]]
+                assert all(int(m["inl"]) == 1 for m in O[i:i + k])
+                assert 2 <= kinds.count(emu.TOP_KRAUS) <= 4
+                for m in O[i:i + k]:
+                    if int(m["kind"]) == emu.TOP_MIX:
+                        assert np.all(np.abs(np.abs(m["cf"][2:6]) - 1.0) <= 1e-15)
+                assert all(int(m["grp"]) == 0 for m in O[i + 1:i + k])
+                covered[i:i + k] = True
+        damp = np.array([int(o["kind"]) == emu.TOP_KRAUS and int(o["inl"]) == 1 for o in O])
+        assert damp.any()
+        if n == 12:
+            assert covered[damp].all()
+
+
+@pytest.mark.parametrize("n,T", [(10, 6), (12, 4)])
+def test_grouped_draws_match_oracle(vqd_host, n, T):
+    """The grouped draw rule (every damping weight of a run from the run's
+    input populations, one normalisation at the end) gives the oracle's
+    trajectories on the same uniforms, through both of its paths: runs with
+    no jump, and runs where a jump sends the members one by one."""
+    ops = damped_layer_circuit(n, 3, seed=40 + n)
+    t = vqd_host.Trajectories(n, ops)
+    t.plan()
+    plan = emu.parse(t.export())
+    U = uniforms(T, tj.n_channels(ops), seed=70 + n)
+    st = {}
+    Z, N, order = emu.run(plan, U, groups=True, stats=st)
+    assert order == list(range(tj.n_channels(ops)))
+    Zr, Nr = tj.run_many(n, ops, U)
+    assert np.abs(Z - Zr).max() <= 1e-12
+    assert np.abs(N - Nr).max() <= 1e-12
+    assert st["grouped"] > 0 and st["fallback"] > 0, st

@@ -22,4 +22,4 @@ from .circuits import (  # noqa: F401
     count_gates,
     GATE_KINDS,
 )
-from .trajectories import TRAJ_SEED, random_tp_ops, traj_grid_circuit, uniforms  # noqa: F401,E402
+from .trajectories import TRAJ_SEED, damped_layer_circuit, random_tp_ops, traj_grid_circuit, uniforms  # noqa: F401,E402

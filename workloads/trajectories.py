@@ -52,3 +52,20 @@ def traj_grid_circuit(n_gates: int = 2000) -> List[Op]:
     """The layered grid circuit (SU(2) layers, CZ + depol2, ZZ crosstalk,
     T1/T2 damping every layer) on a 2x6 grid: 12 qubits."""
     return c2_grid_circuit(rows=2, cols=6, n_gates=n_gates)
+
+
+def damped_layer_circuit(n: int, layers: int, seed: int, dt_t1: float = 0.25, dt_t2: float = 0.3) -> List[Op]:
+    """Layers of seeded SU(2) gates, a CZ chain, then T1 and T2 noise on every
+    qubit with dt/T1 and dt/T2 large enough that damping jumps are common
+    (a stress case for the runs of damping draws)."""
+    rng = np.random.default_rng(seed)
+    ops: List[Op] = []
+    for _ in range(layers):
+        for q in range(n):
+            ops.append(("su2", (q,), tuple(rng.standard_normal(4))))
+        for q in range(0, n - 1, 2):
+            ops.append(("cz", (q, q + 1), ()))
+        for q in range(n):
+            ops.append(("amp_t1", (q,), (dt_t1, 1.0)))
+            ops.append(("deph_t2", (q,), (dt_t2, 1.0)))
+    return ops
