@@ -412,7 +412,7 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
         y = emu.run(P).float().contiguous()
         torch.cuda.synchronize()
         t_data = time.perf_counter() - t0
-        gpu_data = emu.last_gpu_s
+        gpu_data, idle_data = emu.last_gpu_s, emu.last_idle_s
         log("surrogate: %d training samples in %.1f s" % (n_tr, t_data))
         model = SurrogateModel(init_ensemble(), max_batch=1024)
         t0 = time.perf_counter()
@@ -436,6 +436,7 @@ def surrogate_leg(vqd, torch, n_train: int, n_test: int, epochs: int):
         res.update({"train_samples": n_tr, "data_gen_s": round(t_data, 2),
                     "data_gen_evals_per_s": round(n_tr / t_data, 1),
                     "data_gen_batched_kernel_only_evals_per_s": round(n_tr / gpu_data, 1),
+                    "data_gen_device_idle_between_chunks_s": round(idle_data, 3),
                     "epochs": ep, "batch": 512,
                     "train_s": round(t_train, 2), "final_train_mse": [float(v) for v in model.history[-1]]})
         return res

@@ -39,12 +39,14 @@ class TemplateEmulator:
         self._arena = None
         self._out = None
         self.last_gpu_s = 0.0         # time of the batched launches alone in the last run()
+        self.last_idle_s = 0.0        # device time between consecutive chunks' launches in the last run()
 
     def run(self, params: np.ndarray):
-        """The host work of a chunk (coefficients of every instance) runs while
-        the previous chunk's launch is still on the GPU."""
+        """The host work of a chunk (coefficients of every instance, and a
+        contiguous copy of its parameters when ``params`` is a strided view)
+        runs while the previous chunk's launch is still on the GPU."""
         import torch
-        P = np.ascontiguousarray(params, dtype=np.float64)
+        P = np.asarray(params, dtype=np.float64)
         count = P.shape[0]
         res = torch.empty((count, self.n), dtype=torch.float64, device=self.device)
         prev = None
@@ -85,6 +87,7 @@ class TemplateEmulator:
             prev.close()
         torch.cuda.synchronize()
         self.last_gpu_s = sum(a.elapsed_time(z) for a, z in events) / 1e3
+        self.last_idle_s = sum(events[k - 1][1].elapsed_time(events[k][0]) for k in range(1, len(events))) / 1e3
         return res
 
     def reserve(self, params: np.ndarray):

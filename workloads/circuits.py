@@ -278,7 +278,7 @@ def c5_params(structure, dev: np.ndarray, angles: np.ndarray) -> np.ndarray:
         idx[i, :len(slots)] = slots
     out = v[:, np.maximum(idx, 0)]
     out[:, idx < 0] = 0.0
-    return out
+    return np.ascontiguousarray(out)
 
 
 def c5_draw_samples(count: int, seed: int = SEED_BASE + 4, n_angles: int = 4 * C5_LAYERS):
