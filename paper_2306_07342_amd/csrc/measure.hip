@@ -7,8 +7,9 @@
 //                   written without being read.
 // * k_diag_probs -- the diagonal probabilities max(0, Re rho[x][x]) into a
 //                   contiguous array.
-// * k_cdf        -- their running sums, left to right in one wave (the
-//                   order the draw rule fixes; 2^n <= 65536 terms).
+// * k_cdf        -- their running sums in one workgroup: per-thread runs
+//                   of consecutive terms, chained by thread totals
+//                   (2^n <= 65536 terms).
 // * k_sample     -- one basis state per uniform: binary search of the
 //                   running sums for the first one above u W.
 #include <hip/hip_runtime.h>
@@ -56,50 +57,57 @@ k_diag_probs(const double2 *__restrict__ amps, uint32_t n, double *__restrict__ 
         p[x] = fmax(0.0, amps[x + (x << n)].x);
 }
 
-// cum[x] = p[0] + ... + p[x] formed left to right; cum[D] holds the last x
-// with p[x] > 0 (or 0), as a double.  One wave: each block of 64 terms
-// arrives in one coalesced load (the next block is loaded while this one is
-// summed), the sum runs through the block term by term in every lane alike,
-// and lane j keeps the running sum at term j for one coalesced store.
-__device__ __forceinline__ double lane_value(double v, uint32_t j)
-{
-    const uint64_t b = __double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, (int)j);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), (int)j);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
+// cum[x] = p[0] + ... + p[x]; cum[D] holds the last x with p[x] > 0 (or 0),
+// as a double.  One workgroup: thread t owns the C = D / 256 consecutive
+// terms from t C (all D when D < 256, in thread 0) and forms their running
+// sums l_j left to right; thread 0 chains the thread totals,
+// P_(t+1) = P_t + l_last(t); then cum[t C + j] = P_t + l_j.  Each sum is
+// rounded once onto P_t and P_(t+1) is the same rounding of thread t's last
+// sum, so the sums never decrease across thread boundaries either (the
+// binary search of k_sample relies on it).  They differ from a single
+// left-to-right chain only in rounding.
+constexpr int kCdfThreads = 256;
 
-__global__ void __launch_bounds__(64) k_cdf(const double *__restrict__ p, uint32_t n, double *__restrict__ cum)
+__global__ void __launch_bounds__(kCdfThreads) k_cdf(const double *__restrict__ p, uint32_t n, double *__restrict__ cum)
 {
-    const uint32_t lane = threadIdx.x, D = 1u << n;
-    double s = 0.0;
-    uint32_t last = 0;
-    double nxt = (lane < D) ? p[lane] : 0.0;
-    for (uint32_t base = 0; base < D; base += 64) {
-        const double v = nxt;
-        nxt = (base + 64 + lane < D) ? p[base + 64 + lane] : 0.0;
-        const uint32_t cnt = (D - base < 64u) ? D - base : 64u;
-        double mine = 0.0;
-        if (cnt == 64u) {
-            // unrolled: the lane reads do not depend on the sum and issue ahead
-#pragma unroll
-            for (uint32_t j = 0; j < 64u; ++j) {
-                const double x = lane_value(v, j);
-                s += x;
-                mine = (lane == j) ? s : mine;
-                last = (x > 0.0) ? base + j : last;
-            }
-        } else {
-            for (uint32_t j = 0; j < cnt; ++j) {
-                const double x = lane_value(v, j);
-                s += x;
-                mine = (lane == j) ? s : mine;
-                last = (x > 0.0) ? base + j : last;
-            }
+    __shared__ double pre[kCdfThreads + 1];
+    __shared__ int lastpos[kCdfThreads];
+    const uint32_t t = threadIdx.x, D = 1u << n;
+    const uint32_t C = (D >= (uint32_t)kCdfThreads) ? D / kCdfThreads : D;
+    const uint32_t T = D / C;                   // threads with terms
+    const uint32_t x0 = t * C;
+    double l = 0.0;
+    int lp = -1;
+    if (t < T) {
+        for (uint32_t j = 0; j < C; ++j) {
+            const double v = p[x0 + j];
+            l += v;
+            lp = (v > 0.0) ? (int)(x0 + j) : lp;
         }
-        if (lane < cnt) cum[base + lane] = mine;
     }
-    if (lane == 0) cum[D] = (double)last;
+    pre[t + 1] = l;
+    lastpos[t] = lp;
+    __syncthreads();
+    if (t == 0) {
+        double P = 0.0;
+        int last = 0;
+        for (uint32_t k = 0; k < T; ++k) {
+            const double tot = pre[k + 1];
+            pre[k] = P;                             // thread k's offset
+            P += tot;
+            last = (lastpos[k] >= 0) ? lastpos[k] : last;
+        }
+        cum[D] = (double)last;
+    }
+    __syncthreads();
+    if (t < T) {
+        const double P = pre[t];
+        l = 0.0;
+        for (uint32_t j = 0; j < C; ++j) {
+            l += p[x0 + j];
+            cum[x0 + j] = P + l;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kMeasThreads)
@@ -148,7 +156,7 @@ int launch_sample(const double2 *amps, int n, double *scratch, const double *U, 
     double *p = scratch, *cum = scratch + D;
     hipLaunchKernelGGL(k_diag_probs, dim3(grid_for(D)), dim3(kMeasThreads), 0, st, amps, (uint32_t)n, p);
     VQD_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_cdf, dim3(1), dim3(64), 0, st, p, (uint32_t)n, cum);
+    hipLaunchKernelGGL(k_cdf, dim3(1), dim3(kCdfThreads), 0, st, p, (uint32_t)n, cum);
     VQD_HIP(hipGetLastError());
     if (shots == 0) return VQD_OK;
     hipLaunchKernelGGL(k_sample, dim3(grid_for(shots)), dim3(kMeasThreads), 0, st, cum, (uint32_t)n, U, shots, out);
