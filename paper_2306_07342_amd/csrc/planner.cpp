@@ -633,6 +633,105 @@ void relabel_passes(int n, HostPlan &plan)
     plan.relabelled = true;
 }
 
+// Tile-local bit positions are labels of the LDS layout alone, so a pass
+// may permute them (every phase's register and thread positions and the
+// local positions of its runtime-diagonal ops together).  The permutation
+// puts lanes 0-3 of the phase that loads HBM on tile bits of residues
+// 0, 1, 2, 3 (mod 4), and the lanes of the phase that stores HBM on
+// distinct residues too, where possible: their lane order is fixed by the
+// global accesses, and under the LDS swizzle tile bit p lands in bank-group
+// bit p mod 4.
+void relabel_tile_bits(HostPlan &plan)
+{
+    for (const KPass &P : plan.passes) {
+        if (P.phase_end - P.phase_begin < 2) continue;
+        const uint32_t L = P.L, nthr = L - 4, nl = nthr < 4 ? nthr : 4;
+        const KPhase &F = plan.phases[P.phase_begin], &S = plan.phases[P.phase_end - 1];
+        std::vector<int> colour(L, -1);
+        for (uint32_t j = 0; j < nl; ++j) colour[F.thr_local[j]] = (int)j;
+        std::vector<bool> used_b(4, false);
+        for (uint32_t j = 0; j < nl; ++j)
+            if (colour[S.thr_local[j]] >= 0) used_b[colour[S.thr_local[j]]] = true;
+        for (uint32_t j = 0; j < nl; ++j) {
+            const uint32_t p = S.thr_local[j];
+            if (colour[p] >= 0) continue;
+            for (int c = 0; c < 4; ++c)
+                if (!used_b[c]) {
+                    colour[p] = c;
+                    used_b[c] = true;
+                    break;
+                }
+        }
+        // pi: coloured positions first (lane order of the load phase, then
+        // of the store phase), each to the lowest free target of its residue
+        std::vector<int> pi(L, -1);
+        std::vector<bool> taken(L, false);
+        auto place = [&](uint32_t p) {
+            if (pi[p] >= 0 || colour[p] < 0) return;
+            for (uint32_t t = (uint32_t)colour[p]; t < L; t += 4)
+                if (!taken[t]) {
+                    pi[p] = (int)t;
+                    taken[t] = true;
+                    return;
+                }
+        };
+        for (uint32_t j = 0; j < nl; ++j) place(F.thr_local[j]);
+        for (uint32_t j = 0; j < nl; ++j) place(S.thr_local[j]);
+        uint32_t next = 0;
+        for (uint32_t p = 0; p < L; ++p) {
+            if (pi[p] >= 0) continue;
+            while (taken[next]) ++next;
+            pi[p] = (int)next;
+            taken[next] = true;
+        }
+        for (uint32_t ph = P.phase_begin; ph < P.phase_end; ++ph) {
+            KPhase &H = plan.phases[ph];
+            for (int b = 0; b < kRegBits; ++b) H.reg_local[b] = (uint32_t)pi[H.reg_local[b]];
+            for (uint32_t t = 0; t < nthr; ++t) H.thr_local[t] = (uint32_t)pi[H.thr_local[t]];
+            for (uint32_t oi = H.op_begin; oi < H.op_end; ++oi) {
+                KOp &o = plan.ops[oi];
+                if (o.kind != KOP_DIAG_RT) continue;
+                for (uint32_t j = 0; j < o.nbits; ++j)
+                    if (o.lpos[j] != kNotLocal) o.lpos[j] = (uint32_t)pi[o.lpos[j]];
+            }
+        }
+    }
+}
+
+// Lane order of the phases that neither load nor store HBM (their thread
+// bits may be permuted freely: an exchange addresses LDS by tile-local index
+// alone).  The LDS index swizzle xors the three nibbles of the tile-local
+// index into the low one, so tile bit p lands in bank-group bit p mod 4
+// (16-byte groups).  Lanes 0-2 take thread bits of residues 0, 1, 2 and lane
+// 3 one of residue 3, where the phase has them: then the 16 lanes of a
+// 128-bit LDS access (or any 8 of them) hit distinct bank groups.
+void spread_lane_banks(HostPlan &plan)
+{
+    for (const KPass &P : plan.passes) {
+        const uint32_t nthr = P.L - 4;
+        for (uint32_t ph = P.phase_begin + 1; ph + 1 < P.phase_end; ++ph) {
+            KPhase &H = plan.phases[ph];
+            std::vector<uint32_t> order;
+            std::vector<bool> used(nthr, false);
+            for (uint32_t r = 0; r < 4 && r < nthr; ++r)
+                for (uint32_t t = 0; t < nthr; ++t)
+                    if (!used[t] && H.thr_local[t] % 4 == r) {
+                        order.push_back(t);
+                        used[t] = true;
+                        break;
+                    }
+            for (uint32_t t = 0; t < nthr; ++t)
+                if (!used[t]) order.push_back(t);
+            const KPhase old = H;
+            for (uint32_t t = 0; t < nthr; ++t) {
+                H.thr_local[t] = old.thr_local[order[t]];
+                H.thr_gpos[t] = old.thr_gpos[order[t]];
+                H.thr_mpos[t] = old.thr_mpos[order[t]];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out)
@@ -1240,6 +1339,8 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         }
         if (opt.relayout) relabel_passes(n, out);
     }
+    relabel_tile_bits(out);
+    spread_lane_banks(out);
     finish_slot_tables(n, out);
     return VQD_OK;
 }
