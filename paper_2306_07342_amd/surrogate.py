@@ -201,14 +201,17 @@ class SurrogateModel:
         threshold defaults to the one set by calibrate(); without one every
         sample falls back, so no answer is accepted that the emulator has not
         vouched for.  Returns (values [B, 10] float32 device tensor,
-        fell_back bool device tensor)."""
+        fell_back bool device tensor).  A threshold that accepts nothing
+        (none, or at most 0: spreads are never negative) leaves the network
+        unconsulted: every sample goes to the fallback at once."""
         import torch
-        mean, spread = self.net.predict(x)
         thr = self.threshold if threshold is None else threshold
-        if thr is None:
-            fell = torch.ones_like(spread, dtype=torch.bool)
-        else:
-            fell = spread >= thr
+        if thr is None or thr <= 0.0:
+            B = x.shape[0]
+            vals = fallback(np.arange(B)).to(torch.float32)
+            return vals, torch.ones(B, dtype=torch.bool, device=vals.device)
+        mean, spread = self.net.predict(x)
+        fell = spread >= thr
         idx = torch.nonzero(fell).flatten()
         if idx.numel():
             mean[idx] = fallback(idx.cpu().numpy()).to(mean.dtype)
@@ -237,7 +240,7 @@ def measure_gain(model: SurrogateModel, emulator: TemplateEmulator, params: np.n
     thr = model.threshold if threshold is None else threshold
     exact, t_emu = timed(lambda: emulator.run(params))
     (vals, fell), t_sur = timed(lambda: model.predict_with_fallback(
-        x, lambda idx: emulator.run(params[idx]), thr))
+        x, lambda idx: emulator.run(params if len(idx) == B else params[idx]), thr))
     err = (vals.double() - exact).abs().max(dim=1).values
     fell_np = fell.cpu().numpy()
     err_np = err.cpu().numpy()
