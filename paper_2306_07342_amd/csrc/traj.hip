@@ -510,6 +510,31 @@ __device__ __forceinline__ uint32_t member_bit(uint32_t mask)
     return (mask & 1u) ? 0u : (mask & 2u) ? 1u : (mask & 4u) ? 2u : 3u;
 }
 
+// One damping member of a run, register bit MASK: this thread's parts of
+// C_(k+1) = sum_e q_e G0(e) and D_k = sum_e q_e G1(e), from the populations
+// with the bit clear (s0) and set (s1), each summed as a tree; then q_e *=
+// G0(e).
+template <int MASK>
+__device__ __forceinline__ void damp_member(double (&q)[16], double g00, double g01, double g10, double g11,
+                                            double &cs, double &ds)
+{
+    double h[2][8];
+    int n0 = 0, n1 = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        if (e & MASK) h[1][n1++] = q[e];
+        else h[0][n0++] = q[e];
+    }
+    double s[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+        s[b] = ((h[b][0] + h[b][1]) + (h[b][2] + h[b][3])) + ((h[b][4] + h[b][5]) + (h[b][6] + h[b][7]));
+    cs = fma(g01, s[1], g00 * s[0]);
+    ds = fma(g11, s[1], g10 * s[0]);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) q[e] *= (e & MASK) ? g01 : g00;
+}
+
 template <bool WIDE>
 __device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
                                            uint32_t k, UBlock &ub, uint32_t &next_ch, uint32_t log_tt,
@@ -531,15 +556,13 @@ __device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[
 #pragma unroll
     for (uint32_t i = 0; i < kTrajGroupMax; ++i) {
         if (i < k && uni(op[i].kind) == TOP_KRAUS) {
-            const uint32_t bit = member_bit(uni(op[i].mask));
             const double g00 = op[i].cf[0], g01 = op[i].cf[1], g10 = op[i].cf[2], g11 = op[i].cf[3];
-            double cs = 0.0, ds = 0.0;
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const bool one = ((uint32_t)e >> bit) & 1u;
-                ds = fma(q[e], one ? g11 : g10, ds);
-                q[e] *= one ? g01 : g00;
-                cs += q[e];
+            double cs, ds;
+            switch (uni(op[i].mask)) {
+            case 1: damp_member<1>(q, g00, g01, g10, g11, cs, ds); break;
+            case 2: damp_member<2>(q, g00, g01, g10, g11, cs, ds); break;
+            case 4: damp_member<4>(q, g00, g01, g10, g11, cs, ds); break;
+            default: damp_member<8>(q, g00, g01, g10, g11, cs, ds); break;
             }
 #pragma unroll
             for (int j = 0; j < NK; ++j) {
