@@ -514,10 +514,10 @@ void place_phase(KPhase &H, uint32_t nthr, const Layout &phi, int n)
 // layout; a single-phase pass keeps its layout (its one phase loads and
 // stores); a pass that changes the layout stores into the other buffer, so
 // the number of changes is made even by giving up the least useful one.
-void relabel_passes(int n, HostPlan &plan)
+bool relabel_passes(int n, HostPlan &plan)
 {
     const size_t K = plan.passes.size();
-    if (K < 2) return;
+    if (K < 2) return true;
     const uint32_t full = (1u << n) - 1u;
     struct PInfo {
         uint32_t tile = 0, reg_first = 0, reg_last = 0;
@@ -591,6 +591,20 @@ void relabel_passes(int n, HostPlan &plan)
         if (best) lam[best] = lam[best - 1];
         else std::fill(lam.begin(), lam.end(), vec);
     }
+    // whether every pass loads and stores with its lowest physical qubit (the
+    // one whose row bit is position 0) outside the registers of the phase
+    // doing it, so that its lanes start on a contiguous run
+    bool io_ok = true;
+    auto lowest = [&](const Layout &phi) {
+        for (int q = 0; q < n; ++q)
+            if (phi[q] == 0) return q;
+        return 0;
+    };
+    for (size_t p = 0; p < K; ++p) {
+        const uint32_t in_q = 1u << lowest(lam[p]), out_q = 1u << lowest(lam[p + 1]);
+        io_ok = io_ok && (info[p].tile & in_q) && !(info[p].reg_first & in_q);
+        io_ok = io_ok && (info[p].tile & out_q) && !(info[p].reg_last & out_q);
+    }
     for (size_t p = 0; p < K; ++p) {
         KPass &P = plan.passes[p];
         const Layout &li = lam[p], &lo = lam[p + 1];
@@ -631,6 +645,25 @@ void relabel_passes(int n, HostPlan &plan)
         if (P.phase_end - P.phase_begin > 1) coalesce_lanes(plan.phases[P.phase_end - 1], nthr, lo, n);
     }
     plan.relabelled = true;
+    return io_ok;
+}
+
+// Qubits of a Hermitian pass's tile (logical positions: before relabelling).
+uint32_t pass_tile(const KPass &P, int n)
+{
+    const uint32_t m = P.n_group_bits >> 1;
+    uint32_t g = 0;
+    for (uint32_t k = 0; k < m; ++k) g |= 1u << P.group_gpos[k];
+    return ((1u << n) - 1u) & ~g;
+}
+
+// Qubits with a bit among a phase's register bits.
+uint32_t reg_qubits(const KPhase &H, int n)
+{
+    uint32_t m = 0;
+    for (int b = 0; b < kRegBits; ++b)
+        if (H.reg_gpos[b] < 2u * (uint32_t)n) m |= 1u << (H.reg_gpos[b] % (uint32_t)n);
+    return m;
 }
 
 // Tile-local bit positions are labels of the LDS layout alone, so a pass
@@ -734,7 +767,15 @@ void spread_lane_banks(HostPlan &plan)
 
 }  // namespace
 
-int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out)
+// share_mode (Hermitian plans with relabelled layouts): instead of keeping
+// qubits 0..hc-1 in every tile, each tile keeps a qubit of the previous
+// tile that the previous pass's storing phase holds outside its registers,
+// and the loading phase is padded only where that qubit would be in its
+// registers; the relabelled layout between the two passes leads with it.
+// Returns kPlanRetry when some pass's I/O would still start in a register.
+constexpr int kPlanRetry = 1;
+
+int plan_program_mode(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out, bool share_mode)
 {
     out = HostPlan{};
     const int n2 = 2 * n;
@@ -754,7 +795,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
     int kmax = 1;
     for (const LOp &op : ops)
         if (!op.diag) kmax = std::max(kmax, op.k);
-    const int hc = herm ? std::max(0, std::min(std::min(std::min(contig, 3), n), L / 2 - kmax)) : 0;
+    const int hc = (herm && !share_mode) ? std::max(0, std::min(std::min(std::min(contig, 3), n), L / 2 - kmax)) : 0;
     const uint32_t forced = (1u << hc) - 1u;        // qubits in every Hermitian tile
     const int max_take = opt.max_ops_per_pass;
     // LDS left for the runtime-diagonal tables beside the staged tile
@@ -783,6 +824,9 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
     size_t first = 0;
     SimResult sim, sim2;
     int retry_take = 0;     // > 0: the last attempt at this pass overflowed LDS
+    // share_mode: the previous tile's qubits outside its storing registers
+    // (before the first pass: qubit 0, which leads the caller's layout)
+    uint32_t prev_free = share_mode ? 1u : 0u;
     while (true) {
         while (first < ops.size() && applied[first]) ++first;
         if (first >= ops.size()) break;
@@ -800,7 +844,8 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 const uint32_t Q2 = Q | c;
                 // the contiguous low bits are a preference: the first op of a
                 // pass may use them when it cannot fit otherwise
-                const bool fits = herm ? (int)tile_bits_for(Q2 | forced, n, 0).size() <= L
+                const int reserve = (share_mode && prev_free && !(Q2 & prev_free)) ? 2 : 0;
+                const bool fits = herm ? (int)tile_bits_for(Q2 | forced, n, 0).size() + reserve <= L
                                        : ((int)tile_bits_for(Q2, n, contig).size() <= L ||
                                           (Q == 0 && (int)tile_bits_for(Q2, n, 0).size() <= L));
                 if (!fits) continue;
@@ -813,6 +858,8 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             if (bestQ == Q) break;
             Q = bestQ;
         }
+        if (share_mode && prev_free && !(Q & prev_free) && popc(Q) < L / 2)
+            Q |= 1u << __builtin_ctz(prev_free);
         if (herm)      // the tile's filler qubits are the lowest others: ops on them may join too
             for (int q = 0; popc(Q) < L / 2 && q < n; ++q) Q |= 1u << q;
         simulate(ops, qm, applied, first, Q, n, take_cap, sim, false);
@@ -1250,14 +1297,36 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
                 return false;
             };
             const size_t first_ph = kp.phase_begin;
-            const bool pad_front = io_in_regs(out.phases[first_ph]);
-            const bool pad_back = io_in_regs(out.phases.back());
+            bool pad_front = io_in_regs(out.phases[first_ph]);
+            bool pad_back = io_in_regs(out.phases.back());
+            std::vector<int> avoid = io_gpos, avoid_back = io_gpos;
+            if (share_mode) {
+                // the loading phase must leave a shared free qubit out of its
+                // registers (qubit 0 for the first pass, which loads the
+                // caller's layout); the last pass stores the caller's layout,
+                // led by qubit 0
+                const uint32_t S = tq & prev_free;
+                pad_front = S && !(S & ~reg_qubits(out.phases[first_ph], n));
+                if (pad_front) avoid = {__builtin_ctz(S), __builtin_ctz(S) + n};
+                bool last_pass = true;
+                for (size_t i = first; i < ops.size() && last_pass; ++i) last_pass = applied[i] != 0;
+                pad_back = last_pass && (reg_qubits(out.phases.back(), n) & 1u);
+                avoid_back = {0, n};
+                // a pass with one phase would load and store through the same
+                // registers and keep its layout: give it a storing phase of
+                // its own, so that every boundary gets its relabelled layout
+                if (out.phases.size() - first_ph == 1) pad_back = true;
+            }
             if (pad_front || pad_back) {
-                int reg[4];
-                fill_regs(reg, {}, io_gpos);
                 const std::vector<Block> none;
-                if (pad_back) emit_phase(reg, none, {});
+                if (pad_back) {
+                    int reg[4];
+                    fill_regs(reg, {}, avoid_back);
+                    emit_phase(reg, none, {});
+                }
                 if (pad_front) {
+                    int reg[4];
+                    fill_regs(reg, {}, avoid);
                     const uint32_t ob = out.phases[first_ph].op_begin;
                     emit_phase(reg, none, {});
                     KPhase dummy = out.phases.back();
@@ -1329,6 +1398,7 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
         std::copy(kp.group_gpos, kp.group_gpos + 32, kp.out_gpos);   // the layout stays
         kp.swap_out = 0;
         out.passes.push_back(kp);
+        if (share_mode) prev_free = pass_tile(kp, n) & ~reg_qubits(out.phases[kp.phase_end - 1], n);
     }
     if (herm) {
         // between the passes of a program only the computed half is stored;
@@ -1337,12 +1407,21 @@ int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPl
             if (i > 0) out.passes[i].herm |= kHermHalfIn;
             if (i + 1 == out.passes.size()) out.passes[i].herm |= kHermMirror;
         }
-        if (opt.relayout) relabel_passes(n, out);
+        if (opt.relayout && !relabel_passes(n, out) && share_mode) return kPlanRetry;
     }
     relabel_tile_bits(out);
     spread_lane_banks(out);
     finish_slot_tables(n, out);
     return VQD_OK;
+}
+
+int plan_program(int n, const std::vector<LOp> &ops, const PlanOpts &opt, HostPlan &out)
+{
+    if (opt.relayout && opt.hermitian) {
+        const int rc = plan_program_mode(n, ops, opt, out, true);
+        if (rc != kPlanRetry) return rc;
+    }
+    return plan_program_mode(n, ops, opt, out, false);
 }
 
 void finish_slot_tables(int n, HostPlan &plan)

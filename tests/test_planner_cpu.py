@@ -337,7 +337,9 @@ def test_relabelling_makes_tiles_contiguous(vqd_host):
     tile's qubits lowest: almost every pass loads whole waves of 64
     consecutive amplitudes (6 or more leading lanes), and half or more store
     runs of 16 or more; the vectorised layout leads with its forced qubits'
-    row bits only (runs of 2 to 8)."""
+    row bits only (runs of 2 to 8).  With relabelled layouts a tile keeps a
+    qubit of the previous tile instead of qubit 0, which needs fewer passes
+    (136 against 168)."""
     n = 14
     ops = c2_grid_circuit(rows=2, cols=7, n_gates=2000)
     plans = {}
@@ -345,7 +347,7 @@ def test_relabelling_makes_tiles_contiguous(vqd_host):
         prog = vqd_host.Program(n, ops)
         prog.plan(vqd_host.plan_opts(tile_bits=12, min_contig_bits=1, hermitian=True, relayout=rel))
         plans[rel] = (emu.parse(prog.export()), prog.info())
-    assert plans[True][1]["n_passes"] == plans[False][1]["n_passes"]
+    assert plans[True][1]["n_passes"] < plans[False][1]["n_passes"]
     load_rel, store_rel = lane_runs(plans[True][0], 0), lane_runs(plans[True][0], 1)
     load_vec, store_vec = lane_runs(plans[False][0], 0), lane_runs(plans[False][0], 1)
     assert np.mean(load_rel[1:] >= 6) > 0.95
