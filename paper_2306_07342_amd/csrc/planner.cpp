@@ -10,6 +10,8 @@
 // diagonal ops may join wherever their dependencies allow, because their
 // factor depends only on an amplitude's own index.  Q is grown greedily,
 // each step adding the blocked op's qubits that let the most ops join.
+// Hermitian plans with relabelled layouts replace the forced low qubits by
+// one qubit shared with the previous tile (see plan_program_mode).
 //
 // Phases.  Inside a pass, ops are grouped into register phases of at most
 // two qubits (4 register bits: row and column bit of each).  Ops of a phase
