@@ -348,6 +348,9 @@ def test_relabelling_makes_tiles_contiguous(vqd_host):
         prog.plan(vqd_host.plan_opts(tile_bits=12, min_contig_bits=1, hermitian=True, relayout=rel))
         plans[rel] = (emu.parse(prog.export()), prog.info())
     assert plans[True][1]["n_passes"] < plans[False][1]["n_passes"]
+    # every boundary leads with a qubit both tiles hold, outside the
+    # registers of the storing and the loading phase: no 16-byte scatter
+    assert lane_runs(plans[True][0], 1).min() >= 2 and lane_runs(plans[True][0], 0)[1:].min() >= 2
     load_rel, store_rel = lane_runs(plans[True][0], 0), lane_runs(plans[True][0], 1)
     load_vec, store_vec = lane_runs(plans[False][0], 0), lane_runs(plans[False][0], 1)
     assert np.mean(load_rel[1:] >= 6) > 0.95
