@@ -393,14 +393,17 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
 // mixed-unitary member must leave every population as it is (diagonal
 // entries of magnitude 1, up to the rounding of the stored unitary's
 // normalisation), so that the damping members' weights can all be formed
-// from the run's input state.
+// from the run's input state; a damping member must be trace preserving.
 constexpr double kUnitTol = 1e-15;
 
 void mark_groups(std::vector<TOp> &kops, uint32_t begin, uint32_t end)
 {
     auto member = [&](const TOp &k) {
         if (k.inl != 1u) return false;
-        if (k.kind == TOP_KRAUS) return true;
+        // damping: trace preserving (G0 + G1 = I), so that a run's draws
+        // need only the running sums of the no-jump weights
+        if (k.kind == TOP_KRAUS)
+            return std::abs(k.cf[0] + k.cf[2] - 1.0) <= kUnitTol && std::abs(k.cf[1] + k.cf[3] - 1.0) <= kUnitTol;
         if (k.kind != TOP_MIX) return false;
         for (int j = 2; j < 6; ++j)
             if (std::abs(std::abs(k.cf[j]) - 1.0) > kUnitTol) return false;

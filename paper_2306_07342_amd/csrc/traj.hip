@@ -496,13 +496,16 @@ struct UBlock {
 // diagonal when no jump is drawn and the mixed-unitary members leave the
 // populations alone, so every damping draw's weights follow from the run's
 // input populations p_e: with q_e^(k) = p_e times the no-jump Gram factors
-// G0 of the damping members before member k, and C_k = sum_e q_e^(k)
-// (C_0 = 1), the state before member k is the input scaled by its no-jump
-// factors over sqrt(C_k), so that member's weights are C_(k+1) / C_k for the
-// no-jump operator and D_k / C_k (D_k: the same sum with G1) for the jump.
-// The draws compare C_(k+1) and C_(k+1) + D_k with u times the total (the
-// common factor 1 / C_k dropped); the result is the input times every
-// member's diagonal factors, over sqrt of the last C.  When some member
+// G0 of the damping members before member k, and C_k = sum_e q_e^(k), the
+// state before member k is the input scaled by its no-jump factors over
+// sqrt(C_k / C_0), so that member's weights are proportional to C_(k+1) for
+// the no-jump operator and to D_k = sum_e q_e^(k) G1(e) for the jump.  The
+// members are trace preserving (G0 + G1 = I, checked by the planner), so
+// C_(k+1) + D_k = C_k: the reduction carries C_0 .. C_K only, and the draws
+// compare C_(k+1) and C_k with u C_k.  The result is the input times every
+// member's diagonal factors, over sqrt(C_K / C_0) with the sequential
+// draws' normalisation (which divides by the weights as formed, C_0
+// included), i.e. over sqrt of C_K.  When some member
 // draws its jump nothing is written and false is returned: the caller then
 // takes the members one by one, which repeats the same draws.
 __device__ __forceinline__ uint32_t member_bit(uint32_t mask)
@@ -510,13 +513,11 @@ __device__ __forceinline__ uint32_t member_bit(uint32_t mask)
     return (mask & 1u) ? 0u : (mask & 2u) ? 1u : (mask & 4u) ? 2u : 3u;
 }
 
-// One damping member of a run, register bit MASK: this thread's parts of
-// C_(k+1) = sum_e q_e G0(e) and D_k = sum_e q_e G1(e), from the populations
-// with the bit clear (s0) and set (s1), each summed as a tree; then q_e *=
-// G0(e).
+// One damping member of a run, register bit MASK: this thread's part of
+// C_(k+1) = sum_e q_e G0(e), from the populations with the bit clear (s0)
+// and set (s1), each summed as a tree; then q_e *= G0(e).
 template <int MASK>
-__device__ __forceinline__ void damp_member(double (&q)[16], double g00, double g01, double g10, double g11,
-                                            double &cs, double &ds)
+__device__ __forceinline__ void damp_member(double (&q)[16], double g00, double g01, double &cs)
 {
     double h[2][8];
     int n0 = 0, n1 = 0;
@@ -530,7 +531,6 @@ __device__ __forceinline__ void damp_member(double (&q)[16], double g00, double 
     for (int b = 0; b < 2; ++b)
         s[b] = ((h[b][0] + h[b][1]) + (h[b][2] + h[b][3])) + ((h[b][4] + h[b][5]) + (h[b][6] + h[b][7]));
     cs = fma(g01, s[1], g00 * s[0]);
-    ds = fma(g11, s[1], g10 * s[0]);
 #pragma unroll
     for (int e = 0; e < 16; ++e) q[e] *= (e & MASK) ? g01 : g00;
 }
@@ -547,32 +547,31 @@ __device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[
         u[i] = 0.0;
         if (i < k) u[i] = ub.take<WIDE>(next_ch++);
     }
-    double q[16], r[2 * NK];
+    double q[16], r[NK + 1];
 #pragma unroll
     for (int e = 0; e < 16; ++e) q[e] = fma(x[e].x, x[e].x, x[e].y * x[e].y);
+    r[0] = (((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]))) +
+           (((q[8] + q[9]) + (q[10] + q[11])) + ((q[12] + q[13]) + (q[14] + q[15])));
 #pragma unroll
-    for (int j = 0; j < 2 * NK; ++j) r[j] = 0.0;
+    for (int j = 1; j <= NK; ++j) r[j] = 0.0;
     uint32_t kk = 0;
 #pragma unroll
     for (uint32_t i = 0; i < kTrajGroupMax; ++i) {
         if (i < k && uni(op[i].kind) == TOP_KRAUS) {
-            const double g00 = op[i].cf[0], g01 = op[i].cf[1], g10 = op[i].cf[2], g11 = op[i].cf[3];
-            double cs, ds;
+            const double g00 = op[i].cf[0], g01 = op[i].cf[1];
+            double cs;
             switch (uni(op[i].mask)) {
-            case 1: damp_member<1>(q, g00, g01, g10, g11, cs, ds); break;
-            case 2: damp_member<2>(q, g00, g01, g10, g11, cs, ds); break;
-            case 4: damp_member<4>(q, g00, g01, g10, g11, cs, ds); break;
-            default: damp_member<8>(q, g00, g01, g10, g11, cs, ds); break;
+            case 1: damp_member<1>(q, g00, g01, cs); break;
+            case 2: damp_member<2>(q, g00, g01, cs); break;
+            case 4: damp_member<4>(q, g00, g01, cs); break;
+            default: damp_member<8>(q, g00, g01, cs); break;
             }
 #pragma unroll
-            for (int j = 0; j < NK; ++j) {
-                r[2 * j] += (kk == (uint32_t)j) ? cs : 0.0;
-                r[2 * j + 1] += (kk == (uint32_t)j) ? ds : 0.0;
-            }
+            for (int j = 0; j < NK; ++j) r[j + 1] += (kk == (uint32_t)j) ? cs : 0.0;
             ++kk;
         }
     }
-    group_sum<2 * NK, WIDE>(r, log_tt, red, wave, wpt, flip);
+    group_sum<NK + 1, WIDE>(r, log_tt, red, wave, wpt, flip);
     bool jump = false;
     double last = 1.0, f0b[4] = {1.0, 1.0, 1.0, 1.0}, f1b[4] = {1.0, 1.0, 1.0, 1.0};
     kk = 0;
@@ -587,13 +586,13 @@ __device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[
                 f0 = j ? m.cf[4] : m.cf[2];
                 f1 = j ? m.cf[5] : m.cf[3];
             } else {
-                double cw = r[0], dw = r[1];
+                double tot = r[0], cw = r[1];
 #pragma unroll
                 for (int j = 1; j < NK; ++j) {
-                    cw = (kk == (uint32_t)j) ? r[2 * j] : cw;
-                    dw = (kk == (uint32_t)j) ? r[2 * j + 1] : dw;
+                    tot = (kk == (uint32_t)j) ? r[j] : tot;
+                    cw = (kk == (uint32_t)j) ? r[j + 1] : cw;
                 }
-                const double tot = cw + dw, thr = u[i] * tot;
+                const double dw = tot - cw, thr = u[i] * tot;
                 jump = jump || (!(cw > thr) && (tot > thr || dw > 0.0));
                 last = cw;
                 ++kk;

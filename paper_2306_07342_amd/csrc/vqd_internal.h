@@ -322,8 +322,8 @@ struct alignas(16) TOp {
     uint32_t inl;
     // On the first op of a run of inl = 1 channels in one phase (at most
     // kTrajGroupMax ops, at most kTrajGroupKraus of them damping, at least
-    // two; the mixed-unitary ones with diagonal entries of magnitude 1 within
-    // 1e-15): the run's length.  Trajectories of whole waves draw the run with
+    // two, trace preserving within 1e-15; the mixed-unitary ones with
+    // diagonal entries of magnitude 1 within 1e-15): the run's length.  Trajectories of whole waves draw the run with
     // one reduction; 0 elsewhere.
     uint32_t grp;
     uint32_t pad_[2];

@@ -88,17 +88,18 @@ def _group(psi, members, reg, urow):
     """A marked run of inline one-qubit channels drawn the way trajectories
     of whole waves draw it: every damping member's weights from the run's
     input populations (times the no-jump Gram factors of the damping members
-    before it), one product of diagonal factors, one normalisation.  None if
-    some damping member draws its jump (the kernel then takes the members
-    one by one)."""
+    before it), one product of diagonal factors, one normalisation.  The
+    damping members are trace preserving, so member k's total weight is the
+    previous running sum C_k.  None if some damping member draws its jump
+    (the kernel then takes the members one by one)."""
     x = np.arange(psi.size)
     bits = [(x >> int(reg[int(m["mask"]).bit_length() - 1])) & 1 for m in members]
     q = np.abs(psi) ** 2
-    C, D = [], []
+    C = [float(np.sum(q))]
     for m, b in zip(members, bits):
         if int(m["kind"]) == TOP_KRAUS:
             cf = m["cf"]
-            D.append(float(np.sum(q * np.where(b == 1, cf[3], cf[2]))))
+            assert abs(cf[0] + cf[2] - 1) <= 1e-15 and abs(cf[1] + cf[3] - 1) <= 1e-15
             q = q * np.where(b == 1, cf[1], cf[0])
             C.append(float(np.sum(q)))
     f = np.ones(psi.size)
@@ -109,8 +110,8 @@ def _group(psi, members, reg, urow):
             j = cf[0] <= u * cf[1]
             f0, f1 = (cf[4], cf[5]) if j else (cf[2], cf[3])
         else:
-            c, d = C[kk], D[kk]
-            tot = c + d
+            tot, c = C[kk], C[kk + 1]
+            d = tot - c
             thr = u * tot
             if not (c > thr) and (tot > thr or d > 0.0):
                 return None
