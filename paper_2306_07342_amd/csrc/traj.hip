@@ -503,11 +503,13 @@ struct UBlock {
 // members are trace preserving (G0 + G1 = I, checked by the planner), so
 // C_(k+1) + D_k = C_k: the reduction carries C_0 .. C_K only, and the draws
 // compare C_(k+1) and C_k with u C_k.  The result is the input times every
-// member's diagonal factors, over sqrt(C_K / C_0) with the sequential
-// draws' normalisation (which divides by the weights as formed, C_0
-// included), i.e. over sqrt of C_K.  When some member
-// draws its jump nothing is written and false is returned: the caller then
-// takes the members one by one, which repeats the same draws.
+// member's diagonal factors over sqrt(C_K): the member-by-member draws
+// normalise by the weights as they form them, whose product is C_K.  When a
+// damping member draws its jump, only the members before it are applied
+// (over sqrt of the running sum before it) and their count is returned:
+// the caller takes the rest one by one, from the member that jumped, which
+// repeats its draw.  Returns the number of members applied (0: nothing
+// written).
 __device__ __forceinline__ uint32_t member_bit(uint32_t mask)
 {
     return (mask & 1u) ? 0u : (mask & 2u) ? 1u : (mask & 4u) ? 2u : 3u;
@@ -536,7 +538,7 @@ __device__ __forceinline__ void damp_member(double (&q)[16], double g00, double 
 }
 
 template <bool WIDE>
-__device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+__device__ __forceinline__ uint32_t traj_group(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
                                            uint32_t k, UBlock &ub, uint32_t &next_ch, uint32_t log_tt,
                                            double *red, uint32_t wave, uint32_t wpt, uint32_t &flip)
 {
@@ -572,12 +574,16 @@ __device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[
         }
     }
     group_sum<NK + 1, WIDE>(r, log_tt, red, wave, wpt, flip);
+    // members before the first drawn jump (all of them when none is) are
+    // applied: their factors, and the normalisation 1 / sqrt(C_kk) of the kk
+    // damping members among them (none: 1)
     bool jump = false;
+    uint32_t used = k;
     double last = 1.0, f0b[4] = {1.0, 1.0, 1.0, 1.0}, f1b[4] = {1.0, 1.0, 1.0, 1.0};
     kk = 0;
 #pragma unroll
     for (uint32_t i = 0; i < kTrajGroupMax; ++i) {
-        if (i < k) {
+        if (i < k && !jump) {
             const TOp &m = op[i];
             const uint32_t bit = member_bit(uni(m.mask));
             double f0, f1;
@@ -593,11 +599,12 @@ __device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[
                     cw = (kk == (uint32_t)j) ? r[j + 1] : cw;
                 }
                 const double dw = tot - cw, thr = u[i] * tot;
-                jump = jump || (!(cw > thr) && (tot > thr || dw > 0.0));
-                last = cw;
-                ++kk;
-                f0 = m.cf[4];
-                f1 = m.cf[5];
+                jump = !(cw > thr) && (tot > thr || dw > 0.0);
+                f0 = jump ? 1.0 : m.cf[4];
+                f1 = jump ? 1.0 : m.cf[5];
+                used = jump ? i : used;
+                last = jump ? last : cw;
+                kk += jump ? 0u : 1u;
             }
 #pragma unroll
             for (uint32_t b = 0; b < 4; ++b) {
@@ -606,8 +613,8 @@ __device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[
             }
         }
     }
-    if (jump) return false;
-    const double s = 1.0 / sqrt(last);
+    if (used == 0) return 0;
+    const double s = (kk == 0) ? 1.0 : 1.0 / sqrt(last);
     double lo[4], hi[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -619,7 +626,7 @@ __device__ __forceinline__ bool traj_group(const double2 (&x)[16], double2 (&y)[
         const double f = lo[e & 3] * hi[e >> 2];
         y[e] = make_double2(f * x[e].x, f * x[e].y);
     }
-    return true;
+    return used;
 }
 
 // One step of a phase's op list, x -> y: a marked run as one draw when the
@@ -637,12 +644,16 @@ __device__ __forceinline__ uint32_t traj_step(const double2 (&x)[16], double2 (&
         if (k > 1u) {
             const uint32_t base = ub.base, ch = next_ch;
             const double cur = ub.cur, nxt = ub.nxt;
-            if (traj_group<WIDE>(x, y, op, k, ub, next_ch, log_tt, red, wave, wpt, flip)) return oi + k;
-            // the members one by one, from the same uniforms
+            const uint32_t used = traj_group<WIDE>(x, y, op, k, ub, next_ch, log_tt, red, wave, wpt, flip);
+            if (used == k) return oi + k;
+            // the rest of the run one by one, from the same uniforms: the
+            // member that drew its jump comes next (at oi itself when it is
+            // the first, and nothing has been written)
             ub.base = base;
             ub.cur = cur;
             ub.nxt = nxt;
-            next_ch = ch;
+            next_ch = ch + used;
+            if (used) return oi + used;
         }
     }
     double u = 0.0;

@@ -90,8 +90,10 @@ def _group(psi, members, reg, urow):
     input populations (times the no-jump Gram factors of the damping members
     before it), one product of diagonal factors, one normalisation.  The
     damping members are trace preserving, so member k's total weight is the
-    previous running sum C_k.  None if some damping member draws its jump
-    (the kernel then takes the members one by one)."""
+    previous running sum C_k.  Returns (state, members applied): when a
+    damping member draws its jump only the members before it are applied
+    (the kernel takes the rest one by one, from that member); (None, 0) when
+    the first member jumps."""
     x = np.arange(psi.size)
     bits = [(x >> int(reg[int(m["mask"]).bit_length() - 1])) & 1 for m in members]
     q = np.abs(psi) ** 2
@@ -104,7 +106,7 @@ def _group(psi, members, reg, urow):
             C.append(float(np.sum(q)))
     f = np.ones(psi.size)
     last, kk = 1.0, 0
-    for m, b in zip(members, bits):
+    for i, (m, b) in enumerate(zip(members, bits)):
         cf, u = m["cf"], float(urow[int(m["chan"])])
         if int(m["kind"]) == TOP_MIX:
             j = cf[0] <= u * cf[1]
@@ -114,11 +116,13 @@ def _group(psi, members, reg, urow):
             d = tot - c
             thr = u * tot
             if not (c > thr) and (tot > thr or d > 0.0):
-                return None
+                if i == 0:
+                    return None, 0
+                return psi * f / (math.sqrt(last) if kk else 1.0), i
             last, kk = c, kk + 1
             f0, f1 = cf[4], cf[5]
         f = f * np.where(b == 1, f1, f0)
-    return psi * f / math.sqrt(last)
+    return psi * f / math.sqrt(last), len(members)
 
 
 def run(plan: dict, U: np.ndarray, groups: bool = False, stats: dict = None):
@@ -150,14 +154,14 @@ def run(plan: dict, U: np.ndarray, groups: bool = False, stats: dict = None):
                 k = int(op["grp"])
                 if groups and k > 1:
                     members = plan["ops"][idx:idx + k]
-                    out = _group(psi, members, ph["reg"], U[t])
+                    out, used = _group(psi, members, ph["reg"], U[t])
                     if stats is not None:
-                        stats["grouped" if out is not None else "fallback"] += 1
-                    if out is not None:
+                        stats["grouped" if used == k else "fallback"] += 1
+                    if used:
                         psi = out
-                        skip = k - 1
+                        skip = used - 1
                         if t == 0:
-                            order.extend(int(m["chan"]) for m in members)
+                            order.extend(int(m["chan"]) for m in members[:used])
                         continue
                 kind = int(op["kind"])
                 if kind == TOP_DTHR:
