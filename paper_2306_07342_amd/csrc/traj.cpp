@@ -197,6 +197,7 @@ uint32_t put_matrix(std::vector<cd> &pool, const std::vector<cd> &M, const std::
 // Encode the ops of one phase with register qubits R.
 int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
 {
+    const size_t first_k = t->kops.size();
     for (const POp &o : ops) {
         TOp k{};
         const int nq = (int)o.qs.size(), d = 1 << nq;
@@ -383,6 +384,17 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                 // drawn operator, its scaling, and this thread's part of rho_T
                 t->fma_per_amp += op_cost(Ks[mode]) + 2.0 + (k.gdiag ? 2.0 : 2.0 * d);
             }
+        }
+        // a register diagonal right after another one: one set of 16
+        // factors, their products (diagonal factors commute)
+        if (k.kind == TOP_DREG && t->kops.size() > first_k && t->kops.back().kind == TOP_DREG &&
+            k.mat + kSlots == t->pool.size()) {
+            TOp &p = t->kops.back();
+            for (int e = 0; e < kSlots; ++e) t->pool[p.mat + e] *= t->pool[k.mat + e];
+            t->pool.resize(k.mat);
+            p.real = (p.real && k.real) ? 1u : 0u;
+            t->fma_per_amp -= k.real ? 2.0 : 4.0;
+            continue;
         }
         t->kops.push_back(k);
     }
