@@ -396,6 +396,30 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
             t->fma_per_amp -= k.real ? 2.0 : 4.0;
             continue;
         }
+        // a register diagonal and a one-register, one-thread-qubit diagonal
+        // next to each other (either order): one op, one descriptor and one
+        // coefficient block
+        if (t->kops.size() > first_k && !t->kops.back().inl) {
+            TOp &p = t->kops.back();
+            const bool reg_then_mix = p.kind == TOP_DREG && k.kind == TOP_DMIX && k.mat + 4 == t->pool.size() &&
+                                      p.mat + kSlots == k.mat;
+            const bool mix_then_reg = p.kind == TOP_DMIX && k.kind == TOP_DREG &&
+                                      k.mat + kSlots == t->pool.size() && p.mat + 4 == k.mat;
+            if (reg_then_mix || mix_then_reg) {
+                std::vector<cd> block(kSlots + 4);
+                const size_t reg_at = reg_then_mix ? p.mat : k.mat, mix_at = reg_then_mix ? k.mat : p.mat;
+                for (int e = 0; e < kSlots; ++e) block[e] = t->pool[reg_at + e];
+                for (int j = 0; j < 4; ++j) block[kSlots + j] = t->pool[mix_at + j];
+                std::copy(block.begin(), block.end(), t->pool.begin() + p.mat);
+                const TOp &mix = reg_then_mix ? k : p;
+                const uint32_t mask = mix.mask, dq0 = mix.dq[0];
+                p.kind = TOP_DRM;
+                p.mask = mask;
+                p.dq[0] = dq0;
+                p.real = (p.real && k.real) ? 1u : 0u;
+                continue;
+            }
+        }
         t->kops.push_back(k);
     }
     return VQD_OK;

@@ -397,6 +397,18 @@ __device__ __forceinline__ void traj_dmix(const double2 (&x)[16], double2 (&y)[1
     for (int e = 0; e < 16; ++e) y[e] = cmul((e & MASK) ? f1 : f0, x[e]);
 }
 
+// A register diagonal and a one-register, one-thread-qubit diagonal as one
+// op: the 16 slot factors times the two factors the thread bit selects.
+template <int MASK>
+__device__ __forceinline__ void traj_drm(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+                                         const double2 *__restrict__ M, const TCtx &c)
+{
+    const uint32_t tb = (c.tl >> (uni(op->dq[0]) & 31u)) & 1u;
+    const double2 f0 = tb ? M[18] : M[16], f1 = tb ? M[19] : M[17];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) y[e] = cmul(cmul(M[e], (e & MASK) ? f1 : f0), x[e]);
+}
+
 template <bool WIDE>
 __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
                                         const double2 *__restrict__ pool, const TCtx &c, double u, uint32_t log_tt,
@@ -427,6 +439,13 @@ __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16]
         case 2: traj_dmix<2>(x, y, op, M, c); break;
         case 4: traj_dmix<4>(x, y, op, M, c); break;
         default: traj_dmix<8>(x, y, op, M, c); break;
+        }
+    } else if (kind == TOP_DRM) {
+        switch (mask) {
+        case 1: traj_drm<1>(x, y, op, M, c); break;
+        case 2: traj_drm<2>(x, y, op, M, c); break;
+        case 4: traj_drm<4>(x, y, op, M, c); break;
+        default: traj_drm<8>(x, y, op, M, c); break;
         }
     } else if (WIDE && uni(op->inl) == 2u && op->cf[0] > u * op->cf[1]) {
         // operator 0, the identity, is drawn (no running sum is <= u W);

@@ -293,6 +293,8 @@ enum TOpKind : uint32_t {
     TOP_DREG = 5,     // diagonal gate on register qubits only: 16 factors, one per register slot
     TOP_DMIX = 6,     // two-qubit diagonal gate, one register qubit (bit `mask`) and one thread
                       // qubit dq[0]: factors (thread bit, register bit) = 00, 01, 10, 11
+    TOP_DRM = 7,      // a TOP_DREG and a TOP_DMIX in a row, as one op: 16 slot factors, then
+                      // the four TOP_DMIX factors (register bit `mask`, thread qubit dq[0])
 };
 
 struct alignas(16) TOp {
