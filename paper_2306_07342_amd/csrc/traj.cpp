@@ -405,6 +405,13 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                                       p.mat + kSlots == k.mat;
             const bool mix_then_reg = p.kind == TOP_DMIX && k.kind == TOP_DREG &&
                                       k.mat + kSlots == t->pool.size() && p.mat + 4 == k.mat;
+            if (p.kind == TOP_DMIX && k.kind == TOP_DMIX && p.mat + 4 == k.mat && k.mat + 4 == t->pool.size()) {
+                p.kind = TOP_DMIX2;
+                p.dmask = k.mask;
+                p.dq[1] = k.dq[0];
+                p.real = (p.real && k.real) ? 1u : 0u;
+                continue;
+            }
             if (reg_then_mix || mix_then_reg) {
                 std::vector<cd> block(kSlots + 4);
                 const size_t reg_at = reg_then_mix ? p.mat : k.mat, mix_at = reg_then_mix ? k.mat : p.mat;

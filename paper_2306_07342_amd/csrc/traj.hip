@@ -409,6 +409,22 @@ __device__ __forceinline__ void traj_drm(const double2 (&x)[16], double2 (&y)[16
     for (int e = 0; e < 16; ++e) y[e] = cmul(cmul(M[e], (e & MASK) ? f1 : f0), x[e]);
 }
 
+// Two one-register, one-thread-qubit diagonals as one op: per slot, the
+// factor the first's thread bit and register bit MASK select times the one
+// the second's select (its register bit a uniform runtime value).
+template <int MASK>
+__device__ __forceinline__ void traj_dmix2(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+                                           const double2 *__restrict__ M, const TCtx &c)
+{
+    const uint32_t ta = (c.tl >> (uni(op->dq[0]) & 31u)) & 1u, tb = (c.tl >> (uni(op->dq[1]) & 31u)) & 1u;
+    const uint32_t bit2 = uni(op->dmask);
+    const double2 a0 = ta ? M[2] : M[0], a1 = ta ? M[3] : M[1];
+    const double2 b0 = tb ? M[6] : M[4], b1 = tb ? M[7] : M[5];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+        y[e] = cmul(cmul((e & MASK) ? a1 : a0, ((uint32_t)e & bit2) ? b1 : b0), x[e]);
+}
+
 template <bool WIDE>
 __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
                                         const double2 *__restrict__ pool, const TCtx &c, double u, uint32_t log_tt,
@@ -439,6 +455,13 @@ __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16]
         case 2: traj_dmix<2>(x, y, op, M, c); break;
         case 4: traj_dmix<4>(x, y, op, M, c); break;
         default: traj_dmix<8>(x, y, op, M, c); break;
+        }
+    } else if (kind == TOP_DMIX2) {
+        switch (mask) {
+        case 1: traj_dmix2<1>(x, y, op, M, c); break;
+        case 2: traj_dmix2<2>(x, y, op, M, c); break;
+        case 4: traj_dmix2<4>(x, y, op, M, c); break;
+        default: traj_dmix2<8>(x, y, op, M, c); break;
         }
     } else if (kind == TOP_DRM) {
         switch (mask) {

@@ -295,6 +295,9 @@ enum TOpKind : uint32_t {
                       // qubit dq[0]: factors (thread bit, register bit) = 00, 01, 10, 11
     TOP_DRM = 7,      // a TOP_DREG and a TOP_DMIX in a row, as one op: 16 slot factors, then
                       // the four TOP_DMIX factors (register bit `mask`, thread qubit dq[0])
+    TOP_DMIX2 = 8,    // two TOP_DMIX in a row, as one op: the first's four factors (register
+                      // bit `mask`, thread qubit dq[0]), then the second's (register bit
+                      // `dmask`, thread qubit dq[1])
 };
 
 struct alignas(16) TOp {

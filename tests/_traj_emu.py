@@ -17,7 +17,7 @@ import numpy as np
 from oracle.trajectories import apply_matrix
 
 MAGIC = 0x54445156
-TOP_MAT, TOP_DTHR, TOP_MIX, TOP_KRAUS, TOP_DREG, TOP_DMIX, TOP_DRM = 1, 2, 3, 4, 5, 6, 7
+TOP_MAT, TOP_DTHR, TOP_MIX, TOP_KRAUS, TOP_DREG, TOP_DMIX, TOP_DRM, TOP_DMIX2 = 1, 2, 3, 4, 5, 6, 7, 8
 
 PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4", 9), ("flags", "<u4")])
 PHASE_REDUCES = 1
@@ -176,6 +176,14 @@ def run(plan: dict, U: np.ndarray, groups: bool = False, stats: dict = None):
                     if op["real"]:
                         assert np.all(f.imag == 0)
                     psi = apply_matrix(psi, [int(q) for q in ph["reg"]], np.diag(f))
+                    continue
+                if kind == TOP_DMIX2:
+                    # two TOP_DMIX: register bits mask and dmask, thread qubits dq
+                    f = pool[int(op["mat"]):int(op["mat"]) + 8]
+                    for j, m in enumerate((op["mask"], op["dmask"])):
+                        qr = _qubits(m, ph["reg"])
+                        assert len(qr) == 1
+                        psi = apply_matrix(psi, [qr[0], int(op["dq"][j])], np.diag(f[4 * j:4 * j + 4]))
                     continue
                 if kind == TOP_DRM:
                     # 16 factors by register slot, then a TOP_DMIX's four

@@ -59,7 +59,7 @@ def test_named_gates_and_channels(vqd_host):
            ("offres", (0,), (1.0, 2.0, 0.7)), ("crz", (1, 4), (0.8,)), ("parity_decay", (2, 0), ())]
     _, plan = check_plan(vqd_host, n, ops * 3, T=24)
     kinds = set(int(k) for k in plan["ops"]["kind"])
-    assert kinds == {emu.TOP_MAT, emu.TOP_DTHR, emu.TOP_DREG, emu.TOP_DMIX, emu.TOP_DRM, emu.TOP_MIX, emu.TOP_KRAUS}
+    assert kinds >= {emu.TOP_MAT, emu.TOP_DTHR, emu.TOP_DREG, emu.TOP_DMIX, emu.TOP_DRM, emu.TOP_MIX, emu.TOP_KRAUS}
 
 
 def test_workload_circuits(vqd_host):
