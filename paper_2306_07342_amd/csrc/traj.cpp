@@ -405,6 +405,47 @@ int encode_phase(vqd_traj *t, const int *R, const std::vector<POp> &ops)
                                       p.mat + kSlots == k.mat;
             const bool mix_then_reg = p.kind == TOP_DMIX && k.kind == TOP_DREG &&
                                       k.mat + kSlots == t->pool.size() && p.mat + 4 == k.mat;
+            // one-qubit gates in a row on register bits (each 2x2, complex,
+            // column-major), up to four
+            auto one_bit = [](const TOp &o) {
+                return o.kind == TOP_MAT && (o.mask == 1u || o.mask == 2u || o.mask == 4u || o.mask == 8u);
+            };
+            auto coefs = [&](const TOp &o, std::vector<cd> &c) {
+                if (o.real) {
+                    for (int i = 0; i < 2; ++i) {
+                        c.push_back(cd(t->pool[o.mat + i].real(), 0.0));
+                        c.push_back(cd(t->pool[o.mat + i].imag(), 0.0));
+                    }
+                } else {
+                    for (int i = 0; i < 4; ++i) c.push_back(t->pool[o.mat + i]);
+                }
+            };
+            auto bit_of = [](uint32_t m) { return (uint32_t)__builtin_ctz(m); };
+            const bool p_mats = p.kind == TOP_MATS && p.nd < 4u;
+            if (one_bit(k) && (one_bit(p) || p_mats) && k.mat + (k.real ? 2u : 4u) == t->pool.size()) {
+                std::vector<cd> block;
+                if (p_mats) {
+                    for (uint32_t i = 0; i < 4u * p.nd; ++i) block.push_back(t->pool[p.mat + i]);
+                } else {
+                    coefs(p, block);
+                    p.dmask = bit_of(p.mask);
+                    p.nd = 1;
+                }
+                coefs(k, block);
+                if (p.mat + (p_mats ? 4u * p.nd : (p.real ? 2u : 4u)) == k.mat) {
+                    t->pool.resize(p.mat);
+                    t->pool.insert(t->pool.end(), block.begin(), block.end());
+                    p.dmask |= bit_of(k.mask) << (2u * p.nd);
+                    ++p.nd;
+                    p.kind = TOP_MATS;
+                    p.real = 0;
+                    continue;
+                }
+                if (!p_mats) {   // not adjacent in the pool: leave both as they are
+                    p.nd = 0;
+                    p.dmask = 0;
+                }
+            }
             if (p.kind == TOP_DMIX && k.kind == TOP_DMIX && p.mat + 4 == k.mat && k.mat + 4 == t->pool.size()) {
                 p.kind = TOP_DMIX2;
                 p.dmask = k.mask;

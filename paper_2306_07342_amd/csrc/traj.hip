@@ -425,6 +425,45 @@ __device__ __forceinline__ void traj_dmix2(const double2 (&x)[16], double2 (&y)[
         y[e] = cmul(cmul((e & MASK) ? a1 : a0, ((uint32_t)e & bit2) ? b1 : b0), x[e]);
 }
 
+// A 2x2 complex matrix (column-major) on register bit MASK, in place.
+template <int MASK>
+__device__ __forceinline__ void mat1_inplace(double2 (&y)[16], const double2 *__restrict__ M)
+{
+    const double2 m00 = M[0], m10 = M[1], m01 = M[2], m11 = M[3];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        if (e & MASK) continue;
+        const double2 a0 = y[e], a1 = y[e | MASK];
+        double2 r0 = cmul(m00, a0), r1 = cmul(m10, a0);
+        cmac<false>(r0, m01, a1);
+        cmac<false>(r1, m11, a1);
+        y[e] = r0;
+        y[e | MASK] = r1;
+    }
+}
+
+// nd one-qubit gates on register bits as one op (TOP_MATS).
+__device__ __forceinline__ void traj_mats(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
+                                          const double2 *__restrict__ M)
+{
+    const uint32_t nd = uni(op->nd), bits = uni(op->dmask);
+    switch (bits & 3u) {
+    case 0: apply_mat<1, false>(x, y, M); break;
+    case 1: apply_mat<2, false>(x, y, M); break;
+    case 2: apply_mat<4, false>(x, y, M); break;
+    default: apply_mat<8, false>(x, y, M); break;
+    }
+    for (uint32_t j = 1; j < nd; ++j) {
+        const double2 *Mj = M + 4 * j;
+        switch ((bits >> (2 * j)) & 3u) {
+        case 0: mat1_inplace<1>(y, Mj); break;
+        case 1: mat1_inplace<2>(y, Mj); break;
+        case 2: mat1_inplace<4>(y, Mj); break;
+        default: mat1_inplace<8>(y, Mj); break;
+        }
+    }
+}
+
 template <bool WIDE>
 __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ op,
                                         const double2 *__restrict__ pool, const TCtx &c, double u, uint32_t log_tt,
@@ -456,6 +495,8 @@ __device__ __forceinline__ void traj_op(const double2 (&x)[16], double2 (&y)[16]
         case 4: traj_dmix<4>(x, y, op, M, c); break;
         default: traj_dmix<8>(x, y, op, M, c); break;
         }
+    } else if (kind == TOP_MATS) {
+        traj_mats(x, y, op, M);
     } else if (kind == TOP_DMIX2) {
         switch (mask) {
         case 1: traj_dmix2<1>(x, y, op, M, c); break;

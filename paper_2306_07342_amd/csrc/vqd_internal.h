@@ -298,6 +298,9 @@ enum TOpKind : uint32_t {
     TOP_DMIX2 = 8,    // two TOP_DMIX in a row, as one op: the first's four factors (register
                       // bit `mask`, thread qubit dq[0]), then the second's (register bit
                       // `dmask`, thread qubit dq[1])
+    TOP_MATS = 9,     // nd (2 to 4) one-qubit TOP_MATs in a row, as one op: matrix j acts on
+                      // register bit (dmask >> 2j) & 3, its 2x2 complex coefficients
+                      // (column-major) at 4j
 };
 
 struct alignas(16) TOp {

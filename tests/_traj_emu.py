@@ -17,7 +17,7 @@ import numpy as np
 from oracle.trajectories import apply_matrix
 
 MAGIC = 0x54445156
-TOP_MAT, TOP_DTHR, TOP_MIX, TOP_KRAUS, TOP_DREG, TOP_DMIX, TOP_DRM, TOP_DMIX2 = 1, 2, 3, 4, 5, 6, 7, 8
+TOP_MAT, TOP_DTHR, TOP_MIX, TOP_KRAUS, TOP_DREG, TOP_DMIX, TOP_DRM, TOP_DMIX2, TOP_MATS = 1, 2, 3, 4, 5, 6, 7, 8, 9
 
 PHASE = np.dtype([("ob", "<u4"), ("oe", "<u4"), ("reg", "<u4", 4), ("thr", "<u4", 9), ("flags", "<u4")])
 PHASE_REDUCES = 1
@@ -176,6 +176,14 @@ def run(plan: dict, U: np.ndarray, groups: bool = False, stats: dict = None):
                     if op["real"]:
                         assert np.all(f.imag == 0)
                     psi = apply_matrix(psi, [int(q) for q in ph["reg"]], np.diag(f))
+                    continue
+                if kind == TOP_MATS:
+                    # nd one-qubit matrices: register bit (dmask >> 2j) & 3, 2x2 column-major
+                    assert 2 <= int(op["nd"]) <= 4
+                    for j in range(int(op["nd"])):
+                        b = (int(op["dmask"]) >> (2 * j)) & 3
+                        off = int(op["mat"]) + 4 * j
+                        psi = apply_matrix(psi, [int(ph["reg"][b])], pool[off:off + 4].reshape(2, 2).T)
                     continue
                 if kind == TOP_DMIX2:
                     # two TOP_DMIX: register bits mask and dmask, thread qubits dq
