@@ -717,11 +717,27 @@ __device__ __forceinline__ uint32_t traj_group(const double2 (&x)[16], double2 (
 // Returns the index of the next op.
 template <bool WIDE>
 __device__ __forceinline__ uint32_t traj_step(const double2 (&x)[16], double2 (&y)[16], const TOp *__restrict__ ops,
-                                              uint32_t oi, const double2 *__restrict__ pool, const TCtx &c,
-                                              UBlock &ub, uint32_t &next_ch, uint32_t log_tt, double *red,
-                                              uint32_t wave, uint32_t wpt, uint32_t &flip)
+                                              uint32_t oi, uint32_t oe, const double2 *__restrict__ pool,
+                                              const TCtx &c, UBlock &ub, uint32_t &next_ch, uint32_t log_tt,
+                                              double *red, uint32_t wave, uint32_t wpt, uint32_t &flip)
 {
     const TOp *op = ops + oi;
+    if (WIDE && uni(op->inl) == 2u && oi + 1 < oe && uni(op[1].inl) == 2u) {
+        // two identity-first channels in a row: when both draw operator 0
+        // (the common case) the state is copied once
+        const uint32_t base = ub.base, ch = next_ch;
+        const double cur = ub.cur, nxt = ub.nxt;
+        const double u0 = ub.take<WIDE>(next_ch++), u1 = ub.take<WIDE>(next_ch++);
+        if (op->cf[0] > u0 * op->cf[1] && op[1].cf[0] > u1 * op[1].cf[1]) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) y[e] = x[e];
+            return oi + 2;
+        }
+        ub.base = base;
+        ub.cur = cur;
+        ub.nxt = nxt;
+        next_ch = ch;
+    }
     if (WIDE) {
         const uint32_t k = uni(op->grp);
         if (k > 1u) {
@@ -811,9 +827,9 @@ k_traj(const TPhase *__restrict__ phases, uint32_t n_phases, const TOp *__restri
             const uint32_t oe = uni(H->op_end);
             uint32_t oi = uni(H->op_begin);
             while (oi < oe) {
-                oi = traj_step<WIDE>(a, b, ops, oi, pool, c, ub, next_ch, log_tt, red, wave, wpt, flip);
+                oi = traj_step<WIDE>(a, b, ops, oi, oe, pool, c, ub, next_ch, log_tt, red, wave, wpt, flip);
                 if (oi < oe) {
-                    oi = traj_step<WIDE>(b, a, ops, oi, pool, c, ub, next_ch, log_tt, red, wave, wpt, flip);
+                    oi = traj_step<WIDE>(b, a, ops, oi, oe, pool, c, ub, next_ch, log_tt, red, wave, wpt, flip);
                 } else {
 #pragma unroll
                     for (int e = 0; e < 16; ++e) a[e] = b[e];
